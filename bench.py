@@ -1,0 +1,225 @@
+"""Benchmark of the RSRR hot path on one MI355X.
+
+A step is one full solve (Alg. 2 around Alg. 1: assembly, batched LU + solves
+with refinement, basis, projection, reduced problem, eigenpair recovery and
+residual filter) of one synthetic workload whose inputs are already resident
+in device memory.  The default workload is the dense delay eigenproblem
+T(z) = -z I + A0 + A1 exp(-z), n = 2048, circle |z| < 3, N = 48 nodes, L = 48
+probing vectors, complex64 factorisations with fp64 refinement.
+
+Prints one JSON line.  `value` = resolvent samples per second of the whole
+step (N samples per solve); eigenpairs per second and per-step latency
+percentiles are reported beside it.  The roofline object covers the kernel
+class that takes most of the step's device time (HIP events on its stream,
+recorded inside the library during the timed steps).  `cpu_baseline` is the
+CPU oracle timed on a bounded sample of the same workload (a few of its
+sampling nodes).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+PEAK = {"fp32_mfma": 157.3e12, "fp64_mfma": 78.6e12, "hbm": 8.0e12}
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def workload(name: str):
+    import nep_inputs as ni
+    if name == "c1":
+        p, c, N, L, U = ni.config_c1()
+        return dict(prob=p, contour=c, N=N, L=L, U=U,
+                    desc="delay NEP -zI + A0 + A1 exp(-z), n=2048, circle |z|<3, N=48, L=48")
+    if name == "c0":
+        p, c, N, L, U = ni.config_c0()
+        return dict(prob=p, contour=c, N=N, L=L, U=U,
+                    desc="dense QEP z^2 I + z C + K, n=200, circle centre 5i r=2, N=32, L=20")
+    if name == "c3":
+        p, c, N, L, U = ni.config_c3()
+        return dict(prob=p, contour=c, N=N, L=L, U=U,
+                    desc="Helmholtz BEM sphere n=8192, ellipse centre 3 (1.5, 0.3), N=40, L=64")
+    if name.startswith("c1n"):           # reduced-size variant of c1, e.g. c1n1024
+        n = int(name[3:])
+        p, c, N, L, U = ni.config_c1(n=n)
+        return dict(prob=p, contour=c, N=N, L=L, U=U, desc=f"delay NEP as c1 with n={n}")
+    raise SystemExit(f"unknown workload {name}")
+
+
+def kernel_roofline(timers: dict, steps: int):
+    """Dominant kernel class by device time; its algorithmic rate vs peak."""
+    if not timers:
+        return None, None
+    name, t = max(timers.items(), key=lambda kv: kv[1]["ms"])
+    avg_s = t["ms"] / 1e3 / max(1, t["launches"])
+    if t["flops"] > 0:
+        peak = PEAK["fp32_mfma"] if "c64" in name else PEAK["fp64_mfma"]
+        ach = t["flops"] / max(1, t["launches"]) / avg_s
+        roof = {"kernel": name, "bound": "mfma", "achieved": ach / 1e12, "peak": peak / 1e12,
+                "unit": "TFLOP/s", "frac": ach / peak, "traffic": None,
+                "launches_per_step": t["launches"] / steps, "avg_launch_ms": avg_s * 1e3,
+                "share_of_step_device_ms": None}
+    else:
+        ach = t["bytes"] / max(1, t["launches"]) / avg_s
+        roof = {"kernel": name, "bound": "hbm", "achieved": ach / 1e9, "peak": PEAK["hbm"] / 1e9,
+                "unit": "GB/s", "frac": ach / PEAK["hbm"], "traffic": None,
+                "launches_per_step": t["launches"] / steps, "avg_launch_ms": avg_s * 1e3}
+    return name, roof
+
+
+def cpu_baseline(w, max_nodes: int, budget_s: float):
+    """Oracle (Alg. 2 Step 2: zgesv per node) on the host for a few nodes."""
+    from oracle import rsrr_ref as R
+    try:
+        from threadpoolctl import threadpool_info
+        cores = max([d.get("num_threads", 0) for d in threadpool_info()] + [1])
+    except Exception:
+        cores = os.cpu_count()
+    _, z, _ = R.contour_nodes(w["contour"], w["N"])
+    t0 = time.perf_counter()
+    done = 0
+    for zj in z[:max_nodes]:
+        R.sample_resolvent(w["prob"], [zj], w["U"])
+        done += 1
+        if time.perf_counter() - t0 > budget_s:
+            break
+    dt = time.perf_counter() - t0
+    return {"value": done / dt, "unit": "resolvent samples/s", "cores": cores, "kind": "oracle",
+            "sample": f"Alg. 2 Step 2 only (dense LU solve per node, complex128) on {done} of the "
+                      f"{w['N']} sampling nodes of the same workload; the oracle's full solve "
+                      f"(projection + reduced problem) is not included, so this is an upper bound "
+                      f"on its end-to-end samples/s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="c1")
+    ap.add_argument("--precision", default="c64_ir", choices=["c64_ir", "c128"])
+    ap.add_argument("--cpu-nodes", type=int, default=4)
+    ap.add_argument("--cpu-budget", type=float, default=20.0)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--sample-compare", type=int, default=3,
+                    help="repetitions of the sampling stage alone in both precisions")
+    a = ap.parse_args()
+    if a.gpus != 1:
+        print(json.dumps({"error": "this build runs on exactly one GPU; --gpus must be 1"}))
+        sys.exit(2)
+
+    import torch
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    import paper_1510_07522_amd as P
+
+    w = workload(a.workload)
+    prob, c, N, L = w["prob"], w["contour"], w["N"], w["L"]
+    log(f"workload {a.workload}: {w['desc']}")
+    h = P.Problem(prob)
+    U = P.to_device(w["U"])
+    ct = P.contour(c.center, c.a, c.b)
+    prm = P.default_params(N=N, L=L, precision=a.precision)
+
+    for i in range(a.warmup):
+        t0 = time.perf_counter()
+        out = h.solve(ct, prm, U)
+        torch.cuda.synchronize()
+        log(f"warmup {i}: {time.perf_counter() - t0:.3f}s n_eig={out['info']['n_eig']}")
+
+    P.timers_reset()
+    P.timers_enable(True)
+    lat = []
+    n_eig = []
+    infos = []
+    torch.cuda.synchronize()
+    t_start = time.perf_counter()
+    for i in range(a.steps):
+        t0 = time.perf_counter()
+        out = h.solve(ct, prm, U)
+        torch.cuda.synchronize()
+        lat.append(time.perf_counter() - t0)
+        n_eig.append(out["info"]["n_eig"])
+        infos.append(out["info"])
+        log(f"step {i}: {lat[-1]:.3f}s n_eig={n_eig[-1]} res_max="
+            f"{(out['res'].max() if len(out['res']) else 0):.2e}")
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t_start
+    P.timers_enable(False)
+    timers = P.timers_read()
+    ms_step = elapsed / a.steps * 1e3
+    samples_s = N * a.steps / elapsed
+    eig_s = sum(n_eig) / elapsed
+    kname, roof = kernel_roofline(timers, a.steps)
+    dev_ms = sum(t["ms"] for t in timers.values()) / a.steps
+    if roof is not None:
+        roof["share_of_timed_device_ms"] = timers[kname]["ms"] / a.steps / max(dev_ms, 1e-9)
+
+    # sampling stage alone, both precisions (the c64 + refinement vs complex128 comparison)
+    stage = {}
+    if a.sample_compare > 0:
+        S = P.empty_device(prob.n, N * L)
+        for prec in ("c128", "c64_ir"):
+            pp = P.default_params(N=N, L=L, precision=prec)
+            h.sample(ct, pp, U, S)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(a.sample_compare):
+                _, info, _ = h.sample(ct, pp, U, S)
+            torch.cuda.synchronize()
+            dt = (time.perf_counter() - t0) / a.sample_compare
+            stage[prec] = {"samples_per_s": N / dt, "ms": dt * 1e3, "ir_iters": info.ir_iters,
+                           "ir_fallback": info.ir_fallback}
+            log(f"sampling stage {prec}: {dt * 1e3:.2f} ms ({N / dt:.1f} samples/s)")
+        del S
+    h.close()
+
+    cpu = None
+    if not a.no_cpu:
+        log("cpu baseline (oracle) ...")
+        cpu = cpu_baseline(w, a.cpu_nodes, a.cpu_budget)
+
+    lat_s = np.array(lat)
+    res = {
+        "metric": "resolvent samples/sec + eigenpairs/sec at residual<=1e-10; p50/p99 solve latency",
+        "value": samples_s,
+        "unit": "resolvent samples/s",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "c64+f64" if a.precision == "c64_ir" else "c128",
+        "data": "synthetic (seeded)",
+        "config": {"workload": a.workload, "description": w["desc"], "n": prob.n, "N": N, "L": L,
+                   "NS": prm.NS, "K": prm.K, "precision": a.precision, "parallelism": "single GPU"},
+        "eigenpairs_per_s": eig_s,
+        "n_eig": n_eig[-1],
+        "latency_s": {"p50": float(np.percentile(lat_s, 50)), "p99": float(np.percentile(lat_s, 99))},
+        "stages_s": {k: infos[-1][k] for k in ("t_sample", "t_basis", "t_project", "t_reduced",
+                                                "t_residual")},
+        "solve_info": {k: infos[-1][k] for k in ("k_S", "m", "n_wind", "n_gap", "n_eig",
+                                                  "n_candidates", "ir_iters", "ir_fallback")},
+        "sampling_stage": stage,
+        "kernel_ms_per_step": {k: v["ms"] / a.steps for k, v in sorted(
+            timers.items(), key=lambda kv: -kv[1]["ms"])},
+        "roofline": roof,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(res))
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,226 @@
+/*
+ * rsrr.h -- C ABI of the MI355X (gfx950) resolvent-sampling Rayleigh-Ritz
+ * library for nonlinear eigenvalue problems T(lambda) v = 0.
+ *
+ * Method: J. Xiao, S. Meng, C. Zhang, C. Zheng, "Resolvent sampling based
+ * Rayleigh-Ritz method for large-scale nonlinear eigenvalue problems"
+ * (arXiv 1510.07522).  Algorithm 2 (RSRR) around Algorithm 1 (modified block
+ * Sakurai-Sugiura for the projected problem).
+ *
+ * Conventions
+ *  - Complex numbers are interleaved (re, im) doubles (rsrr_complex), the same
+ *    bytes as C99 double complex, std::complex<double> and torch.complex128.
+ *  - Matrices are column-major.  "host" pointers are ordinary CPU memory,
+ *    "device" pointers are HIP device memory of the current device.
+ *  - Every call returns an int status: 0 = success, < 0 = error (nothing of
+ *    the output is valid; rsrr_last_error() has a message), > 0 = success
+ *    with warnings (a bitwise OR of RSRR_WARN_*).
+ *  - The library owns every buffer it allocates; callers own the buffers they
+ *    pass.  Calls on one problem handle must not overlap (not thread-safe per
+ *    handle); distinct handles may be used from distinct threads.
+ *  - Work is issued on the HIP stream given at creation (NULL = the default
+ *    stream).  Calls return after their results are complete.
+ */
+#ifndef RSRR_H
+#define RSRR_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct { double re, im; } rsrr_complex;
+
+enum {
+  RSRR_OK = 0,
+  RSRR_EINVAL = -1,      /* invalid argument */
+  RSRR_ENOMEM = -2,      /* device or host allocation failed */
+  RSRR_EHIP = -3,        /* a HIP runtime call or kernel launch failed */
+  RSRR_ESINGULAR = -4,   /* T(z_j) exactly singular at a sampling node */
+  RSRR_EBUSY = -5,       /* request does not fit the memory budget */
+  RSRR_ENOTCONV = -6,    /* an inner iteration (eigen / SVD) did not converge */
+  RSRR_WARN_RANK_SATURATED = 1,  /* k_S == N*L < n: the sample space may be too small (eq. eq-rank-nc) */
+  RSRR_WARN_COUNT_MISMATCH = 2,  /* final count differs from the winding count (eq. eq-ncs) */
+  RSRR_WARN_IR_FALLBACK = 4      /* some nodes needed the complex128 factorisation */
+};
+
+/* Kinds of coefficient matrices A_k in T(z) = sum_k f_k(z) A_k (eq. eq-Z-expr). */
+enum {
+  RSRR_MAT_IDENTITY = 0,  /* A_k = I; data pointer ignored (may be NULL) */
+  RSRR_MAT_DIAG = 1,      /* A_k = diag(d); data = n rsrr_complex */
+  RSRR_MAT_REAL = 2,      /* dense real; data = n*n double, column-major */
+  RSRR_MAT_DENSE = 3      /* dense complex; data = n*n rsrr_complex, column-major */
+};
+
+/* Scalar functions f_k (evaluated by the library on the host, with their
+ * derivatives, at the sampling nodes, the reduced-problem nodes and the
+ * eigenvalues):
+ *   RSRR_F_POW : f(z) = c z^p
+ *   RSRR_F_EXP : f(z) = c z^p exp(t z)
+ *   RSRR_F_RAT : f(z) = c z^p / (z - t)                                       */
+enum { RSRR_F_POW = 0, RSRR_F_EXP = 1, RSRR_F_RAT = 2 };
+typedef struct {
+  int kind;          /* RSRR_F_* */
+  int p;             /* power of z, p >= 0 */
+  rsrr_complex c;    /* scale */
+  rsrr_complex t;    /* exponent rate (EXP) or pole (RAT); unused for POW */
+} rsrr_fn;
+
+/* Ellipse phi(theta) = center + a cos(theta) + i b sin(theta) (eq.
+ * eq-contour); a is the semi-axis along the real direction, b along the
+ * imaginary one (a = b = r for a circle).  Interior = strictly inside. */
+typedef struct { rsrr_complex center; double a, b; } rsrr_contour;
+
+enum { RSRR_PREC_C128 = 0, RSRR_PREC_C64_IR = 1 };
+
+typedef struct {
+  int N;              /* sampling nodes on the contour (trapezoid angles 2 pi (j+1/2)/N) */
+  int L;              /* probing vectors (columns of U) */
+  int NS;             /* trapezoid nodes of the reduced problem (eq. eq-Ap-num), default 512 */
+  int K;              /* Hankel blocks (eq. eq-HH), default 2 */
+  double delta;       /* basis truncation: keep singular directions above delta*sigma_1, default 1e-14 */
+  double tol_gap;     /* singular-value gap threshold (eq. eq-gap), default 1e3 */
+  double tol_res;     /* returned pairs have ||T v||/(||T||_F ||v||) <= tol_res, default 1e-10 */
+  double hankel_tol;  /* Hankel truncation sigma_j > hankel_tol*sigma_1, default 1e-13 */
+  int precision;      /* RSRR_PREC_C128 or RSRR_PREC_C64_IR (default) */
+  int ir_max_iter;    /* refinement sweeps before the complex128 fallback, default 5 */
+  double ir_tol;      /* refinement stop: normwise backward error, default 1e-14 */
+  int cheb_degree;    /* BEM only: Chebyshev degree d (eq. eq-T-interp), default 40 */
+  int nb;             /* LU panel width (1..64), default 64 */
+  uint64_t seed;      /* seed of the probing matrix when U is not supplied */
+} rsrr_params;
+
+/* Diagnostics of one solve. */
+typedef struct {
+  int n, N, L;
+  int k_S;            /* dimension of the Rayleigh-Ritz basis (Alg. 2 Step 3) */
+  int m;              /* retained Hankel singular values */
+  int n_wind;         /* eigenvalue count by the winding number (eq. eq-ncs), rounded */
+  int n_gap;          /* count by the singular-value gap (eq. eq-gap); -1 if no gap >= tol_gap */
+  int n_eig;          /* returned eigenpairs (inside, residual <= tol_res) */
+  int n_candidates;   /* extracted eigenvalues inside the contour before the residual test */
+  int ir_iters;       /* refinement sweeps used (max over nodes) */
+  int ir_fallback;    /* nodes solved again in complex128 */
+  int status;         /* the status the solve returned */
+  double wind_re, wind_im;   /* unrounded winding integral */
+  double t_sample, t_basis, t_project, t_reduced, t_residual;  /* seconds per stage */
+} rsrr_info;
+
+typedef struct rsrr_problem rsrr_problem;
+typedef struct rsrr_result rsrr_result;
+
+/* Fills p with the defaults listed above (N = 32, L = 16). */
+void rsrr_default_params(rsrr_params* p);
+
+/* Coefficient-form problem T(z) = sum_{k<J} f_k(z) A_k (eq. eq-Z-expr).
+ * kinds[k] is RSRR_MAT_*, A[k] a host pointer to its data (copied to the
+ * device; the caller may free it on return), f[k] its scalar function.
+ * 1 <= n <= 8192, 1 <= J <= 16.  stream: hipStream_t or NULL. */
+int rsrr_create(rsrr_problem** out, int n, int J, const int* kinds,
+                const void* const* A, const rsrr_fn* f, void* stream);
+
+/* Helmholtz single-layer matrix on a point set (cf. eq. eq-nyes):
+ * T_ij(z) = exp(i z r_ij)/(4 pi r_ij) for i != j, T_ii(z) = i z/(4 pi) + 1/(2h).
+ * xyz: host, n*3 doubles (x, y, z per point).  Entries are generated on the fly
+ * at every node; the reduced problem uses the Chebyshev interpolation of
+ * eq. eq-Ts-coefs on [Re(center) - a, Re(center) + a]. */
+int rsrr_create_bem(rsrr_problem** out, int n, const double* xyz, double h, void* stream);
+
+void rsrr_destroy(rsrr_problem* p);
+
+/* Alg. 2 Steps 1-2: the sampling matrix S_hat = [T(z_0)^{-1} U ... T(z_{N-1})^{-1} U]
+ * (eq. eq-hatS).  U: device, n x L complex, leading dimension ldu >= n.
+ * S: device, n x (N*L) complex, leading dimension lds >= n, block j = columns
+ * [j*L, (j+1)*L).  With precision RSRR_PREC_C64_IR the factorisations are
+ * complex64 and fp64 iterative refinement brings every block to a normwise
+ * backward error <= ir_tol (else that node is redone in complex128).
+ * info (may be NULL) receives ir_iters / ir_fallback / t_sample. */
+int rsrr_sample(rsrr_problem* p, const rsrr_contour* c, const rsrr_params* prm,
+                const rsrr_complex* U, int ldu, rsrr_complex* S, int lds, rsrr_info* info);
+
+/* Alg. 2 Step 3: orthonormal basis Q of the columns of S_hat (device, rows x
+ * cols, leading dim lds; not modified) spanning its singular directions above
+ * delta * sigma_1.  Q: device, rows x min(rows, cols), leading dim ldq; the
+ * first *k_S columns are the basis (Q^H Q = I to rounding). */
+int rsrr_orthonormalize(int rows, int cols, const rsrr_complex* S, int lds, double delta,
+                        rsrr_complex* Q, int ldq, int* k_S, void* stream);
+
+/* Alg. 2 Step 4, projection (eq. eq-Zs-expr): B_k = Q^H A_k Q for every
+ * coefficient, written to B (device) as J blocks of k_S x k_S (leading dim
+ * k_S, block stride k_S*k_S).  For a BEM problem the J = d+1 blocks are the
+ * Chebyshev coefficients P_hat_j (eq. eq-Ts-coefs) on [Re(center) - a,
+ * Re(center) + a] and *J_out = d+1.  Q: device, n x k_S, leading dim ldq. */
+int rsrr_project(rsrr_problem* p, const rsrr_contour* c, const rsrr_params* prm,
+                 const rsrr_complex* Q, int ldq, int k_S, rsrr_complex* B, int* J_out);
+
+/* Alg. 2 end to end: eigenvalues strictly inside the contour with residual
+ * ||T(l) v||_2 / (||T(l)||_F ||v||_2) <= tol_res, their eigenvectors (unit
+ * 2-norm, largest-modulus entry real positive) and residuals.  U: device n x L
+ * (leading dim n) or NULL to draw a complex Gaussian U from prm->seed. */
+int rsrr_solve(rsrr_problem* p, const rsrr_contour* c, const rsrr_params* prm,
+               const rsrr_complex* U, rsrr_result** out);
+
+int rsrr_result_info(const rsrr_result* r, rsrr_info* info);
+/* Host copies; any pointer may be NULL.  lambda: n_eig; V: n x n_eig
+ * (leading dim n); resid: n_eig; resid_paper: ||T v||/||v|| (n_eig);
+ * hankel_sigma: K*k_S singular values of H (descending). */
+int rsrr_result_copy(const rsrr_result* r, rsrr_complex* lambda, rsrr_complex* V, double* resid,
+                     double* resid_paper, double* hankel_sigma);
+void rsrr_result_free(rsrr_result* r);
+
+/* ------------------------------------------------------------------------
+ * Dense building blocks of the sampling step, exposed for direct use.
+ * All pointers are device pointers; matrices are column-major; batch b uses
+ * A + b*sA, B + b*sB, C + b*sC (strides in elements).  Work is issued on
+ * `stream` and the call returns when it is complete.
+ * ---------------------------------------------------------------------- */
+enum { RSRR_OP_N = 0, RSRR_OP_T = 1, RSRR_OP_C = 2 };
+
+/* C = alpha op(A) op(B) + beta C in complex128 on the fp64 matrix cores
+ * (the complex product as four real products).  op(A) is M x K, op(B) K x N. */
+int rsrr_zgemm_batched(int opA, int opB, int M, int N, int K, rsrr_complex alpha,
+                       const rsrr_complex* A, int lda, long long sA,
+                       const rsrr_complex* B, int ldb, long long sB, rsrr_complex beta,
+                       rsrr_complex* C, int ldc, long long sC, int batch, void* stream);
+
+/* The same in complex64 (A, B, C hold interleaved float pairs; alpha/beta are
+ * rounded to fp32).  gauss3m != 0 forms each complex product with three real
+ * matrix-core products (Cr = P1 - P2, Ci = P3 - P1 - P2) instead of four. */
+int rsrr_cgemm_batched(int opA, int opB, int M, int N, int K, rsrr_complex alpha,
+                       const void* A, int lda, long long sA, const void* B, int ldb,
+                       long long sB, rsrr_complex beta, void* C, int ldc, long long sC,
+                       int batch, int gauss3m, void* stream);
+
+/* Solves A_b X_b = B_b for `batch` n x n systems with the blocked LU with
+ * partial pivoting of the sampling step (panel width nb in [1, 64]); A is
+ * overwritten by its factors (interchanges of later panels are not applied to
+ * the L columns of earlier ones), B by the solution.  complex128 when
+ * precision = RSRR_PREC_C128, complex64 (interleaved floats) when
+ * RSRR_PREC_C64_IR.  info_host (may be NULL): batch ints, 0 or the 1-based
+ * index of the first exactly-zero pivot.  Returns RSRR_ESINGULAR if any. */
+int rsrr_gesv_batched(int precision, int n, int nrhs, void* A, int lda, long long sA, void* B,
+                      int ldb, long long sB, int batch, int nb, int* info_host, void* stream);
+
+/* ------------------------------------------------------------------------
+ * Kernel timers: when enabled, the main kernel classes (LU panel, LU trailing
+ * update, solves, Gram/Cholesky, Jacobi rounds, QR sweeps, ...) are bracketed
+ * by HIP events on the stream they are launched on.  Reading synchronises
+ * those events.  Each class accumulates launches, total milliseconds and the
+ * algorithmic flops and bytes of its launches (real flops, one complex
+ * multiply-add = 8).  Process-wide; not for concurrent use with solves.
+ * ---------------------------------------------------------------------- */
+void rsrr_timers_enable(int on);
+void rsrr_timers_reset(void);
+int rsrr_timers_count(void);
+int rsrr_timers_get(int index, char* name, int name_len, long long* launches, double* total_ms,
+                    double* flops, double* bytes);
+
+/* Thread-local message of the last error (empty string if none). */
+const char* rsrr_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* RSRR_H */

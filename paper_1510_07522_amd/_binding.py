@@ -1,0 +1,337 @@
+"""ctypes binding of librsrr.so (the C ABI in include/rsrr.h).
+
+Argument marshalling only: every step of the method runs inside the library.
+PyTorch supplies device memory (and the current HIP stream); matrices cross
+the boundary column-major, i.e. a column-major n x m matrix is a contiguous
+torch tensor of shape (m, n) (see ``to_device`` / ``from_device``).
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "librsrr.so")
+
+
+class RsrrError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"rsrr error {code}: {msg}")
+        self.code = code
+
+
+class cplx(C.Structure):
+    _fields_ = [("re", C.c_double), ("im", C.c_double)]
+
+
+class fn_t(C.Structure):
+    _fields_ = [("kind", C.c_int), ("p", C.c_int), ("c", cplx), ("t", cplx)]
+
+
+class contour_t(C.Structure):
+    _fields_ = [("center", cplx), ("a", C.c_double), ("b", C.c_double)]
+
+
+class params_t(C.Structure):
+    _fields_ = [("N", C.c_int), ("L", C.c_int), ("NS", C.c_int), ("K", C.c_int),
+                ("delta", C.c_double), ("tol_gap", C.c_double), ("tol_res", C.c_double),
+                ("hankel_tol", C.c_double), ("precision", C.c_int), ("ir_max_iter", C.c_int),
+                ("ir_tol", C.c_double), ("cheb_degree", C.c_int), ("nb", C.c_int),
+                ("seed", C.c_uint64)]
+
+
+class info_t(C.Structure):
+    _fields_ = [("n", C.c_int), ("N", C.c_int), ("L", C.c_int), ("k_S", C.c_int), ("m", C.c_int),
+                ("n_wind", C.c_int), ("n_gap", C.c_int), ("n_eig", C.c_int),
+                ("n_candidates", C.c_int), ("ir_iters", C.c_int), ("ir_fallback", C.c_int),
+                ("status", C.c_int), ("wind_re", C.c_double), ("wind_im", C.c_double),
+                ("t_sample", C.c_double), ("t_basis", C.c_double), ("t_project", C.c_double),
+                ("t_reduced", C.c_double), ("t_residual", C.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+PREC_C128, PREC_C64_IR = 0, 1
+MAT_KIND = {"identity": 0, "diag": 1, "real": 2, "dense": 3}
+FN_KIND = {"pow": 0, "exp": 1, "rat": 2}
+WARN_RANK_SATURATED, WARN_COUNT_MISMATCH, WARN_IR_FALLBACK = 1, 2, 4
+
+# Every symbol declared in include/rsrr.h, with its ctypes signature.
+_vp, _i, _d, _ll = C.c_void_p, C.c_int, C.c_double, C.c_longlong
+SIGNATURES = {
+    "rsrr_default_params": (None, [C.POINTER(params_t)]),
+    "rsrr_create": (_i, [C.POINTER(_vp), _i, _i, C.POINTER(_i), C.POINTER(_vp), C.POINTER(fn_t), _vp]),
+    "rsrr_create_bem": (_i, [C.POINTER(_vp), _i, C.POINTER(_d), _d, _vp]),
+    "rsrr_destroy": (None, [_vp]),
+    "rsrr_sample": (_i, [_vp, C.POINTER(contour_t), C.POINTER(params_t), _vp, _i, _vp, _i,
+                         C.POINTER(info_t)]),
+    "rsrr_orthonormalize": (_i, [_i, _i, _vp, _i, _d, _vp, _i, C.POINTER(_i), _vp]),
+    "rsrr_project": (_i, [_vp, C.POINTER(contour_t), C.POINTER(params_t), _vp, _i, _i, _vp,
+                          C.POINTER(_i)]),
+    "rsrr_solve": (_i, [_vp, C.POINTER(contour_t), C.POINTER(params_t), _vp, C.POINTER(_vp)]),
+    "rsrr_result_info": (_i, [_vp, C.POINTER(info_t)]),
+    "rsrr_result_copy": (_i, [_vp, _vp, _vp, _vp, _vp, _vp]),
+    "rsrr_result_free": (None, [_vp]),
+    "rsrr_zgemm_batched": (_i, [_i, _i, _i, _i, _i, cplx, _vp, _i, _ll, _vp, _i, _ll, cplx, _vp, _i,
+                                _ll, _i, _vp]),
+    "rsrr_cgemm_batched": (_i, [_i, _i, _i, _i, _i, cplx, _vp, _i, _ll, _vp, _i, _ll, cplx, _vp, _i,
+                                _ll, _i, _i, _vp]),
+    "rsrr_gesv_batched": (_i, [_i, _i, _i, _vp, _i, _ll, _vp, _i, _ll, _i, _i, C.POINTER(_i), _vp]),
+    "rsrr_timers_enable": (None, [_i]),
+    "rsrr_timers_reset": (None, []),
+    "rsrr_timers_count": (_i, []),
+    "rsrr_timers_get": (_i, [_i, C.c_char_p, _i, C.POINTER(_ll), C.POINTER(_d), C.POINTER(_d),
+                             C.POINTER(_d)]),
+    "rsrr_last_error": (C.c_char_p, []),
+}
+
+_lib = None
+
+
+def load(path: str = LIB_PATH):
+    """Loads librsrr.so; raises if it is missing (there is no fallback path)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is missing: build it with `python -m paper_1510_07522_amd.build`"
+                           " (there is no CPU fallback)")
+    lib = C.CDLL(path)
+    for name, (res, args) in SIGNATURES.items():
+        f = getattr(lib, name)
+        f.restype = res
+        f.argtypes = args
+    _lib = lib
+    return lib
+
+
+def check(code: int) -> int:
+    if code < 0:
+        raise RsrrError(code, load().rsrr_last_error().decode(errors="replace"))
+    return code
+
+
+# ------------------------------------------------------------ memory helpers
+def _torch():
+    import torch
+    return torch
+
+
+def stream_ptr():
+    torch = _torch()
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def to_device(a: np.ndarray, dtype=None):
+    """Column-major copy of a 2-D (or 1-D) numpy array on cuda:0.  An n x m
+    matrix becomes a tensor of shape (m, n) whose memory is column-major."""
+    torch = _torch()
+    a = np.asarray(a)
+    if dtype is not None:
+        a = a.astype(dtype)
+    if a.ndim == 1:
+        return torch.from_numpy(np.ascontiguousarray(a)).to("cuda")
+    return torch.from_numpy(np.ascontiguousarray(a.T)).to("cuda")
+
+
+def from_device(t, rows: int | None = None) -> np.ndarray:
+    """Inverse of to_device: an (m, n) tensor -> n x m numpy array."""
+    a = t.detach().cpu().numpy()
+    if a.ndim == 1:
+        return a
+    out = a.T
+    return out[:rows] if rows is not None else out
+
+
+def empty_device(rows: int, cols: int, dtype="complex128"):
+    torch = _torch()
+    dt = {"complex128": torch.complex128, "complex64": torch.complex64}[dtype]
+    return torch.empty((cols, rows), dtype=dt, device="cuda")
+
+
+def _ptr(t):
+    return C.c_void_p(t.data_ptr())
+
+
+# --------------------------------------------------------------- parameters
+def default_params(**kw) -> params_t:
+    p = params_t()
+    load().rsrr_default_params(C.byref(p))
+    for k, v in kw.items():
+        if k == "precision" and isinstance(v, str):
+            v = {"c128": PREC_C128, "c64_ir": PREC_C64_IR}[v]
+        setattr(p, k, v)
+    return p
+
+
+def contour(center: complex, a: float, b: float) -> contour_t:
+    c = contour_t()
+    c.center = cplx(float(np.real(center)), float(np.imag(center)))
+    c.a, c.b = float(a), float(b)
+    return c
+
+
+def _fn(spec) -> fn_t:
+    f = fn_t()
+    f.kind = FN_KIND[spec[0]]
+    f.c = cplx(float(np.real(spec[1])), float(np.imag(spec[1])))
+    f.p = int(spec[2])
+    f.t = cplx(0.0, 0.0)
+    if spec[0] in ("exp", "rat"):
+        f.t = cplx(float(np.real(spec[3])), float(np.imag(spec[3])))
+    return f
+
+
+# ------------------------------------------------------------------ problems
+class Problem:
+    """A problem handle: coefficient form (nep_inputs.CoeffProblem) or BEM
+    (nep_inputs.BemProblem)."""
+
+    def __init__(self, prob):
+        lib = load()
+        h = C.c_void_p()
+        self.n = prob.n
+        self._keep = []
+        if hasattr(prob, "xyz"):
+            xyz = np.ascontiguousarray(prob.xyz, dtype=np.float64)
+            check(lib.rsrr_create_bem(C.byref(h), prob.n, xyz.ctypes.data_as(C.POINTER(C.c_double)),
+                                      float(prob.h), stream_ptr()))
+            self.bem = True
+        else:
+            J = prob.J
+            kinds = (C.c_int * J)(*[MAT_KIND[k] for k in prob.kinds])
+            ptrs = (C.c_void_p * J)()
+            for k in range(J):
+                kind, A = prob.kinds[k], prob.mats[k]
+                if kind == "identity":
+                    ptrs[k] = None
+                    continue
+                if kind == "diag":
+                    arr = np.ascontiguousarray(A, dtype=np.complex128)
+                elif kind == "real":
+                    arr = np.asfortranarray(np.real(A), dtype=np.float64)
+                else:
+                    arr = np.asfortranarray(A, dtype=np.complex128)
+                self._keep.append(arr)
+                ptrs[k] = arr.ctypes.data
+            fns = (fn_t * J)(*[_fn(s) for s in prob.fspecs])
+            check(lib.rsrr_create(C.byref(h), prob.n, J, kinds, ptrs, fns, stream_ptr()))
+            self._keep = []
+            self.bem = False
+        self.handle = h
+
+    def close(self):
+        if self.handle:
+            load().rsrr_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def sample(self, c: contour_t, prm: params_t, U, S=None):
+        """S_hat = [T(z_j)^{-1} U] as a column-major device tensor (NL, n)."""
+        n, NL = self.n, prm.N * prm.L
+        if S is None:
+            S = empty_device(n, NL)
+        info = info_t()
+        st = check(load().rsrr_sample(self.handle, C.byref(c), C.byref(prm), _ptr(U), n, _ptr(S),
+                                      n, C.byref(info)))
+        return S, info, st
+
+    def project(self, c: contour_t, prm: params_t, Q, kS: int, J_max: int = 64):
+        torch = _torch()
+        B = torch.empty((J_max * kS, kS), dtype=torch.complex128, device="cuda")
+        J = C.c_int(0)
+        check(load().rsrr_project(self.handle, C.byref(c), C.byref(prm), _ptr(Q), self.n, kS,
+                                  _ptr(B), C.byref(J)))
+        return B[: J.value * kS], J.value
+
+    def solve(self, c: contour_t, prm: params_t, U=None):
+        lib = load()
+        r = C.c_void_p()
+        st = check(lib.rsrr_solve(self.handle, C.byref(c), C.byref(prm),
+                                  _ptr(U) if U is not None else None, C.byref(r)))
+        try:
+            info = info_t()
+            check(lib.rsrr_result_info(r, C.byref(info)))
+            ne = info.n_eig
+            lam = np.zeros(ne, np.complex128)
+            V = np.zeros((ne, self.n), np.complex128)
+            res = np.zeros(ne)
+            resp = np.zeros(ne)
+            hs = np.zeros(max(1, prm.K * info.k_S))
+            check(lib.rsrr_result_copy(r, lam.ctypes.data, V.ctypes.data, res.ctypes.data,
+                                       resp.ctypes.data, hs.ctypes.data))
+        finally:
+            lib.rsrr_result_free(r)
+        return dict(lam=lam, V=V.T, res=res, res_paper=resp, hankel_sigma=hs[: prm.K * info.k_S],
+                    info=info.as_dict(), status=st)
+
+
+def orthonormalize(S, rows: int, cols: int, delta: float = 1e-14):
+    """Orthonormal basis of the columns of a device matrix (column-major)."""
+    torch = _torch()
+    Q = torch.empty((min(rows, cols), rows), dtype=torch.complex128, device="cuda")
+    k = C.c_int(0)
+    check(load().rsrr_orthonormalize(rows, cols, _ptr(S), rows, float(delta), _ptr(Q), rows,
+                                     C.byref(k), stream_ptr()))
+    return Q[: k.value], k.value
+
+
+def timers_enable(on: bool = True):
+    load().rsrr_timers_enable(int(on))
+
+
+def timers_reset():
+    load().rsrr_timers_reset()
+
+
+def timers_read() -> dict:
+    """{kernel class: {launches, ms, flops, bytes}} accumulated since reset."""
+    lib = load()
+    out = {}
+    for i in range(lib.rsrr_timers_count()):
+        name = C.create_string_buffer(128)
+        la, ms, fl, by = C.c_longlong(), C.c_double(), C.c_double(), C.c_double()
+        check(lib.rsrr_timers_get(i, name, 128, C.byref(la), C.byref(ms), C.byref(fl), C.byref(by)))
+        out[name.value.decode()] = dict(launches=la.value, ms=ms.value, flops=fl.value,
+                                        bytes=by.value)
+    return out
+
+
+OPS = {"N": 0, "T": 1, "C": 2}
+
+
+def gemm(opA: str, opB: str, A, B, Cm, M: int, N: int, K: int, alpha=1.0, beta=0.0,
+         lda=None, ldb=None, ldc=None, batch: int = 1, sA=0, sB=0, sC=0, gauss3m=False):
+    """Batched complex GEMM on device tensors (complex128 or complex64)."""
+    torch = _torch()
+    lib = load()
+    lda = lda or (M if opA == "N" else K)
+    ldb = ldb or (K if opB == "N" else N)
+    ldc = ldc or M
+    al = cplx(float(np.real(alpha)), float(np.imag(alpha)))
+    be = cplx(float(np.real(beta)), float(np.imag(beta)))
+    if Cm.dtype == torch.complex128:
+        return check(lib.rsrr_zgemm_batched(OPS[opA], OPS[opB], M, N, K, al, _ptr(A), lda, sA,
+                                            _ptr(B), ldb, sB, be, _ptr(Cm), ldc, sC, batch,
+                                            stream_ptr()))
+    return check(lib.rsrr_cgemm_batched(OPS[opA], OPS[opB], M, N, K, al, _ptr(A), lda, sA,
+                                        _ptr(B), ldb, sB, be, _ptr(Cm), ldc, sC, batch,
+                                        int(gauss3m), stream_ptr()))
+
+
+def gesv(A, B, n: int, nrhs: int, batch: int, nb: int = 64):
+    """Batched LU solve in place (A: batch x n x n, B: batch x n x nrhs, column-major)."""
+    torch = _torch()
+    prec = PREC_C128 if A.dtype == torch.complex128 else PREC_C64_IR
+    info = (C.c_int * batch)()
+    st = load().rsrr_gesv_batched(prec, n, nrhs, _ptr(A), n, n * n, _ptr(B), n, n * nrhs, batch,
+                                  nb, info, stream_ptr())
+    return st, list(info)

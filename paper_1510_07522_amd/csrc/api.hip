@@ -1,0 +1,306 @@
+// C ABI of the RSRR library: handles, parameters, errors and dispatch.
+#include <chrono>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <cstdlib>
+
+#include "driver.h"
+
+namespace rsrr {
+
+static thread_local char g_err[1024] = "";
+
+int set_error(int code, const char* fmt, ...) {
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(g_err, sizeof(g_err), fmt, ap);
+  va_end(ap);
+  return code;
+}
+
+void vlog(const char* fmt, ...) {
+  static int on = -1;
+  if (on < 0) {
+    const char* e = getenv("RSRR_VERBOSE");
+    on = (e && e[0] == '1') ? 1 : 0;
+  }
+  if (!on) return;
+  va_list ap;
+  va_start(ap, fmt);
+  fprintf(stderr, "[rsrr] ");
+  vfprintf(stderr, fmt, ap);
+  fprintf(stderr, "\n");
+  fflush(stderr);
+  va_end(ap);
+}
+
+double now_s() {
+  using namespace std::chrono;
+  return duration<double>(steady_clock::now().time_since_epoch()).count();
+}
+
+int Arena::get(const char* name, size_t bytes, void** out) {
+  if (bytes == 0) bytes = 256;
+  auto it = bufs.find(name);
+  if (it != bufs.end() && it->second.second >= bytes) {
+    *out = it->second.first;
+    return ST_OK;
+  }
+  if (it != bufs.end()) {
+    (void)hipFree(it->second.first);
+    bufs.erase(it);
+  }
+  void* p = nullptr;
+  if (hipMalloc(&p, bytes) != hipSuccess) {
+    (void)hipGetLastError();
+    return set_error(ST_ENOMEM, "device allocation of %zu bytes for '%s' failed", bytes, name);
+  }
+  bufs[name] = std::make_pair(p, bytes);
+  *out = p;
+  return ST_OK;
+}
+
+void Arena::release() {
+  for (auto& kv : bufs) (void)hipFree(kv.second.first);
+  bufs.clear();
+}
+
+void eval_fn(const rsrr_fn& f, cd z, cd* val, cd* der) {
+  const cd c(f.c.re, f.c.im), t(f.t.re, f.t.im);
+  const int p = f.p;
+  // integer powers by repeated multiplication (exact for small p, no log/exp)
+  cd zpm1(1, 0);
+  for (int q = 1; q < p; ++q) zpm1 *= z;
+  const cd zp = (p == 0) ? cd(1, 0) : zpm1 * z;
+  const cd dzp = (p == 0) ? cd(0, 0) : (double)p * zpm1;
+  switch (f.kind) {
+    case RSRR_F_EXP: {
+      const cd e = std::exp(t * z);
+      *val = c * zp * e;
+      if (der) *der = c * e * (dzp + t * zp);
+      break;
+    }
+    case RSRR_F_RAT: {
+      const cd d = z - t;
+      *val = c * zp / d;
+      if (der) *der = c * (dzp * d - zp) / (d * d);
+      break;
+    }
+    default:
+      *val = c * zp;
+      if (der) *der = c * dzp;
+  }
+}
+
+void contour_nodes(const rsrr_contour* c, int N, std::vector<cd>* z, std::vector<cd>* dz) {
+  z->resize(N);
+  if (dz) dz->resize(N);
+  const cd g(c->center.re, c->center.im);
+  for (int j = 0; j < N; ++j) {
+    const double th = 2.0 * M_PI * (j + 0.5) / N;
+    (*z)[j] = g + cd(c->a * cos(th), c->b * sin(th));
+    if (dz) (*dz)[j] = cd(-c->a * sin(th), c->b * cos(th));
+  }
+}
+
+}  // namespace rsrr
+
+using namespace rsrr;
+
+extern "C" {
+
+const char* rsrr_last_error(void) { return rsrr::g_err; }
+
+void rsrr_default_params(rsrr_params* p) {
+  if (!p) return;
+  memset(p, 0, sizeof(*p));
+  p->N = 32;
+  p->L = 16;
+  p->NS = 512;
+  p->K = 2;
+  p->delta = 1e-14;
+  p->tol_gap = 1e3;
+  p->tol_res = 1e-10;
+  p->hankel_tol = 1e-13;
+  p->precision = RSRR_PREC_C64_IR;
+  p->ir_max_iter = 5;
+  p->ir_tol = 1e-14;
+  p->cheb_degree = 40;
+  p->nb = 64;
+  p->seed = 1;
+}
+
+int rsrr_create(rsrr_problem** out, int n, int J, const int* kinds, const void* const* A,
+                const rsrr_fn* f, void* stream) {
+  if (!out || !kinds || !f || !A) return set_error(ST_EINVAL, "rsrr_create: null argument");
+  *out = nullptr;
+  if (n < 1 || n > 8192) return set_error(ST_EINVAL, "rsrr_create: n=%d outside [1, 8192]", n);
+  if (J < 1 || J > 16) return set_error(ST_EINVAL, "rsrr_create: J=%d outside [1, 16]", J);
+  for (int k = 0; k < J; ++k) {
+    if (kinds[k] < 0 || kinds[k] > 3) return set_error(ST_EINVAL, "rsrr_create: kind[%d]=%d", k, kinds[k]);
+    if (kinds[k] != RSRR_MAT_IDENTITY && !A[k]) return set_error(ST_EINVAL, "rsrr_create: A[%d] is NULL", k);
+    if (f[k].kind < 0 || f[k].kind > 2 || f[k].p < 0)
+      return set_error(ST_EINVAL, "rsrr_create: bad scalar function %d", k);
+  }
+  rsrr_problem* p = new rsrr_problem();
+  p->n = n;
+  p->J = J;
+  p->stream = (hipStream_t)stream;
+  p->kinds.assign(kinds, kinds + J);
+  p->fns.assign(f, f + J);
+  p->mats.assign(J, nullptr);
+  const size_t nn = (size_t)n * n;
+  for (int k = 0; k < J; ++k) {
+    size_t bytes = 0;
+    if (kinds[k] == RSRR_MAT_DIAG) bytes = n * sizeof(c128);
+    else if (kinds[k] == RSRR_MAT_REAL) bytes = nn * sizeof(double);
+    else if (kinds[k] == RSRR_MAT_DENSE) bytes = nn * sizeof(c128);
+    if (!bytes) continue;
+    if (hipMalloc(&p->mats[k], bytes) != hipSuccess ||
+        hipMemcpy(p->mats[k], A[k], bytes, hipMemcpyHostToDevice) != hipSuccess) {
+      (void)hipGetLastError();
+      rsrr_destroy(p);
+      return set_error(ST_ENOMEM, "rsrr_create: cannot upload coefficient %d", k);
+    }
+  }
+  // Gram of the coefficients, gram[k,l] = sum_ij conj(A_k)_ij (A_l)_ij, so that
+  // ||T(z)||_F^2 = sum_kl conj(f_k) f_l gram[k,l] exactly.
+  p->gram.assign(2 * J * J, 0.0);
+  auto entry = [&](int k, size_t e, size_t i, size_t j) -> cd {
+    switch (kinds[k]) {
+      case RSRR_MAT_IDENTITY: return i == j ? cd(1, 0) : cd(0, 0);
+      case RSRR_MAT_DIAG: { const rsrr_complex* d = (const rsrr_complex*)A[k];
+                            return i == j ? cd(d[i].re, d[i].im) : cd(0, 0); }
+      case RSRR_MAT_REAL: return cd(((const double*)A[k])[e], 0);
+      default: { const rsrr_complex* d = (const rsrr_complex*)A[k]; return cd(d[e].re, d[e].im); }
+    }
+  };
+  bool anydense = false;
+  for (int k = 0; k < J; ++k) anydense |= (kinds[k] >= RSRR_MAT_REAL);
+  for (int k = 0; k < J; ++k)
+    for (int l = 0; l < J; ++l) {
+      cd s(0, 0);
+      const bool dk = kinds[k] >= RSRR_MAT_REAL, dl = kinds[l] >= RSRR_MAT_REAL;
+      if (dk && dl) {
+        for (size_t e = 0; e < nn; ++e) s += std::conj(entry(k, e, e % n, e / n)) * entry(l, e, e % n, e / n);
+      } else {
+        for (size_t i = 0; i < (size_t)n; ++i) {
+          const size_t e = i + i * n;
+          s += std::conj(entry(k, e, i, i)) * entry(l, e, i, i);
+        }
+      }
+      p->gram[2 * (k * J + l)] = s.real();
+      p->gram[2 * (k * J + l) + 1] = s.imag();
+    }
+  (void)anydense;
+  *out = p;
+  return ST_OK;
+}
+
+int rsrr_create_bem(rsrr_problem** out, int n, const double* xyz, double h, void* stream) {
+  if (!out || !xyz) return set_error(ST_EINVAL, "rsrr_create_bem: null argument");
+  *out = nullptr;
+  if (n < 2 || n > 8192) return set_error(ST_EINVAL, "rsrr_create_bem: n=%d outside [2, 8192]", n);
+  if (!(h > 0)) return set_error(ST_EINVAL, "rsrr_create_bem: h must be positive");
+  rsrr_problem* p = new rsrr_problem();
+  p->n = n;
+  p->bem = true;
+  p->h = h;
+  p->stream = (hipStream_t)stream;
+  if (hipMalloc(&p->xyz, (size_t)n * 3 * sizeof(double)) != hipSuccess ||
+      hipMemcpy(p->xyz, xyz, (size_t)n * 3 * sizeof(double), hipMemcpyHostToDevice) != hipSuccess) {
+    (void)hipGetLastError();
+    rsrr_destroy(p);
+    return set_error(ST_ENOMEM, "rsrr_create_bem: cannot upload points");
+  }
+  *out = p;
+  return ST_OK;
+}
+
+void rsrr_destroy(rsrr_problem* p) {
+  if (!p) return;
+  if (p->stream) (void)hipStreamSynchronize(p->stream);
+  else (void)hipDeviceSynchronize();
+  for (void* m : p->mats) if (m) (void)hipFree(m);
+  if (p->xyz) (void)hipFree(p->xyz);
+  p->ws.release();
+  delete p;
+}
+
+static int check_params(const rsrr_problem* p, const rsrr_contour* c, const rsrr_params* prm) {
+  if (!p || !c || !prm) return set_error(ST_EINVAL, "null argument");
+  if (prm->N < 1 || prm->L < 1) return set_error(ST_EINVAL, "N and L must be >= 1");
+  if (!(c->a > 0) || !(c->b > 0)) return set_error(ST_EINVAL, "contour semi-axes must be > 0");
+  if (prm->nb < 1 || prm->nb > 64) return set_error(ST_EINVAL, "nb must be in [1, 64]");
+  if (prm->precision != RSRR_PREC_C128 && prm->precision != RSRR_PREC_C64_IR)
+    return set_error(ST_EINVAL, "unknown precision %d", prm->precision);
+  if (prm->NS < 2 || prm->K < 1) return set_error(ST_EINVAL, "NS >= 2 and K >= 1 required");
+  if ((long)prm->N * prm->L > (1L << 20)) return set_error(ST_EINVAL, "N*L too large");
+  return ST_OK;
+}
+
+int rsrr_sample(rsrr_problem* p, const rsrr_contour* c, const rsrr_params* prm,
+                const rsrr_complex* U, int ldu, rsrr_complex* S, int lds, rsrr_info* info) {
+  RSRR_TRY(check_params(p, c, prm));
+  if (!U || !S || ldu < p->n || lds < p->n) return set_error(ST_EINVAL, "rsrr_sample: bad buffers");
+  return sample_impl(p, c, prm, (const c128*)U, ldu, (c128*)S, lds, info);
+}
+
+int rsrr_orthonormalize(int rows, int cols, const rsrr_complex* S, int lds, double delta,
+                        rsrr_complex* Q, int ldq, int* k_S, void* stream) {
+  if (!S || !Q || !k_S || rows < 1 || cols < 1 || lds < rows || ldq < rows || !(delta > 0))
+    return set_error(ST_EINVAL, "rsrr_orthonormalize: bad arguments");
+  Arena ws;
+  int st = ortho_impl(rows, cols, (const c128*)S, lds, delta, (c128*)Q, ldq, k_S, ws,
+                      (hipStream_t)stream);
+  (void)hipStreamSynchronize((hipStream_t)stream);
+  return st;
+}
+
+int rsrr_project(rsrr_problem* p, const rsrr_contour* c, const rsrr_params* prm,
+                 const rsrr_complex* Q, int ldq, int k_S, rsrr_complex* B, int* J_out) {
+  RSRR_TRY(check_params(p, c, prm));
+  if (!Q || !B || k_S < 1 || ldq < p->n || k_S > p->n) return set_error(ST_EINVAL, "rsrr_project: bad arguments");
+  return project_impl(p, c, prm, (const c128*)Q, ldq, k_S, (c128*)B, J_out);
+}
+
+int rsrr_solve(rsrr_problem* p, const rsrr_contour* c, const rsrr_params* prm,
+               const rsrr_complex* U, rsrr_result** out) {
+  if (!out) return set_error(ST_EINVAL, "rsrr_solve: null result pointer");
+  *out = nullptr;
+  RSRR_TRY(check_params(p, c, prm));
+  rsrr_result* r = new rsrr_result();
+  memset(&r->info, 0, sizeof(r->info));
+  int st = solve_impl(p, c, prm, (const c128*)U, r);
+  if (st < 0) {
+    delete r;
+    return st;
+  }
+  r->info.status = st;
+  *out = r;
+  return st;
+}
+
+int rsrr_result_info(const rsrr_result* r, rsrr_info* info) {
+  if (!r || !info) return set_error(ST_EINVAL, "rsrr_result_info: null argument");
+  *info = r->info;
+  return ST_OK;
+}
+
+int rsrr_result_copy(const rsrr_result* r, rsrr_complex* lambda, rsrr_complex* V, double* resid,
+                     double* resid_paper, double* hankel_sigma) {
+  if (!r) return set_error(ST_EINVAL, "rsrr_result_copy: null result");
+  if (lambda && !r->lambda.empty()) memcpy(lambda, r->lambda.data(), r->lambda.size() * sizeof(rsrr_complex));
+  if (V && !r->V.empty()) memcpy(V, r->V.data(), r->V.size() * sizeof(rsrr_complex));
+  if (resid && !r->resid.empty()) memcpy(resid, r->resid.data(), r->resid.size() * sizeof(double));
+  if (resid_paper && !r->resid_paper.empty())
+    memcpy(resid_paper, r->resid_paper.data(), r->resid_paper.size() * sizeof(double));
+  if (hankel_sigma && !r->hankel_sigma.empty())
+    memcpy(hankel_sigma, r->hankel_sigma.data(), r->hankel_sigma.size() * sizeof(double));
+  return ST_OK;
+}
+
+void rsrr_result_free(rsrr_result* r) { delete r; }
+
+}  // extern "C"

@@ -1,0 +1,68 @@
+// Host-side driver structures shared by the C-ABI implementation files.
+#pragma once
+#include <complex>
+#include <map>
+#include <string>
+#include <vector>
+
+#include "../../include/rsrr.h"
+#include "common.h"
+#include "kernels.h"
+
+namespace rsrr {
+
+typedef std::complex<double> cd;
+
+// Named, grow-only device buffers owned by one handle.  Calls on a handle do
+// not overlap, so a buffer is reused across calls without re-allocation.
+struct Arena {
+  std::map<std::string, std::pair<void*, size_t>> bufs;
+  int get(const char* name, size_t bytes, void** out);
+  template <typename T> int get(const char* name, size_t count, T** out) {
+    return get(name, count * sizeof(T), (void**)out);
+  }
+  void release();
+  ~Arena() { release(); }
+};
+
+// Evaluates f(z) and f'(z) of a scalar-function spec.
+void eval_fn(const rsrr_fn& f, cd z, cd* val, cd* der);
+
+}  // namespace rsrr
+
+struct rsrr_problem {
+  int n = 0, J = 0;
+  bool bem = false;
+  hipStream_t stream = nullptr;
+  std::vector<int> kinds;
+  std::vector<rsrr_fn> fns;
+  std::vector<void*> mats;            // device data per coefficient (nullptr for identity)
+  std::vector<double> gram;           // J x J complex (re, im): gram[k,l] = sum conj(A_k) A_l
+  double* xyz = nullptr;              // BEM points (device, n*3)
+  double h = 0.0;
+  rsrr::Arena ws;
+};
+
+struct rsrr_result {
+  rsrr_info info;
+  std::vector<rsrr_complex> lambda, V;
+  std::vector<double> resid, resid_paper, hankel_sigma;
+};
+
+namespace rsrr {
+
+// Stage implementations (driver_*.hip).
+int sample_impl(rsrr_problem* p, const rsrr_contour* c, const rsrr_params* prm,
+                const c128* U, long ldu, c128* S, long lds, rsrr_info* info);
+int ortho_impl(int rows, int cols, const c128* S, long lds, double delta, c128* Q, long ldq,
+               int* k_S, Arena& ws, hipStream_t s);
+int project_impl(rsrr_problem* p, const rsrr_contour* c, const rsrr_params* prm, const c128* Q,
+                 long ldq, int kS, c128* B, int* J_out);
+int solve_impl(rsrr_problem* p, const rsrr_contour* c, const rsrr_params* prm, const c128* U,
+               rsrr_result* res);
+void contour_nodes(const rsrr_contour* c, int N, std::vector<cd>* z, std::vector<cd>* dz);
+double now_s();
+// Progress line on stderr when RSRR_VERBOSE=1 (stage boundaries of long solves).
+void vlog(const char* fmt, ...);
+
+}  // namespace rsrr

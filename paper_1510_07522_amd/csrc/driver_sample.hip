@@ -1,0 +1,238 @@
+// Alg. 2, Steps 1-2: the sampling matrix S_hat = [T(z_0)^{-1} U ... T(z_{N-1})^{-1} U].
+//
+// complex128 form: assemble T(z_j) for all j, one batched LU, one batched solve.
+// complex64 + refinement form: the same in complex64, then fp64 iterative
+// refinement  R_j = U - T(z_j) Y_j (fp64),  D_j = T~_j^{-1} R_j (complex64),
+// Y_j += D_j,  until eta_j = ||R_j||_F / (||T(z_j)||_F ||Y_j||_F + ||U||_F) <= ir_tol.
+// Nodes that do not reach ir_tol in ir_max_iter sweeps are factored again in
+// complex128.
+#include <algorithm>
+#include <cmath>
+
+#include "driver.h"
+#include "timers.h"
+
+namespace rsrr {
+
+// Scalar coefficients f_k(z_j) for the given nodes (row j holds J values).
+static void node_coefs(const rsrr_problem* p, const std::vector<cd>& z, std::vector<c128>* f) {
+  f->resize(z.size() * p->J);
+  for (size_t j = 0; j < z.size(); ++j)
+    for (int k = 0; k < p->J; ++k) {
+      cd v;
+      eval_fn(p->fns[k], z[j], &v, nullptr);
+      (*f)[j * p->J + k] = mk<double>(v.real(), v.imag());
+    }
+}
+
+// ||T(z_j)||_F^2 for coefficient-form problems from the coefficient Gram.
+static double fro2_coeff(const rsrr_problem* p, const c128* f) {
+  cd s(0, 0);
+  for (int k = 0; k < p->J; ++k)
+    for (int l = 0; l < p->J; ++l) {
+      const cd g(p->gram[2 * (k * p->J + l)], p->gram[2 * (k * p->J + l) + 1]);
+      s += std::conj(cd(f[k].re, f[k].im)) * cd(f[l].re, f[l].im) * g;
+    }
+  return std::max(0.0, s.real());
+}
+
+template <typename R>
+static int assemble_nodes(rsrr_problem* p, int nz, const c128* f_dev, const c128* z_dev,
+                          cplx<R>* T, hipStream_t s) {
+  const long n = p->n;
+  if (p->bem) return assemble_bem<R>(p->n, p->xyz, p->h, nz, z_dev, T, n, n * n, s);
+  std::vector<const void*> mats(p->mats.begin(), p->mats.end());
+  CoeffSet cs;
+  cs.n = p->n;
+  cs.J = p->J;
+  cs.kinds_host = p->kinds.data();
+  cs.mats = mats.data();
+  return assemble_coeff<R>(cs, nz, f_dev, T, n, n * n, s);
+}
+
+static int check_info(const int* info_dev, int batch, hipStream_t s, const std::vector<cd>& z) {
+  std::vector<int> h(batch);
+  RSRR_HIP(hipMemcpyAsync(h.data(), info_dev, batch * sizeof(int), hipMemcpyDeviceToHost, s));
+  RSRR_HIP(hipStreamSynchronize(s));
+  for (int j = 0; j < batch; ++j)
+    if (h[j] != 0)
+      return set_error(ST_ESINGULAR, "T(z) is exactly singular at node %d (z = %.17g%+.17gi, pivot %d)",
+                       j, z[j].real(), z[j].imag(), h[j]);
+  return ST_OK;
+}
+
+// Residual R = U - T(z_j) Y_j (fp64) for all nodes; P is scratch for A_k Y.
+static int residual_fp64(rsrr_problem* p, int N, int L, const c128* f_dev, const c128* z_dev,
+                         const c128* U, long ldu, const c128* Y, long ldy, c128* Rb, hipStream_t s) {
+  const int n = p->n;
+  const long cols = (long)N * L;
+  if (p->bem)
+    return bem_residual(n, p->xyz, p->h, N, z_dev, U, ldu, Y, ldy, (long)L * ldy, L, Rb, n,
+                        (long)L * n, s);
+  std::vector<const c128*> P(p->J);
+  for (int k = 0; k < p->J; ++k) {
+    c128* Pk = nullptr;
+    char name[32];
+    snprintf(name, sizeof(name), "ir_P%d", k);
+    RSRR_TRY(p->ws.get<c128>(name, (size_t)n * cols, &Pk));
+    switch (p->kinds[k]) {
+      case RSRR_MAT_IDENTITY:
+        RSRR_TRY((convert<double, double>(Y, ldy, 0, Pk, n, 0, n, (int)cols, 1, s)));
+        break;
+      case RSRR_MAT_DIAG:
+        RSRR_TRY(diag_scale((const c128*)p->mats[k], Y, ldy, Pk, n, n, (int)cols, s));
+        break;
+      default: {
+        GemmBatch<double> g;
+        g.M = n; g.N = (int)cols; g.K = n;
+        g.A = p->mats[k]; g.lda = n;
+        g.a_real = (p->kinds[k] == RSRR_MAT_REAL);
+        g.B = Y; g.ldb = ldy;
+        g.C = Pk; g.ldc = n;
+        g.tag = "ir_residual_gemm";
+        RSRR_TRY(gemm_batched<double>(g, s));
+      }
+    }
+    P[k] = Pk;
+  }
+  return combine_residual(U, ldu, P.data(), p->J, f_dev, n, L, N, Rb, n, s);
+}
+
+int sample_impl(rsrr_problem* p, const rsrr_contour* c, const rsrr_params* prm, const c128* U,
+                long ldu, c128* S, long lds, rsrr_info* info) {
+  const double t0 = now_s();
+  hipStream_t s = p->stream;
+  const int n = p->n, N = prm->N, L = prm->L, nb = prm->nb;
+  const long nn = (long)n * n;
+  std::vector<cd> z;
+  contour_nodes(c, N, &z, nullptr);
+  std::vector<c128> f, zc(N);
+  for (int j = 0; j < N; ++j) zc[j] = mk<double>(z[j].real(), z[j].imag());
+  if (!p->bem) node_coefs(p, z, &f);
+
+  c128 *f_dev = nullptr, *z_dev = nullptr;
+  int *ipiv = nullptr, *infod = nullptr;
+  RSRR_TRY(p->ws.get<c128>("s_f", std::max<size_t>(1, f.size()), &f_dev));
+  RSRR_TRY(p->ws.get<c128>("s_z", N, &z_dev));
+  RSRR_TRY(p->ws.get<int>("s_ipiv", (size_t)N * n, &ipiv));
+  RSRR_TRY(p->ws.get<int>("s_info", N, &infod));
+  if (!f.empty()) RSRR_HIP(hipMemcpyAsync(f_dev, f.data(), f.size() * sizeof(c128), hipMemcpyHostToDevice, s));
+  RSRR_HIP(hipMemcpyAsync(z_dev, zc.data(), N * sizeof(c128), hipMemcpyHostToDevice, s));
+  int ir_iters = 0, fallback = 0, warn = 0;
+
+  if (prm->precision == RSRR_PREC_C128) {
+    c128 *T = nullptr, *dinv = nullptr;
+    RSRR_TRY(p->ws.get<c128>("s_T128", (size_t)N * nn, &T));
+    RSRR_TRY(p->ws.get<c128>("s_dinv128", LUWork<double>::dinv_elems(n, nb, N), &dinv));
+    RSRR_TRY(assemble_nodes<double>(p, N, f_dev, z_dev, T, s));
+    LUWork<double> w;
+    w.n = n; w.nb = nb; w.batch = N; w.lda = n; w.sA = nn; w.A = T;
+    w.ipiv = ipiv; w.dinv = dinv; w.info = infod;
+    w.tag = "sample_lu_c128";
+    RSRR_TRY(lu_factor<double>(w, s));
+    RSRR_TRY(check_info(infod, N, s, z));
+    RSRR_TRY(replicate<double>(U, ldu, S, lds, (long)L * lds, n, L, N, s));
+    RSRR_TRY(lu_solve<double>(w, S, lds, (long)L * lds, L, s));
+  } else {
+    c64 *T = nullptr, *dinv = nullptr, *Y32 = nullptr;
+    c128* Rb = nullptr;
+    double* nrm = nullptr;
+    int* active_dev = nullptr;
+    const long cols = (long)N * L;
+    RSRR_TRY(p->ws.get<c64>("s_T64", (size_t)N * nn, &T));
+    RSRR_TRY(p->ws.get<c64>("s_dinv64", LUWork<float>::dinv_elems(n, nb, N), &dinv));
+    RSRR_TRY(p->ws.get<c64>("s_Y32", (size_t)n * cols, &Y32));
+    RSRR_TRY(p->ws.get<c128>("s_R", (size_t)n * cols, &Rb));
+    RSRR_TRY(p->ws.get<double>("s_nrm", 3 * (size_t)N + 1, &nrm));
+    RSRR_TRY(p->ws.get<int>("s_active", N, &active_dev));
+    RSRR_TRY(assemble_nodes<float>(p, N, f_dev, z_dev, T, s));
+    LUWork<float> w;
+    w.n = n; w.nb = nb; w.batch = N; w.lda = n; w.sA = nn; w.A = T;
+    w.ipiv = ipiv; w.dinv = dinv; w.info = infod;
+    w.tag = "sample_lu_c64";
+    RSRR_TRY(lu_factor<float>(w, s));
+    RSRR_TRY(check_info(infod, N, s, z));
+    // Y0 = T~^{-1} U in complex64, widened to fp64
+    RSRR_TRY((convert<float, double>(U, ldu, 0, Y32, n, (long)L * n, n, L, N, s)));
+    RSRR_TRY(lu_solve<float>(w, Y32, n, (long)L * n, L, s));
+    RSRR_TRY((convert<double, float>(Y32, n, (long)L * n, S, lds, (long)L * lds, n, L, N, s)));
+    // normalisation terms of the backward error
+    std::vector<double> fro2(N), u2(1);
+    if (p->bem) {
+      double* part = nullptr;
+      RSRR_TRY(p->ws.get<double>("s_bempart", (size_t)N * n, &part));
+      RSRR_TRY(bem_fro2(n, p->xyz, p->h, N, z_dev, part, nrm, s));
+      RSRR_HIP(hipMemcpyAsync(fro2.data(), nrm, N * sizeof(double), hipMemcpyDeviceToHost, s));
+    } else {
+      for (int j = 0; j < N; ++j) fro2[j] = fro2_coeff(p, &f[(size_t)j * p->J]);
+    }
+    RSRR_TRY(block_fro2(U, ldu, 0, n, L, 1, nrm + 3 * N, s));
+    RSRR_HIP(hipMemcpyAsync(u2.data(), nrm + 3 * N, sizeof(double), hipMemcpyDeviceToHost, s));
+    std::vector<int> active(N, 1);
+    std::vector<double> r2(N), y2(N);
+    for (int it = 0;; ++it) {
+      RSRR_TRY(residual_fp64(p, N, L, f_dev, z_dev, U, ldu, S, lds, Rb, s));
+      RSRR_TRY(block_fro2(Rb, n, (long)L * n, n, L, N, nrm, s));
+      RSRR_TRY(block_fro2(S, lds, (long)L * lds, n, L, N, nrm + N, s));
+      RSRR_HIP(hipMemcpyAsync(r2.data(), nrm, N * sizeof(double), hipMemcpyDeviceToHost, s));
+      RSRR_HIP(hipMemcpyAsync(y2.data(), nrm + N, N * sizeof(double), hipMemcpyDeviceToHost, s));
+      RSRR_HIP(hipStreamSynchronize(s));
+      int nact = 0;
+      for (int j = 0; j < N; ++j) {
+        const double eta = sqrt(r2[j]) / (sqrt(fro2[j]) * sqrt(y2[j]) + sqrt(u2[0]));
+        active[j] = (eta > prm->ir_tol) || !(eta == eta);
+        nact += active[j];
+      }
+      if (nact == 0 || it >= prm->ir_max_iter) break;
+      ir_iters = it + 1;
+      RSRR_HIP(hipMemcpyAsync(active_dev, active.data(), N * sizeof(int), hipMemcpyHostToDevice, s));
+      RSRR_TRY((convert<float, double>(Rb, n, (long)L * n, Y32, n, (long)L * n, n, L, N, s)));
+      RSRR_TRY(lu_solve<float>(w, Y32, n, (long)L * n, L, s));
+      RSRR_TRY(add_correction(S, lds, (long)L * lds, Y32, n, (long)L * n, n, L, N, active_dev, s));
+    }
+    // complex128 fallback for the nodes that did not converge
+    std::vector<int> bad;
+    for (int j = 0; j < N; ++j) if (active[j]) bad.push_back(j);
+    if (!bad.empty()) {
+      fallback = (int)bad.size();
+      warn |= RSRR_WARN_IR_FALLBACK;
+      const int nbad = (int)bad.size();
+      std::vector<cd> zb(nbad);
+      std::vector<c128> zbc(nbad), fb;
+      for (int q = 0; q < nbad; ++q) { zb[q] = z[bad[q]]; zbc[q] = zc[bad[q]]; }
+      if (!p->bem) node_coefs(p, zb, &fb);
+      c128 *Tb = nullptr, *dinvb = nullptr, *Yb = nullptr, *fbd = nullptr, *zbd = nullptr;
+      RSRR_TRY(p->ws.get<c128>("s_T128", (size_t)nbad * nn, &Tb));
+      RSRR_TRY(p->ws.get<c128>("s_dinv128", LUWork<double>::dinv_elems(n, nb, nbad), &dinvb));
+      RSRR_TRY(p->ws.get<c128>("s_Yfb", (size_t)nbad * n * L, &Yb));
+      RSRR_TRY(p->ws.get<c128>("s_ffb", std::max<size_t>(1, fb.size()), &fbd));
+      RSRR_TRY(p->ws.get<c128>("s_zfb", nbad, &zbd));
+      if (!fb.empty()) RSRR_HIP(hipMemcpyAsync(fbd, fb.data(), fb.size() * sizeof(c128), hipMemcpyHostToDevice, s));
+      RSRR_HIP(hipMemcpyAsync(zbd, zbc.data(), nbad * sizeof(c128), hipMemcpyHostToDevice, s));
+      RSRR_TRY(assemble_nodes<double>(p, nbad, fbd, zbd, Tb, s));
+      LUWork<double> wb;
+      wb.n = n; wb.nb = nb; wb.batch = nbad; wb.lda = n; wb.sA = nn; wb.A = Tb;
+      wb.ipiv = ipiv; wb.dinv = dinvb; wb.info = infod;
+      wb.tag = "fallback_lu_c128";
+      RSRR_TRY(lu_factor<double>(wb, s));
+      RSRR_TRY(check_info(infod, nbad, s, zb));
+      RSRR_TRY(replicate<double>(U, ldu, Yb, n, (long)n * L, n, L, nbad, s));
+      RSRR_TRY(lu_solve<double>(wb, Yb, n, (long)n * L, L, s));
+      for (int q = 0; q < nbad; ++q)
+        RSRR_TRY((convert<double, double>(Yb + (long)q * n * L, n, 0, S + (long)bad[q] * L * lds, lds,
+                                          0, n, L, 1, s)));
+    }
+  }
+  RSRR_HIP(hipStreamSynchronize(s));
+  if (info) {
+    info->n = n;
+    info->N = N;
+    info->L = L;
+    info->ir_iters = ir_iters;
+    info->ir_fallback = fallback;
+    info->t_sample = now_s() - t0;
+  }
+  return warn;
+}
+
+}  // namespace rsrr

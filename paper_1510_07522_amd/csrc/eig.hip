@@ -1,0 +1,501 @@
+// Dense fp64 kernels of the projected problem (Alg. 1, Steps 3-4):
+//   * one-sided (Hestenes) Jacobi SVD of the block Hankel matrix H, and
+//   * the standard eigenproblem of A = V0^H H^< W0 S0^{-1}: Householder
+//     reduction to Hessenberg form, single-shift complex QR to Schur form
+//     T = Z^H A Z, and eigenvectors of T by back substitution.
+#include <algorithm>
+#include <cmath>
+#include <numeric>
+
+#include "driver.h"
+#include "eig.h"
+#include "timers.h"
+
+namespace rsrr {
+
+// ------------------------------------------------------------------- SVD
+// One round of the cyclic (circle-method) ordering: Mp/2 disjoint column
+// pairs, one workgroup each.  Column q is first multiplied by conj(e^{i phi})
+// (phi = arg of the inner product), then a real rotation zeroes the pair.
+__global__ __launch_bounds__(256) void jacobi_round_kernel(c128* H, long ldh, c128* W, long ldw,
+                                                           int M, int Mp, int round, double tol,
+                                                           int* counter) {
+  __shared__ double red[4][256];
+  const int i = blockIdx.x;
+  int a = (round + i) % (Mp - 1);
+  int b = (i == 0) ? Mp - 1 : (round - i + Mp - 1) % (Mp - 1);
+  const int p = min(a, b), q = max(a, b);
+  if (q >= M) return;
+  c128* hp = H + (long)p * ldh;
+  c128* hq = H + (long)q * ldh;
+  double al = 0, be = 0, gr = 0, gi = 0;
+  for (int r = threadIdx.x; r < M; r += 256) {
+    const c128 x = hp[r], y = hq[r];
+    al += abs2(x);
+    be += abs2(y);
+    const c128 g = cmul(x, y);     // conj(x) y
+    gr += g.re;
+    gi += g.im;
+  }
+  red[0][threadIdx.x] = al; red[1][threadIdx.x] = be;
+  red[2][threadIdx.x] = gr; red[3][threadIdx.x] = gi;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (threadIdx.x < o)
+      for (int t = 0; t < 4; ++t) red[t][threadIdx.x] += red[t][threadIdx.x + o];
+    __syncthreads();
+  }
+  al = red[0][0]; be = red[1][0]; gr = red[2][0]; gi = red[3][0];
+  const double g = sqrt(gr * gr + gi * gi);
+  if (!(g > tol * sqrt(al * be))) return;
+  if (threadIdx.x == 0) atomicAdd(counter, 1);
+  const c128 phc = mk<double>(gr / g, -gi / g);   // conj(e^{i phi})
+  const double zeta = (be - al) / (2.0 * g);
+  const double t = (zeta >= 0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+  const double c = 1.0 / sqrt(1.0 + t * t), s = c * t;
+  for (int r = threadIdx.x; r < M; r += 256) {
+    const c128 x = hp[r], y = hq[r] * phc;
+    hp[r] = mk<double>(c * x.re - s * y.re, c * x.im - s * y.im);
+    hq[r] = mk<double>(s * x.re + c * y.re, s * x.im + c * y.im);
+  }
+  c128* wp = W + (long)p * ldw;
+  c128* wq = W + (long)q * ldw;
+  for (int r = threadIdx.x; r < M; r += 256) {
+    const c128 x = wp[r], y = wq[r] * phc;
+    wp[r] = mk<double>(c * x.re - s * y.re, c * x.im - s * y.im);
+    wq[r] = mk<double>(s * x.re + c * y.re, s * x.im + c * y.im);
+  }
+}
+
+__global__ __launch_bounds__(256) void col_norms_kernel(const c128* H, long ldh, int M, int ncol,
+                                                        double* out) {
+  __shared__ double red[256];
+  const int j = blockIdx.x;
+  if (j >= ncol) return;
+  double acc = 0;
+  for (int r = threadIdx.x; r < M; r += 256) acc += abs2(H[r + (long)j * ldh]);
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[j] = sqrt(red[0]);
+}
+
+// out[:, j] = in[:, perm[j]] * scale[j]  (scale may be null)
+__global__ __launch_bounds__(256) void permute_cols_kernel(const c128* in, long ldi, const int* perm,
+                                                           const double* scale, int rows, int ncol,
+                                                           c128* out, long ldo) {
+  const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= (long)rows * ncol) return;
+  const int r = (int)(e % rows), j = (int)(e / rows);
+  const int src = perm[j];
+  c128 v = in[r + (long)src * ldi];
+  if (scale) v = scale[j] * v;
+  out[r + (long)j * ldo] = v;
+}
+
+__global__ void identity_kernel(c128* X, long ldx, int m) {
+  const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= (long)m * m) return;
+  const int r = (int)(e % m), c = (int)(e / m);
+  X[r + (long)c * ldx] = mk<double>(r == c ? 1.0 : 0.0, 0);
+}
+
+int set_identity(c128* X, long ldx, int m, hipStream_t s) {
+  if (m <= 0) return ST_OK;
+  hipLaunchKernelGGL(identity_kernel, dim3((unsigned)cdivl((long)m * m, 256)), dim3(256), 0, s, X, ldx, m);
+  RSRR_LAUNCH_CHECK();
+  return ST_OK;
+}
+
+int jacobi_svd(c128* H, long ldh, int M, c128* U, long ldu, c128* W, long ldw,
+               std::vector<double>* sigma, Arena& ws, hipStream_t s) {
+  if (M <= 0) return ST_OK;
+  c128* Wt = nullptr;
+  int* cnt = nullptr;
+  double* sg = nullptr;
+  int* perm = nullptr;
+  RSRR_TRY(ws.get<c128>("sv_W", (size_t)M * M, &Wt));
+  RSRR_TRY(ws.get<int>("sv_cnt", 64, &cnt));
+  RSRR_TRY(ws.get<double>("sv_sig", M, &sg));
+  RSRR_TRY(ws.get<int>("sv_perm", M, &perm));
+  RSRR_TRY(set_identity(Wt, M, M, s));
+  const int Mp = M + (M & 1);
+  const double tol = 2.0 * 2.220446049250313e-16 * sqrt((double)M);
+  const int maxsweep = 40;
+  std::vector<int> hc(maxsweep, 0);
+  RSRR_HIP(hipMemsetAsync(cnt, 0, 64 * sizeof(int), s));
+  int sweep = 0;
+  bool converged = (Mp < 2);
+  for (; sweep < maxsweep && !converged; ++sweep) {
+    for (int r = 0; r < Mp - 1; ++r) {
+      // per round: Mp/2 pairs, each reads 2 and writes 2 columns of H and W (M rows)
+      KernelTimer kt("jacobi_round", s, 0.0, (Mp / 2) * 8.0 * M * sizeof(c128));
+      hipLaunchKernelGGL(jacobi_round_kernel, dim3(Mp / 2), dim3(256), 0, s, H, ldh, Wt, M, M, Mp,
+                         r, tol, cnt + (sweep % 64));
+      RSRR_LAUNCH_CHECK();
+    }
+    int c = 0;
+    RSRR_HIP(hipMemcpyAsync(&c, cnt + (sweep % 64), sizeof(int), hipMemcpyDeviceToHost, s));
+    RSRR_HIP(hipStreamSynchronize(s));
+    if (c == 0) converged = true;
+  }
+  if (!converged) return set_error(ST_ENOTCONV, "Jacobi SVD did not converge in %d sweeps", maxsweep);
+  hipLaunchKernelGGL(col_norms_kernel, dim3(M), dim3(256), 0, s, H, ldh, M, M, sg);
+  RSRR_LAUNCH_CHECK();
+  std::vector<double> hs(M);
+  RSRR_HIP(hipMemcpyAsync(hs.data(), sg, M * sizeof(double), hipMemcpyDeviceToHost, s));
+  RSRR_HIP(hipStreamSynchronize(s));
+  std::vector<int> order(M);
+  std::iota(order.begin(), order.end(), 0);
+  std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return hs[x] > hs[y]; });
+  sigma->resize(M);
+  std::vector<double> inv(M);
+  for (int j = 0; j < M; ++j) {
+    (*sigma)[j] = hs[order[j]];
+    inv[j] = hs[order[j]] > 0 ? 1.0 / hs[order[j]] : 0.0;
+  }
+  double* invd = nullptr;
+  RSRR_TRY(ws.get<double>("sv_inv", M, &invd));
+  RSRR_HIP(hipMemcpyAsync(perm, order.data(), M * sizeof(int), hipMemcpyHostToDevice, s));
+  RSRR_HIP(hipMemcpyAsync(invd, inv.data(), M * sizeof(double), hipMemcpyHostToDevice, s));
+  const unsigned g = (unsigned)cdivl((long)M * M, 256);
+  hipLaunchKernelGGL(permute_cols_kernel, dim3(g), dim3(256), 0, s, H, ldh, perm, invd, M, M, U, ldu);
+  RSRR_LAUNCH_CHECK();
+  hipLaunchKernelGGL(permute_cols_kernel, dim3(g), dim3(256), 0, s, Wt, M, perm, nullptr, M, M, W, ldw);
+  RSRR_LAUNCH_CHECK();
+  RSRR_HIP(hipStreamSynchronize(s));
+  return ST_OK;
+}
+
+// ------------------------------------------------------------ Hessenberg
+// Householder vector of x = A[k+1:m, k]: v (unit, stored in Vh[:, k]),
+// A[k+1][k] = alpha, A[k+2:m][k] = 0.  Reflector P = I - 2 v v^H.
+__global__ __launch_bounds__(256) void house_kernel(c128* A, long lda, int m, int k, c128* Vh,
+                                                    long ldv, int* skip) {
+  __shared__ double red[256];
+  const int n1 = m - k - 1;
+  double acc = 0;
+  for (int r = threadIdx.x; r < n1; r += 256) acc += abs2(A[k + 1 + r + (long)k * lda]);
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+    __syncthreads();
+  }
+  const double nx = sqrt(red[0]);
+  const c128 x0 = A[k + 1 + (long)k * lda];
+  const double ax0 = sqrt(abs2(x0));
+  // tail norm (entries below the first)
+  const double tail2 = red[0] - abs2(x0);
+  c128* v = Vh + (long)k * ldv;
+  if (!(tail2 > 0.0) || nx == 0.0) {        // already reduced
+    for (int r = threadIdx.x; r < m; r += 256) v[r] = mk<double>(0, 0);
+    if (threadIdx.x == 0) *skip = 1;
+    return;
+  }
+  const c128 ph = ax0 > 0 ? mk<double>(x0.re / ax0, x0.im / ax0) : mk<double>(1, 0);
+  const c128 alpha = mk<double>(-ph.re * nx, -ph.im * nx);
+  // v = x - alpha e1, ||v||^2 = ||x||^2 - 2 Re(conj(alpha) x0) + |alpha|^2 = 2 nx (nx + ax0)
+  const double vn = sqrt(2.0 * nx * (nx + ax0));
+  for (int r = threadIdx.x; r < m; r += 256) {
+    c128 val = mk<double>(0, 0);
+    if (r > k) {
+      val = A[r + (long)k * lda];
+      if (r == k + 1) val = val - alpha;
+      val = (1.0 / vn) * val;
+    }
+    v[r] = val;
+  }
+  __syncthreads();
+  for (int r = threadIdx.x; r < n1; r += 256)
+    A[k + 1 + r + (long)k * lda] = (r == 0) ? alpha : mk<double>(0, 0);
+  if (threadIdx.x == 0) *skip = 0;
+}
+
+// w[c] = sum_r conj(v[r]) X[r][c] over rows r in [r0, m), columns c in [c0, c1)
+__global__ __launch_bounds__(256) void vhx_kernel(const c128* v, const c128* X, long ldx, int r0,
+                                                  int m, int c0, int c1, c128* w, const int* skip) {
+  if (*skip) return;
+  __shared__ double re_[256], im_[256];
+  const int c = c0 + blockIdx.x;
+  if (c >= c1) return;
+  double ar = 0, ai = 0;
+  for (int r = r0 + threadIdx.x; r < m; r += 256) {
+    const c128 t = cmul(v[r], X[r + (long)c * ldx]);
+    ar += t.re;
+    ai += t.im;
+  }
+  re_[threadIdx.x] = ar;
+  im_[threadIdx.x] = ai;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (threadIdx.x < o) { re_[threadIdx.x] += re_[threadIdx.x + o]; im_[threadIdx.x] += im_[threadIdx.x + o]; }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) w[c] = mk<double>(re_[0], im_[0]);
+}
+
+// X[r][c] -= 2 v[r] w[c]  for r in [r0, m), c in [c0, c1)
+__global__ __launch_bounds__(256) void left_update_kernel(const c128* v, c128* X, long ldx, int r0,
+                                                          int m, int c0, int c1, const c128* w,
+                                                          const int* skip) {
+  if (*skip) return;
+  const long nr = m - r0, cnt = nr * (long)(c1 - c0);
+  const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= cnt) return;
+  const int r = r0 + (int)(e % nr), c = c0 + (int)(e / nr);
+  const c128 t = v[r] * w[c];
+  c128& x = X[r + (long)c * ldx];
+  x = mk<double>(x.re - 2.0 * t.re, x.im - 2.0 * t.im);
+}
+
+// u[r] = sum_c X[r][c] v[c] over c in [c0, m), rows r in [0, nrow)
+__global__ __launch_bounds__(256) void xv_kernel(const c128* X, long ldx, const c128* v, int c0, int m,
+                                                 int nrow, c128* u, const int* skip) {
+  if (*skip) return;
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= nrow) return;
+  c128 acc = mk<double>(0, 0);
+  for (int c = c0; c < m; ++c) acc = acc + X[r + (long)c * ldx] * v[c];
+  u[r] = acc;
+}
+
+// X[r][c] -= 2 u[r] conj(v[c])  for r in [0, nrow), c in [c0, m)
+__global__ __launch_bounds__(256) void right_update_kernel(c128* X, long ldx, const c128* u,
+                                                           const c128* v, int c0, int m, int nrow,
+                                                           const int* skip) {
+  if (*skip) return;
+  const long cnt = (long)nrow * (m - c0);
+  const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= cnt) return;
+  const int r = (int)(e % nrow), c = c0 + (int)(e / nrow);
+  const c128 t = mulc(u[r], v[c]);
+  c128& x = X[r + (long)c * ldx];
+  x = mk<double>(x.re - 2.0 * t.re, x.im - 2.0 * t.im);
+}
+
+// ------------------------------------------------------------- Schur QR
+// Single-shift complex QR on the Hessenberg matrix (one workgroup), with the
+// full Schur form (rotations applied to all columns right / rows above) and
+// the accumulated unitary Z.
+constexpr int QT = 1024;
+__device__ inline c128 csqrt_d(c128 z) {
+  const double r = sqrt(sqrt(abs2(z)));
+  const double th = 0.5 * atan2(z.im, z.re);
+  return mk<double>(r * cos(th), r * sin(th));
+}
+
+__global__ __launch_bounds__(QT) void hqr_kernel(c128* H, long ldh, c128* Z, long ldz, int m,
+                                                 int maxit, int* status) {
+  __shared__ int s_l, s_i, s_its, s_total;
+  __shared__ c128 s_rot[2];     // (c, s) with c real in rot[0].re
+  __shared__ int s_red[QT / 64];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const double ulp = 2.220446049250313e-16;
+  if (tid == 0) { s_i = m - 1; s_its = 0; s_total = 0; }
+  __syncthreads();
+  while (true) {
+    const int i = s_i;
+    if (i < 0) break;
+    // deflation: largest k in [1, i] with a negligible subdiagonal (else 0)
+    int best = 0;
+    for (int k = 1 + tid; k <= i; k += QT) {
+      const double sub = cabs1(H[k + (long)(k - 1) * ldh]);
+      const double dsum = cabs1(H[k - 1 + (long)(k - 1) * ldh]) + cabs1(H[k + (long)k * ldh]);
+      if (sub <= ulp * dsum) best = max(best, k);
+    }
+    for (int off = 32; off >= 1; off >>= 1) best = max(best, __shfl_xor(best, off));
+    if (lane == 0) s_red[wave] = best;
+    __syncthreads();
+    if (tid == 0) {
+      int b = 0;
+      for (int q = 0; q < QT / 64; ++q) b = max(b, s_red[q]);
+      if (b > 0) H[b + (long)(b - 1) * ldh] = mk<double>(0, 0);
+      s_l = b;
+    }
+    __syncthreads();
+    const int l = s_l;
+    if (l == i) {                        // 1x1 block converged
+      if (tid == 0) { s_i = i - 1; s_its = 0; }
+      __syncthreads();
+      continue;
+    }
+    if (tid == 0) {
+      s_its += 1;
+      s_total += 1;
+    }
+    __syncthreads();
+    if (s_total > maxit) {
+      if (tid == 0) *status = -1;
+      return;
+    }
+    // shift and first rotation (thread 0)
+    for (int k = l; k < i; ++k) {
+      if (tid == 0) {
+        c128 x, y;
+        if (k == l) {
+          c128 mu;
+          const int its = s_its;
+          if (its == 10 || its == 20) {
+            const c128 hii = H[i + (long)i * ldh];
+            mu = mk<double>(hii.re + 0.75 * fabs(H[i + (long)(i - 1) * ldh].re), hii.im);
+          } else {
+            const c128 a = H[i - 1 + (long)(i - 1) * ldh], b = H[i - 1 + (long)i * ldh];
+            const c128 c = H[i + (long)(i - 1) * ldh], d = H[i + (long)i * ldh];
+            const c128 tr = 0.5 * (a + d);
+            const c128 disc = csqrt_d(tr * tr - (a * d - b * c));
+            const c128 e1 = tr + disc, e2 = tr - disc;
+            mu = (abs2(e1 - d) < abs2(e2 - d)) ? e1 : e2;
+          }
+          x = H[l + (long)l * ldh] - mu;
+          y = H[l + 1 + (long)l * ldh];
+        } else {
+          x = H[k + (long)(k - 1) * ldh];
+          y = H[k + 1 + (long)(k - 1) * ldh];
+        }
+        const double ax = sqrt(abs2(x)), ay = sqrt(abs2(y));
+        const double rho = hypot(ax, ay);
+        c128 cc = mk<double>(1, 0), ss = mk<double>(0, 0);
+        if (rho > 0) {
+          if (ax == 0) { cc = mk<double>(0, 0); ss = mk<double>(y.re / ay, -y.im / ay); }
+          else {
+            cc = mk<double>(ax / rho, 0);
+            const c128 ph = mk<double>(x.re / ax, x.im / ax);
+            ss = (1.0 / rho) * mulc(ph, y);     // ph * conj(y) / rho
+          }
+        }
+        s_rot[0] = cc;
+        s_rot[1] = ss;
+      }
+      __syncthreads();
+      const double c = s_rot[0].re;
+      const c128 sn = s_rot[1];
+      // rows k, k+1:  [r_k; r_k1] = [c, s; -conj(s), c] [r_k; r_k1]
+      const int c0 = (k == l) ? l : k - 1;
+      for (int col = c0 + tid; col < m; col += QT) {
+        const c128 a = H[k + (long)col * ldh], b = H[k + 1 + (long)col * ldh];
+        H[k + (long)col * ldh] = c * a + sn * b;
+        H[k + 1 + (long)col * ldh] = c * b - conj(sn) * a;
+      }
+      __syncthreads();
+      // columns k, k+1:  [c_k, c_k1] = [c_k, c_k1] G^H, G^H = [c, -s; conj(s), c]
+      const int r1 = min(k + 2, i);
+      for (int row = tid; row <= r1; row += QT) {
+        const c128 a = H[row + (long)k * ldh], b = H[row + (long)(k + 1) * ldh];
+        H[row + (long)k * ldh] = c * a + conj(sn) * b;
+        H[row + (long)(k + 1) * ldh] = c * b - sn * a;
+      }
+      for (int row = tid; row < m; row += QT) {
+        const c128 a = Z[row + (long)k * ldz], b = Z[row + (long)(k + 1) * ldz];
+        Z[row + (long)k * ldz] = c * a + conj(sn) * b;
+        Z[row + (long)(k + 1) * ldz] = c * b - sn * a;
+      }
+      __syncthreads();
+      if (k > l && tid == 0) H[k + 1 + (long)(k - 1) * ldh] = mk<double>(0, 0);
+      __syncthreads();
+    }
+  }
+  if (tid == 0) *status = s_total;
+}
+
+// Eigenvector i of the upper-triangular T (one workgroup per eigenvalue):
+// x_i = 1, x_j = -(sum_{l>j} T[j][l] x_l) / (T[j][j] - T[i][i]) for j < i.
+__global__ __launch_bounds__(256) void trevc_kernel(const c128* T, long ldt, int m, double small,
+                                                    c128* X, long ldx) {
+  extern __shared__ c128 r_acc[];      // m partial sums
+  const int i = blockIdx.x;
+  const c128 lam = T[i + (long)i * ldt];
+  c128* x = X + (long)i * ldx;
+  for (int j = threadIdx.x; j < m; j += 256) {
+    r_acc[j] = mk<double>(0, 0);
+    x[j] = mk<double>(j == i ? 1.0 : 0.0, 0);
+  }
+  __syncthreads();
+  c128 xl = mk<double>(1, 0);
+  for (int l = i; l >= 1; --l) {
+    // column l of T contributes to rows j < l
+    for (int j = threadIdx.x; j < l; j += 256) r_acc[j] = r_acc[j] + T[j + (long)l * ldt] * xl;
+    __syncthreads();
+    c128 d = T[l - 1 + (long)(l - 1) * ldt] - lam;
+    if (abs2(d) < small * small) d = mk<double>(small, 0);
+    const c128 r = r_acc[l - 1];
+    xl = cdiv(mk<double>(-r.re, -r.im), d);
+    if (threadIdx.x == 0) x[l - 1] = xl;
+    __syncthreads();
+  }
+}
+
+int eig_general(c128* A, long lda, int m, std::vector<cd>* lam, c128* V, long ldv, Arena& ws,
+                hipStream_t s) {
+  lam->clear();
+  if (m <= 0) return ST_OK;
+  c128 *Vh = nullptr, *Z = nullptr, *w = nullptr, *X = nullptr;
+  int* skip = nullptr;
+  RSRR_TRY(ws.get<c128>("eg_Vh", (size_t)m * m, &Vh));
+  RSRR_TRY(ws.get<c128>("eg_Z", (size_t)m * m, &Z));
+  RSRR_TRY(ws.get<c128>("eg_w", m, &w));
+  RSRR_TRY(ws.get<c128>("eg_X", (size_t)m * m, &X));
+  RSRR_TRY(ws.get<int>("eg_skip", 2, &skip));
+  RSRR_TRY(set_identity(Z, m, m, s));
+  // ---- Hessenberg reduction A = Q Hs Q^H; Z accumulates Q
+  for (int k = 0; k + 2 < m; ++k) {
+    KernelTimer kt("hessenberg", s, 8.0 * 4.0 * (double)m * (m - k), 16.0 * 6 * (double)m * (m - k));
+    hipLaunchKernelGGL(house_kernel, dim3(1), dim3(256), 0, s, A, lda, m, k, Vh, m, skip);
+    RSRR_LAUNCH_CHECK();
+    const c128* v = Vh + (long)k * m;
+    // left: A[k+1:, k+1:] -= 2 v (v^H A[k+1:, k+1:])
+    hipLaunchKernelGGL(vhx_kernel, dim3(m - k - 1), dim3(256), 0, s, v, A, lda, k + 1, m, k + 1, m, w, skip);
+    RSRR_LAUNCH_CHECK();
+    long cnt = (long)(m - k - 1) * (m - k - 1);
+    hipLaunchKernelGGL(left_update_kernel, dim3((unsigned)cdivl(cnt, 256)), dim3(256), 0, s, v, A, lda,
+                       k + 1, m, k + 1, m, w, skip);
+    RSRR_LAUNCH_CHECK();
+    // right: A[:, k+1:] -= 2 (A[:, k+1:] v) v^H ; same for Z
+    hipLaunchKernelGGL(xv_kernel, dim3((unsigned)cdivl(m, 256)), dim3(256), 0, s, A, lda, v, k + 1, m, m, w, skip);
+    RSRR_LAUNCH_CHECK();
+    cnt = (long)m * (m - k - 1);
+    hipLaunchKernelGGL(right_update_kernel, dim3((unsigned)cdivl(cnt, 256)), dim3(256), 0, s, A, lda, w, v,
+                       k + 1, m, m, skip);
+    RSRR_LAUNCH_CHECK();
+    hipLaunchKernelGGL(xv_kernel, dim3((unsigned)cdivl(m, 256)), dim3(256), 0, s, Z, m, v, k + 1, m, m, w, skip);
+    RSRR_LAUNCH_CHECK();
+    hipLaunchKernelGGL(right_update_kernel, dim3((unsigned)cdivl(cnt, 256)), dim3(256), 0, s, Z, m, w, v,
+                       k + 1, m, m, skip);
+    RSRR_LAUNCH_CHECK();
+  }
+  // ---- Schur form
+  {
+  KernelTimer kt("hqr", s, 0.0, 0.0);
+  hipLaunchKernelGGL(hqr_kernel, dim3(1), dim3(QT), 0, s, A, lda, Z, m, m, 60 * m + 100, skip + 1);
+  RSRR_LAUNCH_CHECK();
+  }
+  int st = 0;
+  RSRR_HIP(hipMemcpyAsync(&st, skip + 1, sizeof(int), hipMemcpyDeviceToHost, s));
+  RSRR_HIP(hipStreamSynchronize(s));
+  if (st < 0) return set_error(ST_ENOTCONV, "Hessenberg QR did not converge (m=%d)", m);
+  // ---- eigenvalues and eigenvectors
+  std::vector<c128> diag(m);
+  RSRR_HIP(hipMemcpy2DAsync(diag.data(), sizeof(c128), A, (lda + 1) * sizeof(c128), sizeof(c128), m,
+                            hipMemcpyDeviceToHost, s));
+  RSRR_HIP(hipStreamSynchronize(s));
+  double tnorm = 0;
+  for (int j = 0; j < m; ++j) tnorm = std::max(tnorm, sqrt(abs2(diag[j])));
+  const double small = std::max(tnorm, 1e-300) * 2.220446049250313e-16;
+  const size_t shm = (size_t)m * sizeof(c128);
+  if (shm > 150 * 1024) return set_error(ST_EINVAL, "eigenvectors: m=%d too large", m);
+  KernelTimer kt("trevc", s, 8.0 * (double)m * m * m / 6, 16.0 * (double)m * m * m / 2);
+  hipLaunchKernelGGL(trevc_kernel, dim3(m), dim3(256), shm, s, A, lda, m, small, X, m);
+  RSRR_LAUNCH_CHECK();
+  GemmBatch<double> g;                    // V = Z X
+  g.M = m; g.N = m; g.K = m;
+  g.A = Z; g.lda = m; g.B = X; g.ldb = m; g.C = V; g.ldc = ldv;
+  RSRR_TRY(gemm_batched<double>(g, s));
+  lam->resize(m);
+  for (int j = 0; j < m; ++j) (*lam)[j] = cd(diag[j].re, diag[j].im);
+  return ST_OK;
+}
+
+}  // namespace rsrr

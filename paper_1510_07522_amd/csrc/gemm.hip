@@ -1,0 +1,230 @@
+// Batched complex GEMM on CDNA4 matrix cores.
+//
+//   C_b = alpha * op(A_b) * op(B_b) + beta * C_b,   b = 0 .. batch-1
+//
+// Complex products are split into real MFMA products on interleaved data:
+//   4M:  Cr += Ar Br - Ai Bi,  Ci += Ar Bi + Ai Br          (4 MFMA / k-quad)
+//   3M:  P1 += Ar Br, P2 += Ai Bi, P3 += (Ar+Ai)(Br+Bi);    (3 MFMA / k-quad)
+//        Cr = P1 - P2, Ci = P3 - P1 - P2                    (fp32 only)
+// A may be real (fp64/fp32 values), which halves the products.
+//
+// Tiling: 64x64 C tile per 256-thread workgroup, 4 waves in a 2x2 layout,
+// each wave owns 32x32 = 2x2 blocks of the 16x16x4 MFMA.  K is staged through
+// LDS 16 at a time with one register-prefetched tile in flight.
+#include "common.h"
+#include "kernels.h"
+#include "timers.h"
+
+namespace rsrr {
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+typedef float f4 __attribute__((ext_vector_type(4)));
+
+template <typename R> struct V4;
+template <> struct V4<double> { typedef d4 T; };
+template <> struct V4<float> { typedef f4 T; };
+
+__device__ inline d4 mfma16(double a, double b, d4 c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+__device__ inline f4 mfma16(float a, float b, f4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+
+constexpr int BM = 64, BN = 64, BK = 16, PAD = 16, NT = 256;
+
+template <typename R, int OPA, int OPB, bool AREAL, bool G3M>
+__global__ __launch_bounds__(NT) void gemm_kernel(GemmBatch<R> g) {
+  typedef typename V4<R>::T acc_t;
+  __shared__ R As_re[BK][BM + PAD];
+  __shared__ R As_im[AREAL ? 1 : BK][BM + PAD];
+  __shared__ R Bs_re[BK][BN + PAD];
+  __shared__ R Bs_im[BK][BN + PAD];
+
+  const int bz = blockIdx.z;
+  const int M = g.M, N = g.N, K = g.K;
+  const int m0 = blockIdx.x * BM, n0 = blockIdx.y * BN;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = wave & 1, wn = wave >> 1;
+
+  const R* Ar = AREAL ? (const R*)g.A + (long)bz * g.sA : nullptr;
+  const cplx<R>* Ac = AREAL ? nullptr : (const cplx<R>*)g.A + (long)bz * g.sA;
+  const cplx<R>* Bp = g.B + (long)bz * g.sB;
+  cplx<R>* Cp = g.C + (long)bz * g.sC;
+
+  acc_t acc0[2][2], acc1[2][2], acc2[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      acc0[i][j] = acc_t{0, 0, 0, 0};
+      acc1[i][j] = acc_t{0, 0, 0, 0};
+      acc2[i][j] = acc_t{0, 0, 0, 0};
+    }
+
+  // register staging of one A and one B tile (4 elements per thread each)
+  cplx<R> ra[4], rb[4];
+  auto load_tiles = [&](int k0) {
+#pragma unroll
+    for (int p = 0; p < 4; ++p) {
+      int m, k;
+      if (OPA == OP_N) { m = tid & 63; k = (tid >> 6) + 4 * p; }
+      else             { k = tid & 15; m = (tid >> 4) + 16 * p; }
+      int gm = m0 + m, gk = k0 + k;
+      cplx<R> v = mk<R>(0, 0);
+      if (gm < M && gk < K) {
+        long idx = (OPA == OP_N) ? (long)gm + (long)gk * g.lda : (long)gk + (long)gm * g.lda;
+        if (AREAL) v.re = Ar[idx];
+        else {
+          v = Ac[idx];
+          if (OPA == OP_C) v.im = -v.im;
+        }
+      }
+      ra[p] = v;
+    }
+#pragma unroll
+    for (int p = 0; p < 4; ++p) {
+      int n, k;
+      if (OPB == OP_N) { k = tid & 15; n = (tid >> 4) + 16 * p; }
+      else             { n = tid & 63; k = (tid >> 6) + 4 * p; }
+      int gn = n0 + n, gk = k0 + k;
+      cplx<R> v = mk<R>(0, 0);
+      if (gn < N && gk < K) {
+        long idx = (OPB == OP_N) ? (long)gk + (long)gn * g.ldb : (long)gn + (long)gk * g.ldb;
+        v = Bp[idx];
+        if (OPB == OP_C) v.im = -v.im;
+      }
+      rb[p] = v;
+    }
+  };
+  auto store_tiles = [&]() {
+#pragma unroll
+    for (int p = 0; p < 4; ++p) {
+      int m, k;
+      if (OPA == OP_N) { m = tid & 63; k = (tid >> 6) + 4 * p; }
+      else             { k = tid & 15; m = (tid >> 4) + 16 * p; }
+      As_re[k][m] = ra[p].re;
+      if (!AREAL) As_im[k][m] = ra[p].im;
+    }
+#pragma unroll
+    for (int p = 0; p < 4; ++p) {
+      int n, k;
+      if (OPB == OP_N) { k = tid & 15; n = (tid >> 4) + 16 * p; }
+      else             { n = tid & 63; k = (tid >> 6) + 4 * p; }
+      Bs_re[k][n] = rb[p].re;
+      Bs_im[k][n] = rb[p].im;
+    }
+  };
+
+  const int ntiles = (K + BK - 1) / BK;
+  if (ntiles > 0) load_tiles(0);
+  for (int t = 0; t < ntiles; ++t) {
+    store_tiles();
+    __syncthreads();
+    if (t + 1 < ntiles) load_tiles((t + 1) * BK);
+#pragma unroll
+    for (int kq = 0; kq < BK / 4; ++kq) {
+      const int kk = kq * 4 + (lane >> 4);
+      R ar[2], ai[2], br[2], bi[2];
+#pragma unroll
+      for (int i = 0; i < 2; ++i) {
+        int mm = wm * 32 + i * 16 + (lane & 15);
+        ar[i] = As_re[kk][mm];
+        ai[i] = AREAL ? R(0) : As_im[kk][mm];
+      }
+#pragma unroll
+      for (int j = 0; j < 2; ++j) {
+        int nn = wn * 32 + j * 16 + (lane & 15);
+        br[j] = Bs_re[kk][nn];
+        bi[j] = Bs_im[kk][nn];
+      }
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+          if (AREAL) {
+            acc0[i][j] = mfma16(ar[i], br[j], acc0[i][j]);
+            acc1[i][j] = mfma16(ar[i], bi[j], acc1[i][j]);
+          } else if (G3M) {
+            acc0[i][j] = mfma16(ar[i], br[j], acc0[i][j]);
+            acc1[i][j] = mfma16(ai[i], bi[j], acc1[i][j]);
+            acc2[i][j] = mfma16(ar[i] + ai[i], br[j] + bi[j], acc2[i][j]);
+          } else {
+            acc0[i][j] = mfma16(ar[i], br[j], acc0[i][j]);
+            acc0[i][j] = mfma16(-ai[i], bi[j], acc0[i][j]);
+            acc1[i][j] = mfma16(ar[i], bi[j], acc1[i][j]);
+            acc1[i][j] = mfma16(ai[i], br[j], acc1[i][j]);
+          }
+        }
+    }
+    __syncthreads();
+  }
+
+  // epilogue.  Accumulator lane layout (column lane%16 of each 16x16 block):
+  //   f32 16x16x4: element r holds row 4*(lane/16) + r
+  //   f64 16x16x4: element r holds row lane/16 + 4*r
+  const bool beta0 = (g.beta.re == R(0) && g.beta.im == R(0));
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      int col = n0 + wn * 32 + j * 16 + (lane & 15);
+      if (col >= N) continue;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int rr = (sizeof(R) == 8) ? (lane >> 4) + 4 * r : 4 * (lane >> 4) + r;
+        int row = m0 + wm * 32 + i * 16 + rr;
+        if (row >= M) continue;
+        cplx<R> v;
+        if (AREAL) { v.re = acc0[i][j][r]; v.im = acc1[i][j][r]; }
+        else if (G3M) {
+          v.re = acc0[i][j][r] - acc1[i][j][r];
+          v.im = acc2[i][j][r] - acc0[i][j][r] - acc1[i][j][r];
+        } else { v.re = acc0[i][j][r]; v.im = acc1[i][j][r]; }
+        cplx<R> out = g.alpha * v;
+        long idx = (long)row + (long)col * g.ldc;
+        if (!beta0) out = out + g.beta * Cp[idx];
+        Cp[idx] = out;
+      }
+    }
+}
+
+template <typename R, int OPA, int OPB, bool AREAL, bool G3M>
+static int launch_one(const GemmBatch<R>& g, hipStream_t s) {
+  dim3 grid((unsigned)cdivl(g.M, BM), (unsigned)cdivl(g.N, BN), (unsigned)g.batch);
+  const double es = (double)sizeof(cplx<R>);
+  const double flops = (AREAL ? 4.0 : 8.0) * g.M * (double)g.N * g.K * g.batch;
+  const double bytes = g.batch * ((AREAL ? es / 2 : es) * (double)g.M * g.K + es * (double)g.K * g.N +
+                                  es * (double)g.M * g.N *
+                                      ((g.beta.re != R(0) || g.beta.im != R(0)) ? 2.0 : 1.0));
+  KernelTimer kt(g.tag, s, flops, bytes);
+  hipLaunchKernelGGL((gemm_kernel<R, OPA, OPB, AREAL, G3M>), grid, dim3(NT), 0, s, g);
+  RSRR_LAUNCH_CHECK();
+  return ST_OK;
+}
+
+template <typename R, bool AREAL, bool G3M>
+static int launch_ops(const GemmBatch<R>& g, hipStream_t s) {
+#define RSRR_CASE(a, b) if (g.opA == a && g.opB == b) return launch_one<R, a, b, AREAL, G3M>(g, s);
+  RSRR_CASE(OP_N, OP_N) RSRR_CASE(OP_N, OP_T) RSRR_CASE(OP_N, OP_C)
+  RSRR_CASE(OP_T, OP_N) RSRR_CASE(OP_T, OP_T) RSRR_CASE(OP_T, OP_C)
+  RSRR_CASE(OP_C, OP_N) RSRR_CASE(OP_C, OP_T) RSRR_CASE(OP_C, OP_C)
+#undef RSRR_CASE
+  return set_error(ST_EINVAL, "gemm: bad op pair %d,%d", g.opA, g.opB);
+}
+
+template <typename R>
+int gemm_batched(const GemmBatch<R>& g, hipStream_t s) {
+  if (g.M < 0 || g.N < 0 || g.K < 0 || g.batch < 0)
+    return set_error(ST_EINVAL, "gemm: negative size");
+  if (g.M == 0 || g.N == 0 || g.batch == 0) return ST_OK;
+  if (g.a_real && g.opA == OP_C) return set_error(ST_EINVAL, "gemm: real A with conj op");
+  if (g.a_real) return launch_ops<R, true, false>(g, s);
+  if (g.gauss3m && sizeof(R) == 4) return launch_ops<R, false, true>(g, s);
+  return launch_ops<R, false, false>(g, s);
+}
+
+template int gemm_batched<double>(const GemmBatch<double>&, hipStream_t);
+template int gemm_batched<float>(const GemmBatch<float>&, hipStream_t);
+
+}  // namespace rsrr

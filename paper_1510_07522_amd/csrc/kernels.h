@@ -1,0 +1,98 @@
+// Internal (C++) interfaces between the RSRR host driver and its kernels.
+#pragma once
+#include "common.h"
+
+namespace rsrr {
+
+enum { OP_N = 0, OP_T = 1, OP_C = 2 };
+
+// Strided batched complex GEMM descriptor (column-major operands).
+template <typename R> struct GemmBatch {
+  int opA = OP_N, opB = OP_N;
+  int M = 0, N = 0, K = 0;
+  cplx<R> alpha = {1, 0}, beta = {0, 0};
+  const void* A = nullptr; long lda = 0, sA = 0;   // complex or (a_real) real R
+  const cplx<R>* B = nullptr; long ldb = 0, sB = 0;
+  cplx<R>* C = nullptr; long ldc = 0, sC = 0;
+  int batch = 1;
+  bool a_real = false;
+  bool gauss3m = false;   // 3-multiplication complex product (fp32 only)
+  const char* tag = "gemm";   // kernel-timer class
+};
+template <typename R> int gemm_batched(const GemmBatch<R>& g, hipStream_t s);
+
+// ---------------------------------------------------------------- batched LU
+// Factors `batch` n x n matrices stored with leading dimension lda and batch
+// stride sA (elements).  Partial pivoting with row interchanges recorded in
+// ipiv[b*n + i] (0-based, LAPACK order).  Row interchanges are applied only
+// to the columns right of each panel: the L columns of panel p keep the row
+// order they had when panel p was factored, and the solver applies the
+// interchanges panel by panel.  The inverses of the unit-lower and upper
+// diagonal blocks of every panel are kept in dinv (batch x npanel x 2 x nb x nb).
+// info[b] = 0 or the 1-based index of the first exactly-zero pivot.
+template <typename R> struct LUWork {
+  int n = 0, nb = 64, batch = 0;
+  long lda = 0, sA = 0;
+  cplx<R>* A = nullptr;
+  int* ipiv = nullptr;       // batch * n
+  cplx<R>* dinv = nullptr;   // batch * npanel * 2 * nb * nb
+  int* info = nullptr;       // batch
+  const char* tag = "lu";    // kernel-timer class prefix (<tag>_panel, <tag>_update, ...)
+  int npanel() const { return (n + nb - 1) / nb; }
+  static size_t dinv_elems(int n, int nb, int batch) {
+    return (size_t)batch * ((n + nb - 1) / nb) * 2 * nb * nb;
+  }
+};
+template <typename R> int lu_factor(const LUWork<R>& w, hipStream_t s);
+// Solves A_b X_b = B_b in place for nrhs columns (B leading dim ldb, stride sB).
+template <typename R> int lu_solve(const LUWork<R>& w, cplx<R>* B, long ldb, long sB,
+                                   int nrhs, hipStream_t s);
+
+// ----------------------------------------------------------------- assembly
+// Coefficient form: T_j = sum_k f[j*J + k] * A_k for j < nz, written to
+// T + j*sT (leading dim ldt).  Coefficient k has kind kinds[k]:
+//   0 identity, 1 diagonal (complex128 vector), 2 dense real (float64),
+//   3 dense complex (complex128).
+struct CoeffSet {
+  int n = 0, J = 0;
+  const int* kinds_host = nullptr;     // J kinds (host)
+  const void* const* mats = nullptr;   // J device pointers (host array)
+};
+template <typename R> int assemble_coeff(const CoeffSet& cs, int nz, const c128* f_dev,
+                                         cplx<R>* T, long ldt, long sT, hipStream_t s);
+// BEM single layer: T_ij = exp(i z r_ij)/(4 pi r_ij), T_ii = i z/(4 pi) + 1/(2h).
+template <typename R> int assemble_bem(int n, const double* xyz, double h, int nz,
+                                       const c128* z_dev, cplx<R>* T, long ldt, long sT,
+                                       hipStream_t s);
+// Frobenius norms of the BEM matrices at nz nodes (fp64), fro2[j] = ||T(z_j)||_F^2.
+int bem_fro2(int n, const double* xyz, double h, int nz, const c128* z_dev,
+             double* partial, double* fro2, hipStream_t s);
+// R_j = U - T(z_j) Y_j for the BEM matrix, assembled on the fly in fp64.
+int bem_residual(int n, const double* xyz, double h, int nz, const c128* z_dev,
+                 const c128* U, long ldu, const c128* Y, long ldy, long sY, int L,
+                 c128* Rout, long ldr, long sR, hipStream_t s);
+
+// ------------------------------------------------------------- elementwise
+template <typename D, typename S>
+int convert(const cplx<S>* src, long lds, long ss, cplx<D>* dst, long ldd, long sd,
+            int rows, int cols, int batch, hipStream_t s);
+// dst_b = src (same block replicated batch times)
+template <typename R>
+int replicate(const cplx<R>* src, long lds, cplx<R>* dst, long ldd, long sd, int rows,
+              int cols, int batch, hipStream_t s);
+// Y_b += D_b (fp64 += fp32) for the batches with active[b] != 0
+int add_correction(c128* Y, long ldy, long sY, const c64* D, long ldd, long sD, int rows,
+                   int cols, int batch, const int* active, hipStream_t s);
+// R_b = U - sum_k coef[b*J+k] * P_k[:, b*L:(b+1)*L]  (P_k = A_k Y, n x (batch*L))
+int combine_residual(const c128* U, long ldu, const c128* const* P_dev, int J,
+                     const c128* coef, int n, int L, int batch, c128* R, long ldr,
+                     hipStream_t s);
+// Per-batch Frobenius norm squared of an n x cols block: out[b] (deterministic).
+int block_fro2(const c128* X, long ldx, long sX, int rows, int cols, int batch,
+               double* out, hipStream_t s);
+
+// Y = diag(d) X  (n x cols)
+int diag_scale(const c128* d, const c128* X, long ldx, c128* Y, long ldy, int n, int cols,
+               hipStream_t s);
+
+}  // namespace rsrr

@@ -1,0 +1,459 @@
+// Batched blocked right-looking complex LU with partial pivoting, and the
+// matching solve, for the probed-resolvent solves T(z_j) Y_j = U.
+//
+// Per panel of width nb (default 64):
+//   1. lu_panel_kernel (one 1024-thread workgroup per matrix): the panel is
+//      factored in register-resident micro-panels of W columns; pivot search
+//      is a workgroup arg-max of |re|+|im| (first index on ties, as LAPACK);
+//      the rest of the panel is updated in place; finally the unit-lower and
+//      upper diagonal blocks are inverted in LDS (kept for the solves).
+//   2. lu_permute_kernel: the panel's interchanges, applied as one gather to
+//      the columns right of the panel.
+//   3. U12 = inv(L11) A12 and A22 -= L21 U12 as matrix-core GEMMs.
+#include "common.h"
+#include "kernels.h"
+#include "timers.h"
+#include <string>
+
+namespace rsrr {
+
+constexpr int PNT = 1024;           // panel workgroup size (16 waves)
+constexpr int MAXNB = 64;
+
+template <typename R, int ROWS, int W>
+__global__ __launch_bounds__(PNT) void lu_panel_kernel(cplx<R>* A, long lda, long sA, int n,
+                                                        int k, int nbe, int nb, int* ipiv,
+                                                        cplx<R>* dinv, long sD, int* info) {
+  __shared__ R s_val[2][16];
+  __shared__ int s_idx[2][16];
+  __shared__ cplx<R> s_prow[2][W], s_crow[2][W];
+  __shared__ cplx<R> s_L[W][W];
+  __shared__ cplx<R> s_U[W][MAXNB];
+  __shared__ cplx<R> s_D[MAXNB][MAXNB + 1];
+
+  const int b = blockIdx.x;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  cplx<R>* Ab = A + (long)b * sA;
+  int* pv = ipiv + (long)b * n;
+  cplx<R> a[ROWS][W];
+  int parity = 0;
+
+  for (int c = k; c < k + nbe; c += W) {
+    const int w = min(W, k + nbe - c);
+#pragma unroll
+    for (int i = 0; i < ROWS; ++i) {
+      const int r = c + tid + PNT * i;
+#pragma unroll
+      for (int j = 0; j < W; ++j)
+        a[i][j] = (r < n && j < w) ? Ab[r + (long)(c + j) * lda] : mk<R>(0, 0);
+    }
+    for (int jj = 0; jj < w; ++jj) {
+      const int col = c + jj;
+      // ---- arg-max of |re|+|im| over rows >= col
+      R best = -1;
+      int bidx = 0x7fffffff;
+#pragma unroll
+      for (int i = 0; i < ROWS; ++i) {
+        const int r = c + tid + PNT * i;
+        cplx<R> v = mk<R>(0, 0);
+#pragma unroll
+        for (int j = 0; j < W; ++j) if (j == jj) v = a[i][j];
+        if (r >= col && r < n) {
+          R m = cabs1(v);
+          if (m > best) { best = m; bidx = r; }
+        }
+      }
+#pragma unroll
+      for (int off = 32; off >= 1; off >>= 1) {
+        R ob = __shfl_xor(best, off);
+        int oi = __shfl_xor(bidx, off);
+        if (ob > best || (ob == best && oi < bidx)) { best = ob; bidx = oi; }
+      }
+      if (lane == 0) { s_val[parity][wave] = best; s_idx[parity][wave] = bidx; }
+      __syncthreads();
+      best = s_val[parity][0];
+      bidx = s_idx[parity][0];
+#pragma unroll
+      for (int q = 1; q < 16; ++q) {
+        R ob = s_val[parity][q];
+        int oi = s_idx[parity][q];
+        if (ob > best || (ob == best && oi < bidx)) { best = ob; bidx = oi; }
+      }
+      const bool zero = !(best > R(0));
+      const int p = zero ? col : bidx;
+      if (tid == 0) {
+        pv[col] = p;
+        if (zero && info[b] == 0) info[b] = col + 1;
+      }
+      // ---- interchange rows col and p
+      const int tp = (p - c) % PNT, ip = (p - c) / PNT;
+      const int tc = (col - c) % PNT, ic = (col - c) / PNT;
+      if (tid == tp) {
+#pragma unroll
+        for (int i = 0; i < ROWS; ++i)
+          if (i == ip)
+#pragma unroll
+            for (int j = 0; j < W; ++j) s_prow[parity][j] = a[i][j];
+      }
+      if (tid == tc) {
+#pragma unroll
+        for (int i = 0; i < ROWS; ++i)
+          if (i == ic)
+#pragma unroll
+            for (int j = 0; j < W; ++j) s_crow[parity][j] = a[i][j];
+      }
+      __syncthreads();
+      if (p != col) {
+        if (tid == tc) {
+#pragma unroll
+          for (int i = 0; i < ROWS; ++i)
+            if (i == ic)
+#pragma unroll
+              for (int j = 0; j < W; ++j) a[i][j] = s_prow[parity][j];
+        }
+        if (tid == tp) {
+#pragma unroll
+          for (int i = 0; i < ROWS; ++i)
+            if (i == ip)
+#pragma unroll
+              for (int j = 0; j < W; ++j) a[i][j] = s_crow[parity][j];
+        }
+        // other columns of this panel (outside the micro-panel)
+        if (tid < nbe) {
+          const int cc = k + tid;
+          if (cc < c || cc >= c + w) {
+            cplx<R> x = Ab[col + (long)cc * lda];
+            cplx<R> y = Ab[p + (long)cc * lda];
+            Ab[col + (long)cc * lda] = y;
+            Ab[p + (long)cc * lda] = x;
+          }
+        }
+      }
+      // ---- scale the column and update the rest of the micro-panel
+      cplx<R> piv = mk<R>(1, 0);
+#pragma unroll
+      for (int j = 0; j < W; ++j) if (j == jj) piv = s_prow[parity][j];
+      const cplx<R> inv = zero ? mk<R>(1, 0) : crecip(piv);
+#pragma unroll
+      for (int i = 0; i < ROWS; ++i) {
+        const int r = c + tid + PNT * i;
+        if (r > col && r < n) {
+          cplx<R> l = mk<R>(0, 0);
+#pragma unroll
+          for (int j = 0; j < W; ++j) if (j == jj) { a[i][j] = a[i][j] * inv; l = a[i][j]; }
+#pragma unroll
+          for (int j = 0; j < W; ++j)
+            if (j > jj) a[i][j] = a[i][j] - l * s_prow[parity][j];
+        }
+      }
+      parity ^= 1;
+    }
+    // ---- write the micro-panel back
+#pragma unroll
+    for (int i = 0; i < ROWS; ++i) {
+      const int r = c + tid + PNT * i;
+      if (r < n)
+#pragma unroll
+        for (int j = 0; j < W; ++j)
+          if (j < w) Ab[r + (long)(c + j) * lda] = a[i][j];
+    }
+    const int rc0 = c + w, ncols = k + nbe - rc0;
+    if (ncols > 0) {
+      if (tid < w) {
+#pragma unroll
+        for (int j = 0; j < W; ++j) s_L[tid][j] = a[0][j];
+      }
+      __syncthreads();
+      // U rows of the micro-panel: unit-lower solve, one column per thread
+      if (tid < ncols) {
+        const int cc = rc0 + tid;
+        cplx<R> x[W];
+#pragma unroll
+        for (int j = 0; j < W; ++j)
+          x[j] = (j < w) ? Ab[c + j + (long)cc * lda] : mk<R>(0, 0);
+#pragma unroll
+        for (int j = 1; j < W; ++j)
+#pragma unroll
+          for (int l = 0; l < W; ++l)
+            if (l < j && j < w) x[j] = x[j] - s_L[j][l] * x[l];
+#pragma unroll
+        for (int j = 0; j < W; ++j) {
+          s_U[j][tid] = x[j];
+          if (j < w) Ab[c + j + (long)cc * lda] = x[j];
+        }
+      }
+      __syncthreads();
+      // rank-w update of the remaining panel rows
+#pragma unroll
+      for (int i = 0; i < ROWS; ++i) {
+        const int r = c + tid + PNT * i;
+        if (r >= rc0 && r < n) {
+          for (int t = 0; t < ncols; ++t) {
+            const long idx = r + (long)(rc0 + t) * lda;
+            cplx<R> acc = Ab[idx];
+#pragma unroll
+            for (int j = 0; j < W; ++j)
+              if (j < w) acc = acc - a[i][j] * s_U[j][t];
+            Ab[idx] = acc;
+          }
+        }
+      }
+    }
+    __syncthreads();
+  }
+
+  // ---- invert the unit-lower and upper diagonal blocks (kept for solves)
+  for (int e = tid; e < nbe * nbe; e += PNT) {
+    const int i = e % nbe, j = e / nbe;
+    s_D[i][j] = Ab[k + i + (long)(k + j) * lda];
+  }
+  __syncthreads();
+  if (wave == 0) {
+    // L^{-1}: row sweep; X[i][j] (j < i) overwrites L[i][j]
+    const int j = lane;
+    for (int i = 1; i < nbe; ++i) {
+      cplx<R> v = mk<R>(0, 0);
+      if (j < i) {
+        v = s_D[i][j];
+        for (int l = j + 1; l < i; ++l) v = v + s_D[i][l] * s_D[l][j];
+        v = mk<R>(-v.re, -v.im);
+      }
+      wave_sync();
+      if (j < i) s_D[i][j] = v;
+      wave_sync();
+    }
+  } else if (wave == 1) {
+    // U^{-1}: bottom-up row sweep; X[i][j] (j >= i) overwrites U[i][j]
+    const int j = lane;
+    for (int i = nbe - 1; i >= 0; --i) {
+      const cplx<R> d = crecip(s_D[i][i]);
+      cplx<R> v = mk<R>(0, 0);
+      if (j > i && j < nbe) {
+        for (int l = i + 1; l <= j; ++l) v = v + s_D[i][l] * s_D[l][j];
+        v = mk<R>(-v.re, -v.im) * d;
+      }
+      wave_sync();
+      if (j > i && j < nbe) s_D[i][j] = v;
+      if (j == i) s_D[i][i] = d;
+      wave_sync();
+    }
+  }
+  __syncthreads();
+  cplx<R>* DL = dinv + (long)b * sD;
+  cplx<R>* DU = DL + (long)nb * nb;
+  for (int e = tid; e < nb * nb; e += PNT) {
+    const int i = e % nb, j = e / nb;
+    cplx<R> l = mk<R>(0, 0), u = mk<R>(0, 0);
+    if (i < nbe && j < nbe) {
+      if (i > j) l = s_D[i][j];
+      else if (i == j) { l = mk<R>(1, 0); u = s_D[i][i]; }
+      else u = s_D[i][j];
+    }
+    DL[e] = l;
+    DU[e] = u;
+  }
+}
+
+// Applies the interchanges ipiv[k .. k+nbe) (each row i swapped with
+// ipiv[i] >= i, in order) to columns [0, ncols) of X as one gather: every
+// touched row gets its final source row.
+template <typename R> struct SwCols { static constexpr int v = 8 * 16 / (int)sizeof(cplx<R>) * 2; };  // 32 (fp32) / 16 (fp64) columns per workgroup
+template <typename R>
+__global__ __launch_bounds__(256) void lu_permute_kernel(cplx<R>* X, long ldx, long sX, int ncols,
+                                                         const int* ipiv, int ipiv_stride, int k,
+                                                         int nbe) {
+  __shared__ int t_row[2 * MAXNB], t_src[2 * MAXNB];
+  __shared__ int s_cnt;
+  constexpr int SWC = SwCols<R>::v;
+  __shared__ cplx<R> vals[2 * MAXNB][SWC];
+  const int b = blockIdx.y;
+  const int tid = threadIdx.x;
+  const int* pv = ipiv + (long)b * ipiv_stride;
+  cplx<R>* Xb = X + (long)b * sX;
+  if (tid < 64) {
+    const int lane = tid;
+    for (int e = lane; e < nbe; e += 64) { t_row[e] = k + e; t_src[e] = k + e; }
+    int cnt = nbe;
+    wave_sync();
+    for (int i = 0; i < nbe; ++i) {
+      const int p = pv[k + i];
+      if (p == k + i) continue;
+      // locate p among the touched rows (rows k..k+nbe-1 sit at index row-k)
+      int pos = -1;
+      if (p < k + nbe) pos = p - k;
+      else {
+        for (int base = nbe; base < cnt; base += 64) {
+          const int e = base + lane;
+          const bool hit = (e < cnt) && (t_row[e] == p);
+          const unsigned long long m = __ballot(hit);
+          if (m) { pos = base + __ffsll((long long)m) - 1; break; }
+        }
+        if (pos < 0) {
+          pos = cnt;
+          if (lane == 0) { t_row[cnt] = p; t_src[cnt] = p; }
+          cnt += 1;
+          wave_sync();
+        }
+      }
+      if (lane == 0) {
+        const int s = t_src[i];
+        t_src[i] = t_src[pos];
+        t_src[pos] = s;
+      }
+      wave_sync();
+    }
+    if (lane == 0) s_cnt = cnt;
+  }
+  __syncthreads();
+  const int cnt = s_cnt;
+  const int c0 = blockIdx.x * SWC;
+  const int jc = tid % SWC;
+  const int col = c0 + jc;
+  for (int e = tid / SWC; e < cnt; e += 256 / SWC)
+    if (col < ncols) vals[e][jc] = Xb[t_src[e] + (long)col * ldx];
+  __syncthreads();
+  for (int e = tid / SWC; e < cnt; e += 256 / SWC)
+    if (col < ncols) Xb[t_row[e] + (long)col * ldx] = vals[e][jc];
+}
+
+template <typename R>
+static int launch_permute(cplx<R>* X, long ldx, long sX, int ncols, const int* ipiv,
+                          int ipiv_stride, int k, int nbe, int batch, hipStream_t s) {
+  if (ncols <= 0) return ST_OK;
+  dim3 grid((unsigned)cdivl(ncols, SwCols<R>::v), (unsigned)batch);
+  KernelTimer kt("lu_permute", s, 0.0, 4.0 * sizeof(cplx<R>) * nbe * (double)ncols * batch);
+  hipLaunchKernelGGL((lu_permute_kernel<R>), grid, dim3(256), 0, s, X, ldx, sX, ncols, ipiv,
+                     ipiv_stride, k, nbe);
+  RSRR_LAUNCH_CHECK();
+  return ST_OK;
+}
+
+__global__ void zero_int_kernel(int* p, int count) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < count) p[i] = 0;
+}
+
+template <typename R, int ROWS>
+static int launch_panel_rows(const LUWork<R>& w, int k, int nbe, hipStream_t s) {
+  constexpr int W = (sizeof(R) == 8) ? (ROWS == 1 ? 8 : 16 / ROWS)
+                                     : (ROWS <= 2 ? 16 : 32 / ROWS);
+  const long sD = (long)w.npanel() * 2 * w.nb * w.nb;
+  cplx<R>* dslot = w.dinv + (long)(k / w.nb) * 2 * w.nb * w.nb;
+  const std::string tn = std::string(w.tag) + "_panel";
+  KernelTimer kt(tn.c_str(), s, 8.0 * nbe * nbe * (w.n - k) * w.batch / 2.0,
+                 2.0 * sizeof(cplx<R>) * (double)(w.n - k) * nbe * w.batch);
+  hipLaunchKernelGGL((lu_panel_kernel<R, ROWS, W>), dim3(w.batch), dim3(PNT), 0, s, w.A, w.lda,
+                     w.sA, w.n, k, nbe, w.nb, w.ipiv, dslot, sD, w.info);
+  RSRR_LAUNCH_CHECK();
+  return ST_OK;
+}
+
+template <typename R>
+static int launch_panel(const LUWork<R>& w, int k, int nbe, hipStream_t s) {
+  const int m = w.n - k;
+  if (m <= PNT) return launch_panel_rows<R, 1>(w, k, nbe, s);
+  if (m <= 2 * PNT) return launch_panel_rows<R, 2>(w, k, nbe, s);
+  if (m <= 4 * PNT) return launch_panel_rows<R, 4>(w, k, nbe, s);
+  return launch_panel_rows<R, 8>(w, k, nbe, s);
+}
+
+template <typename R>
+int lu_factor(const LUWork<R>& w, hipStream_t s) {
+  if (w.n <= 0 || w.batch <= 0) return ST_OK;
+  if (w.n > 8 * PNT) return set_error(ST_EINVAL, "lu_factor: n=%d exceeds 8192", w.n);
+  if (w.nb < 1 || w.nb > MAXNB) return set_error(ST_EINVAL, "lu_factor: nb=%d", w.nb);
+  hipLaunchKernelGGL(zero_int_kernel, dim3((unsigned)cdivl(w.batch, 256)), dim3(256), 0, s,
+                     w.info, w.batch);
+  RSRR_LAUNCH_CHECK();
+  const int n = w.n, nb = w.nb;
+  const long sD = (long)w.npanel() * 2 * nb * nb;
+  const std::string t_trsm = std::string(w.tag) + "_trsm", t_upd = std::string(w.tag) + "_update";
+  for (int k = 0; k < n; k += nb) {
+    const int nbe = min(nb, n - k);
+    RSRR_TRY(launch_panel<R>(w, k, nbe, s));
+    const int rest = n - k - nbe;
+    if (rest <= 0) continue;
+    RSRR_TRY(launch_permute<R>(w.A + (long)(k + nbe) * w.lda, w.lda, w.sA, rest, w.ipiv, n, k,
+                               nbe, w.batch, s));
+    GemmBatch<R> g;                       // U12 = inv(L11) A12 (in place)
+    g.M = nbe; g.N = rest; g.K = nbe;
+    g.A = w.dinv + (long)(k / nb) * 2 * nb * nb; g.lda = nb; g.sA = sD;
+    g.B = w.A + k + (long)(k + nbe) * w.lda; g.ldb = w.lda; g.sB = w.sA;
+    g.C = w.A + k + (long)(k + nbe) * w.lda; g.ldc = w.lda; g.sC = w.sA;
+    g.batch = w.batch;
+    g.tag = t_trsm.c_str();
+    RSRR_TRY(gemm_batched<R>(g, s));
+    GemmBatch<R> u;                       // A22 -= L21 U12
+    u.M = rest; u.N = rest; u.K = nbe;
+    u.alpha = mk<R>(-1, 0); u.beta = mk<R>(1, 0);
+    u.A = w.A + (k + nbe) + (long)k * w.lda; u.lda = w.lda; u.sA = w.sA;
+    u.B = w.A + k + (long)(k + nbe) * w.lda; u.ldb = w.lda; u.sB = w.sA;
+    u.C = w.A + (k + nbe) + (long)(k + nbe) * w.lda; u.ldc = w.lda; u.sC = w.sA;
+    u.batch = w.batch;
+    u.tag = t_upd.c_str();
+    RSRR_TRY(gemm_batched<R>(u, s));
+  }
+  return ST_OK;
+}
+
+template <typename R>
+int lu_solve(const LUWork<R>& w, cplx<R>* B, long ldb, long sB, int nrhs, hipStream_t s) {
+  if (w.n <= 0 || w.batch <= 0 || nrhs <= 0) return ST_OK;
+  const int n = w.n, nb = w.nb;
+  const std::string t_solve = std::string(w.tag) + "_solve";
+  const long sD = (long)w.npanel() * 2 * nb * nb;
+  for (int k = 0; k < n; k += nb) {                      // forward: L
+    const int nbe = min(nb, n - k);
+    RSRR_TRY(launch_permute<R>(B, ldb, sB, nrhs, w.ipiv, n, k, nbe, w.batch, s));
+    GemmBatch<R> g;
+    g.M = nbe; g.N = nrhs; g.K = nbe;
+    g.A = w.dinv + (long)(k / nb) * 2 * nb * nb; g.lda = nb; g.sA = sD;
+    g.B = B + k; g.ldb = ldb; g.sB = sB;
+    g.C = B + k; g.ldc = ldb; g.sC = sB;
+    g.batch = w.batch;
+    g.tag = t_solve.c_str();
+    RSRR_TRY(gemm_batched<R>(g, s));
+    const int rest = n - k - nbe;
+    if (rest > 0) {
+      GemmBatch<R> u;
+      u.M = rest; u.N = nrhs; u.K = nbe;
+      u.alpha = mk<R>(-1, 0); u.beta = mk<R>(1, 0);
+      u.A = w.A + (k + nbe) + (long)k * w.lda; u.lda = w.lda; u.sA = w.sA;
+      u.B = B + k; u.ldb = ldb; u.sB = sB;
+      u.C = B + k + nbe; u.ldc = ldb; u.sC = sB;
+      u.batch = w.batch;
+      u.tag = t_solve.c_str();
+      RSRR_TRY(gemm_batched<R>(u, s));
+    }
+  }
+  for (int p = w.npanel() - 1; p >= 0; --p) {          // backward: U
+    const int k = p * nb, nbe = min(nb, n - k);
+    GemmBatch<R> g;
+    g.M = nbe; g.N = nrhs; g.K = nbe;
+    g.A = w.dinv + (long)p * 2 * nb * nb + (long)nb * nb; g.lda = nb; g.sA = sD;
+    g.B = B + k; g.ldb = ldb; g.sB = sB;
+    g.C = B + k; g.ldc = ldb; g.sC = sB;
+    g.batch = w.batch;
+    g.tag = t_solve.c_str();
+    RSRR_TRY(gemm_batched<R>(g, s));
+    if (k > 0) {
+      GemmBatch<R> u;
+      u.M = k; u.N = nrhs; u.K = nbe;
+      u.alpha = mk<R>(-1, 0); u.beta = mk<R>(1, 0);
+      u.A = w.A + (long)k * w.lda; u.lda = w.lda; u.sA = w.sA;
+      u.B = B + k; u.ldb = ldb; u.sB = sB;
+      u.C = B; u.ldc = ldb; u.sC = sB;
+      u.batch = w.batch;
+      u.tag = t_solve.c_str();
+      RSRR_TRY(gemm_batched<R>(u, s));
+    }
+  }
+  return ST_OK;
+}
+
+template int lu_factor<double>(const LUWork<double>&, hipStream_t);
+template int lu_factor<float>(const LUWork<float>&, hipStream_t);
+template int lu_solve<double>(const LUWork<double>&, c128*, long, long, int, hipStream_t);
+template int lu_solve<float>(const LUWork<float>&, c64*, long, long, int, hipStream_t);
+
+}  // namespace rsrr

@@ -1,0 +1,356 @@
+// Alg. 2, Step 3: an orthonormal basis of the sampling matrix S_hat keeping its
+// singular directions above delta * sigma_1.
+//
+// A Gram matrix squares singular values, so a single Gram pass resolves only
+// sigma_i / sigma_1 down to about sqrt(u) ~ 1e-8.  Two levels are used:
+//   level 1: G = S^H S, pivoted (rank-revealing) Cholesky G = P L L^H P^T
+//            stopped when the largest remaining pivot drops below tau1*sigma_1^2,
+//            S1 = S P(:, 1:k1) L11^{-H}, then one more Cholesky-QR pass
+//            (CholeskyQR2).
+//   level 2: R = (I - S1 S1^H)^2 S, the same on R^H R with the absolute stop
+//            (delta sigma_1)^2, orthogonalised against S1 and CholeskyQR2'd.
+// sigma_1^2 is the largest eigenvalue of G (power iteration).
+#include <algorithm>
+#include <cmath>
+
+#include "driver.h"
+#include "timers.h"
+
+namespace rsrr {
+
+constexpr int PCT = 1024;     // threads of the pivoted-Cholesky panel kernel
+constexpr int PBS = 64;       // block size
+
+// One block of the right-looking pivoted Cholesky, in place on G (m x m, both
+// triangles stored).  Columns j0 .. j0+jb-1 of L are written to the lower part
+// of G.  d holds the diagonal of the current Schur complement, perm the
+// symmetric permutation.  Stops at the first pivot <= tol (rank -> *rank).
+__global__ __launch_bounds__(PCT) void pchol_panel_kernel(c128* G, long ldg, int m, int j0, int jb,
+                                                          int* perm, double* d, double tol,
+                                                          int pivot, int* rank) {
+  __shared__ double s_v[16];
+  __shared__ int s_i[16];
+  __shared__ c128 s_lj[PBS];
+  __shared__ int s_stop;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  if (j0 == 0) {
+    for (int i = tid; i < m; i += PCT) {
+      d[i] = G[i + (long)i * ldg].re;
+      perm[i] = i;
+    }
+    __syncthreads();
+  }
+  if (tid == 0) s_stop = 0;
+  for (int jj = 0; jj < jb; ++jj) {
+    const int j = j0 + jj;
+    int p = j;
+    double best = d[j];
+    if (pivot) {
+      best = -1.0;
+      int bi = 0x7fffffff;
+      for (int i = j + tid; i < m; i += PCT) {
+        const double v = d[i];
+        if (v > best) { best = v; bi = i; }
+      }
+      for (int off = 32; off >= 1; off >>= 1) {
+        const double ob = __shfl_xor(best, off);
+        const int oi = __shfl_xor(bi, off);
+        if (ob > best || (ob == best && oi < bi)) { best = ob; bi = oi; }
+      }
+      if (lane == 0) { s_v[wave] = best; s_i[wave] = bi; }
+      __syncthreads();
+      best = s_v[0];
+      bi = s_i[0];
+      for (int q = 1; q < 16; ++q)
+        if (s_v[q] > best || (s_v[q] == best && s_i[q] < bi)) { best = s_v[q]; bi = s_i[q]; }
+      p = bi;
+    }
+    if (!(best > tol)) {                       // rank found
+      if (tid == 0) { *rank = j; s_stop = 1; }
+      __syncthreads();
+      break;
+    }
+    if (p != j) {
+      for (int c = tid; c < m; c += PCT) {     // rows
+        const c128 a = G[j + (long)c * ldg];
+        G[j + (long)c * ldg] = G[p + (long)c * ldg];
+        G[p + (long)c * ldg] = a;
+      }
+      __syncthreads();
+      for (int r = tid; r < m; r += PCT) {     // columns
+        const c128 a = G[r + (long)j * ldg];
+        G[r + (long)j * ldg] = G[r + (long)p * ldg];
+        G[r + (long)p * ldg] = a;
+      }
+      if (tid == 0) {
+        const double t = d[j]; d[j] = d[p]; d[p] = t;
+        const int q = perm[j]; perm[j] = perm[p]; perm[p] = q;
+      }
+      __syncthreads();
+    }
+    const double ljj = sqrt(d[j]);
+    for (int l = tid; l < jj; l += PCT) s_lj[l] = G[j + (long)(j0 + l) * ldg];
+    __syncthreads();
+    for (int i = j + 1 + tid; i < m; i += PCT) {
+      c128 v = G[i + (long)j * ldg];
+      for (int l = 0; l < jj; ++l) v = v - mulc(G[i + (long)(j0 + l) * ldg], s_lj[l]);
+      v = (1.0 / ljj) * v;
+      G[i + (long)j * ldg] = v;
+      d[i] -= abs2(v);
+    }
+    if (tid == 0) {
+      G[j + (long)j * ldg] = mk<double>(ljj, 0);
+      d[j] = 0.0;
+    }
+    __syncthreads();
+  }
+  if (tid == 0 && !s_stop) *rank = j0 + jb;
+}
+
+// Inverts the diagonal blocks (bs x bs, lower triangular, non-unit) of L, one
+// wave per block, in place in LDS by a row sweep:
+//   X[i][i] = 1/L[i][i],  X[i][j] = -(sum_{l=j}^{i-1} L[i][l] X[l][j]) / L[i][i].
+__global__ __launch_bounds__(64) void tri_inv_lower_blocks(const c128* L, long ldl, int k, int bs,
+                                                           c128* out) {
+  __shared__ c128 s[PBS][PBS + 1];
+  const int blk = blockIdx.x;
+  const int b0 = blk * bs, be = min(bs, k - b0);
+  const int j = threadIdx.x;
+  for (int e = j; e < be * be; e += 64) {
+    const int r = e % be, c = e / be;
+    s[r][c] = (r >= c) ? L[b0 + r + (long)(b0 + c) * ldl] : mk<double>(0, 0);
+  }
+  __syncthreads();
+  for (int i = 0; i < be; ++i) {
+    const c128 dii = s[i][i];
+    c128 v = mk<double>(0, 0);
+    if (j < i) {
+      for (int l = j; l < i; ++l) v = v + s[i][l] * s[l][j];
+      v = cdiv(mk<double>(-v.re, -v.im), dii);
+    }
+    wave_sync();
+    if (j < i) s[i][j] = v;
+    if (j == i) s[i][i] = crecip(dii);
+    wave_sync();
+  }
+  __syncthreads();
+  c128* o = out + (long)blk * bs * bs;
+  for (int e = j; e < bs * bs; e += 64) {
+    const int r = e % bs, c = e / bs;
+    o[e] = (r < be && c < be && r >= c) ? s[r][c] : mk<double>(0, 0);
+  }
+}
+
+__global__ __launch_bounds__(256) void gather_cols_kernel(const c128* S, long lds, const int* perm,
+                                                          int rows, int k, c128* out, long ldo) {
+  const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= (long)rows * k) return;
+  const int i = (int)(e % rows), c = (int)(e / rows);
+  out[i + (long)c * ldo] = S[i + (long)perm[c] * lds];
+}
+
+// x <- y / ||y|| (one workgroup), lam[0] <- ||y||
+__global__ __launch_bounds__(1024) void normalize_kernel(const c128* y, c128* x, int m, double* lam) {
+  __shared__ double red[1024];
+  double acc = 0;
+  for (int i = threadIdx.x; i < m; i += 1024) acc += abs2(y[i]);
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int o = 512; o > 0; o >>= 1) {
+    if (threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+    __syncthreads();
+  }
+  const double nrm = sqrt(red[0]);
+  const double inv = nrm > 0 ? 1.0 / nrm : 0.0;
+  for (int i = threadIdx.x; i < m; i += 1024) x[i] = inv * y[i];
+  if (threadIdx.x == 0) *lam = nrm;
+}
+
+__global__ void fill_kernel(c128* x, int m, c128 v) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < m) x[i] = v;
+}
+
+static int gemm_z(int opA, int opB, int M, int N, int K, c128 alpha, const c128* A, long lda,
+                  const c128* B, long ldb, c128 beta, c128* C, long ldc, hipStream_t s) {
+  GemmBatch<double> g;
+  g.opA = opA; g.opB = opB; g.M = M; g.N = N; g.K = K;
+  g.alpha = alpha; g.beta = beta;
+  g.A = A; g.lda = lda; g.B = B; g.ldb = ldb; g.C = C; g.ldc = ldc;
+  g.tag = "ortho_gemm";
+  return gemm_batched<double>(g, s);
+}
+
+static const c128 ONE = {1, 0}, ZERO = {0, 0}, MONE = {-1, 0};
+
+// Largest eigenvalue of the Hermitian PSD m x m matrix G (power iteration).
+static int power_lambda(const c128* G, long ldg, int m, Arena& ws, hipStream_t s, double* lam) {
+  c128 *x = nullptr, *y = nullptr;
+  double* l = nullptr;
+  RSRR_TRY(ws.get<c128>("pw_x", m, &x));
+  RSRR_TRY(ws.get<c128>("pw_y", m, &y));
+  RSRR_TRY(ws.get<double>("pw_l", 1, &l));
+  hipLaunchKernelGGL(fill_kernel, dim3((unsigned)cdivl(m, 256)), dim3(256), 0, s, x, m,
+                     mk<double>(1.0 / sqrt((double)m), 0));
+  RSRR_LAUNCH_CHECK();
+  for (int it = 0; it < 12; ++it) {
+    RSRR_TRY(gemm_z(OP_N, OP_N, m, 1, m, ONE, G, ldg, x, m, ZERO, y, m, s));
+    hipLaunchKernelGGL(normalize_kernel, dim3(1), dim3(1024), 0, s, y, x, m, l);
+    RSRR_LAUNCH_CHECK();
+  }
+  RSRR_HIP(hipMemcpyAsync(lam, l, sizeof(double), hipMemcpyDeviceToHost, s));
+  RSRR_HIP(hipStreamSynchronize(s));
+  return ST_OK;
+}
+
+__global__ __launch_bounds__(1024) void max_diag_kernel(const c128* G, long ldg, int m, double* out) {
+  __shared__ double red[1024];
+  double b = 0;
+  for (int i = threadIdx.x; i < m; i += 1024) b = fmax(b, G[i + (long)i * ldg].re);
+  red[threadIdx.x] = b;
+  __syncthreads();
+  for (int o = 512; o > 0; o >>= 1) {
+    if (threadIdx.x < o) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + o]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *out = red[0];
+}
+
+static int max_real_diag(const c128* G, long ldg, int m, Arena& ws, hipStream_t s, double* out) {
+  double* d = nullptr;
+  RSRR_TRY(ws.get<double>("md_out", 1, &d));
+  hipLaunchKernelGGL(max_diag_kernel, dim3(1), dim3(1024), 0, s, G, ldg, m, d);
+  RSRR_LAUNCH_CHECK();
+  RSRR_HIP(hipMemcpyAsync(out, d, sizeof(double), hipMemcpyDeviceToHost, s));
+  RSRR_HIP(hipStreamSynchronize(s));
+  return ST_OK;
+}
+
+// Blocked pivoted Cholesky of G (m x m, overwritten; L in the lower part).
+static int pchol(c128* G, long ldg, int m, int maxrank, double tol, bool pivot, int* perm,
+                 Arena& ws, hipStream_t s, int* rank_out) {
+  double* d = nullptr;
+  int* rk = nullptr;
+  RSRR_TRY(ws.get<double>("pc_d", m, &d));
+  RSRR_TRY(ws.get<int>("pc_rank", 1, &rk));
+  int rank = 0;
+  for (int j0 = 0; j0 < maxrank; j0 += PBS) {
+    const int jb = std::min(PBS, maxrank - j0);
+    KernelTimer kt("pchol_panel", s, 8.0 * (double)m * jb * jb / 2, 16.0 * 4 * (double)m * jb);
+    hipLaunchKernelGGL(pchol_panel_kernel, dim3(1), dim3(PCT), 0, s, G, ldg, m, j0, jb, perm, d,
+                       tol, pivot ? 1 : 0, rk);
+    RSRR_LAUNCH_CHECK();
+    RSRR_HIP(hipMemcpyAsync(&rank, rk, sizeof(int), hipMemcpyDeviceToHost, s));
+    RSRR_HIP(hipStreamSynchronize(s));
+    if (rank < j0 + jb) break;
+    const int t = j0 + jb, rest = m - t;
+    if (rest > 0 && t < maxrank)
+      RSRR_TRY(gemm_z(OP_N, OP_C, rest, rest, jb, MONE, G + t + (long)j0 * ldg, ldg,
+                      G + t + (long)j0 * ldg, ldg, ONE, G + t + (long)t * ldg, ldg, s));
+  }
+  *rank_out = rank;
+  return ST_OK;
+}
+
+// X (rows x k) <- X L^{-H} with L (k x k) lower triangular (the Cholesky factor).
+static int trsm_right_lh(const c128* L, long ldl, int k, c128* X, long ldx, int rows, Arena& ws,
+                         hipStream_t s) {
+  const int nblk = (k + PBS - 1) / PBS;
+  c128* inv = nullptr;
+  c128* tmp = nullptr;
+  RSRR_TRY(ws.get<c128>("tr_inv", (size_t)nblk * PBS * PBS, &inv));
+  RSRR_TRY(ws.get<c128>("tr_tmp", (size_t)rows * PBS, &tmp));
+  hipLaunchKernelGGL(tri_inv_lower_blocks, dim3(nblk), dim3(64), 0, s, L, ldl, k, PBS, inv);
+  RSRR_LAUNCH_CHECK();
+  for (int b = 0; b < nblk; ++b) {
+    const int j = b * PBS, be = std::min(PBS, k - j);
+    if (j > 0)   // X_b -= X[:, :j] (L[b, :j])^H
+      RSRR_TRY(gemm_z(OP_N, OP_C, rows, be, j, MONE, X, ldx, L + j, ldl, ONE, X + (long)j * ldx,
+                      ldx, s));
+    // X_b <- X_b inv(L_bb)^H
+    RSRR_TRY(gemm_z(OP_N, OP_C, rows, be, be, ONE, X + (long)j * ldx, ldx, inv + (long)b * PBS * PBS,
+                    PBS, ZERO, tmp, rows, s));
+    RSRR_TRY((convert<double, double>(tmp, rows, 0, X + (long)j * ldx, ldx, 0, rows, be, 1, s)));
+  }
+  return ST_OK;
+}
+
+// One Cholesky-QR pass on X (rows x k, in place): X <- X chol(X^H X)^{-H}.
+static int cholqr_pass(c128* X, long ldx, int rows, int k, Arena& ws, hipStream_t s, bool* ok) {
+  c128* G = nullptr;
+  int* perm = nullptr;
+  RSRR_TRY(ws.get<c128>("cq_G", (size_t)k * k, &G));
+  RSRR_TRY(ws.get<int>("cq_perm", k, &perm));
+  RSRR_TRY(gemm_z(OP_C, OP_N, k, k, rows, ONE, X, ldx, X, ldx, ZERO, G, k, s));
+  int r = 0;
+  RSRR_TRY(pchol(G, k, k, k, 0.0, false, perm, ws, s, &r));
+  *ok = (r == k);
+  if (!*ok) return ST_OK;
+  return trsm_right_lh(G, k, k, X, ldx, rows, ws, s);
+}
+
+int ortho_impl(int rows, int cols, const c128* S, long lds, double delta, c128* Q, long ldq,
+               int* k_S, Arena& ws, hipStream_t s) {
+  const int m = cols, kmax = std::min(rows, cols);
+  c128* G = nullptr;
+  int* perm = nullptr;
+  RSRR_TRY(ws.get<c128>("or_G", (size_t)m * m, &G));
+  RSRR_TRY(ws.get<int>("or_perm", m, &perm));
+  // ---- level 1
+  RSRR_TRY(gemm_z(OP_C, OP_N, m, m, rows, ONE, S, lds, S, lds, ZERO, G, m, s));
+  double lam1 = 0;
+  RSRR_TRY(power_lambda(G, m, m, ws, s, &lam1));
+  if (!(lam1 > 0)) { *k_S = 0; return ST_OK; }
+  const double tau1 = 1e-14;           // level-1 pivots: sigma ratio >= ~1e-7
+  int k1 = 0;
+  RSRR_TRY(pchol(G, m, m, kmax, tau1 * lam1, true, perm, ws, s, &k1));
+  if (k1 == 0) { *k_S = 0; return ST_OK; }
+  hipLaunchKernelGGL(gather_cols_kernel, dim3((unsigned)cdivl((long)rows * k1, 256)), dim3(256), 0,
+                     s, S, lds, perm, rows, k1, Q, ldq);
+  RSRR_LAUNCH_CHECK();
+  RSRR_TRY(trsm_right_lh(G, m, k1, Q, ldq, rows, ws, s));
+  bool ok = true;
+  RSRR_TRY(cholqr_pass(Q, ldq, rows, k1, ws, s, &ok));
+  if (!ok) return set_error(ST_ENOTCONV, "orthonormalize: second Cholesky-QR pass broke down");
+  int kS = k1;
+  // ---- level 2: directions of S outside span(S1) above delta * sigma_1
+  if (k1 < kmax) {
+    c128 *Rm = nullptr, *Cc = nullptr;
+    RSRR_TRY(ws.get<c128>("or_R", (size_t)rows * m, &Rm));
+    RSRR_TRY(ws.get<c128>("or_C", (size_t)k1 * m, &Cc));
+    RSRR_TRY((convert<double, double>(S, lds, 0, Rm, rows, 0, rows, m, 1, s)));
+    for (int pass = 0; pass < 2; ++pass) {
+      RSRR_TRY(gemm_z(OP_C, OP_N, k1, m, rows, ONE, Q, ldq, Rm, rows, ZERO, Cc, k1, s));
+      RSRR_TRY(gemm_z(OP_N, OP_N, rows, m, k1, MONE, Q, ldq, Cc, k1, ONE, Rm, rows, s));
+    }
+    RSRR_TRY(gemm_z(OP_C, OP_N, m, m, rows, ONE, Rm, rows, Rm, rows, ZERO, G, m, s));
+    // stop at (delta sigma_1)^2, but not below the rounding floor of the Gram
+    // matrix of R: pivots under rows * u * max_i ||R_i||^2 are noise
+    double dmax = 0;
+    RSRR_TRY(max_real_diag(G, m, m, ws, s, &dmax));
+    const double tau2 = std::max(delta * delta * lam1, rows * 1.1102230246251565e-16 * dmax);
+    int k2 = 0;
+    RSRR_TRY(pchol(G, m, m, kmax - k1, tau2, true, perm, ws, s, &k2));
+    if (k2 > 0) {
+      c128* Q2 = Q + (long)k1 * ldq;
+      hipLaunchKernelGGL(gather_cols_kernel, dim3((unsigned)cdivl((long)rows * k2, 256)), dim3(256),
+                         0, s, Rm, rows, perm, rows, k2, Q2, ldq);
+      RSRR_LAUNCH_CHECK();
+      RSRR_TRY(trsm_right_lh(G, m, k2, Q2, ldq, rows, ws, s));
+      for (int pass = 0; pass < 2; ++pass) {
+        c128* C2 = Cc;
+        RSRR_TRY(gemm_z(OP_C, OP_N, k1, k2, rows, ONE, Q, ldq, Q2, ldq, ZERO, C2, k1, s));
+        RSRR_TRY(gemm_z(OP_N, OP_N, rows, k2, k1, MONE, Q, ldq, C2, k1, ONE, Q2, ldq, s));
+        bool ok2 = true;
+        RSRR_TRY(cholqr_pass(Q2, ldq, rows, k2, ws, s, &ok2));
+        if (!ok2) { k2 = 0; break; }
+      }
+      kS += k2;
+    }
+  }
+  RSRR_HIP(hipStreamSynchronize(s));
+  *k_S = kS;
+  return ST_OK;
+}
+
+}  // namespace rsrr

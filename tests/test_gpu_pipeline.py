@@ -1,0 +1,182 @@
+"""GPU parity of the basis (Alg. 2 Step 3), the projection (Step 4) and the
+whole solve (Alg. 1 + Alg. 2) against the CPU oracle on the same seeded inputs."""
+import numpy as np
+import pytest
+import scipy.special as sps
+
+import nep_inputs as ni
+from oracle import rsrr_ref as R
+from tests._util import match_sets
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def P():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a ROCm device"
+    import paper_1510_07522_amd as P
+    P.load()
+    return P
+
+
+# ----------------------------------------------------------- basis (a5)
+@pytest.mark.parametrize("rows,cols,r", [(60, 40, 23), (300, 200, 130), (150, 400, 150)])
+def test_orthonormalize_known_rank(P, rows, cols, r):
+    rng = np.random.default_rng(rows + cols)
+    Q1, _ = np.linalg.qr(rng.standard_normal((rows, r)) + 1j * rng.standard_normal((rows, r)))
+    Q2, _ = np.linalg.qr(rng.standard_normal((cols, r)) + 1j * rng.standard_normal((cols, r)))
+    s = np.logspace(0, -12, r)
+    S = (Q1 * s) @ Q2.conj().T
+    _, _, k_ref = R.truncated_basis(S, 1e-14)
+    Qg, k = P.orthonormalize(P.to_device(S), rows, cols, 1e-14)
+    Qh = P.from_device(Qg)
+    print("k_S gpu", k, "oracle", k_ref)
+    assert abs(k - k_ref) <= 2
+    assert np.linalg.norm(Qh.conj().T @ Qh - np.eye(k)) <= 1e-13 * np.sqrt(k)
+    assert np.linalg.norm(S - Qh @ (Qh.conj().T @ S)) <= 1e-13 * np.linalg.norm(S)
+
+
+def test_orthonormalize_c0_samples(P):
+    p, c, N, L, U = ni.config_c0()
+    _, z, _ = R.contour_nodes(c, N)
+    S = R.sample_resolvent(p, z, U)
+    Qg, k = P.orthonormalize(P.to_device(S), p.n, N * L, 1e-14)
+    Qh = P.from_device(Qg)
+    assert k == p.n
+    assert np.linalg.norm(Qh.conj().T @ Qh - np.eye(k)) <= 1e-13 * np.sqrt(k)
+
+
+# ------------------------------------------------------ projection (a6)
+def test_project_coefficients_match_oracle(P):
+    p, c, N, L, U = ni.config_small_qep(n=150, seed=3)
+    rng = np.random.default_rng(1)
+    Q, _ = np.linalg.qr(rng.standard_normal((150, 70)) + 1j * rng.standard_normal((150, 70)))
+    h = P.Problem(p)
+    try:
+        B, J = h.project(P.contour(c.center, c.a, c.b), P.default_params(N=N, L=L), P.to_device(Q), 70)
+    finally:
+        h.close()
+    Bh = P.from_device(B)                     # (J*k) x k column-major blocks
+    ref = R.project_coefficients(p, Q)
+    assert J == 3
+    for k in range(J):
+        blk = Bh.T.reshape(J, 70, 70)[k].T
+        assert np.linalg.norm(blk - ref[k]) <= 1e-13 * max(1.0, np.linalg.norm(ref[k]))
+
+
+def test_project_delay_real_coefficients(P):
+    p = ni.delay_dense(200, seed=4)
+    rng = np.random.default_rng(2)
+    Q, _ = np.linalg.qr(rng.standard_normal((200, 64)) + 1j * rng.standard_normal((200, 64)))
+    h = P.Problem(p)
+    try:
+        B, J = h.project(P.contour(0, 1, 1), P.default_params(N=8, L=8), P.to_device(Q), 64)
+    finally:
+        h.close()
+    Bh = P.from_device(B).T.reshape(J, 64, 64)
+    ref = R.project_coefficients(p, Q)
+    for k in range(J):
+        assert np.linalg.norm(Bh[k].T - ref[k]) <= 1e-13 * max(1.0, np.linalg.norm(ref[k]))
+
+
+def test_project_bem_chebyshev_matches_oracle(P):
+    p = ni.bem_sphere(200)
+    c = ni.Contour(3.0, 1.5, 0.3)
+    rng = np.random.default_rng(3)
+    Q, _ = np.linalg.qr(rng.standard_normal((200, 30)) + 1j * rng.standard_normal((200, 30)))
+    d = 12
+    h = P.Problem(p)
+    try:
+        B, J = h.project(P.contour(c.center, c.a, c.b), P.default_params(N=8, L=8, cheb_degree=d),
+                         P.to_device(Q), 30)
+    finally:
+        h.close()
+    assert J == d + 1
+    Bh = P.from_device(B).T.reshape(J, 30, 30)
+    ref = R.chebyshev_projection(p, Q, 3.0, 1.5, d)
+    for j in range(J):
+        assert np.linalg.norm(Bh[j].T - ref[j]) <= 1e-12 * max(1.0, np.linalg.norm(ref[0]))
+
+
+# ----------------------------------------------------- full solve (a1-a8)
+def gpu_solve(P, prob, c, N, L, U, prec, **kw):
+    h = P.Problem(prob)
+    try:
+        prm = P.default_params(N=N, L=L, precision=prec, **kw)
+        return h.solve(P.contour(c.center, c.a, c.b), prm, P.to_device(U))
+    finally:
+        h.close()
+
+
+@pytest.mark.parametrize("prec,tol", [("c128", 1e-10), ("c64_ir", 1e-9)])
+def test_solve_c0_matches_oracle(P, prec, tol):
+    p, c, N, L, U = ni.config_c0()
+    ref = R.rsrr(p, c, N, L, U)
+    out = gpu_solve(P, p, c, N, L, U, prec)
+    info = out["info"]
+    print(prec, "n_eig", info["n_eig"], "ref", len(ref["lam"]), "kS", info["k_S"], "m", info["m"],
+          "wind", info["wind_re"], "gap", info["n_gap"], "times", info["t_sample"], info["t_basis"],
+          info["t_project"], info["t_reduced"], info["t_residual"])
+    assert info["n_eig"] == len(ref["lam"])
+    assert info["n_wind"] == ref["n_wind"]
+    scale = max(np.max(np.abs(ref["lam"])), 2.0)
+    assert match_sets(out["lam"], ref["lam"]) <= tol * scale
+    assert np.all(out["res"] <= 1e-10)
+    # eigenvectors: unit norm, largest entry real positive, residual recomputed here
+    V = out["V"]
+    assert np.allclose(np.linalg.norm(V, axis=0), 1.0, atol=1e-12)
+    for i, lam in enumerate(out["lam"][:10]):
+        T = R.T_matrix(p, lam)
+        r = np.linalg.norm(T @ V[:, i]) / np.linalg.norm(T)
+        assert r <= 1e-10
+
+
+def test_solve_diagonal_qep_closed_form(P):
+    rng = np.random.default_rng(31)
+    n = 40
+    m, cc, k = np.ones(n), rng.uniform(0.0, 0.4, n), rng.uniform(1, 30, n)
+    d = np.sqrt(cc.astype(complex) ** 2 - 4 * m * k)
+    lam_all = np.concatenate([(-cc + d) / 2, (-cc - d) / 2])
+    c = ni.Contour(3j, 1.2, 1.2)
+    p = ni.qep_diag(m, cc, k)
+    U = ni.probing_matrix(n, 4, seed=32)
+    out = gpu_solve(P, p, c, 24, 4, U, "c64_ir", NS=256)
+    ref = lam_all[R.inside(c, lam_all)]
+    assert len(out["lam"]) == len(ref) > 3
+    assert match_sets(out["lam"], ref) <= 1e-10 * 3.2
+
+
+def test_solve_diagonal_delay_lambert_w(P):
+    rng = np.random.default_rng(41)
+    n = 12
+    a, b = rng.uniform(-1, 1, n), rng.uniform(-1, 1, n)
+    lam_all = np.array([ai + sps.lambertw(bi * np.exp(-ai), br) for ai, bi in zip(a, b)
+                        for br in range(-40, 41)])
+    c = ni.Contour(0.0, 2.5, 2.5)
+    p = ni.delay_diag(a, b)
+    U = ni.probing_matrix(n, 4, seed=42)
+    out = gpu_solve(P, p, c, 24, 4, U, "c128", NS=512, K=3)
+    ref = lam_all[R.inside(c, lam_all)]
+    assert len(out["lam"]) == len(ref) > n
+    assert match_sets(out["lam"], ref) <= 1e-10 * 2.5
+
+
+def test_solve_small_delay_matches_oracle(P):
+    p, c, N, L, U = ni.config_small_delay(n=64, seed=11)
+    ref = R.rsrr(p, c, N, L, U)
+    out = gpu_solve(P, p, c, N, L, U, "c64_ir")
+    assert out["info"]["n_eig"] == len(ref["lam"])
+    assert match_sets(out["lam"], ref["lam"]) <= 1e-9 * 1.5
+
+
+def test_solve_bem_sphere_matches_oracle(P):
+    p = ni.bem_sphere(256)
+    c = ni.Contour(3.0, 1.5, 0.3)
+    U = ni.probing_matrix(256, 8, seed=9)
+    ref = R.rsrr(p, c, 40, 8, U, NS=256, K=2, cheb_degree=40)
+    out = gpu_solve(P, p, c, 40, 8, U, "c64_ir", NS=256, cheb_degree=40)
+    print("bem", out["info"], ref["lam"])
+    assert out["info"]["n_eig"] == len(ref["lam"])
+    assert match_sets(out["lam"], ref["lam"]) <= 1e-9 * 4.5
+    assert np.all(out["res"] <= 1e-10)
