@@ -56,6 +56,8 @@ int sample_impl(rsrr_problem* p, const rsrr_contour* c, const rsrr_params* prm,
                 const c128* U, long ldu, c128* S, long lds, rsrr_info* info);
 int ortho_impl(int rows, int cols, const c128* S, long lds, double delta, c128* Q, long ldq,
                int* k_S, Arena& ws, hipStream_t s);
+int basis_of_columns(const c128* X, long ldx, int rows, int cols, int rank, c128* Q, long ldq,
+                     Arena& ws, hipStream_t s);
 int project_impl(rsrr_problem* p, const rsrr_contour* c, const rsrr_params* prm, const c128* Q,
                  long ldq, int kS, c128* B, int* J_out);
 int solve_impl(rsrr_problem* p, const rsrr_contour* c, const rsrr_params* prm, const c128* U,

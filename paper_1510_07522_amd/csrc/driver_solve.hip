@@ -220,7 +220,7 @@ int solve_impl(rsrr_problem* p, const rsrr_contour* c, const rsrr_params* prm, c
   RSRR_TRY(build_hankel(Amom, kS, K, 0, H, M, s));
   RSRR_TRY(build_hankel(Amom, kS, K, 1, Hs, M, s));
   std::vector<double> sigma;
-  RSRR_TRY(jacobi_svd(H, M, M, Uh, M, Wh, M, &sigma, ws, s));
+  RSRR_TRY(jacobi_svd(H, M, M, Uh, M, Wh, M, &sigma, ws, s, prm->hankel_tol));
   res->hankel_sigma = sigma;
   vlog("hankel svd M=%d %.3fs", M, now_s() - t0);
   // gap count (eq. eq-gap), reading: zero tail excluded, smallest j on ties

@@ -14,56 +14,152 @@
 namespace rsrr {
 
 // ------------------------------------------------------------------- SVD
-// One round of the cyclic (circle-method) ordering: Mp/2 disjoint column
-// pairs, one workgroup each.  Column q is first multiplied by conj(e^{i phi})
-// (phi = arg of the inner product), then a real rotation zeroes the pair.
-__global__ __launch_bounds__(256) void jacobi_round_kernel(c128* H, long ldh, c128* W, long ldw,
-                                                           int M, int Mp, int round, double tol,
-                                                           int* counter) {
-  __shared__ double red[4][256];
+// One-sided block Jacobi.  Workgroup i of a round takes the pair of column
+// blocks (a, c) of width JB given by the circle method over the blocks, forms
+// the Gram matrix G of those 2*JB columns, diagonalises G by cyclic two-sided
+// Jacobi in LDS (accumulated in V) and applies V to the columns of H and W.
+// A column pair (p, q) with inner product g, squared norms al, be is rotated
+// only if |g| > tol sqrt(al be) (relative criterion) and |g| > gfloor (the
+// absolute noise floor: rotations below it cannot move a singular value by
+// more than ~sqrt(gfloor)) and both squared norms exceed nfloor (columns below
+// the truncation level of the caller are not orthogonalised among themselves
+// or against others: they are dropped afterwards).  For |g| > 0 the rotation is: column q times
+// conj(g)/|g|, then the real rotation with t = sign(z)/(|z| + sqrt(1+z^2)),
+// z = (be - al)/(2|g|).  `counter` counts the block pairs that were rotated.
+constexpr int JB = 16, J2 = 2 * JB, JCH = 32;
+__global__ __launch_bounds__(256) void bjacobi_round_kernel(c128* H, long ldh, c128* W, long ldw, int M,
+                                                            int nbk, int round, double tol,
+                                                            double gfloor, double nfloor, int* counter) {
+  __shared__ c128 G[J2][J2 + 1];
+  __shared__ c128 V[J2][J2 + 1];
+  __shared__ c128 X[JCH][J2 + 1];
+  __shared__ double s_rc[J2 / 2], s_rs[J2 / 2];
+  __shared__ c128 s_ph[J2 / 2];
+  __shared__ int s_pp[J2 / 2], s_qq[J2 / 2];
+  __shared__ int s_flag;
+  const int tid = threadIdx.x;
   const int i = blockIdx.x;
-  int a = (round + i) % (Mp - 1);
-  int b = (i == 0) ? Mp - 1 : (round - i + Mp - 1) % (Mp - 1);
-  const int p = min(a, b), q = max(a, b);
-  if (q >= M) return;
-  c128* hp = H + (long)p * ldh;
-  c128* hq = H + (long)q * ldh;
-  double al = 0, be = 0, gr = 0, gi = 0;
-  for (int r = threadIdx.x; r < M; r += 256) {
-    const c128 x = hp[r], y = hq[r];
-    al += abs2(x);
-    be += abs2(y);
-    const c128 g = cmul(x, y);     // conj(x) y
-    gr += g.re;
-    gi += g.im;
-  }
-  red[0][threadIdx.x] = al; red[1][threadIdx.x] = be;
-  red[2][threadIdx.x] = gr; red[3][threadIdx.x] = gi;
-  __syncthreads();
-  for (int o = 128; o > 0; o >>= 1) {
-    if (threadIdx.x < o)
-      for (int t = 0; t < 4; ++t) red[t][threadIdx.x] += red[t][threadIdx.x + o];
+  const int a = (round + i) % (nbk - 1);
+  const int cb = (i == 0) ? nbk - 1 : (round - i + nbk - 1) % (nbk - 1);
+  // column index of local j
+  auto gcol = [&](int j) -> int { return (j < JB) ? a * JB + j : cb * JB + (j - JB); };
+  // ---- Gram G = X^H X over all rows
+  const int gi = tid / 8, gj0 = (tid % 8) * 4;
+  c128 acc[4] = {mk<double>(0, 0), mk<double>(0, 0), mk<double>(0, 0), mk<double>(0, 0)};
+  for (int r0 = 0; r0 < M; r0 += JCH) {
+    for (int e = tid; e < JCH * J2; e += 256) {
+      const int rr = e % JCH, j = e / JCH;
+      const int r = r0 + rr, c = gcol(j);
+      X[rr][j] = (r < M && c < M) ? H[r + (long)c * ldh] : mk<double>(0, 0);
+    }
+    __syncthreads();
+    for (int rr = 0; rr < JCH; ++rr) {
+      const c128 xi = X[rr][gi];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) acc[q] = acc[q] + cmul(xi, X[rr][gj0 + q]);
+    }
     __syncthreads();
   }
-  al = red[0][0]; be = red[1][0]; gr = red[2][0]; gi = red[3][0];
-  const double g = sqrt(gr * gr + gi * gi);
-  if (!(g > tol * sqrt(al * be))) return;
-  if (threadIdx.x == 0) atomicAdd(counter, 1);
-  const c128 phc = mk<double>(gr / g, -gi / g);   // conj(e^{i phi})
-  const double zeta = (be - al) / (2.0 * g);
-  const double t = (zeta >= 0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
-  const double c = 1.0 / sqrt(1.0 + t * t), s = c * t;
-  for (int r = threadIdx.x; r < M; r += 256) {
-    const c128 x = hp[r], y = hq[r] * phc;
-    hp[r] = mk<double>(c * x.re - s * y.re, c * x.im - s * y.im);
-    hq[r] = mk<double>(s * x.re + c * y.re, s * x.im + c * y.im);
+#pragma unroll
+  for (int q = 0; q < 4; ++q) G[gi][gj0 + q] = acc[q];
+  for (int e = tid; e < J2 * J2; e += 256) V[e % J2][e / J2] = mk<double>((e % J2) == (e / J2) ? 1.0 : 0.0, 0);
+  if (tid == 0) s_flag = 0;
+  __syncthreads();
+  // ---- any pair off-diagonal above tol?
+  for (int e = tid; e < J2 * J2; e += 256) {
+    const int p = e % J2, q = e / J2;
+    if (p < q) {
+      const double al = G[p][p].re, be = G[q][q].re, g = sqrt(abs2(G[p][q]));
+      if (al > nfloor && be > nfloor && g > tol * sqrt(al * be) && g > gfloor) s_flag = 1;
+    }
   }
-  c128* wp = W + (long)p * ldw;
-  c128* wq = W + (long)q * ldw;
-  for (int r = threadIdx.x; r < M; r += 256) {
-    const c128 x = wp[r], y = wq[r] * phc;
-    wp[r] = mk<double>(c * x.re - s * y.re, c * x.im - s * y.im);
-    wq[r] = mk<double>(s * x.re + c * y.re, s * x.im + c * y.im);
+  __syncthreads();
+  if (!s_flag) return;
+  if (tid == 0) atomicAdd(counter, 1);
+  // ---- cyclic Jacobi on G (circle method over J2 indices), at most 3 sweeps
+  // per visit (the outer sweeps complete the convergence)
+  for (int sweep = 0; sweep < 3; ++sweep) {
+    if (tid == 0) s_flag = 0;
+    __syncthreads();
+    for (int step = 0; step < J2 - 1; ++step) {
+      if (tid < J2 / 2) {
+        const int x = (step + tid) % (J2 - 1);
+        const int y = (tid == 0) ? J2 - 1 : (step - tid + J2 - 1) % (J2 - 1);
+        const int p = min(x, y), q = max(x, y);
+        const double al = G[p][p].re, be = G[q][q].re;
+        const c128 gpq = G[p][q];
+        const double g = sqrt(abs2(gpq));
+        double c = 1, sn = 0;
+        c128 phc = mk<double>(1, 0);
+        if (al > nfloor && be > nfloor && g > tol * sqrt(al * be) && g > gfloor) {
+          s_flag = 1;
+          phc = mk<double>(gpq.re / g, -gpq.im / g);
+          const double zeta = (be - al) / (2.0 * g);
+          const double t = (zeta >= 0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+          c = 1.0 / sqrt(1.0 + t * t);
+          sn = c * t;
+        }
+        s_pp[tid] = p; s_qq[tid] = q; s_rc[tid] = c; s_rs[tid] = sn; s_ph[tid] = phc;
+      }
+      __syncthreads();
+      // columns: [g_p, g_q] <- [c g_p - s phc g_q, s g_p + c phc g_q]  (same for V)
+      for (int e = tid; e < (J2 / 2) * J2; e += 256) {
+        const int k = e / J2, r = e % J2;
+        if (s_rs[k] == 0.0) continue;
+        const int p = s_pp[k], q = s_qq[k];
+        const double c = s_rc[k], sn = s_rs[k];
+        const c128 ph = s_ph[k];
+        c128 x = G[r][p], y = G[r][q] * ph;
+        G[r][p] = mk<double>(c * x.re - sn * y.re, c * x.im - sn * y.im);
+        G[r][q] = mk<double>(sn * x.re + c * y.re, sn * x.im + c * y.im);
+        x = V[r][p]; y = V[r][q] * ph;
+        V[r][p] = mk<double>(c * x.re - sn * y.re, c * x.im - sn * y.im);
+        V[r][q] = mk<double>(sn * x.re + c * y.re, sn * x.im + c * y.im);
+      }
+      __syncthreads();
+      // rows: [g_p; g_q] <- J^H [g_p; g_q]
+      for (int e = tid; e < (J2 / 2) * J2; e += 256) {
+        const int k = e / J2, cc = e % J2;
+        if (s_rs[k] == 0.0) continue;
+        const int p = s_pp[k], q = s_qq[k];
+        const double c = s_rc[k], sn = s_rs[k];
+        const c128 phb = conj(s_ph[k]);
+        const c128 x = G[p][cc], y = G[q][cc] * phb;
+        G[p][cc] = mk<double>(c * x.re - sn * y.re, c * x.im - sn * y.im);
+        G[q][cc] = mk<double>(sn * x.re + c * y.re, sn * x.im + c * y.im);
+      }
+      __syncthreads();
+    }
+    if (!s_flag) break;
+  }
+  // ---- apply V to the 2*JB columns of H and of W
+  for (int pass = 0; pass < 2; ++pass) {
+    c128* Mx = pass == 0 ? H : W;
+    const long ld = pass == 0 ? ldh : ldw;
+    for (int r0 = 0; r0 < M; r0 += JCH) {
+      for (int e = tid; e < JCH * J2; e += 256) {
+        const int rr = e % JCH, j = e / JCH;
+        const int r = r0 + rr, c = gcol(j);
+        X[rr][j] = (r < M && c < M) ? Mx[r + (long)c * ld] : mk<double>(0, 0);
+      }
+      __syncthreads();
+      {   // 4 outputs per thread: row rr, columns j0 .. j0+3 (JCH * J2 = 4 * 256)
+        const int rr = tid / 8, j0 = (tid % 8) * 4;
+        c128 v[4] = {mk<double>(0, 0), mk<double>(0, 0), mk<double>(0, 0), mk<double>(0, 0)};
+        for (int l = 0; l < J2; ++l) {
+          const c128 x = X[rr][l];
+#pragma unroll
+          for (int q = 0; q < 4; ++q) v[q] = v[q] + x * V[l][j0 + q];
+        }
+        const int r = r0 + rr;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int c = gcol(j0 + q);
+          if (r < M && c < M) Mx[r + (long)c * ld] = v[q];
+        }
+      }
+      __syncthreads();
+    }
   }
 }
 
@@ -111,39 +207,84 @@ int set_identity(c128* X, long ldx, int m, hipStream_t s) {
 }
 
 int jacobi_svd(c128* H, long ldh, int M, c128* U, long ldu, c128* W, long ldw,
-               std::vector<double>* sigma, Arena& ws, hipStream_t s) {
+               std::vector<double>* sigma, Arena& ws, hipStream_t s, double trunc) {
   if (M <= 0) return ST_OK;
   c128* Wt = nullptr;
   int* cnt = nullptr;
   double* sg = nullptr;
   int* perm = nullptr;
   RSRR_TRY(ws.get<c128>("sv_W", (size_t)M * M, &Wt));
+  c128* const Wsave = Wt;
   RSRR_TRY(ws.get<int>("sv_cnt", 64, &cnt));
   RSRR_TRY(ws.get<double>("sv_sig", M, &sg));
   RSRR_TRY(ws.get<int>("sv_perm", M, &perm));
   RSRR_TRY(set_identity(Wt, M, M, s));
   const int Mp = M + (M & 1);
-  const double tol = 2.0 * 2.220446049250313e-16 * sqrt((double)M);
+  const double tol = 8.0 * 2.220446049250313e-16 * sqrt((double)M);
   const int maxsweep = 40;
   std::vector<int> hc(maxsweep, 0);
   RSRR_HIP(hipMemsetAsync(cnt, 0, 64 * sizeof(int), s));
   int sweep = 0;
   bool converged = (Mp < 2);
+  // absolute floor from the largest column norm
+  hipLaunchKernelGGL(col_norms_kernel, dim3(M), dim3(256), 0, s, H, ldh, M, M, sg);
+  RSRR_LAUNCH_CHECK();
+  std::vector<double> h0(M);
+  RSRR_HIP(hipMemcpyAsync(h0.data(), sg, M * sizeof(double), hipMemcpyDeviceToHost, s));
+  RSRR_HIP(hipStreamSynchronize(s));
+  double smax = 0;
+  for (double v : h0) smax = std::max(smax, v);
+  const double fl = sqrt((double)M) * 2.220446049250313e-16 * smax;
+  const double gfloor = fl * fl;
+  const double nfloor = (trunc * smax) * (trunc * smax);
+  // block pairs: nbk blocks of JB columns (padded to an even count)
+  int nbk = (M + JB - 1) / JB;
+  nbk += (nbk & 1);
+  // columns are kept sorted by decreasing norm at the start of every sweep
+  // (faster convergence on graded matrices); H and W ping-pong with Hb, Wb
+  c128 *Hb = nullptr, *Wb = nullptr;
+  RSRR_TRY(ws.get<c128>("sv_Hb", (size_t)M * M, &Hb));
+  RSRR_TRY(ws.get<c128>("sv_Wb", (size_t)M * M, &Wb));
+  c128* Hc = H;
+  long ldc = ldh;
+  std::vector<int> ord(M);
   for (; sweep < maxsweep && !converged; ++sweep) {
-    for (int r = 0; r < Mp - 1; ++r) {
-      // per round: Mp/2 pairs, each reads 2 and writes 2 columns of H and W (M rows)
-      KernelTimer kt("jacobi_round", s, 0.0, (Mp / 2) * 8.0 * M * sizeof(c128));
-      hipLaunchKernelGGL(jacobi_round_kernel, dim3(Mp / 2), dim3(256), 0, s, H, ldh, Wt, M, M, Mp,
-                         r, tol, cnt + (sweep % 64));
-      RSRR_LAUNCH_CHECK();
+    hipLaunchKernelGGL(col_norms_kernel, dim3(M), dim3(256), 0, s, Hc, ldc, M, M, sg);
+    RSRR_LAUNCH_CHECK();
+    RSRR_HIP(hipMemcpyAsync(h0.data(), sg, M * sizeof(double), hipMemcpyDeviceToHost, s));
+    RSRR_HIP(hipStreamSynchronize(s));
+    std::iota(ord.begin(), ord.end(), 0);
+    std::stable_sort(ord.begin(), ord.end(), [&](int x, int y) { return h0[x] > h0[y]; });
+    RSRR_HIP(hipMemcpyAsync(perm, ord.data(), M * sizeof(int), hipMemcpyHostToDevice, s));
+    const unsigned gq = (unsigned)cdivl((long)M * M, 256);
+    c128* Hn = (Hc == Hb) ? H : Hb;
+    const long ldn = (Hc == Hb) ? ldh : M;
+    c128* Wn = (Wt == Wb) ? Wsave : Wb;
+    hipLaunchKernelGGL(permute_cols_kernel, dim3(gq), dim3(256), 0, s, Hc, ldc, perm, nullptr, M, M, Hn, ldn);
+    RSRR_LAUNCH_CHECK();
+    hipLaunchKernelGGL(permute_cols_kernel, dim3(gq), dim3(256), 0, s, Wt, (long)M, perm, nullptr, M, M, Wn, (long)M);
+    RSRR_LAUNCH_CHECK();
+    Hc = Hn;
+    ldc = ldn;
+    Wt = Wn;
+    if (nbk >= 2) {
+      for (int r = 0; r < nbk - 1; ++r) {
+        // per round: nbk/2 block pairs; each reads its 2*JB columns of H three
+        // times (Gram, apply) and of W twice, and writes both once
+        KernelTimer kt("jacobi_block_round", s, 0.0, (nbk / 2) * 6.0 * J2 * M * sizeof(c128));
+        hipLaunchKernelGGL(bjacobi_round_kernel, dim3(nbk / 2), dim3(256), 0, s, Hc, ldc, Wt, (long)M, M,
+                           nbk, r, tol, gfloor, nfloor, cnt + (sweep % 64));
+        RSRR_LAUNCH_CHECK();
+      }
     }
     int c = 0;
     RSRR_HIP(hipMemcpyAsync(&c, cnt + (sweep % 64), sizeof(int), hipMemcpyDeviceToHost, s));
     RSRR_HIP(hipStreamSynchronize(s));
     if (c == 0) converged = true;
+    vlog("jacobi sweep %d: %d block pairs rotated", sweep, c);
   }
   if (!converged) return set_error(ST_ENOTCONV, "Jacobi SVD did not converge in %d sweeps", maxsweep);
-  hipLaunchKernelGGL(col_norms_kernel, dim3(M), dim3(256), 0, s, H, ldh, M, M, sg);
+  hipLaunchKernelGGL(col_norms_kernel, dim3(M), dim3(256), 0, s, Hc, ldc, M, M, sg);
   RSRR_LAUNCH_CHECK();
   std::vector<double> hs(M);
   RSRR_HIP(hipMemcpyAsync(hs.data(), sg, M * sizeof(double), hipMemcpyDeviceToHost, s));
@@ -162,7 +303,7 @@ int jacobi_svd(c128* H, long ldh, int M, c128* U, long ldu, c128* W, long ldw,
   RSRR_HIP(hipMemcpyAsync(perm, order.data(), M * sizeof(int), hipMemcpyHostToDevice, s));
   RSRR_HIP(hipMemcpyAsync(invd, inv.data(), M * sizeof(double), hipMemcpyHostToDevice, s));
   const unsigned g = (unsigned)cdivl((long)M * M, 256);
-  hipLaunchKernelGGL(permute_cols_kernel, dim3(g), dim3(256), 0, s, H, ldh, perm, invd, M, M, U, ldu);
+  hipLaunchKernelGGL(permute_cols_kernel, dim3(g), dim3(256), 0, s, Hc, ldc, perm, invd, M, M, U, ldu);
   RSRR_LAUNCH_CHECK();
   hipLaunchKernelGGL(permute_cols_kernel, dim3(g), dim3(256), 0, s, Wt, M, perm, nullptr, M, M, W, ldw);
   RSRR_LAUNCH_CHECK();
@@ -282,14 +423,14 @@ __global__ __launch_bounds__(256) void right_update_kernel(c128* X, long ldx, co
 // full Schur form (rotations applied to all columns right / rows above) and
 // the accumulated unitary Z.
 constexpr int QT = 1024;
+constexpr int LEAF_MAX = 512;
 __device__ inline c128 csqrt_d(c128 z) {
   const double r = sqrt(sqrt(abs2(z)));
   const double th = 0.5 * atan2(z.im, z.re);
   return mk<double>(r * cos(th), r * sin(th));
 }
 
-__global__ __launch_bounds__(QT) void hqr_kernel(c128* H, long ldh, c128* Z, long ldz, int m,
-                                                 int maxit, int* status) {
+__device__ __forceinline__ void hqr_body(c128* H, long ldh, c128* Z, long ldz, int m, int maxit, int* status) {
   __shared__ int s_l, s_i, s_its, s_total;
   __shared__ c128 s_rot[2];     // (c, s) with c real in rot[0].re
   __shared__ int s_red[QT / 64];
@@ -401,6 +542,96 @@ __global__ __launch_bounds__(QT) void hqr_kernel(c128* H, long ldh, c128* Z, lon
   if (tid == 0) *status = s_total;
 }
 
+__global__ __launch_bounds__(QT) void hqr_kernel(c128* H, long ldh, c128* Z, long ldz, int m,
+                                                 int maxit, int* status) {
+  hqr_body(H, ldh, Z, ldz, m, maxit, status);
+}
+
+// Schur form of many small independent matrices, one workgroup each:
+// Householder reduction to Hessenberg form (accumulated into Z = I ...), then
+// the single-shift QR of hqr_body.  H_b and Z_b are len_b x len_b, ld len_b.
+struct LeafArgs {
+  c128* const* H;
+  c128* const* Z;
+  const int* len;
+  int* status;
+};
+
+__global__ __launch_bounds__(QT) void leaf_schur_kernel(LeafArgs a) {
+  __shared__ c128 s_v[LEAF_MAX];
+  __shared__ double s_red[QT / 64];
+  const int b = blockIdx.x;
+  c128* H = a.H[b];
+  c128* Z = a.Z[b];
+  const int m = a.len[b];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  for (int e = tid; e < m * m; e += QT) Z[e] = mk<double>((e % m) == (e / m) ? 1.0 : 0.0, 0);
+  __syncthreads();
+  for (int k = 0; k + 2 < m; ++k) {
+    double acc = 0;
+    for (int r = k + 1 + tid; r < m; r += QT) acc += abs2(H[r + (long)k * m]);
+    for (int off = 32; off >= 1; off >>= 1) acc += __shfl_xor(acc, off);
+    if (lane == 0) s_red[wave] = acc;
+    __syncthreads();
+    double nx2 = 0;
+    for (int q = 0; q < QT / 64; ++q) nx2 += s_red[q];
+    const c128 x0 = H[k + 1 + (long)k * m];
+    const double ax0 = sqrt(abs2(x0));
+    if (!(nx2 - abs2(x0) > 0.0)) { __syncthreads(); continue; }
+    const double nx = sqrt(nx2);
+    const c128 ph = ax0 > 0 ? mk<double>(x0.re / ax0, x0.im / ax0) : mk<double>(1, 0);
+    const c128 alpha = mk<double>(-ph.re * nx, -ph.im * nx);
+    const double vn = sqrt(2.0 * nx * (nx + ax0));
+    for (int r = tid; r < m; r += QT) {
+      c128 v = mk<double>(0, 0);
+      if (r > k) {
+        v = H[r + (long)k * m];
+        if (r == k + 1) v = v - alpha;
+        v = (1.0 / vn) * v;
+      }
+      s_v[r] = v;
+    }
+    __syncthreads();
+    for (int r = k + 1 + tid; r < m; r += QT) H[r + (long)k * m] = (r == k + 1) ? alpha : mk<double>(0, 0);
+    // left: columns c > k, one thread per column
+    for (int c = k + 1 + tid; c < m; c += QT) {
+      c128 w = mk<double>(0, 0);
+      for (int r = k + 1; r < m; ++r) w = w + cmul(s_v[r], H[r + (long)c * m]);
+      for (int r = k + 1; r < m; ++r) {
+        const c128 t = s_v[r] * w;
+        H[r + (long)c * m] = mk<double>(H[r + (long)c * m].re - 2 * t.re, H[r + (long)c * m].im - 2 * t.im);
+      }
+    }
+    __syncthreads();
+    // right: rows of H and of Z, one thread per row
+    for (int r = tid; r < m; r += QT) {
+      c128 u = mk<double>(0, 0), uz = mk<double>(0, 0);
+      for (int c = k + 1; c < m; ++c) {
+        u = u + H[r + (long)c * m] * s_v[c];
+        uz = uz + Z[r + (long)c * m] * s_v[c];
+      }
+      for (int c = k + 1; c < m; ++c) {
+        const c128 t = mulc(u, s_v[c]), tz = mulc(uz, s_v[c]);
+        H[r + (long)c * m] = mk<double>(H[r + (long)c * m].re - 2 * t.re, H[r + (long)c * m].im - 2 * t.im);
+        Z[r + (long)c * m] = mk<double>(Z[r + (long)c * m].re - 2 * tz.re, Z[r + (long)c * m].im - 2 * tz.im);
+      }
+    }
+    __syncthreads();
+  }
+  hqr_body(H, m, Z, m, m, 60 * m + 100, a.status + b);
+}
+
+int leaf_schur_batched(c128* const* H_dev, c128* const* Z_dev, const int* len_dev, int count,
+                       int* status_dev, hipStream_t s) {
+  if (count <= 0) return ST_OK;
+  LeafArgs a;
+  a.H = H_dev; a.Z = Z_dev; a.len = len_dev; a.status = status_dev;
+  KernelTimer kt("leaf_schur", s, 0.0, 0.0);
+  hipLaunchKernelGGL(leaf_schur_kernel, dim3(count), dim3(QT), 0, s, a);
+  RSRR_LAUNCH_CHECK();
+  return ST_OK;
+}
+
 // Eigenvector i of the upper-triangular T (one workgroup per eigenvalue):
 // x_i = 1, x_j = -(sum_{l>j} T[j][l] x_l) / (T[j][j] - T[i][i]) for j < i.
 __global__ __launch_bounds__(256) void trevc_kernel(const c128* T, long ldt, int m, double small,
@@ -428,10 +659,27 @@ __global__ __launch_bounds__(256) void trevc_kernel(const c128* T, long ldt, int
   }
 }
 
+int tri_eigvecs(const c128* T, long ldt, int m, c128* X, long ldx, hipStream_t s) {
+  std::vector<c128> diag(m);
+  RSRR_HIP(hipMemcpy2DAsync(diag.data(), sizeof(c128), T, (ldt + 1) * sizeof(c128), sizeof(c128), m,
+                            hipMemcpyDeviceToHost, s));
+  RSRR_HIP(hipStreamSynchronize(s));
+  double tnorm = 0;
+  for (int j = 0; j < m; ++j) tnorm = std::max(tnorm, sqrt(abs2(diag[j])));
+  const double small = std::max(tnorm, 1e-300) * 2.220446049250313e-16;
+  const size_t shm = (size_t)m * sizeof(c128);
+  if (shm > 150 * 1024) return set_error(ST_EINVAL, "eigenvectors: m=%d too large", m);
+  KernelTimer kt("trevc", s, 8.0 * (double)m * m * m / 6, 16.0 * (double)m * m * m / 2);
+  hipLaunchKernelGGL(trevc_kernel, dim3(m), dim3(256), shm, s, T, ldt, m, small, X, ldx);
+  RSRR_LAUNCH_CHECK();
+  return ST_OK;
+}
+
 int eig_general(c128* A, long lda, int m, std::vector<cd>* lam, c128* V, long ldv, Arena& ws,
                 hipStream_t s) {
   lam->clear();
   if (m <= 0) return ST_OK;
+  if (m > DC_LEAF) return eig_dc(A, lda, m, lam, V, ldv, ws, s);
   c128 *Vh = nullptr, *Z = nullptr, *w = nullptr, *X = nullptr;
   int* skip = nullptr;
   RSRR_TRY(ws.get<c128>("eg_Vh", (size_t)m * m, &Vh));

@@ -1,0 +1,378 @@
+// Schur decomposition A = Z T Z^H of a large dense complex matrix by spectral
+// divide and conquer, followed by eigenvectors of T.
+//
+// A diagonal block B of the current T is split along a line through the mean
+// of its eigenvalues: the matrix sign function S = sign(B - sigma I) (or of
+// -i (B - i sigma I) for a horizontal line) is computed by the scaled Newton
+// iteration X <- (mu X + X^{-1}/mu)/2, mu = sqrt(||X^{-1}||_F / ||X||_F);
+// P = (I + S)/2 projects on the eigenvalues right of (above) the line, rank
+// k = tr P.  Q = [Q1 Q2] with Q1 an orthonormal basis of range(P) and Q2 of its
+// orthogonal complement makes Q^H B Q block upper triangular; T and Z are
+// updated with GEMMs and both diagonal blocks are split further.  Blocks of
+// at most DC_LEAF rows are put in Schur form concurrently, one workgroup each.
+// Inversions use the batched LU of the sampling step; bases use the pivoted
+// Cholesky / Cholesky-QR routines of the orthonormalisation step.
+#include <algorithm>
+#include <cmath>
+#include <vector>
+
+#include "driver.h"
+#include "eig.h"
+#include "timers.h"
+
+namespace rsrr {
+
+static const c128 ONE = {1, 0}, ZERO = {0, 0}, MONE = {-1, 0};
+
+static int zg(int opA, int opB, int M, int N, int K, c128 alpha, const c128* A, long lda,
+              const c128* B, long ldb, c128 beta, c128* C, long ldc, hipStream_t s) {
+  GemmBatch<double> g;
+  g.opA = opA; g.opB = opB; g.M = M; g.N = N; g.K = K;
+  g.alpha = alpha; g.beta = beta;
+  g.A = A; g.lda = lda; g.B = B; g.ldb = ldb; g.C = C; g.ldc = ldc;
+  g.tag = "dc_gemm";
+  return gemm_batched<double>(g, s);
+}
+
+// dst = rot * (src - shift I)   (len x len)
+__global__ __launch_bounds__(256) void shift_copy_kernel(const c128* src, long lds, c128* dst, long ldd,
+                                                         int len, c128 shift, c128 rot) {
+  const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= (long)len * len) return;
+  const int r = (int)(e % len), c = (int)(e / len);
+  c128 v = src[r + (long)c * lds];
+  if (r == c) v = v - shift;
+  dst[r + (long)c * ldd] = rot * v;
+}
+
+// per-workgroup partial sums over column ranges: out[2*blk] = sum |X|^2,
+// out[2*blk+1] = sum |Y - X|^2 (when Y given)
+constexpr int FCOLS = 8;
+__global__ __launch_bounds__(256) void fro_partial_kernel(const c128* X, const c128* Y, long ld, int rows,
+                                                          int cols, double* out, int sub_identity = 0) {
+  __shared__ double r0[256], r1[256];
+  const int c0 = blockIdx.x * FCOLS;
+  double a = 0, b = 0;
+  for (int c = c0; c < min(cols, c0 + FCOLS); ++c)
+    for (int r = threadIdx.x; r < rows; r += 256) {
+      c128 x = X[r + (long)c * ld];
+      if (sub_identity && r == c) x.re -= 1.0;
+      a += abs2(x);
+      if (Y) b += abs2(Y[r + (long)c * ld] - x);
+    }
+  r0[threadIdx.x] = a;
+  r1[threadIdx.x] = b;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (threadIdx.x < o) { r0[threadIdx.x] += r0[threadIdx.x + o]; r1[threadIdx.x] += r1[threadIdx.x + o]; }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) { out[2 * blockIdx.x] = r0[0]; out[2 * blockIdx.x + 1] = r1[0]; }
+}
+
+// Y <- a X + b Y
+__global__ __launch_bounds__(256) void axpby_kernel(const c128* X, c128* Y, long ld, int len, double a,
+                                                    double b) {
+  const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= (long)len * len) return;
+  const int r = (int)(e % len), c = (int)(e / len);
+  const c128 x = X[r + (long)c * ld], y = Y[r + (long)c * ld];
+  Y[r + (long)c * ld] = mk<double>(a * x.re + b * y.re, a * x.im + b * y.im);
+}
+
+// P = (I + S)/2 in place; diagonal copied to diag[]
+__global__ __launch_bounds__(256) void projector_kernel(c128* S, long ld, int len, c128* diag) {
+  const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= (long)len * len) return;
+  const int r = (int)(e % len), c = (int)(e / len);
+  c128 v = 0.5 * S[r + (long)c * ld];
+  if (r == c) { v.re += 0.5; diag[r] = v; }
+  S[r + (long)c * ld] = v;
+}
+
+__global__ void diag_copy_kernel(const c128* A, long lda, int len, c128* out) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < len) out[i] = A[i + (long)i * lda];
+}
+
+__global__ __launch_bounds__(256) void zero_block_kernel(c128* A, long lda, int rows, int cols) {
+  const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= (long)rows * cols) return;
+  A[(e % rows) + (e / rows) * lda] = mk<double>(0, 0);
+}
+
+static unsigned nblk(long cnt) { return (unsigned)cdivl(cnt, 256); }
+
+struct DcWork {
+  c128 *X, *Y, *LU, *dinv, *Q, *tmp, *tmp2, *diag;
+  int *ipiv, *info;
+  double* part;
+  int cap;
+};
+
+static int fro_sums(const c128* X, const c128* Y, long ld, int len, DcWork& w, hipStream_t s,
+                    double* fx, double* fd, int sub_identity = 0) {
+  const int nb = (len + FCOLS - 1) / FCOLS;
+  hipLaunchKernelGGL(fro_partial_kernel, dim3(nb), dim3(256), 0, s, X, Y, ld, len, len, w.part, sub_identity);
+  RSRR_LAUNCH_CHECK();
+  std::vector<double> h(2 * nb);
+  RSRR_HIP(hipMemcpyAsync(h.data(), w.part, h.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+  RSRR_HIP(hipStreamSynchronize(s));
+  double a = 0, b = 0;
+  for (int i = 0; i < nb; ++i) { a += h[2 * i]; b += h[2 * i + 1]; }
+  *fx = a;
+  if (fd) *fd = b;
+  return ST_OK;
+}
+
+static int host_diag(const c128* A, long lda, int len, DcWork& w, hipStream_t s, std::vector<c128>* d) {
+  hipLaunchKernelGGL(diag_copy_kernel, dim3((unsigned)cdivl(len, 256)), dim3(256), 0, s, A, lda, len, w.diag);
+  RSRR_LAUNCH_CHECK();
+  d->resize(len);
+  RSRR_HIP(hipMemcpyAsync(d->data(), w.diag, len * sizeof(c128), hipMemcpyDeviceToHost, s));
+  RSRR_HIP(hipStreamSynchronize(s));
+  return ST_OK;
+}
+
+// Sign function of X (len x len, in w.X, destroyed); result in w.X.
+// Scaled Newton X <- (mu X + X^{-1}/mu)/2 while far from convergence; once the
+// relative change is below 1e-2 and ||X^2 - I||_F / sqrt(len) < 0.5, the
+// inverse-free Newton-Schulz step X <- X (3I - X^2)/2 (two GEMMs) finishes.
+// Returns -1 if X became singular or the iteration did not converge.
+static int newton_sign(int len, DcWork& w, Arena& ws, hipStream_t s, int* iters) {
+  const long ll = (long)len * len;
+  const double sq = sqrt((double)len);
+  LUWork<double> lw;
+  lw.n = len; lw.nb = 64; lw.batch = 1; lw.lda = len; lw.sA = ll;
+  lw.ipiv = w.ipiv; lw.dinv = w.dinv; lw.info = w.info;
+  lw.tag = "dc_lu";
+  bool scaling = true, schulz = false;
+  double prev_r = 1e300;
+  for (int it = 0; it < 100; ++it) {
+    if (schulz) {
+      RSRR_TRY(zg(OP_N, OP_N, len, len, len, ONE, w.X, len, w.X, len, ZERO, w.Y, len, s));   // X^2
+      double r2 = 0;
+      RSRR_TRY(fro_sums(w.Y, nullptr, len, len, w, s, &r2, nullptr, 1));
+      const double r = sqrt(r2) / sq;
+      if (r < 1e-13) { *iters = it; return ST_OK; }
+      // stagnation at the rounding level of a non-normal S: converged
+      if (r < 1e-8 && r > 0.5 * prev_r) { *iters = it; return ST_OK; }
+      prev_r = r;
+      if (!(r < 0.5)) { schulz = false; prev_r = 1e300; continue; }   // back to Newton
+      RSRR_TRY(zg(OP_N, OP_N, len, len, len, ONE, w.X, len, w.Y, len, ZERO, w.LU, len, s));  // X^3
+      hipLaunchKernelGGL(axpby_kernel, dim3(nblk(ll)), dim3(256), 0, s, w.X, w.LU, len, len, 1.5, -0.5);
+      RSRR_LAUNCH_CHECK();
+      std::swap(w.X, w.LU);
+      continue;
+    }
+    lw.A = w.LU;
+    RSRR_TRY((convert<double, double>(w.X, len, 0, w.LU, len, 0, len, len, 1, s)));
+    RSRR_TRY(set_identity(w.Y, len, len, s));
+    RSRR_TRY(lu_factor<double>(lw, s));
+    int info = 0;
+    RSRR_HIP(hipMemcpyAsync(&info, w.info, sizeof(int), hipMemcpyDeviceToHost, s));
+    RSRR_HIP(hipStreamSynchronize(s));
+    if (info) { *iters = it; return -1; }
+    RSRR_TRY(lu_solve<double>(lw, w.Y, len, ll, len, s));
+    double fx = 0, fy = 0;
+    RSRR_TRY(fro_sums(w.X, nullptr, len, len, w, s, &fx, nullptr));
+    RSRR_TRY(fro_sums(w.Y, nullptr, len, len, w, s, &fy, nullptr));
+    const double mu = scaling ? sqrt(sqrt(fy) / sqrt(fx)) : 1.0;
+    // Y <- (mu X + Y / mu) / 2
+    hipLaunchKernelGGL(axpby_kernel, dim3(nblk(ll)), dim3(256), 0, s, w.X, w.Y, len, len, 0.5 * mu, 0.5 / mu);
+    RSRR_LAUNCH_CHECK();
+    double fn = 0, fd = 0;
+    RSRR_TRY(fro_sums(w.Y, w.X, len, len, w, s, &fn, &fd));
+    std::swap(w.X, w.Y);
+    const double rel = sqrt(fd / std::max(fn, 1e-300));
+    if (!(rel == rel)) { *iters = it; return -1; }
+    if (rel < 1e-2) { scaling = false; schulz = true; }
+  }
+  *iters = 100;
+  return -1;
+}
+
+// Splits the diagonal block B = T[off.., off..] (len x len).  On success Q
+// (len x len, ld len) holds [Q1 Q2] and *k the size of the leading block.
+static int split_block(const c128* B, long ldb, int len, DcWork& w, Arena& ws, hipStream_t s, int* k_out) {
+  *k_out = 0;
+  std::vector<c128> d;
+  RSRR_TRY(host_diag(B, ldb, len, w, s, &d));
+  double sr = 0, si = 0;
+  for (int i = 0; i < len; ++i) { sr += d[i].re; si += d[i].im; }
+  sr /= len;
+  si /= len;
+  const long ll = (long)len * len;
+  int k = 0;
+  for (int attempt = 0; attempt < 4 && (k <= 0 || k >= len); ++attempt) {
+    // attempts: vertical line through the mean, horizontal line, then nudged lines
+    const bool vert = (attempt % 2 == 0);
+    const double nudge = (attempt >= 2) ? 1e-3 * (1 + sqrt(sr * sr + si * si)) : 0.0;
+    const c128 shift = vert ? mk<double>(sr + nudge, 0) : mk<double>(0, si + nudge);
+    const c128 rot = vert ? mk<double>(1, 0) : mk<double>(0, -1);
+    hipLaunchKernelGGL(shift_copy_kernel, dim3(nblk(ll)), dim3(256), 0, s, B, ldb, w.X, len, len, shift, rot);
+    RSRR_LAUNCH_CHECK();
+    int its = 0;
+    const int st = newton_sign(len, w, ws, s, &its);
+    if (st < 0) { vlog("dc split len=%d attempt %d: no convergence (%d its)", len, attempt, its); continue; }
+    hipLaunchKernelGGL(projector_kernel, dim3(nblk(ll)), dim3(256), 0, s, w.X, len, len, w.diag);
+    RSRR_LAUNCH_CHECK();
+    std::vector<c128> pd(len);
+    RSRR_HIP(hipMemcpyAsync(pd.data(), w.diag, len * sizeof(c128), hipMemcpyDeviceToHost, s));
+    RSRR_HIP(hipStreamSynchronize(s));
+    double tr = 0;
+    for (int i = 0; i < len; ++i) tr += pd[i].re;
+    k = (int)std::lround(tr);
+    vlog("dc split len=%d attempt %d: %d newton its, k=%d (trace %.6f)", len, attempt, its, k, tr);
+  }
+  if (k <= 0 || k >= len) return ST_OK;
+  // Q1 = range(P), Q2 = orthogonal complement of range(Q1)
+  c128* Q1 = w.Q;
+  c128* Q2 = w.Q + (long)k * len;
+  RSRR_TRY(basis_of_columns(w.X, len, len, len, k, Q1, len, ws, s));
+  RSRR_TRY(set_identity(w.Y, len, len, s));
+  RSRR_TRY(zg(OP_N, OP_C, len, len, k, MONE, Q1, len, Q1, len, ONE, w.Y, len, s));
+  RSRR_TRY(basis_of_columns(w.Y, len, len, len, len - k, Q2, len, ws, s));
+  // one more orthogonalisation of Q2 against Q1 (classical Gram-Schmidt, then Cholesky-QR)
+  RSRR_TRY(zg(OP_C, OP_N, k, len - k, len, ONE, Q1, len, Q2, len, ZERO, w.tmp, k, s));
+  RSRR_TRY(zg(OP_N, OP_N, len, len - k, k, MONE, Q1, len, w.tmp, k, ONE, Q2, len, s));
+  RSRR_TRY((convert<double, double>(Q2, len, 0, w.Y, len, 0, len, len - k, 1, s)));
+  RSRR_TRY(basis_of_columns(w.Y, len, len, len - k, len - k, Q2, len, ws, s));
+  *k_out = k;
+  return ST_OK;
+}
+
+// T <- diag(I, Q, I)^H T diag(I, Q, I) on block [off, off+len); Z <- Z diag(I, Q, I).
+static int apply_block(c128* T, long ldt, int m, c128* Z, long ldz, int off, int len, const c128* Q,
+                       long ldq, DcWork& w, hipStream_t s, bool diag_too) {
+  const int right = m - off - len;
+  if (right > 0) {          // rows of the block, columns right of it
+    c128* R = T + off + (long)(off + len) * ldt;
+    RSRR_TRY(zg(OP_C, OP_N, len, right, len, ONE, Q, ldq, R, ldt, ZERO, w.tmp, len, s));
+    RSRR_TRY((convert<double, double>(w.tmp, len, 0, R, ldt, 0, len, right, 1, s)));
+  }
+  if (off > 0) {            // columns of the block, rows above it
+    c128* Ab = T + (long)off * ldt;
+    RSRR_TRY(zg(OP_N, OP_N, off, len, len, ONE, Ab, ldt, Q, ldq, ZERO, w.tmp, off, s));
+    RSRR_TRY((convert<double, double>(w.tmp, off, 0, Ab, ldt, 0, off, len, 1, s)));
+  }
+  if (diag_too) {
+    c128* D = T + off + (long)off * ldt;
+    RSRR_TRY(zg(OP_N, OP_N, len, len, len, ONE, D, ldt, Q, ldq, ZERO, w.tmp, len, s));
+    RSRR_TRY(zg(OP_C, OP_N, len, len, len, ONE, Q, ldq, w.tmp, len, ZERO, w.tmp2, len, s));
+    RSRR_TRY((convert<double, double>(w.tmp2, len, 0, D, ldt, 0, len, len, 1, s)));
+  }
+  c128* Zb = Z + (long)off * ldz;
+  RSRR_TRY(zg(OP_N, OP_N, m, len, len, ONE, Zb, ldz, Q, ldq, ZERO, w.tmp, m, s));
+  RSRR_TRY((convert<double, double>(w.tmp, m, 0, Zb, ldz, 0, m, len, 1, s)));
+  return ST_OK;
+}
+
+int eig_dc(c128* A, long lda, int m, std::vector<cd>* lam, c128* V, long ldv, Arena& ws,
+           hipStream_t s) {
+  const long mm = (long)m * m;
+  DcWork w;
+  c128* Z = nullptr;
+  RSRR_TRY(ws.get<c128>("dc_Z", mm, &Z));
+  RSRR_TRY(ws.get<c128>("dc_X", mm, &w.X));
+  RSRR_TRY(ws.get<c128>("dc_Y", mm, &w.Y));
+  RSRR_TRY(ws.get<c128>("dc_LU", mm, &w.LU));
+  RSRR_TRY(ws.get<c128>("dc_dinv", LUWork<double>::dinv_elems(m, 64, 1), &w.dinv));
+  RSRR_TRY(ws.get<c128>("dc_Q", mm, &w.Q));
+  RSRR_TRY(ws.get<c128>("dc_tmp", mm, &w.tmp));
+  RSRR_TRY(ws.get<c128>("dc_tmp2", mm, &w.tmp2));
+  RSRR_TRY(ws.get<c128>("dc_diag", m, &w.diag));
+  RSRR_TRY(ws.get<int>("dc_ipiv", m, &w.ipiv));
+  RSRR_TRY(ws.get<int>("dc_info", 1, &w.info));
+  RSRR_TRY(ws.get<double>("dc_part", 2 * (size_t)(m / FCOLS + 2), &w.part));
+  RSRR_TRY(set_identity(Z, m, m, s));
+  struct Blk { int off, len; };
+  std::vector<Blk> stack{{0, m}}, leaves;
+  while (!stack.empty()) {
+    const Blk b = stack.back();
+    stack.pop_back();
+    if (b.len <= DC_LEAF) { leaves.push_back(b); continue; }
+    int k = 0;
+    c128* B = A + b.off + (long)b.off * lda;
+    RSRR_TRY(split_block(B, lda, b.len, w, ws, s, &k));
+    if (k <= 0 || k >= b.len) {
+      if (b.len > 512) return set_error(ST_ENOTCONV, "divide and conquer: no split of a %d block", b.len);
+      leaves.push_back(b);
+      continue;
+    }
+    RSRR_TRY(apply_block(A, lda, m, Z, m, b.off, b.len, w.Q, b.len, w, s, true));
+    double f_all = 0, f_low = 0;
+    RSRR_TRY(fro_sums(B, nullptr, lda, b.len, w, s, &f_all, nullptr));
+    {   // norm of the block below the split (should be at rounding level), then zero it
+      std::vector<double> h;
+      const int rows = b.len - k;
+      c128* Lo = B + k;
+      RSRR_TRY((convert<double, double>(Lo, lda, 0, w.tmp, rows, 0, rows, k, 1, s)));
+      double part = 0;
+      const int nb = (k + FCOLS - 1) / FCOLS;
+      hipLaunchKernelGGL(fro_partial_kernel, dim3(nb), dim3(256), 0, s, w.tmp, (const c128*)nullptr, (long)rows, rows, k, w.part);
+      RSRR_LAUNCH_CHECK();
+      h.resize(2 * nb);
+      RSRR_HIP(hipMemcpyAsync(h.data(), w.part, h.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+      RSRR_HIP(hipStreamSynchronize(s));
+      for (int i = 0; i < nb; ++i) part += h[2 * i];
+      f_low = part;
+      hipLaunchKernelGGL(zero_block_kernel, dim3(nblk((long)rows * k)), dim3(256), 0, s, Lo, lda, rows, k);
+      RSRR_LAUNCH_CHECK();
+    }
+    vlog("dc block off=%d len=%d -> %d + %d, ||B21||/||B|| = %.2e", b.off, b.len, k, b.len - k,
+         sqrt(f_low / std::max(f_all, 1e-300)));
+    stack.push_back({b.off + k, b.len - k});
+    stack.push_back({b.off, k});
+  }
+  // ---- leaves: Schur forms of the diagonal blocks, all at once
+  const int nl = (int)leaves.size();
+  std::vector<c128*> hH(nl), hZ(nl);
+  std::vector<int> hlen(nl);
+  size_t total = 0;
+  for (auto& b : leaves) total += (size_t)b.len * b.len;
+  c128 *Lbuf = nullptr, *Zbuf = nullptr;
+  c128** pdev = nullptr;
+  int* idev = nullptr;
+  RSRR_TRY(ws.get<c128>("dc_leafH", total, &Lbuf));
+  RSRR_TRY(ws.get<c128>("dc_leafZ", total, &Zbuf));
+  RSRR_TRY(ws.get<c128*>("dc_leafP", 2 * (size_t)nl, &pdev));
+  RSRR_TRY(ws.get<int>("dc_leafI", 2 * (size_t)nl, &idev));
+  size_t o = 0;
+  for (int i = 0; i < nl; ++i) {
+    hH[i] = Lbuf + o;
+    hZ[i] = Zbuf + o;
+    hlen[i] = leaves[i].len;
+    RSRR_TRY((convert<double, double>(A + leaves[i].off + (long)leaves[i].off * lda, lda, 0, hH[i],
+                                      leaves[i].len, 0, leaves[i].len, leaves[i].len, 1, s)));
+    o += (size_t)leaves[i].len * leaves[i].len;
+  }
+  RSRR_HIP(hipMemcpyAsync(pdev, hH.data(), nl * sizeof(c128*), hipMemcpyHostToDevice, s));
+  RSRR_HIP(hipMemcpyAsync(pdev + nl, hZ.data(), nl * sizeof(c128*), hipMemcpyHostToDevice, s));
+  RSRR_HIP(hipMemcpyAsync(idev, hlen.data(), nl * sizeof(int), hipMemcpyHostToDevice, s));
+  RSRR_TRY(leaf_schur_batched(pdev, pdev + nl, idev, nl, idev + nl, s));
+  std::vector<int> st(nl);
+  RSRR_HIP(hipMemcpyAsync(st.data(), idev + nl, nl * sizeof(int), hipMemcpyDeviceToHost, s));
+  RSRR_HIP(hipStreamSynchronize(s));
+  for (int i = 0; i < nl; ++i)
+    if (st[i] < 0) return set_error(ST_ENOTCONV, "leaf QR did not converge (len %d)", hlen[i]);
+  for (int i = 0; i < nl; ++i) {
+    const Blk& b = leaves[i];
+    RSRR_TRY(apply_block(A, lda, m, Z, m, b.off, b.len, hZ[i], b.len, w, s, false));
+    RSRR_TRY((convert<double, double>(hH[i], b.len, 0, A + b.off + (long)b.off * lda, lda, 0, b.len,
+                                      b.len, 1, s)));
+  }
+  vlog("dc: %d leaves", nl);
+  // ---- eigenvalues and eigenvectors of the Schur form
+  c128* X = nullptr;
+  RSRR_TRY(ws.get<c128>("dc_Xv", mm, &X));
+  RSRR_TRY(tri_eigvecs(A, lda, m, X, m, s));
+  RSRR_TRY(zg(OP_N, OP_N, m, m, m, ONE, Z, m, X, m, ZERO, V, ldv, s));
+  std::vector<c128> d;
+  RSRR_TRY(host_diag(A, lda, m, w, s, &d));
+  lam->resize(m);
+  for (int j = 0; j < m; ++j) (*lam)[j] = cd(d[j].re, d[j].im);
+  return ST_OK;
+}
+
+}  // namespace rsrr

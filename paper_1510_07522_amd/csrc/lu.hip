@@ -24,12 +24,20 @@ template <typename R, int ROWS, int W>
 __global__ __launch_bounds__(PNT) void lu_panel_kernel(cplx<R>* A, long lda, long sA, int n,
                                                         int k, int nbe, int nb, int* ipiv,
                                                         cplx<R>* dinv, long sD, int* info) {
+  // per pivot step: wave arg-max -> every wave leader publishes its value and
+  // index, and the lane owning the wave's best row publishes that row, in LDS
+  // (one barrier); all threads then pick the winner and read the pivot row.
   __shared__ R s_val[2][16];
   __shared__ int s_idx[2][16];
-  __shared__ cplx<R> s_prow[2][W], s_crow[2][W];
+  __shared__ cplx<R> s_cand[2][16][W];
+  __shared__ cplx<R> s_crow[2][W];
   __shared__ cplx<R> s_L[W][W];
   __shared__ cplx<R> s_U[W][MAXNB];
   __shared__ cplx<R> s_D[MAXNB][MAXNB + 1];
+  __shared__ int s_piv[W];
+  __shared__ int t_row[2 * W], t_src[2 * W];
+  __shared__ int s_cnt;
+  __shared__ cplx<R> s_mv[2 * W][MAXNB];
 
   const int b = blockIdx.x;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -49,7 +57,7 @@ __global__ __launch_bounds__(PNT) void lu_panel_kernel(cplx<R>* A, long lda, lon
     }
     for (int jj = 0; jj < w; ++jj) {
       const int col = c + jj;
-      // ---- arg-max of |re|+|im| over rows >= col
+      const int tc = (col - c) % PNT, ic = (col - c) / PNT;
       R best = -1;
       int bidx = 0x7fffffff;
 #pragma unroll
@@ -59,42 +67,23 @@ __global__ __launch_bounds__(PNT) void lu_panel_kernel(cplx<R>* A, long lda, lon
 #pragma unroll
         for (int j = 0; j < W; ++j) if (j == jj) v = a[i][j];
         if (r >= col && r < n) {
-          R m = cabs1(v);
+          const R m = cabs1(v);
           if (m > best) { best = m; bidx = r; }
         }
       }
 #pragma unroll
       for (int off = 32; off >= 1; off >>= 1) {
-        R ob = __shfl_xor(best, off);
-        int oi = __shfl_xor(bidx, off);
+        const R ob = __shfl_xor(best, off);
+        const int oi = __shfl_xor(bidx, off);
         if (ob > best || (ob == best && oi < bidx)) { best = ob; bidx = oi; }
       }
       if (lane == 0) { s_val[parity][wave] = best; s_idx[parity][wave] = bidx; }
-      __syncthreads();
-      best = s_val[parity][0];
-      bidx = s_idx[parity][0];
 #pragma unroll
-      for (int q = 1; q < 16; ++q) {
-        R ob = s_val[parity][q];
-        int oi = s_idx[parity][q];
-        if (ob > best || (ob == best && oi < bidx)) { best = ob; bidx = oi; }
-      }
-      const bool zero = !(best > R(0));
-      const int p = zero ? col : bidx;
-      if (tid == 0) {
-        pv[col] = p;
-        if (zero && info[b] == 0) info[b] = col + 1;
-      }
-      // ---- interchange rows col and p
-      const int tp = (p - c) % PNT, ip = (p - c) / PNT;
-      const int tc = (col - c) % PNT, ic = (col - c) / PNT;
-      if (tid == tp) {
+      for (int i = 0; i < ROWS; ++i)
+        if (c + tid + PNT * i == bidx) {
 #pragma unroll
-        for (int i = 0; i < ROWS; ++i)
-          if (i == ip)
-#pragma unroll
-            for (int j = 0; j < W; ++j) s_prow[parity][j] = a[i][j];
-      }
+          for (int j = 0; j < W; ++j) s_cand[parity][wave][j] = a[i][j];
+        }
       if (tid == tc) {
 #pragma unroll
         for (int i = 0; i < ROWS; ++i)
@@ -103,13 +92,32 @@ __global__ __launch_bounds__(PNT) void lu_panel_kernel(cplx<R>* A, long lda, lon
             for (int j = 0; j < W; ++j) s_crow[parity][j] = a[i][j];
       }
       __syncthreads();
+      best = s_val[parity][0];
+      bidx = s_idx[parity][0];
+      int wb = 0;
+#pragma unroll
+      for (int q = 1; q < 16; ++q) {
+        const R ob = s_val[parity][q];
+        const int oi = s_idx[parity][q];
+        if (ob > best || (ob == best && oi < bidx)) { best = ob; bidx = oi; wb = q; }
+      }
+      const bool zero = !(best > R(0));
+      const int p = zero ? col : bidx;
+      if (tid == 0) {
+        pv[col] = p;
+        s_piv[jj] = p;
+        if (zero && info[b] == 0) info[b] = col + 1;
+      }
+      // pivot row: the winning candidate (or row col itself for a zero column)
+      const cplx<R>* prow = zero ? s_crow[parity] : s_cand[parity][wb];
       if (p != col) {
+        const int tp = (p - c) % PNT, ip = (p - c) / PNT;
         if (tid == tc) {
 #pragma unroll
           for (int i = 0; i < ROWS; ++i)
             if (i == ic)
 #pragma unroll
-              for (int j = 0; j < W; ++j) a[i][j] = s_prow[parity][j];
+              for (int j = 0; j < W; ++j) a[i][j] = prow[j];
         }
         if (tid == tp) {
 #pragma unroll
@@ -118,21 +126,10 @@ __global__ __launch_bounds__(PNT) void lu_panel_kernel(cplx<R>* A, long lda, lon
 #pragma unroll
               for (int j = 0; j < W; ++j) a[i][j] = s_crow[parity][j];
         }
-        // other columns of this panel (outside the micro-panel)
-        if (tid < nbe) {
-          const int cc = k + tid;
-          if (cc < c || cc >= c + w) {
-            cplx<R> x = Ab[col + (long)cc * lda];
-            cplx<R> y = Ab[p + (long)cc * lda];
-            Ab[col + (long)cc * lda] = y;
-            Ab[p + (long)cc * lda] = x;
-          }
-        }
       }
-      // ---- scale the column and update the rest of the micro-panel
       cplx<R> piv = mk<R>(1, 0);
 #pragma unroll
-      for (int j = 0; j < W; ++j) if (j == jj) piv = s_prow[parity][j];
+      for (int j = 0; j < W; ++j) if (j == jj) piv = prow[j];
       const cplx<R> inv = zero ? mk<R>(1, 0) : crecip(piv);
 #pragma unroll
       for (int i = 0; i < ROWS; ++i) {
@@ -143,7 +140,7 @@ __global__ __launch_bounds__(PNT) void lu_panel_kernel(cplx<R>* A, long lda, lon
           for (int j = 0; j < W; ++j) if (j == jj) { a[i][j] = a[i][j] * inv; l = a[i][j]; }
 #pragma unroll
           for (int j = 0; j < W; ++j)
-            if (j > jj) a[i][j] = a[i][j] - l * s_prow[parity][j];
+            if (j > jj) a[i][j] = a[i][j] - l * prow[j];
         }
       }
       parity ^= 1;
@@ -156,6 +153,36 @@ __global__ __launch_bounds__(PNT) void lu_panel_kernel(cplx<R>* A, long lda, lon
 #pragma unroll
         for (int j = 0; j < W; ++j)
           if (j < w) Ab[r + (long)(c + j) * lda] = a[i][j];
+    }
+    // ---- this micro-panel's interchanges on the other columns of the panel,
+    // as one gather: touched rows and their final source rows
+    if (tid == 0) {
+      int cnt = 0;
+      for (int j = 0; j < w; ++j) { t_row[cnt] = c + j; t_src[cnt] = c + j; ++cnt; }
+      for (int j = 0; j < w; ++j) {
+        const int p = s_piv[j];
+        if (p == c + j) continue;
+        int pos = -1;
+        for (int e = 0; e < cnt; ++e) if (t_row[e] == p) { pos = e; break; }
+        if (pos < 0) { pos = cnt; t_row[cnt] = p; t_src[cnt] = p; ++cnt; }
+        const int t = t_src[j];
+        t_src[j] = t_src[pos];
+        t_src[pos] = t;
+      }
+      s_cnt = cnt;
+    }
+    __syncthreads();
+    {
+      const int cnt = s_cnt;
+      for (int e = tid; e < cnt * nbe; e += PNT) {
+        const int q = e % cnt, cc = k + e / cnt;
+        if (cc < c || cc >= c + w) s_mv[q][cc - k] = Ab[t_src[q] + (long)cc * lda];
+      }
+      __syncthreads();
+      for (int e = tid; e < cnt * nbe; e += PNT) {
+        const int q = e % cnt, cc = k + e / cnt;
+        if (cc < c || cc >= c + w) Ab[t_row[q] + (long)cc * lda] = s_mv[q][cc - k];
+      }
     }
     const int rc0 = c + w, ncols = k + nbe - rc0;
     if (ncols > 0) {
@@ -183,18 +210,28 @@ __global__ __launch_bounds__(PNT) void lu_panel_kernel(cplx<R>* A, long lda, lon
         }
       }
       __syncthreads();
-      // rank-w update of the remaining panel rows
+      // rank-w update of the remaining panel rows, 8 columns per batch so that
+      // the loads of a batch are in flight together
 #pragma unroll
       for (int i = 0; i < ROWS; ++i) {
         const int r = c + tid + PNT * i;
         if (r >= rc0 && r < n) {
-          for (int t = 0; t < ncols; ++t) {
-            const long idx = r + (long)(rc0 + t) * lda;
-            cplx<R> acc = Ab[idx];
+          for (int t0 = 0; t0 < ncols; t0 += 8) {
+            cplx<R> acc[8];
 #pragma unroll
-            for (int j = 0; j < W; ++j)
-              if (j < w) acc = acc - a[i][j] * s_U[j][t];
-            Ab[idx] = acc;
+            for (int u = 0; u < 8; ++u)
+              if (t0 + u < ncols) acc[u] = Ab[r + (long)(rc0 + t0 + u) * lda];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+              if (t0 + u < ncols) {
+#pragma unroll
+                for (int j = 0; j < W; ++j)
+                  if (j < w) acc[u] = acc[u] - a[i][j] * s_U[j][t0 + u];
+              }
+            }
+#pragma unroll
+            for (int u = 0; u < 8; ++u)
+              if (t0 + u < ncols) Ab[r + (long)(rc0 + t0 + u) * lda] = acc[u];
           }
         }
       }

@@ -289,6 +289,30 @@ static int cholqr_pass(c128* X, long ldx, int rows, int k, Arena& ws, hipStream_
   return trsm_right_lh(G, k, k, X, ldx, rows, ws, s);
 }
 
+// Orthonormal basis (rows x rank, into Q) of the span of the columns of X
+// (rows x cols) whose rank is known: pivoted Cholesky of X^H X stopped at
+// `rank`, the selected columns times L11^{-H}, then one more Cholesky-QR pass.
+int basis_of_columns(const c128* X, long ldx, int rows, int cols, int rank, c128* Q, long ldq,
+                     Arena& ws, hipStream_t s) {
+  if (rank <= 0) return ST_OK;
+  c128* G = nullptr;
+  int* perm = nullptr;
+  RSRR_TRY(ws.get<c128>("bc_G", (size_t)cols * cols, &G));
+  RSRR_TRY(ws.get<int>("bc_perm", cols, &perm));
+  RSRR_TRY(gemm_z(OP_C, OP_N, cols, cols, rows, ONE, X, ldx, X, ldx, ZERO, G, cols, s));
+  int r = 0;
+  RSRR_TRY(pchol(G, cols, cols, rank, 0.0, true, perm, ws, s, &r));
+  if (r < rank) return set_error(ST_ENOTCONV, "basis_of_columns: rank %d < %d", r, rank);
+  hipLaunchKernelGGL(gather_cols_kernel, dim3((unsigned)cdivl((long)rows * rank, 256)), dim3(256), 0,
+                     s, X, ldx, perm, rows, rank, Q, ldq);
+  RSRR_LAUNCH_CHECK();
+  RSRR_TRY(trsm_right_lh(G, cols, rank, Q, ldq, rows, ws, s));
+  bool ok = true;
+  RSRR_TRY(cholqr_pass(Q, ldq, rows, rank, ws, s, &ok));
+  if (!ok) return set_error(ST_ENOTCONV, "basis_of_columns: Cholesky-QR pass broke down");
+  return ST_OK;
+}
+
 int ortho_impl(int rows, int cols, const c128* S, long lds, double delta, c128* Q, long ldq,
                int* k_S, Arena& ws, hipStream_t s) {
   const int m = cols, kmax = std::min(rows, cols);

@@ -180,3 +180,19 @@ def test_solve_bem_sphere_matches_oracle(P):
     assert out["info"]["n_eig"] == len(ref["lam"])
     assert match_sets(out["lam"], ref["lam"]) <= 1e-9 * 4.5
     assert np.all(out["res"] <= 1e-10)
+
+
+def test_solve_delay_large_reduced_problem_matches_oracle(P):
+    # k_S = n = 256 and m ~ 400 eigenvalue candidates: exercises the block
+    # Jacobi SVD of a 512 x 512 Hankel matrix and the divide-and-conquer Schur
+    # decomposition (m above the single-workgroup size).
+    p, c, N, L, U = ni.config_c1(n=256)
+    ref = R.rsrr(p, c, N, L, U)
+    out = gpu_solve(P, p, c, N, L, U, "c64_ir")
+    info = out["info"]
+    print("n=256 delay: n_eig", info["n_eig"], "ref", len(ref["lam"]), "m", info["m"], "ref m", ref["m"],
+          "times", info["t_reduced"])
+    assert info["m"] > 128
+    assert info["n_eig"] == len(ref["lam"])
+    assert match_sets(out["lam"], ref["lam"]) <= 1e-9 * 3.0
+    assert np.all(out["res"] <= 1e-10)
