@@ -220,9 +220,13 @@ int solve_impl(rsrr_problem* p, const rsrr_contour* c, const rsrr_params* prm, c
   RSRR_TRY(build_hankel(Amom, kS, K, 0, H, M, s));
   RSRR_TRY(build_hankel(Amom, kS, K, 1, Hs, M, s));
   std::vector<double> sigma;
-  RSRR_TRY(jacobi_svd(H, M, M, Uh, M, Wh, M, &sigma, ws, s, prm->hankel_tol));
+  int rH = 0;
+  // basis of range(H) down to a tenth of the truncation level
+  RSRR_TRY(hankel_svd(H, M, 0.1 * prm->hankel_tol, prm->hankel_tol, Uh, M, Wh, M, &sigma, &rH, ws, s));
+  if (rH == 0) return set_error(ST_ESINGULAR, "Hankel matrix is zero: no eigenvalue inside the contour");
+  sigma.resize(M, 0.0);   // directions outside the numerical range: zero
   res->hankel_sigma = sigma;
-  vlog("hankel svd M=%d %.3fs", M, now_s() - t0);
+  vlog("hankel svd M=%d rank %d %.3fs", M, rH, now_s() - t0);
   // gap count (eq. eq-gap), reading: zero tail excluded, smallest j on ties
   {
     const double floor_ = 10.0 * 1.1102230246251565e-16 * M * sigma[0];
@@ -236,7 +240,7 @@ int solve_impl(rsrr_problem* p, const rsrr_contour* c, const rsrr_params* prm, c
     info.n_gap = (best >= prm->tol_gap) ? bj : -1;
   }
   int m = 0;
-  for (int j = 0; j < M; ++j) if (sigma[j] > prm->hankel_tol * sigma[0]) ++m;
+  for (int j = 0; j < rH; ++j) if (sigma[j] > prm->hankel_tol * sigma[0]) ++m;
   info.m = m;
 
   // ---- A = V0^H H^< W0 S0^{-1}; eig; recovery

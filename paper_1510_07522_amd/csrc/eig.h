@@ -6,12 +6,20 @@
 
 namespace rsrr {
 
-// Singular value decomposition of the M x M matrix H (destroyed) by one-sided
-// Jacobi: H = U diag(sigma) W^H, sigma descending.  U, W: M x M outputs.
-// Columns whose norm falls below trunc * (largest column norm) are not
-// orthogonalised (0 = full accuracy for every singular value).
-int jacobi_svd(c128* H, long ldh, int M, c128* U, long ldu, c128* W, long ldw,
+// Singular value decomposition of the rows x cols matrix X (destroyed) by
+// one-sided block Jacobi: X = U diag(sigma) W^H, sigma descending (cols
+// values).  U: rows x cols, W: cols x cols.  Columns whose norm falls below
+// trunc * (largest column norm) are not orthogonalised (0 = full accuracy
+// for every singular value).
+int jacobi_svd(c128* X, long ldx, int rows, int cols, c128* U, long ldu, c128* W, long ldw,
                std::vector<double>* sigma, Arena& ws, hipStream_t s, double trunc = 0.0);
+
+// SVD of the M x M matrix H restricted to its numerical range: a pivoted
+// orthonormal basis Q1 (r columns, directions above basis_tol * sigma_1) and
+// one-sided Jacobi on H^H Q1.  H ~= Vh diag(sigma) Wh^H with Vh, Wh: M x r,
+// sigma: r values, descending.  H is not modified.
+int hankel_svd(const c128* H, int M, double basis_tol, double trunc, c128* Vh, long ldv, c128* Wh, long ldw,
+               std::vector<double>* sigma, int* r_out, Arena& ws, hipStream_t s);
 
 // Eigenvalues lam and eigenvectors V (columns, not normalised) of the general
 // m x m matrix A (destroyed: it ends in Schur form).

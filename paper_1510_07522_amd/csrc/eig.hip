@@ -14,43 +14,43 @@
 namespace rsrr {
 
 // ------------------------------------------------------------------- SVD
-// One-sided block Jacobi.  Workgroup i of a round takes the pair of column
-// blocks (a, c) of width JB given by the circle method over the blocks, forms
-// the Gram matrix G of those 2*JB columns, diagonalises G by cyclic two-sided
-// Jacobi in LDS (accumulated in V) and applies V to the columns of H and W.
-// A column pair (p, q) with inner product g, squared norms al, be is rotated
-// only if |g| > tol sqrt(al be) (relative criterion) and |g| > gfloor (the
-// absolute noise floor: rotations below it cannot move a singular value by
-// more than ~sqrt(gfloor)) and both squared norms exceed nfloor (columns below
-// the truncation level of the caller are not orthogonalised among themselves
-// or against others: they are dropped afterwards).  For |g| > 0 the rotation is: column q times
-// conj(g)/|g|, then the real rotation with t = sign(z)/(|z| + sqrt(1+z^2)),
+// One-sided block Jacobi.  A round pairs the column blocks (width JB) by the
+// circle method.  For every block pair the Gram matrix G of its 2*JB columns
+// is formed (partial sums over row slices, added in a fixed order), G is
+// diagonalised by cyclic two-sided Jacobi in LDS (accumulated in V), and V is
+// applied to the pair's columns of H and W, again by row slices, so a round
+// spreads over (pairs x slices) workgroups.  A column pair (p, q) with inner
+// product g and squared norms al, be is rotated only if |g| > tol sqrt(al be)
+// (relative criterion), |g| > gfloor (absolute noise floor: such rotations
+// cannot move a singular value by more than ~sqrt(gfloor)) and al, be > nfloor
+// (columns below the caller's truncation level are dropped afterwards and are
+// not orthogonalised).  For |g| > 0 the rotation is: column q times
+// conj(g)/|g|, then the real rotation t = sign(z)/(|z| + sqrt(1+z^2)),
 // z = (be - al)/(2|g|).  `counter` counts the block pairs that were rotated.
 constexpr int JB = 16, J2 = 2 * JB, JCH = 32;
-__global__ __launch_bounds__(256) void bjacobi_round_kernel(c128* H, long ldh, c128* W, long ldw, int M,
-                                                            int nbk, int round, double tol,
-                                                            double gfloor, double nfloor, int* counter) {
-  __shared__ c128 G[J2][J2 + 1];
-  __shared__ c128 V[J2][J2 + 1];
-  __shared__ c128 X[JCH][J2 + 1];
-  __shared__ double s_rc[J2 / 2], s_rs[J2 / 2];
-  __shared__ c128 s_ph[J2 / 2];
-  __shared__ int s_pp[J2 / 2], s_qq[J2 / 2];
-  __shared__ int s_flag;
-  const int tid = threadIdx.x;
-  const int i = blockIdx.x;
+constexpr int KSL = 16;   // row slices per block pair in the Gram and apply kernels
+
+// Global column of local column j (0 <= j < 2*JB) of block pair i in `round`
+// of the circle method over nbk blocks.
+__device__ inline int pair_col(int round, int nbk, int i, int j) {
   const int a = (round + i) % (nbk - 1);
   const int cb = (i == 0) ? nbk - 1 : (round - i + nbk - 1) % (nbk - 1);
-  // column index of local j
-  auto gcol = [&](int j) -> int { return (j < JB) ? a * JB + j : cb * JB + (j - JB); };
-  // ---- Gram G = X^H X over all rows
+  return (j < JB) ? a * JB + j : cb * JB + (j - JB);
+}
+
+// Partial Gram X^H X of block pair i = blockIdx.x over row slice ks = blockIdx.y.
+__global__ __launch_bounds__(256) void bj_gram_kernel(const c128* H, long ldh, int rows, int cols, int nbk,
+                                                      int round, int rows_per, c128* part) {
+  __shared__ c128 X[JCH][J2 + 1];
+  const int i = blockIdx.x, ks = blockIdx.y, tid = threadIdx.x;
   const int gi = tid / 8, gj0 = (tid % 8) * 4;
+  const int r_begin = ks * rows_per, r_end = min(rows, r_begin + rows_per);
   c128 acc[4] = {mk<double>(0, 0), mk<double>(0, 0), mk<double>(0, 0), mk<double>(0, 0)};
-  for (int r0 = 0; r0 < M; r0 += JCH) {
+  for (int r0 = r_begin; r0 < r_end; r0 += JCH) {
     for (int e = tid; e < JCH * J2; e += 256) {
       const int rr = e % JCH, j = e / JCH;
-      const int r = r0 + rr, c = gcol(j);
-      X[rr][j] = (r < M && c < M) ? H[r + (long)c * ldh] : mk<double>(0, 0);
+      const int r = r0 + rr, c = pair_col(round, nbk, i, j);
+      X[rr][j] = (r < r_end && c < cols) ? H[r + (long)c * ldh] : mk<double>(0, 0);
     }
     __syncthreads();
     for (int rr = 0; rr < JCH; ++rr) {
@@ -60,12 +60,32 @@ __global__ __launch_bounds__(256) void bjacobi_round_kernel(c128* H, long ldh, c
     }
     __syncthreads();
   }
+  c128* out = part + ((long)i * gridDim.y + ks) * (J2 * J2);
 #pragma unroll
-  for (int q = 0; q < 4; ++q) G[gi][gj0 + q] = acc[q];
-  for (int e = tid; e < J2 * J2; e += 256) V[e % J2][e / J2] = mk<double>((e % J2) == (e / J2) ? 1.0 : 0.0, 0);
+  for (int q = 0; q < 4; ++q) out[gi + (gj0 + q) * J2] = acc[q];
+}
+
+// Gram of block pair i (slices added in a fixed order), convergence test and
+// diagonalisation by cyclic two-sided Jacobi (circle method over the 2*JB
+// indices, at most 3 sweeps per visit; the outer sweeps finish the job).
+// Writes V (2*JB x 2*JB, column-major) and flag[i] = 1 if V is to be applied.
+__global__ __launch_bounds__(256) void bj_rotate_kernel(const c128* part, int nks, double tol, double gfloor,
+                                                        double nfloor, c128* Vout, int* flag, int* counter) {
+  __shared__ c128 G[J2][J2 + 1];
+  __shared__ c128 V[J2][J2 + 1];
+  __shared__ double s_rc[J2 / 2], s_rs[J2 / 2];
+  __shared__ c128 s_ph[J2 / 2];
+  __shared__ int s_pp[J2 / 2], s_qq[J2 / 2];
+  __shared__ int s_flag;
+  const int i = blockIdx.x, tid = threadIdx.x;
+  for (int e = tid; e < J2 * J2; e += 256) {
+    c128 g = mk<double>(0, 0);
+    for (int ks = 0; ks < nks; ++ks) g = g + part[((long)i * nks + ks) * (J2 * J2) + e];
+    G[e % J2][e / J2] = g;
+    V[e % J2][e / J2] = mk<double>((e % J2) == (e / J2) ? 1.0 : 0.0, 0);
+  }
   if (tid == 0) s_flag = 0;
   __syncthreads();
-  // ---- any pair off-diagonal above tol?
   for (int e = tid; e < J2 * J2; e += 256) {
     const int p = e % J2, q = e / J2;
     if (p < q) {
@@ -74,11 +94,14 @@ __global__ __launch_bounds__(256) void bjacobi_round_kernel(c128* H, long ldh, c
     }
   }
   __syncthreads();
-  if (!s_flag) return;
-  if (tid == 0) atomicAdd(counter, 1);
-  // ---- cyclic Jacobi on G (circle method over J2 indices), at most 3 sweeps
-  // per visit (the outer sweeps complete the convergence)
+  const int need = s_flag;
+  if (tid == 0) {
+    flag[i] = need;
+    if (need) atomicAdd(counter, 1);
+  }
+  if (!need) return;
   for (int sweep = 0; sweep < 3; ++sweep) {
+    __syncthreads();
     if (tid == 0) s_flag = 0;
     __syncthreads();
     for (int step = 0; step < J2 - 1; ++step) {
@@ -130,35 +153,47 @@ __global__ __launch_bounds__(256) void bjacobi_round_kernel(c128* H, long ldh, c
       }
       __syncthreads();
     }
-    if (!s_flag) break;
+    if (!s_flag) break;   // every thread reads s_flag before the reset above (barrier first)
   }
-  // ---- apply V to the 2*JB columns of H and of W
-  for (int pass = 0; pass < 2; ++pass) {
-    c128* Mx = pass == 0 ? H : W;
-    const long ld = pass == 0 ? ldh : ldw;
-    for (int r0 = 0; r0 < M; r0 += JCH) {
-      for (int e = tid; e < JCH * J2; e += 256) {
-        const int rr = e % JCH, j = e / JCH;
-        const int r = r0 + rr, c = gcol(j);
-        X[rr][j] = (r < M && c < M) ? Mx[r + (long)c * ld] : mk<double>(0, 0);
-      }
-      __syncthreads();
-      {   // 4 outputs per thread: row rr, columns j0 .. j0+3 (JCH * J2 = 4 * 256)
-        const int rr = tid / 8, j0 = (tid % 8) * 4;
-        c128 v[4] = {mk<double>(0, 0), mk<double>(0, 0), mk<double>(0, 0), mk<double>(0, 0)};
-        for (int l = 0; l < J2; ++l) {
-          const c128 x = X[rr][l];
+  c128* vo = Vout + (long)i * (J2 * J2);
+  for (int e = tid; e < J2 * J2; e += 256) vo[e] = V[e % J2][e / J2];
+}
+
+// Columns of block pair i = blockIdx.x times its V over row slice
+// ks = blockIdx.y, for H (blockIdx.z == 0, rowsH rows) or W (blockIdx.z == 1,
+// rowsW rows); both have `cols` columns.
+__global__ __launch_bounds__(256) void bj_apply_kernel(c128* H, long ldh, int rowsH, c128* W, long ldw,
+                                                       int rowsW, int cols, int nbk, int round, int rows_per,
+                                                       const c128* Vin, const int* flag) {
+  __shared__ c128 X[JCH][J2 + 1];
+  __shared__ c128 V[J2][J2 + 1];
+  const int i = blockIdx.x, ks = blockIdx.y, tid = threadIdx.x;
+  if (!flag[i]) return;
+  c128* Mx = blockIdx.z == 0 ? H : W;
+  const long ld = blockIdx.z == 0 ? ldh : ldw;
+  const int rows = blockIdx.z == 0 ? rowsH : rowsW;
+  for (int e = tid; e < J2 * J2; e += 256) V[e % J2][e / J2] = Vin[(long)i * (J2 * J2) + e];
+  const int r_begin = ks * rows_per, r_end = min(rows, r_begin + rows_per);
+  const int rr = tid / 8, j0 = (tid % 8) * 4;   // 4 outputs per thread (JCH * J2 = 4 * 256)
+  for (int r0 = r_begin; r0 < r_end; r0 += JCH) {
+    __syncthreads();
+    for (int e = tid; e < JCH * J2; e += 256) {
+      const int q = e % JCH, j = e / JCH;
+      const int r = r0 + q, c = pair_col(round, nbk, i, j);
+      X[q][j] = (r < r_end && c < cols) ? Mx[r + (long)c * ld] : mk<double>(0, 0);
+    }
+    __syncthreads();
+    c128 v[4] = {mk<double>(0, 0), mk<double>(0, 0), mk<double>(0, 0), mk<double>(0, 0)};
+    for (int l = 0; l < J2; ++l) {
+      const c128 x = X[rr][l];
 #pragma unroll
-          for (int q = 0; q < 4; ++q) v[q] = v[q] + x * V[l][j0 + q];
-        }
-        const int r = r0 + rr;
+      for (int q = 0; q < 4; ++q) v[q] = v[q] + x * V[l][j0 + q];
+    }
+    const int r = r0 + rr;
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          const int c = gcol(j0 + q);
-          if (r < M && c < M) Mx[r + (long)c * ld] = v[q];
-        }
-      }
-      __syncthreads();
+    for (int q = 0; q < 4; ++q) {
+      const int c = pair_col(round, nbk, i, j0 + q);
+      if (r < r_end && c < cols) Mx[r + (long)c * ld] = v[q];
     }
   }
 }
@@ -206,74 +241,89 @@ int set_identity(c128* X, long ldx, int m, hipStream_t s) {
   return ST_OK;
 }
 
-int jacobi_svd(c128* H, long ldh, int M, c128* U, long ldu, c128* W, long ldw,
+int jacobi_svd(c128* X, long ldx, int rows, int cols, c128* U, long ldu, c128* W, long ldw,
                std::vector<double>* sigma, Arena& ws, hipStream_t s, double trunc) {
-  if (M <= 0) return ST_OK;
-  c128* Wt = nullptr;
+  sigma->clear();
+  if (rows <= 0 || cols <= 0) return ST_OK;
   int* cnt = nullptr;
   double* sg = nullptr;
   int* perm = nullptr;
-  RSRR_TRY(ws.get<c128>("sv_W", (size_t)M * M, &Wt));
-  c128* const Wsave = Wt;
+  c128 *Wa = nullptr, *Wb = nullptr, *Xb = nullptr;
   RSRR_TRY(ws.get<int>("sv_cnt", 64, &cnt));
-  RSRR_TRY(ws.get<double>("sv_sig", M, &sg));
-  RSRR_TRY(ws.get<int>("sv_perm", M, &perm));
-  RSRR_TRY(set_identity(Wt, M, M, s));
-  const int Mp = M + (M & 1);
-  const double tol = 8.0 * 2.220446049250313e-16 * sqrt((double)M);
-  const int maxsweep = 40;
-  std::vector<int> hc(maxsweep, 0);
+  RSRR_TRY(ws.get<double>("sv_sig", cols, &sg));
+  RSRR_TRY(ws.get<int>("sv_perm", cols, &perm));
+  // X and the accumulated W ping-pong with Xb, Wb (columns re-sorted by
+  // decreasing norm at the start of every sweep)
+  RSRR_TRY(ws.get<c128>("sv_Wa", (size_t)cols * cols, &Wa));
+  RSRR_TRY(ws.get<c128>("sv_Wb", (size_t)cols * cols, &Wb));
+  RSRR_TRY(ws.get<c128>("sv_Xb", (size_t)rows * cols, &Xb));
+  RSRR_TRY(set_identity(Wa, cols, cols, s));
   RSRR_HIP(hipMemsetAsync(cnt, 0, 64 * sizeof(int), s));
-  int sweep = 0;
-  bool converged = (Mp < 2);
-  // absolute floor from the largest column norm
-  hipLaunchKernelGGL(col_norms_kernel, dim3(M), dim3(256), 0, s, H, ldh, M, M, sg);
+  const double u = 1.1102230246251565e-16;
+  const double tol = 16.0 * u * sqrt((double)rows);
+  const int maxsweep = 40;
+  // absolute floors from the largest column norm
+  std::vector<double> h0(cols);
+  hipLaunchKernelGGL(col_norms_kernel, dim3(cols), dim3(256), 0, s, X, ldx, rows, cols, sg);
   RSRR_LAUNCH_CHECK();
-  std::vector<double> h0(M);
-  RSRR_HIP(hipMemcpyAsync(h0.data(), sg, M * sizeof(double), hipMemcpyDeviceToHost, s));
+  RSRR_HIP(hipMemcpyAsync(h0.data(), sg, cols * sizeof(double), hipMemcpyDeviceToHost, s));
   RSRR_HIP(hipStreamSynchronize(s));
   double smax = 0;
   for (double v : h0) smax = std::max(smax, v);
-  const double fl = sqrt((double)M) * 2.220446049250313e-16 * smax;
+  const double fl = sqrt((double)rows) * 2.0 * u * smax;
   const double gfloor = fl * fl;
   const double nfloor = (trunc * smax) * (trunc * smax);
-  // block pairs: nbk blocks of JB columns (padded to an even count)
-  int nbk = (M + JB - 1) / JB;
+  // nbk blocks of JB columns (padded to an even count), paired by the circle method
+  int nbk = (cols + JB - 1) / JB;
   nbk += (nbk & 1);
-  // columns are kept sorted by decreasing norm at the start of every sweep
-  // (faster convergence on graded matrices); H and W ping-pong with Hb, Wb
-  c128 *Hb = nullptr, *Wb = nullptr;
-  RSRR_TRY(ws.get<c128>("sv_Hb", (size_t)M * M, &Hb));
-  RSRR_TRY(ws.get<c128>("sv_Wb", (size_t)M * M, &Wb));
-  c128* Hc = H;
-  long ldc = ldh;
-  std::vector<int> ord(M);
+  const int np = nbk / 2;
+  // row slices of the Gram / apply kernels (multiples of JCH rows)
+  const int rows_per = (int)(cdivl(cdivl(std::max(rows, cols), KSL), JCH) * JCH);
+  const int nks = (int)cdivl(std::max(rows, cols), rows_per);
+  c128 *part = nullptr, *Vr = nullptr;
+  int* flg = nullptr;
+  RSRR_TRY(ws.get<c128>("sv_part", (size_t)np * nks * J2 * J2, &part));
+  RSRR_TRY(ws.get<c128>("sv_V", (size_t)np * J2 * J2, &Vr));
+  RSRR_TRY(ws.get<int>("sv_flag", (size_t)np, &flg));
+  c128* Xc = X;
+  long ldc = ldx;
+  c128* Wc = Wa;
+  std::vector<int> ord(cols);
+  bool converged = false;
+  int sweep = 0;
   for (; sweep < maxsweep && !converged; ++sweep) {
-    hipLaunchKernelGGL(col_norms_kernel, dim3(M), dim3(256), 0, s, Hc, ldc, M, M, sg);
+    hipLaunchKernelGGL(col_norms_kernel, dim3(cols), dim3(256), 0, s, Xc, ldc, rows, cols, sg);
     RSRR_LAUNCH_CHECK();
-    RSRR_HIP(hipMemcpyAsync(h0.data(), sg, M * sizeof(double), hipMemcpyDeviceToHost, s));
+    RSRR_HIP(hipMemcpyAsync(h0.data(), sg, cols * sizeof(double), hipMemcpyDeviceToHost, s));
     RSRR_HIP(hipStreamSynchronize(s));
     std::iota(ord.begin(), ord.end(), 0);
     std::stable_sort(ord.begin(), ord.end(), [&](int x, int y) { return h0[x] > h0[y]; });
-    RSRR_HIP(hipMemcpyAsync(perm, ord.data(), M * sizeof(int), hipMemcpyHostToDevice, s));
-    const unsigned gq = (unsigned)cdivl((long)M * M, 256);
-    c128* Hn = (Hc == Hb) ? H : Hb;
-    const long ldn = (Hc == Hb) ? ldh : M;
-    c128* Wn = (Wt == Wb) ? Wsave : Wb;
-    hipLaunchKernelGGL(permute_cols_kernel, dim3(gq), dim3(256), 0, s, Hc, ldc, perm, nullptr, M, M, Hn, ldn);
+    RSRR_HIP(hipMemcpyAsync(perm, ord.data(), cols * sizeof(int), hipMemcpyHostToDevice, s));
+    c128* Xn = (Xc == Xb) ? X : Xb;
+    const long ldn = (Xc == Xb) ? ldx : rows;
+    c128* Wn = (Wc == Wb) ? Wa : Wb;
+    hipLaunchKernelGGL(permute_cols_kernel, dim3((unsigned)cdivl((long)rows * cols, 256)), dim3(256), 0, s, Xc,
+                       ldc, perm, nullptr, rows, cols, Xn, ldn);
     RSRR_LAUNCH_CHECK();
-    hipLaunchKernelGGL(permute_cols_kernel, dim3(gq), dim3(256), 0, s, Wt, (long)M, perm, nullptr, M, M, Wn, (long)M);
+    hipLaunchKernelGGL(permute_cols_kernel, dim3((unsigned)cdivl((long)cols * cols, 256)), dim3(256), 0, s, Wc,
+                       (long)cols, perm, nullptr, cols, cols, Wn, (long)cols);
     RSRR_LAUNCH_CHECK();
-    Hc = Hn;
+    Xc = Xn;
     ldc = ldn;
-    Wt = Wn;
-    if (nbk >= 2) {
+    Wc = Wn;
+    if (cols >= 2) {
+      // per round: np block pairs; each reads its 2*JB columns of X twice
+      // (Gram, apply) and of W once, and writes both once
       for (int r = 0; r < nbk - 1; ++r) {
-        // per round: nbk/2 block pairs; each reads its 2*JB columns of H three
-        // times (Gram, apply) and of W twice, and writes both once
-        KernelTimer kt("jacobi_block_round", s, 0.0, (nbk / 2) * 6.0 * J2 * M * sizeof(c128));
-        hipLaunchKernelGGL(bjacobi_round_kernel, dim3(nbk / 2), dim3(256), 0, s, Hc, ldc, Wt, (long)M, M,
-                           nbk, r, tol, gfloor, nfloor, cnt + (sweep % 64));
+        KernelTimer kt("jacobi_block_round", s, 0.0, np * J2 * (3.0 * rows + 2.0 * cols) * sizeof(c128));
+        hipLaunchKernelGGL(bj_gram_kernel, dim3(np, nks), dim3(256), 0, s, Xc, ldc, rows, cols, nbk, r, rows_per,
+                           part);
+        RSRR_LAUNCH_CHECK();
+        hipLaunchKernelGGL(bj_rotate_kernel, dim3(np), dim3(256), 0, s, part, nks, tol, gfloor, nfloor, Vr, flg,
+                           cnt + (sweep % 64));
+        RSRR_LAUNCH_CHECK();
+        hipLaunchKernelGGL(bj_apply_kernel, dim3(np, nks, 2), dim3(256), 0, s, Xc, ldc, rows, Wc, (long)cols, cols,
+                           cols, nbk, r, rows_per, Vr, flg);
         RSRR_LAUNCH_CHECK();
       }
     }
@@ -284,30 +334,66 @@ int jacobi_svd(c128* H, long ldh, int M, c128* U, long ldu, c128* W, long ldw,
     vlog("jacobi sweep %d: %d block pairs rotated", sweep, c);
   }
   if (!converged) return set_error(ST_ENOTCONV, "Jacobi SVD did not converge in %d sweeps", maxsweep);
-  hipLaunchKernelGGL(col_norms_kernel, dim3(M), dim3(256), 0, s, Hc, ldc, M, M, sg);
+  hipLaunchKernelGGL(col_norms_kernel, dim3(cols), dim3(256), 0, s, Xc, ldc, rows, cols, sg);
   RSRR_LAUNCH_CHECK();
-  std::vector<double> hs(M);
-  RSRR_HIP(hipMemcpyAsync(hs.data(), sg, M * sizeof(double), hipMemcpyDeviceToHost, s));
+  std::vector<double> hs(cols);
+  RSRR_HIP(hipMemcpyAsync(hs.data(), sg, cols * sizeof(double), hipMemcpyDeviceToHost, s));
   RSRR_HIP(hipStreamSynchronize(s));
-  std::vector<int> order(M);
+  std::vector<int> order(cols);
   std::iota(order.begin(), order.end(), 0);
   std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return hs[x] > hs[y]; });
-  sigma->resize(M);
-  std::vector<double> inv(M);
-  for (int j = 0; j < M; ++j) {
+  sigma->resize(cols);
+  std::vector<double> inv(cols);
+  for (int j = 0; j < cols; ++j) {
     (*sigma)[j] = hs[order[j]];
     inv[j] = hs[order[j]] > 0 ? 1.0 / hs[order[j]] : 0.0;
   }
   double* invd = nullptr;
-  RSRR_TRY(ws.get<double>("sv_inv", M, &invd));
-  RSRR_HIP(hipMemcpyAsync(perm, order.data(), M * sizeof(int), hipMemcpyHostToDevice, s));
-  RSRR_HIP(hipMemcpyAsync(invd, inv.data(), M * sizeof(double), hipMemcpyHostToDevice, s));
-  const unsigned g = (unsigned)cdivl((long)M * M, 256);
-  hipLaunchKernelGGL(permute_cols_kernel, dim3(g), dim3(256), 0, s, Hc, ldc, perm, invd, M, M, U, ldu);
+  RSRR_TRY(ws.get<double>("sv_inv", cols, &invd));
+  RSRR_HIP(hipMemcpyAsync(perm, order.data(), cols * sizeof(int), hipMemcpyHostToDevice, s));
+  RSRR_HIP(hipMemcpyAsync(invd, inv.data(), cols * sizeof(double), hipMemcpyHostToDevice, s));
+  hipLaunchKernelGGL(permute_cols_kernel, dim3((unsigned)cdivl((long)rows * cols, 256)), dim3(256), 0, s, Xc, ldc,
+                     perm, invd, rows, cols, U, ldu);
   RSRR_LAUNCH_CHECK();
-  hipLaunchKernelGGL(permute_cols_kernel, dim3(g), dim3(256), 0, s, Wt, M, perm, nullptr, M, M, W, ldw);
+  hipLaunchKernelGGL(permute_cols_kernel, dim3((unsigned)cdivl((long)cols * cols, 256)), dim3(256), 0, s, Wc,
+                     (long)cols, perm, nullptr, cols, cols, W, ldw);
   RSRR_LAUNCH_CHECK();
   RSRR_HIP(hipStreamSynchronize(s));
+  return ST_OK;
+}
+
+// SVD of the M x M Hankel matrix H by one-sided Jacobi preconditioned with a
+// column-pivoted orthonormal basis Q1 of range(H) (H P = Q1 R; pivoted
+// Cholesky of H^H H with a second deflation level, the same basis routine as
+// Alg. 2 Step 3):  Jacobi runs on X = H^H Q1 = P R^H, whose columns are far
+// closer to orthogonal than those of H, so far fewer sweeps are needed.
+// X J = Wh diag(sigma)  =>  H = (Q1 J) diag(sigma) Wh^H.
+static int svd_gemm(int opA, int opB, int M, int N, int K, const c128* A, long lda, const c128* B, long ldb,
+                    c128* C, long ldc, hipStream_t s) {
+  GemmBatch<double> g;
+  g.tag = "svd_gemm";
+  g.opA = opA; g.opB = opB; g.M = M; g.N = N; g.K = K;
+  g.alpha = mk<double>(1, 0); g.beta = mk<double>(0, 0);
+  g.A = A; g.lda = lda; g.B = B; g.ldb = ldb; g.C = C; g.ldc = ldc;
+  return gemm_batched<double>(g, s);
+}
+
+int hankel_svd(const c128* H, int M, double basis_tol, double trunc, c128* Vh, long ldv, c128* Wh, long ldw,
+               std::vector<double>* sigma, int* r_out, Arena& ws, hipStream_t s) {
+  *r_out = 0;
+  sigma->clear();
+  if (M <= 0) return ST_OK;
+  c128 *Q1 = nullptr, *Xh = nullptr, *J = nullptr;
+  RSRR_TRY(ws.get<c128>("hs_Q1", (size_t)M * M, &Q1));
+  int r = 0;
+  RSRR_TRY(ortho_impl(M, M, H, M, basis_tol, Q1, M, &r, ws, s));
+  if (r == 0) return ST_OK;
+  RSRR_TRY(ws.get<c128>("hs_X", (size_t)M * r, &Xh));
+  RSRR_TRY(ws.get<c128>("hs_J", (size_t)r * r, &J));
+  RSRR_TRY(svd_gemm(OP_C, OP_N, M, r, M, H, M, Q1, M, Xh, M, s));
+  RSRR_TRY(jacobi_svd(Xh, M, M, r, Wh, ldw, J, r, sigma, ws, s, trunc));
+  RSRR_TRY(svd_gemm(OP_N, OP_N, M, r, r, Q1, M, J, r, Vh, ldv, s));
+  *r_out = r;
   return ST_OK;
 }
 

@@ -100,6 +100,18 @@ def test_project_bem_chebyshev_matches_oracle(P):
 
 
 # ----------------------------------------------------- full solve (a1-a8)
+def check_hankel_sigma(out, ref, rel=1e-9):
+    # singular values of the block Hankel matrix (Alg. 1 Step 3): the leading
+    # ones (above 1e-3 sigma_1) to a relative tolerance; every one to an
+    # absolute error small against sigma_1 (the small ones sit near the
+    # rounding level of the moments on both sides)
+    sg, sr = np.asarray(out["hankel_sigma"]), np.asarray(ref["hankel_sigma"])
+    assert sg.shape == sr.shape
+    big = sr > 1e-3 * sr[0]
+    assert np.max(np.abs(sg[big] - sr[big]) / sr[big]) <= rel
+    assert np.max(np.abs(sg - sr)) <= 1e-11 * sr[0]
+
+
 def gpu_solve(P, prob, c, N, L, U, prec, **kw):
     h = P.Problem(prob)
     try:
@@ -120,6 +132,7 @@ def test_solve_c0_matches_oracle(P, prec, tol):
           info["t_project"], info["t_reduced"], info["t_residual"])
     assert info["n_eig"] == len(ref["lam"])
     assert info["n_wind"] == ref["n_wind"]
+    check_hankel_sigma(out, ref)
     scale = max(np.max(np.abs(ref["lam"])), 2.0)
     assert match_sets(out["lam"], ref["lam"]) <= tol * scale
     assert np.all(out["res"] <= 1e-10)
@@ -193,6 +206,8 @@ def test_solve_delay_large_reduced_problem_matches_oracle(P):
     print("n=256 delay: n_eig", info["n_eig"], "ref", len(ref["lam"]), "m", info["m"], "ref m", ref["m"],
           "times", info["t_reduced"])
     assert info["m"] > 128
+    assert abs(info["m"] - ref["m"]) <= 2
+    check_hankel_sigma(out, ref)
     assert info["n_eig"] == len(ref["lam"])
     assert match_sets(out["lam"], ref["lam"]) <= 1e-9 * 3.0
     assert np.all(out["res"] <= 1e-10)
