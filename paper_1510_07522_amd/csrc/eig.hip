@@ -175,6 +175,9 @@ __global__ __launch_bounds__(256) void bj_apply_kernel(c128* H, long ldh, int ro
   for (int e = tid; e < J2 * J2; e += 256) V[e % J2][e / J2] = Vin[(long)i * (J2 * J2) + e];
   const int r_begin = ks * rows_per, r_end = min(rows, r_begin + rows_per);
   const int rr = tid / 8, j0 = (tid % 8) * 4;   // 4 outputs per thread (JCH * J2 = 4 * 256)
+  int gc[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) gc[q] = pair_col(round, nbk, i, j0 + q);
   for (int r0 = r_begin; r0 < r_end; r0 += JCH) {
     __syncthreads();
     for (int e = tid; e < JCH * J2; e += 256) {
@@ -183,17 +186,21 @@ __global__ __launch_bounds__(256) void bj_apply_kernel(c128* H, long ldh, int ro
       X[q][j] = (r < r_end && c < cols) ? Mx[r + (long)c * ld] : mk<double>(0, 0);
     }
     __syncthreads();
-    c128 v[4] = {mk<double>(0, 0), mk<double>(0, 0), mk<double>(0, 0), mk<double>(0, 0)};
+    c128 v0 = mk<double>(0, 0), v1 = v0, v2 = v0, v3 = v0;
+#pragma unroll 4
     for (int l = 0; l < J2; ++l) {
       const c128 x = X[rr][l];
-#pragma unroll
-      for (int q = 0; q < 4; ++q) v[q] = v[q] + x * V[l][j0 + q];
+      v0 = v0 + x * V[l][j0];
+      v1 = v1 + x * V[l][j0 + 1];
+      v2 = v2 + x * V[l][j0 + 2];
+      v3 = v3 + x * V[l][j0 + 3];
     }
     const int r = r0 + rr;
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int c = pair_col(round, nbk, i, j0 + q);
-      if (r < r_end && c < cols) Mx[r + (long)c * ld] = v[q];
+    if (r < r_end) {
+      if (gc[0] < cols) Mx[r + (long)gc[0] * ld] = v0;
+      if (gc[1] < cols) Mx[r + (long)gc[1] * ld] = v1;
+      if (gc[2] < cols) Mx[r + (long)gc[2] * ld] = v2;
+      if (gc[3] < cols) Mx[r + (long)gc[3] * ld] = v3;
     }
   }
 }
@@ -315,16 +322,26 @@ int jacobi_svd(c128* X, long ldx, int rows, int cols, c128* U, long ldu, c128* W
       // per round: np block pairs; each reads its 2*JB columns of X twice
       // (Gram, apply) and of W once, and writes both once
       for (int r = 0; r < nbk - 1; ++r) {
-        KernelTimer kt("jacobi_block_round", s, 0.0, np * J2 * (3.0 * rows + 2.0 * cols) * sizeof(c128));
-        hipLaunchKernelGGL(bj_gram_kernel, dim3(np, nks), dim3(256), 0, s, Xc, ldc, rows, cols, nbk, r, rows_per,
-                           part);
-        RSRR_LAUNCH_CHECK();
-        hipLaunchKernelGGL(bj_rotate_kernel, dim3(np), dim3(256), 0, s, part, nks, tol, gfloor, nfloor, Vr, flg,
-                           cnt + (sweep % 64));
-        RSRR_LAUNCH_CHECK();
-        hipLaunchKernelGGL(bj_apply_kernel, dim3(np, nks, 2), dim3(256), 0, s, Xc, ldc, rows, Wc, (long)cols, cols,
-                           cols, nbk, r, rows_per, Vr, flg);
-        RSRR_LAUNCH_CHECK();
+        {
+          KernelTimer kt("jacobi_gram", s, 8.0 * np * J2 * J2 * (double)rows, np * J2 * (double)rows * sizeof(c128));
+          hipLaunchKernelGGL(bj_gram_kernel, dim3(np, nks), dim3(256), 0, s, Xc, ldc, rows, cols, nbk, r, rows_per,
+                             part);
+          RSRR_LAUNCH_CHECK();
+        }
+        {
+          KernelTimer kt("jacobi_rotate", s);
+          hipLaunchKernelGGL(bj_rotate_kernel, dim3(np), dim3(256), 0, s, part, nks, tol, gfloor, nfloor, Vr, flg,
+                             cnt + (sweep % 64));
+          RSRR_LAUNCH_CHECK();
+        }
+        {
+          // upper bound: every pair rotated (skipped pairs cost nothing)
+          KernelTimer kt("jacobi_apply", s, 8.0 * np * J2 * J2 * (double)(rows + cols),
+                         2.0 * np * J2 * (double)(rows + cols) * sizeof(c128));
+          hipLaunchKernelGGL(bj_apply_kernel, dim3(np, nks, 2), dim3(256), 0, s, Xc, ldc, rows, Wc, (long)cols,
+                             cols, cols, nbk, r, rows_per, Vr, flg);
+          RSRR_LAUNCH_CHECK();
+        }
       }
     }
     int c = 0;

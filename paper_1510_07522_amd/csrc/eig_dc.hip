@@ -143,7 +143,9 @@ static int newton_sign(int len, DcWork& w, Arena& ws, hipStream_t s, int* iters)
   const long ll = (long)len * len;
   const double sq = sqrt((double)len);
   LUWork<double> lw;
-  lw.n = len; lw.nb = 64; lw.batch = 1; lw.lda = len; lw.sA = ll;
+  // one matrix: the single-workgroup panel dominates, and a narrower panel
+  // re-reads fewer columns per micro-panel (measured best of 16 / 32 / 64)
+  lw.n = len; lw.nb = 32; lw.batch = 1; lw.lda = len; lw.sA = ll;
   lw.ipiv = w.ipiv; lw.dinv = w.dinv; lw.info = w.info;
   lw.tag = "dc_lu";
   bool scaling = true, schulz = false;

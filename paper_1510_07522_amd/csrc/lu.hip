@@ -372,8 +372,10 @@ __global__ void zero_int_kernel(int* p, int count) {
 
 template <typename R, int ROWS>
 static int launch_panel_rows(const LUWork<R>& w, int k, int nbe, hipStream_t s) {
-  constexpr int W = (sizeof(R) == 8) ? (ROWS == 1 ? 8 : 16 / ROWS)
-                                     : (ROWS <= 2 ? 16 : 32 / ROWS);
+  // micro-panel width: the ROWS x W register block must fit the 128 VGPRs a
+  // 1024-thread workgroup allows
+  constexpr int W = (sizeof(R) == 8) ? (ROWS == 1 ? 8 : 8 / ROWS)
+                                     : (ROWS == 1 ? 16 : 16 / ROWS);
   const long sD = (long)w.npanel() * 2 * w.nb * w.nb;
   cplx<R>* dslot = w.dinv + (long)(k / w.nb) * 2 * w.nb * w.nb;
   const std::string tn = std::string(w.tag) + "_panel";
