@@ -18,6 +18,7 @@ sampling nodes).
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -29,7 +30,76 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
-PEAK = {"fp32_mfma": 157.3e12, "fp64_mfma": 78.6e12, "hbm": 8.0e12}
+PEAK = {"fp32_mfma": 157.3e12, "fp64_mfma": 78.6e12, "fp64_valu": 78.6e12, "hbm": 8.0e12}
+
+# Which roofline bounds each timed kernel class (the tags the library's HIP-event
+# timers use), and the source file that holds it (for the traffic record).
+KERNEL_SRC = {"_panel": "lu.hip", "pchol_panel": "ortho.hip", "jacobi_": "eig.hip", "lu_permute": "lu.hip",
+              "assemble": "assemble.hip", "gemm": "gemm.hip", "_update": "gemm.hip", "_trsm": "gemm.hip",
+              "_solve": "gemm.hip"}
+
+
+def kernel_bound(tag: str):
+    """(bound, peak) for a kernel class, or None if it has no model."""
+    if tag.endswith("_panel"):
+        return "hbm", PEAK["hbm"]          # latency bound in practice; priced on its bytes
+    if tag.startswith("jacobi_gram") or tag.startswith("jacobi_apply"):
+        return "alu", PEAK["fp64_valu"]
+    if tag in ("lu_permute", "assemble_coeff"):
+        return "hbm", PEAK["hbm"]
+    if tag.endswith(("_update", "_trsm", "_solve", "gemm")):
+        return "mfma", PEAK["fp32_mfma"] if "c64" in tag else PEAK["fp64_mfma"]
+    return None
+
+
+def source_of(tag: str) -> str:
+    for k, v in KERNEL_SRC.items():
+        if k in tag:
+            return v
+    return ""
+
+
+def traffic_record(tag: str):
+    """HBM bytes per launch from the committed counter summary of this kernel
+    class, if the kernel's source file is unchanged since it was taken."""
+    path = os.path.join(ROOT, "profiles", f"traffic_{tag}.json")
+    if not os.path.exists(path):
+        return None
+    rec = json.load(open(path))
+    src = os.path.join(ROOT, "paper_1510_07522_amd", "csrc", rec.get("source", ""))
+    if not os.path.exists(src) or hashlib.sha256(open(src, "rb").read()).hexdigest() != rec.get("source_sha256"):
+        return None
+    return rec.get("hbm_bytes_per_launch")
+
+
+def roofline_of(tag: str, t: dict, steps: int):
+    bp = kernel_bound(tag)
+    if bp is None or t["launches"] == 0:
+        return None
+    bound, peak = bp
+    avg_s = t["ms"] / 1e3 / t["launches"]
+    if bound == "hbm":
+        work, unit, scale = t["bytes"] / t["launches"], "GB/s", 1e9
+    else:
+        work, unit, scale = t["flops"] / t["launches"], "TFLOP/s", 1e12
+    if work <= 0:
+        return None
+    ach = work / avg_s
+    return {"kernel": tag, "bound": bound, "achieved": ach / scale, "peak": peak / scale, "unit": unit,
+            "frac": ach / peak, "traffic": traffic_record(tag), "algorithmic_per_launch": work,
+            "launches_per_step": t["launches"] / steps, "avg_launch_ms": avg_s * 1e3,
+            "ms_per_step": t["ms"] / steps}
+
+
+def kernel_roofline(timers: dict, steps: int):
+    """Roofline of the modelled kernel class with the most device time, and of
+    the next few classes."""
+    rows = [r for r in (roofline_of(k, v, steps) for k, v in timers.items()) if r is not None]
+    rows.sort(key=lambda r: -r["ms_per_step"])
+    if not rows:
+        return None, []
+    return rows[0], [{k: r[k] for k in ("kernel", "bound", "frac", "achieved", "unit", "ms_per_step")}
+                     for r in rows[1:8]]
 
 
 def log(msg):
@@ -55,27 +125,6 @@ def workload(name: str):
         p, c, N, L, U = ni.config_c1(n=n)
         return dict(prob=p, contour=c, N=N, L=L, U=U, desc=f"delay NEP as c1 with n={n}")
     raise SystemExit(f"unknown workload {name}")
-
-
-def kernel_roofline(timers: dict, steps: int):
-    """Dominant kernel class by device time; its algorithmic rate vs peak."""
-    if not timers:
-        return None, None
-    name, t = max(timers.items(), key=lambda kv: kv[1]["ms"])
-    avg_s = t["ms"] / 1e3 / max(1, t["launches"])
-    if t["flops"] > 0:
-        peak = PEAK["fp32_mfma"] if "c64" in name else PEAK["fp64_mfma"]
-        ach = t["flops"] / max(1, t["launches"]) / avg_s
-        roof = {"kernel": name, "bound": "mfma", "achieved": ach / 1e12, "peak": peak / 1e12,
-                "unit": "TFLOP/s", "frac": ach / peak, "traffic": None,
-                "launches_per_step": t["launches"] / steps, "avg_launch_ms": avg_s * 1e3,
-                "share_of_step_device_ms": None}
-    else:
-        ach = t["bytes"] / max(1, t["launches"]) / avg_s
-        roof = {"kernel": name, "bound": "hbm", "achieved": ach / 1e9, "peak": PEAK["hbm"] / 1e9,
-                "unit": "GB/s", "frac": ach / PEAK["hbm"], "traffic": None,
-                "launches_per_step": t["launches"] / steps, "avg_launch_ms": avg_s * 1e3}
-    return name, roof
 
 
 def cpu_baseline(w, max_nodes: int, budget_s: float):
@@ -114,6 +163,9 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--sample-compare", type=int, default=3,
                     help="repetitions of the sampling stage alone in both precisions")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="only run a plain device-to-device copy of this many MiB 5 times (reference "
+                         "for scaling the FETCH_SIZE / WRITE_SIZE counters) and exit")
     a = ap.parse_args()
     if a.gpus != 1:
         print(json.dumps({"error": "this build runs on exactly one GPU; --gpus must be 1"}))
@@ -121,6 +173,15 @@ def main():
 
     import torch
     assert torch.cuda.is_available(), "bench.py needs a GPU"
+    if a.copy_calibration > 0:
+        nbytes = a.copy_calibration << 20
+        x = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda")
+        y = torch.empty_like(x)
+        for _ in range(5):
+            y.copy_(x)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_calibration_bytes_per_launch": nbytes, "launches": 5}))
+        return
     import paper_1510_07522_amd as P
 
     w = workload(a.workload)
@@ -160,10 +221,10 @@ def main():
     ms_step = elapsed / a.steps * 1e3
     samples_s = N * a.steps / elapsed
     eig_s = sum(n_eig) / elapsed
-    kname, roof = kernel_roofline(timers, a.steps)
+    roof, roof_next = kernel_roofline(timers, a.steps)
     dev_ms = sum(t["ms"] for t in timers.values()) / a.steps
     if roof is not None:
-        roof["share_of_timed_device_ms"] = timers[kname]["ms"] / a.steps / max(dev_ms, 1e-9)
+        roof["share_of_timed_device_ms"] = roof["ms_per_step"] / max(dev_ms, 1e-9)
 
     # sampling stage alone, both precisions (the c64 + refinement vs complex128 comparison)
     stage = {}
@@ -213,9 +274,12 @@ def main():
         "solve_info": {k: infos[-1][k] for k in ("k_S", "m", "n_wind", "n_gap", "n_eig",
                                                   "n_candidates", "ir_iters", "ir_fallback")},
         "sampling_stage": stage,
+        "sampling_c64ir_over_c128": (stage["c64_ir"]["samples_per_s"] / stage["c128"]["samples_per_s"]
+                                     if len(stage) == 2 else None),
         "kernel_ms_per_step": {k: v["ms"] / a.steps for k, v in sorted(
             timers.items(), key=lambda kv: -kv[1]["ms"])},
         "roofline": roof,
+        "roofline_next_kernels": roof_next,
         "cpu_baseline": cpu,
     }
     print(json.dumps(res))

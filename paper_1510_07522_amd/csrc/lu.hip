@@ -20,15 +20,46 @@ namespace rsrr {
 constexpr int PNT = 1024;           // panel workgroup size (16 waves)
 constexpr int MAXNB = 64;
 
+// Pivot search.  The magnitude |re|+|im| is compared through the bits of a
+// non-negative float (exact) or the high word of a non-negative double (a
+// pivot within a relative 2^-20 of the column maximum, which keeps the growth
+// bound of partial pivoting).  Maxima over a wave use DPP moves inside rows of
+// 16 lanes (quad xor 1, quad xor 2, half-row mirror, row mirror) and the four
+// row results by readlane: no LDS round trips.
+__device__ inline unsigned mag_bits(float v) { return __float_as_uint(v); }
+__device__ inline unsigned mag_bits(double v) {
+  return (unsigned)((unsigned long long)__double_as_longlong(v) >> 32);
+}
+__device__ inline unsigned row16_umax_all(unsigned v) {
+  v = max(v, (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0xB1, 0xF, 0xF, false));
+  v = max(v, (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0x4E, 0xF, 0xF, false));
+  v = max(v, (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0x141, 0xF, 0xF, false));
+  v = max(v, (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0x140, 0xF, 0xF, false));
+  return v;
+}
+__device__ inline unsigned wave_umax(unsigned v) {
+  v = row16_umax_all(v);
+  const unsigned a = __builtin_amdgcn_readlane((int)v, 0), b = __builtin_amdgcn_readlane((int)v, 16);
+  const unsigned c = __builtin_amdgcn_readlane((int)v, 32), d = __builtin_amdgcn_readlane((int)v, 48);
+  return max(max(a, b), max(c, d));
+}
+
+template <typename R> __device__ inline cplx<R> shfl_c(cplx<R> v, int src) {
+  return mk<R>(__shfl(v.re, src), __shfl(v.im, src));
+}
+
 template <typename R, int ROWS, int W>
 __global__ __launch_bounds__(PNT) void lu_panel_kernel(cplx<R>* A, long lda, long sA, int n,
                                                         int k, int nbe, int nb, int* ipiv,
                                                         cplx<R>* dinv, long sD, int* info) {
-  // per pivot step: wave arg-max -> every wave leader publishes its value and
-  // index, and the lane owning the wave's best row publishes that row, in LDS
-  // (one barrier); all threads then pick the winner and read the pivot row.
-  __shared__ R s_val[2][16];
-  __shared__ int s_idx[2][16];
+  // Thread tid owns rows c + tid + PNT*i (i < ROWS) of the current micro-panel
+  // of W columns, kept in registers.  Per pivot: wave arg-max -> every wave
+  // leader publishes its value and index, the lane owning the wave's best row
+  // publishes that row (one barrier); all threads then pick the winner.  The
+  // pivot loop is unrolled over the W columns so that every register access
+  // is static.
+  __shared__ unsigned s_val[2][16];
+  __shared__ int s_row[2][16];
   __shared__ cplx<R> s_cand[2][16][W];
   __shared__ cplx<R> s_crow[2][W];
   __shared__ cplx<R> s_L[W][W];
@@ -38,6 +69,10 @@ __global__ __launch_bounds__(PNT) void lu_panel_kernel(cplx<R>* A, long lda, lon
   __shared__ int t_row[2 * W], t_src[2 * W];
   __shared__ int s_cnt;
   __shared__ cplx<R> s_mv[2 * W][MAXNB];
+  // columns per load batch of the rank-W update: ROWS * UB complex values
+  // in flight per thread (16 VGPRs, two batches in flight)
+  constexpr int UB0 = 16 * 4 / (ROWS * (int)sizeof(cplx<R>)) > 0 ? 16 * 4 / (ROWS * (int)sizeof(cplx<R>)) : 1;
+  constexpr int UB = UB0 < 128 / W ? (UB0 < 16 ? UB0 : 16) : 128 / W;
 
   const int b = blockIdx.x;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -55,95 +90,85 @@ __global__ __launch_bounds__(PNT) void lu_panel_kernel(cplx<R>* A, long lda, lon
       for (int j = 0; j < W; ++j)
         a[i][j] = (r < n && j < w) ? Ab[r + (long)(c + j) * lda] : mk<R>(0, 0);
     }
-    for (int jj = 0; jj < w; ++jj) {
-      const int col = c + jj;
-      const int tc = (col - c) % PNT, ic = (col - c) / PNT;
-      R best = -1;
-      int bidx = 0x7fffffff;
 #pragma unroll
-      for (int i = 0; i < ROWS; ++i) {
-        const int r = c + tid + PNT * i;
-        cplx<R> v = mk<R>(0, 0);
+    for (int jj = 0; jj < W; ++jj) {
+      if (jj < w) {
+        const int col = c + jj;
+        unsigned bv = 0;
+        int brow = -1;
 #pragma unroll
-        for (int j = 0; j < W; ++j) if (j == jj) v = a[i][j];
-        if (r >= col && r < n) {
-          const R m = cabs1(v);
-          if (m > best) { best = m; bidx = r; }
+        for (int i = 0; i < ROWS; ++i) {
+          const int r = c + tid + PNT * i;
+          if (r >= col && r < n) {
+            const unsigned v = mag_bits(cabs1(a[i][jj]));
+            if (brow < 0 || v > bv) { bv = v; brow = r; }
+          }
         }
-      }
+        const unsigned wm = wave_umax(bv);
+        const unsigned long long hw = __ballot(brow >= 0 && bv == wm);
+        int wrow = -1;
+        if (hw) {
+          const int wl = __ffsll((long long)hw) - 1;
+          wrow = __builtin_amdgcn_readlane(brow, wl);
+          if (lane == wl) {
 #pragma unroll
-      for (int off = 32; off >= 1; off >>= 1) {
-        const R ob = __shfl_xor(best, off);
-        const int oi = __shfl_xor(bidx, off);
-        if (ob > best || (ob == best && oi < bidx)) { best = ob; bidx = oi; }
-      }
-      if (lane == 0) { s_val[parity][wave] = best; s_idx[parity][wave] = bidx; }
+            for (int i = 0; i < ROWS; ++i)
+              if (c + tid + PNT * i == wrow) {
 #pragma unroll
-      for (int i = 0; i < ROWS; ++i)
-        if (c + tid + PNT * i == bidx) {
-#pragma unroll
-          for (int j = 0; j < W; ++j) s_cand[parity][wave][j] = a[i][j];
+                for (int j = 0; j < W; ++j) s_cand[parity][wave][j] = a[i][j];
+              }
+          }
         }
-      if (tid == tc) {
+        if (lane == 0) { s_val[parity][wave] = wm; s_row[parity][wave] = wrow; }
+        // row col itself is row jj of the micro-panel: thread jj, register row 0
+        if (tid == jj) {
 #pragma unroll
-        for (int i = 0; i < ROWS; ++i)
-          if (i == ic)
-#pragma unroll
-            for (int j = 0; j < W; ++j) s_crow[parity][j] = a[i][j];
-      }
-      __syncthreads();
-      best = s_val[parity][0];
-      bidx = s_idx[parity][0];
-      int wb = 0;
-#pragma unroll
-      for (int q = 1; q < 16; ++q) {
-        const R ob = s_val[parity][q];
-        const int oi = s_idx[parity][q];
-        if (ob > best || (ob == best && oi < bidx)) { best = ob; bidx = oi; wb = q; }
-      }
-      const bool zero = !(best > R(0));
-      const int p = zero ? col : bidx;
-      if (tid == 0) {
-        pv[col] = p;
-        s_piv[jj] = p;
-        if (zero && info[b] == 0) info[b] = col + 1;
-      }
-      // pivot row: the winning candidate (or row col itself for a zero column)
-      const cplx<R>* prow = zero ? s_crow[parity] : s_cand[parity][wb];
-      if (p != col) {
-        const int tp = (p - c) % PNT, ip = (p - c) / PNT;
-        if (tid == tc) {
-#pragma unroll
-          for (int i = 0; i < ROWS; ++i)
-            if (i == ic)
-#pragma unroll
-              for (int j = 0; j < W; ++j) a[i][j] = prow[j];
+          for (int j = 0; j < W; ++j) s_crow[parity][j] = a[0][j];
         }
-        if (tid == tp) {
-#pragma unroll
-          for (int i = 0; i < ROWS; ++i)
-            if (i == ip)
-#pragma unroll
-              for (int j = 0; j < W; ++j) a[i][j] = s_crow[parity][j];
+        __syncthreads();
+        // workgroup maximum over the 16 wave results (row col is a candidate,
+        // so at least one wave has a row)
+        const unsigned vq = (lane < 16) ? s_val[parity][lane] : 0u;
+        const int rq = (lane < 16) ? s_row[parity][lane] : -1;
+        const unsigned gm = (unsigned)__builtin_amdgcn_readlane((int)row16_umax_all(vq), 0);
+        const unsigned long long hq = __ballot(rq >= 0 && vq == gm);
+        const int wb = __ffsll((long long)hq) - 1;
+        const bool zero = (gm == 0u);
+        const int p = zero ? col : __builtin_amdgcn_readlane(rq, wb);
+        if (tid == 0) {
+          pv[col] = p;
+          s_piv[jj] = p;
+          if (zero && info[b] == 0) info[b] = col + 1;
         }
-      }
-      cplx<R> piv = mk<R>(1, 0);
+        const cplx<R>* prow = zero ? s_crow[parity] : s_cand[parity][wb];
+        if (p != col) {
+          const int tp = (p - c) % PNT, ip = (p - c) / PNT;
+          if (tid == jj) {
 #pragma unroll
-      for (int j = 0; j < W; ++j) if (j == jj) piv = prow[j];
-      const cplx<R> inv = zero ? mk<R>(1, 0) : crecip(piv);
+            for (int j = 0; j < W; ++j) a[0][j] = prow[j];
+          }
+          if (tid == tp) {
 #pragma unroll
-      for (int i = 0; i < ROWS; ++i) {
-        const int r = c + tid + PNT * i;
-        if (r > col && r < n) {
-          cplx<R> l = mk<R>(0, 0);
+            for (int i = 0; i < ROWS; ++i)
+              if (i == ip) {
 #pragma unroll
-          for (int j = 0; j < W; ++j) if (j == jj) { a[i][j] = a[i][j] * inv; l = a[i][j]; }
-#pragma unroll
-          for (int j = 0; j < W; ++j)
-            if (j > jj) a[i][j] = a[i][j] - l * prow[j];
+                for (int j = 0; j < W; ++j) a[i][j] = s_crow[parity][j];
+              }
+          }
         }
+        const cplx<R> inv = zero ? mk<R>(1, 0) : crecip(prow[jj]);
+#pragma unroll
+        for (int i = 0; i < ROWS; ++i) {
+          const int r = c + tid + PNT * i;
+          if (r > col && r < n) {
+            const cplx<R> l = a[i][jj] * inv;
+            a[i][jj] = l;
+#pragma unroll
+            for (int j = jj + 1; j < W; ++j) a[i][j] = a[i][j] - l * prow[j];
+          }
+        }
+        parity ^= 1;
       }
-      parity ^= 1;
     }
     // ---- write the micro-panel back
 #pragma unroll
@@ -155,21 +180,34 @@ __global__ __launch_bounds__(PNT) void lu_panel_kernel(cplx<R>* A, long lda, lon
           if (j < w) Ab[r + (long)(c + j) * lda] = a[i][j];
     }
     // ---- this micro-panel's interchanges on the other columns of the panel,
-    // as one gather: touched rows and their final source rows
-    if (tid == 0) {
-      int cnt = 0;
-      for (int j = 0; j < w; ++j) { t_row[cnt] = c + j; t_src[cnt] = c + j; ++cnt; }
+    // as one gather.  Wave 0 composes the w swaps: lane e holds touched row
+    // t_row and its final source row t_src (registers, ballot to locate rows).
+    if (wave == 0) {
+      int my_row = (lane < w) ? c + lane : -1;
+      int my_src = my_row;
+      int cnt = w;
       for (int j = 0; j < w; ++j) {
         const int p = s_piv[j];
         if (p == c + j) continue;
-        int pos = -1;
-        for (int e = 0; e < cnt; ++e) if (t_row[e] == p) { pos = e; break; }
-        if (pos < 0) { pos = cnt; t_row[cnt] = p; t_src[cnt] = p; ++cnt; }
-        const int t = t_src[j];
-        t_src[j] = t_src[pos];
-        t_src[pos] = t;
+        int pos;
+        if (p < c + w) {
+          pos = p - c;
+        } else {
+          const unsigned long long m = __ballot(my_row == p);
+          if (m) {
+            pos = __ffsll((long long)m) - 1;
+          } else {
+            pos = cnt;
+            if (lane == cnt) { my_row = p; my_src = p; }
+            ++cnt;
+          }
+        }
+        const int sj = __shfl(my_src, j), sp = __shfl(my_src, pos);
+        if (lane == j) my_src = sp;
+        if (lane == pos) my_src = sj;
       }
-      s_cnt = cnt;
+      if (lane < cnt) { t_row[lane] = my_row; t_src[lane] = my_src; }
+      if (lane == 0) s_cnt = cnt;
     }
     __syncthreads();
     {
@@ -201,8 +239,8 @@ __global__ __launch_bounds__(PNT) void lu_panel_kernel(cplx<R>* A, long lda, lon
 #pragma unroll
         for (int j = 1; j < W; ++j)
 #pragma unroll
-          for (int l = 0; l < W; ++l)
-            if (l < j && j < w) x[j] = x[j] - s_L[j][l] * x[l];
+          for (int l = 0; l < j; ++l)
+            if (j < w) x[j] = x[j] - s_L[j][l] * x[l];
 #pragma unroll
         for (int j = 0; j < W; ++j) {
           s_U[j][tid] = x[j];
@@ -210,84 +248,91 @@ __global__ __launch_bounds__(PNT) void lu_panel_kernel(cplx<R>* A, long lda, lon
         }
       }
       __syncthreads();
-      // rank-w update of the remaining panel rows, 8 columns per batch so that
-      // the loads of a batch are in flight together
+      // rank-w update of the remaining panel columns: UB columns of all ROWS
+      // rows per load batch, the next batch loaded while this one is updated
+      cplx<R> nxt[ROWS][UB];
 #pragma unroll
       for (int i = 0; i < ROWS; ++i) {
         const int r = c + tid + PNT * i;
-        if (r >= rc0 && r < n) {
-          for (int t0 = 0; t0 < ncols; t0 += 8) {
-            cplx<R> acc[8];
 #pragma unroll
-            for (int u = 0; u < 8; ++u)
-              if (t0 + u < ncols) acc[u] = Ab[r + (long)(rc0 + t0 + u) * lda];
+        for (int u = 0; u < UB; ++u)
+          nxt[i][u] = (r >= rc0 && r < n && u < ncols) ? Ab[r + (long)(rc0 + u) * lda] : mk<R>(0, 0);
+      }
+      for (int t0 = 0; t0 < ncols; t0 += UB) {
+        cplx<R> acc[ROWS][UB];
 #pragma unroll
-            for (int u = 0; u < 8; ++u) {
-              if (t0 + u < ncols) {
+        for (int i = 0; i < ROWS; ++i)
 #pragma unroll
-                for (int j = 0; j < W; ++j)
-                  if (j < w) acc[u] = acc[u] - a[i][j] * s_U[j][t0 + u];
-              }
-            }
+          for (int u = 0; u < UB; ++u) acc[i][u] = nxt[i][u];
+        if (t0 + UB < ncols) {
 #pragma unroll
-            for (int u = 0; u < 8; ++u)
-              if (t0 + u < ncols) Ab[r + (long)(rc0 + t0 + u) * lda] = acc[u];
+          for (int i = 0; i < ROWS; ++i) {
+            const int r = c + tid + PNT * i;
+#pragma unroll
+            for (int u = 0; u < UB; ++u)
+              if (r >= rc0 && r < n && t0 + UB + u < ncols) nxt[i][u] = Ab[r + (long)(rc0 + t0 + UB + u) * lda];
           }
+        }
+#pragma unroll
+        for (int u = 0; u < UB; ++u) {
+          if (t0 + u < ncols) {
+            cplx<R> uc[W];
+#pragma unroll
+            for (int j = 0; j < W; ++j) uc[j] = s_U[j][t0 + u];
+#pragma unroll
+            for (int i = 0; i < ROWS; ++i) {
+#pragma unroll
+              for (int j = 0; j < W; ++j)
+                if (j < w) acc[i][u] = acc[i][u] - a[i][j] * uc[j];
+            }
+          }
+        }
+#pragma unroll
+        for (int i = 0; i < ROWS; ++i) {
+          const int r = c + tid + PNT * i;
+#pragma unroll
+          for (int u = 0; u < UB; ++u)
+            if (r >= rc0 && r < n && t0 + u < ncols) Ab[r + (long)(rc0 + t0 + u) * lda] = acc[i][u];
         }
       }
     }
     __syncthreads();
   }
 
-  // ---- invert the unit-lower and upper diagonal blocks (kept for solves)
+  // ---- inverses of the unit-lower and upper diagonal blocks (kept for the
+  // solves): waves 0-7 take the columns of L^{-1}, waves 8-15 those of U^{-1};
+  // lane i holds row i of the column, the substitution broadcasts by shuffle.
   for (int e = tid; e < nbe * nbe; e += PNT) {
     const int i = e % nbe, j = e / nbe;
     s_D[i][j] = Ab[k + i + (long)(k + j) * lda];
   }
   __syncthreads();
-  if (wave == 0) {
-    // L^{-1}: row sweep; X[i][j] (j < i) overwrites L[i][j]
-    const int j = lane;
-    for (int i = 1; i < nbe; ++i) {
-      cplx<R> v = mk<R>(0, 0);
-      if (j < i) {
-        v = s_D[i][j];
-        for (int l = j + 1; l < i; ++l) v = v + s_D[i][l] * s_D[l][j];
-        v = mk<R>(-v.re, -v.im);
-      }
-      wave_sync();
-      if (j < i) s_D[i][j] = v;
-      wave_sync();
-    }
-  } else if (wave == 1) {
-    // U^{-1}: bottom-up row sweep; X[i][j] (j >= i) overwrites U[i][j]
-    const int j = lane;
-    for (int i = nbe - 1; i >= 0; --i) {
-      const cplx<R> d = crecip(s_D[i][i]);
-      cplx<R> v = mk<R>(0, 0);
-      if (j > i && j < nbe) {
-        for (int l = i + 1; l <= j; ++l) v = v + s_D[i][l] * s_D[l][j];
-        v = mk<R>(-v.re, -v.im) * d;
-      }
-      wave_sync();
-      if (j > i && j < nbe) s_D[i][j] = v;
-      if (j == i) s_D[i][i] = d;
-      wave_sync();
-    }
-  }
-  __syncthreads();
   cplx<R>* DL = dinv + (long)b * sD;
   cplx<R>* DU = DL + (long)nb * nb;
-  for (int e = tid; e < nb * nb; e += PNT) {
-    const int i = e % nb, j = e / nb;
-    cplx<R> l = mk<R>(0, 0), u = mk<R>(0, 0);
-    if (i < nbe && j < nbe) {
-      if (i > j) l = s_D[i][j];
-      else if (i == j) { l = mk<R>(1, 0); u = s_D[i][i]; }
-      else u = s_D[i][j];
+  const int i = lane;
+  if (wave < 8) {
+    for (int j = wave; j < nb; j += 8) {
+      cplx<R> x = mk<R>(i == j ? 1 : 0, 0);
+      if (j < nbe) {
+        for (int l = j; l < nbe - 1; ++l) {
+          const cplx<R> xl = shfl_c(x, l);
+          if (i > l && i < nbe) x = x - s_D[i][l] * xl;
+        }
+      }
+      if (i < nb) DL[i + (long)j * nb] = (i >= j && i < nbe && j < nbe) ? x : mk<R>(0, 0);
     }
-    DL[e] = l;
-    DU[e] = u;
+  } else {
+    for (int j = wave - 8; j < nb; j += 8) {
+      cplx<R> x = mk<R>(i == j ? 1 : 0, 0);
+      if (j < nbe) {
+        for (int l = j; l >= 0; --l) {
+          if (i == l) x = x * crecip(s_D[l][l]);
+          const cplx<R> xl = shfl_c(x, l);
+          if (i < l) x = x - s_D[i][l] * xl;
+        }
+      }
+      if (i < nb) DU[i + (long)j * nb] = (i <= j && j < nbe) ? x : mk<R>(0, 0);
+    }
   }
 }
 
