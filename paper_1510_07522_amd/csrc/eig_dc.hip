@@ -194,9 +194,221 @@ static int newton_sign(int len, DcWork& w, Arena& ws, hipStream_t s, int* iters)
   return -1;
 }
 
+// ---------------------------------------------------------------- batched
+// The blocks of one level of the split tree are iterated together: block b is
+// stored at X + b * Lmax^2 with leading dimension Lmax (the largest block of
+// the batch) and padded with the identity, which every update keeps exact
+// (the padding is reset after each step), so the blocks never interact.
+__global__ __launch_bounds__(256) void pad_identity_kernel(c128* X, int Lmax, const int* lens) {
+  const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= (long)Lmax * Lmax) return;
+  const int b = blockIdx.y, len = lens[b];
+  const int r = (int)(e % Lmax), c = (int)(e / Lmax);
+  if (r < len && c < len) return;
+  X[(long)b * Lmax * Lmax + e] = mk<double>(r == c ? 1.0 : 0.0, 0);
+}
+
+// out[2*(b*nch + x)] = sum |X_b|^2 over FCOLS columns of block b (minus I if
+// sub_identity), out[... + 1] = sum |Y_b - X_b|^2 (when Y given)
+__global__ __launch_bounds__(256) void fro_partial_batched_kernel(const c128* X, const c128* Y, int Lmax,
+                                                                  const int* lens, int nch, double* out,
+                                                                  int sub_identity) {
+  __shared__ double r0[256], r1[256];
+  const int b = blockIdx.y, len = lens[b];
+  const long base = (long)b * Lmax * Lmax;
+  const int c0 = blockIdx.x * FCOLS;
+  double a = 0, d = 0;
+  for (int c = c0; c < min(len, c0 + FCOLS); ++c)
+    for (int r = threadIdx.x; r < len; r += 256) {
+      c128 x = X[base + r + (long)c * Lmax];
+      if (sub_identity && r == c) x.re -= 1.0;
+      a += abs2(x);
+      if (Y) d += abs2(Y[base + r + (long)c * Lmax] - x);
+    }
+  r0[threadIdx.x] = a;
+  r1[threadIdx.x] = d;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (threadIdx.x < o) { r0[threadIdx.x] += r0[threadIdx.x + o]; r1[threadIdx.x] += r1[threadIdx.x + o]; }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    out[2 * ((long)b * nch + blockIdx.x)] = r0[0];
+    out[2 * ((long)b * nch + blockIdx.x) + 1] = r1[0];
+  }
+}
+
+// Y_b <- coef[2b] X_b + coef[2b+1] Y_b
+__global__ __launch_bounds__(256) void axpby_batched_kernel(const c128* X, c128* Y, int Lmax, const double* coef) {
+  const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= (long)Lmax * Lmax) return;
+  const int b = blockIdx.y;
+  const double a = coef[2 * b], c = coef[2 * b + 1];
+  const long i = (long)b * Lmax * Lmax + e;
+  const c128 x = X[i], y = Y[i];
+  Y[i] = mk<double>(a * x.re + c * y.re, a * x.im + c * y.im);
+}
+
+struct DcBatch {
+  int nbk = 0, Lmax = 0;
+  std::vector<int> lens;
+  int* lens_dev = nullptr;
+  c128 *X = nullptr, *Y = nullptr, *LU = nullptr, *dinv = nullptr;
+  int *ipiv = nullptr, *info = nullptr;
+  double *part = nullptr, *coef = nullptr;
+  c128* diag = nullptr;
+};
+
+static int fro_batched(const c128* X, const c128* Y, DcBatch& bt, hipStream_t s, std::vector<double>* fx,
+                       std::vector<double>* fd, int sub_identity = 0) {
+  const int nch = (bt.Lmax + FCOLS - 1) / FCOLS;
+  hipLaunchKernelGGL(fro_partial_batched_kernel, dim3(nch, bt.nbk), dim3(256), 0, s, X, Y, bt.Lmax, bt.lens_dev,
+                     nch, bt.part, sub_identity);
+  RSRR_LAUNCH_CHECK();
+  std::vector<double> h(2 * (size_t)nch * bt.nbk);
+  RSRR_HIP(hipMemcpyAsync(h.data(), bt.part, h.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+  RSRR_HIP(hipStreamSynchronize(s));
+  fx->assign(bt.nbk, 0.0);
+  if (fd) fd->assign(bt.nbk, 0.0);
+  for (int b = 0; b < bt.nbk; ++b)
+    for (int x = 0; x < nch; ++x) {
+      (*fx)[b] += h[2 * ((size_t)b * nch + x)];
+      if (fd) (*fd)[b] += h[2 * ((size_t)b * nch + x) + 1];
+    }
+  return ST_OK;
+}
+
+static int axpby_batched(const c128* X, c128* Y, DcBatch& bt, const std::vector<double>& coef, hipStream_t s) {
+  RSRR_HIP(hipMemcpyAsync(bt.coef, coef.data(), coef.size() * sizeof(double), hipMemcpyHostToDevice, s));
+  const long ll = (long)bt.Lmax * bt.Lmax;
+  hipLaunchKernelGGL(axpby_batched_kernel, dim3(nblk(ll), bt.nbk), dim3(256), 0, s, X, Y, bt.Lmax, bt.coef);
+  RSRR_LAUNCH_CHECK();
+  return ST_OK;
+}
+
+static int pad_identity(c128* X, DcBatch& bt, hipStream_t s) {
+  const long ll = (long)bt.Lmax * bt.Lmax;
+  hipLaunchKernelGGL(pad_identity_kernel, dim3(nblk(ll), bt.nbk), dim3(256), 0, s, X, bt.Lmax, bt.lens_dev);
+  RSRR_LAUNCH_CHECK();
+  return ST_OK;
+}
+
+// Sign functions of the nbk matrices in bt.X (destroyed; results in bt.X),
+// the iteration of newton_sign run on all of them in lock step with a scaling
+// factor per matrix.  ok[b] = 0 if matrix b became singular or did not
+// converge (its slot is reset to the identity so it stays inert).
+static int newton_sign_batched(DcBatch& bt, hipStream_t s, std::vector<int>* ok, int* iters) {
+  const int nbk = bt.nbk, L = bt.Lmax;
+  const long ll = (long)L * L;
+  LUWork<double> lw;
+  lw.n = L; lw.nb = 32; lw.batch = nbk; lw.lda = L; lw.sA = ll;
+  lw.ipiv = bt.ipiv; lw.dinv = bt.dinv; lw.info = bt.info;
+  lw.tag = "dc_lu";
+  GemmBatch<double> g;
+  g.tag = "dc_gemm";
+  g.M = g.N = g.K = L;
+  g.lda = g.ldb = g.ldc = L;
+  g.sA = g.sB = g.sC = ll;
+  g.batch = nbk;
+  ok->assign(nbk, 1);
+  std::vector<int> done(nbk, 0);
+  std::vector<double> prev(nbk, 1e300), coef(2 * nbk), fx, fy, fn, fd;
+  bool scaling = true, schulz = false;
+  auto reset = [&](int b) -> int {
+    (*ok)[b] = 0;
+    done[b] = 1;
+    return set_identity(bt.X + (long)b * ll, L, L, s);
+  };
+  for (int it = 0; it < 100; ++it) {
+    if (schulz) {
+      g.alpha = ONE; g.beta = ZERO;
+      g.A = bt.X; g.B = bt.X; g.C = bt.Y;
+      RSRR_TRY(gemm_batched<double>(g, s));                         // X^2
+      std::vector<double> r2;
+      RSRR_TRY(fro_batched(bt.Y, nullptr, bt, s, &r2, nullptr, 1));
+      bool back = false, all = true;
+      for (int b = 0; b < nbk; ++b) {
+        if (done[b]) continue;
+        const double r = sqrt(r2[b] / bt.lens[b]);
+        // converged, or stagnating at the rounding level of a non-normal S
+        if (r < 1e-13 || (r < 1e-8 && r > 0.5 * prev[b])) { done[b] = 1; continue; }
+        prev[b] = r;
+        all = false;
+        if (!(r < 0.5)) back = true;
+      }
+      if (all) { *iters = it; return ST_OK; }
+      if (back) {
+        schulz = false;
+        std::fill(prev.begin(), prev.end(), 1e300);
+        continue;
+      }
+      g.A = bt.X; g.B = bt.Y; g.C = bt.LU;
+      RSRR_TRY(gemm_batched<double>(g, s));                         // X^3
+      for (int b = 0; b < nbk; ++b) { coef[2 * b] = -0.5; coef[2 * b + 1] = 1.5; }
+      RSRR_TRY(axpby_batched(bt.LU, bt.X, bt, coef, s));           // X <- 1.5 X - 0.5 X^3
+      RSRR_TRY(pad_identity(bt.X, bt, s));
+      continue;
+    }
+    RSRR_HIP(hipMemcpyAsync(bt.LU, bt.X, (size_t)nbk * ll * sizeof(c128), hipMemcpyDeviceToDevice, s));
+    lw.A = bt.LU;
+    for (int b = 0; b < nbk; ++b) RSRR_TRY(set_identity(bt.Y + (long)b * ll, L, L, s));
+    RSRR_TRY(lu_factor<double>(lw, s));
+    std::vector<int> info(nbk);
+    RSRR_HIP(hipMemcpyAsync(info.data(), bt.info, nbk * sizeof(int), hipMemcpyDeviceToHost, s));
+    RSRR_HIP(hipStreamSynchronize(s));
+    RSRR_TRY(lu_solve<double>(lw, bt.Y, L, ll, L, s));
+    RSRR_TRY(fro_batched(bt.X, nullptr, bt, s, &fx, nullptr));
+    RSRR_TRY(fro_batched(bt.Y, nullptr, bt, s, &fy, nullptr));
+    for (int b = 0; b < nbk; ++b) {
+      const double mu = (scaling && fx[b] > 0 && fy[b] > 0) ? sqrt(sqrt(fy[b]) / sqrt(fx[b])) : 1.0;
+      coef[2 * b] = 0.5 * mu;
+      coef[2 * b + 1] = 0.5 / mu;
+    }
+    RSRR_TRY(axpby_batched(bt.X, bt.Y, bt, coef, s));               // Y <- (mu X + Y/mu)/2
+    RSRR_TRY(pad_identity(bt.Y, bt, s));
+    RSRR_TRY(fro_batched(bt.Y, bt.X, bt, s, &fn, &fd));
+    std::swap(bt.X, bt.Y);
+    bool all = true;
+    for (int b = 0; b < nbk; ++b) {
+      if (done[b]) continue;
+      const double rel = sqrt(fd[b] / std::max(fn[b], 1e-300));
+      if (info[b] || !(rel == rel)) { RSRR_TRY(reset(b)); continue; }
+      if (!(rel < 1e-2)) all = false;
+    }
+    if (all) { scaling = false; schulz = true; std::fill(prev.begin(), prev.end(), 1e300); }
+    bool any = false;
+    for (int b = 0; b < nbk; ++b) any = any || !done[b];
+    if (!any) { *iters = it; return ST_OK; }
+  }
+  for (int b = 0; b < nbk; ++b)
+    if (!done[b]) (*ok)[b] = 0;
+  *iters = 100;
+  return ST_OK;
+}
+
+// Q = [Q1 Q2] (len x len, ld len): Q1 an orthonormal basis of range(P) (rank
+// k, P len x len with leading dimension ldp), Q2 of its orthogonal complement.
+// scratch: len x len, distinct from P and w.Q.
+static int bases_from_projector(const c128* P, long ldp, int len, int k, c128* Q, c128* scratch, DcWork& w,
+                                Arena& ws, hipStream_t s) {
+  c128* Q1 = Q;
+  c128* Q2 = Q + (long)k * len;
+  RSRR_TRY(basis_of_columns(P, ldp, len, len, k, Q1, len, ws, s));
+  RSRR_TRY(set_identity(scratch, len, len, s));
+  RSRR_TRY(zg(OP_N, OP_C, len, len, k, MONE, Q1, len, Q1, len, ONE, scratch, len, s));
+  RSRR_TRY(basis_of_columns(scratch, len, len, len, len - k, Q2, len, ws, s));
+  // one more orthogonalisation of Q2 against Q1 (classical Gram-Schmidt, then Cholesky-QR)
+  RSRR_TRY(zg(OP_C, OP_N, k, len - k, len, ONE, Q1, len, Q2, len, ZERO, w.tmp, k, s));
+  RSRR_TRY(zg(OP_N, OP_N, len, len - k, k, MONE, Q1, len, w.tmp, k, ONE, Q2, len, s));
+  RSRR_TRY((convert<double, double>(Q2, len, 0, scratch, len, 0, len, len - k, 1, s)));
+  RSRR_TRY(basis_of_columns(scratch, len, len, len - k, len - k, Q2, len, ws, s));
+  return ST_OK;
+}
+
 // Splits the diagonal block B = T[off.., off..] (len x len).  On success Q
 // (len x len, ld len) holds [Q1 Q2] and *k the size of the leading block.
-static int split_block(const c128* B, long ldb, int len, DcWork& w, Arena& ws, hipStream_t s, int* k_out) {
+static int split_block(const c128* B, long ldb, int len, DcWork& w, Arena& ws, hipStream_t s, int* k_out,
+                       int first_attempt = 0) {
   *k_out = 0;
   std::vector<c128> d;
   RSRR_TRY(host_diag(B, ldb, len, w, s, &d));
@@ -206,7 +418,7 @@ static int split_block(const c128* B, long ldb, int len, DcWork& w, Arena& ws, h
   si /= len;
   const long ll = (long)len * len;
   int k = 0;
-  for (int attempt = 0; attempt < 4 && (k <= 0 || k >= len); ++attempt) {
+  for (int attempt = first_attempt; attempt < 4 && (k <= 0 || k >= len); ++attempt) {
     // attempts: vertical line through the mean, horizontal line, then nudged lines
     const bool vert = (attempt % 2 == 0);
     const double nudge = (attempt >= 2) ? 1e-3 * (1 + sqrt(sr * sr + si * si)) : 0.0;
@@ -228,18 +440,7 @@ static int split_block(const c128* B, long ldb, int len, DcWork& w, Arena& ws, h
     vlog("dc split len=%d attempt %d: %d newton its, k=%d (trace %.6f)", len, attempt, its, k, tr);
   }
   if (k <= 0 || k >= len) return ST_OK;
-  // Q1 = range(P), Q2 = orthogonal complement of range(Q1)
-  c128* Q1 = w.Q;
-  c128* Q2 = w.Q + (long)k * len;
-  RSRR_TRY(basis_of_columns(w.X, len, len, len, k, Q1, len, ws, s));
-  RSRR_TRY(set_identity(w.Y, len, len, s));
-  RSRR_TRY(zg(OP_N, OP_C, len, len, k, MONE, Q1, len, Q1, len, ONE, w.Y, len, s));
-  RSRR_TRY(basis_of_columns(w.Y, len, len, len, len - k, Q2, len, ws, s));
-  // one more orthogonalisation of Q2 against Q1 (classical Gram-Schmidt, then Cholesky-QR)
-  RSRR_TRY(zg(OP_C, OP_N, k, len - k, len, ONE, Q1, len, Q2, len, ZERO, w.tmp, k, s));
-  RSRR_TRY(zg(OP_N, OP_N, len, len - k, k, MONE, Q1, len, w.tmp, k, ONE, Q2, len, s));
-  RSRR_TRY((convert<double, double>(Q2, len, 0, w.Y, len, 0, len, len - k, 1, s)));
-  RSRR_TRY(basis_of_columns(w.Y, len, len, len - k, len - k, Q2, len, ws, s));
+  RSRR_TRY(bases_from_projector(w.X, len, len, k, w.Q, w.Y, w, ws, s));
   *k_out = k;
   return ST_OK;
 }
@@ -289,19 +490,10 @@ int eig_dc(c128* A, long lda, int m, std::vector<cd>* lam, c128* V, long ldv, Ar
   RSRR_TRY(ws.get<double>("dc_part", 2 * (size_t)(m / FCOLS + 2), &w.part));
   RSRR_TRY(set_identity(Z, m, m, s));
   struct Blk { int off, len; };
-  std::vector<Blk> stack{{0, m}}, leaves;
-  while (!stack.empty()) {
-    const Blk b = stack.back();
-    stack.pop_back();
-    if (b.len <= DC_LEAF) { leaves.push_back(b); continue; }
-    int k = 0;
+  std::vector<Blk> level{{0, m}}, leaves;
+  // block b of T split into k + (len - k) with the bases in w.Q
+  auto finish_split = [&](const Blk& b, int k, std::vector<Blk>& next) -> int {
     c128* B = A + b.off + (long)b.off * lda;
-    RSRR_TRY(split_block(B, lda, b.len, w, ws, s, &k));
-    if (k <= 0 || k >= b.len) {
-      if (b.len > 512) return set_error(ST_ENOTCONV, "divide and conquer: no split of a %d block", b.len);
-      leaves.push_back(b);
-      continue;
-    }
     RSRR_TRY(apply_block(A, lda, m, Z, m, b.off, b.len, w.Q, b.len, w, s, true));
     double f_all = 0, f_low = 0;
     RSRR_TRY(fro_sums(B, nullptr, lda, b.len, w, s, &f_all, nullptr));
@@ -324,8 +516,91 @@ int eig_dc(c128* A, long lda, int m, std::vector<cd>* lam, c128* V, long ldv, Ar
     }
     vlog("dc block off=%d len=%d -> %d + %d, ||B21||/||B|| = %.2e", b.off, b.len, k, b.len - k,
          sqrt(f_low / std::max(f_all, 1e-300)));
-    stack.push_back({b.off + k, b.len - k});
-    stack.push_back({b.off, k});
+    next.push_back({b.off, k});
+    next.push_back({b.off + k, b.len - k});
+    return ST_OK;
+  };
+  // the split tree level by level; the blocks of a level (largest first, as
+  // many as fit the m x m work buffers) share one batched sign iteration
+  while (!level.empty()) {
+    std::vector<Blk> big, next;
+    for (const Blk& b : level) (b.len <= DC_LEAF ? leaves : big).push_back(b);
+    std::sort(big.begin(), big.end(), [](const Blk& x, const Blk& y) { return x.len > y.len; });
+    for (size_t g0 = 0; g0 < big.size();) {
+      const int L = big[g0].len;
+      const long ll = (long)L * L;
+      const size_t cnt = std::min(std::max<size_t>(1, (size_t)(mm / ll)), big.size() - g0);
+      DcBatch bt;
+      bt.nbk = (int)cnt;
+      bt.Lmax = L;
+      bt.X = w.X; bt.Y = w.Y; bt.LU = w.LU;
+      const int nch = (L + FCOLS - 1) / FCOLS;
+      RSRR_TRY(ws.get<int>("dcb_lens", cnt, &bt.lens_dev));
+      RSRR_TRY(ws.get<c128>("dcb_dinv", LUWork<double>::dinv_elems(L, 32, (int)cnt), &bt.dinv));
+      RSRR_TRY(ws.get<int>("dcb_ipiv", cnt * (size_t)L, &bt.ipiv));
+      RSRR_TRY(ws.get<int>("dcb_info", cnt, &bt.info));
+      RSRR_TRY(ws.get<double>("dcb_part", 2 * cnt * (size_t)nch, &bt.part));
+      RSRR_TRY(ws.get<double>("dcb_coef", 2 * cnt, &bt.coef));
+      RSRR_TRY(ws.get<c128>("dcb_diag", cnt * (size_t)L, &bt.diag));
+      for (size_t i = 0; i < cnt; ++i) {
+        const Blk& b = big[g0 + i];
+        bt.lens.push_back(b.len);
+        // vertical line through the mean of the block's diagonal
+        std::vector<c128> d;
+        const c128* B = A + b.off + (long)b.off * lda;
+        RSRR_TRY(host_diag(B, lda, b.len, w, s, &d));
+        double sr = 0;
+        for (int q = 0; q < b.len; ++q) sr += d[q].re;
+        sr /= b.len;
+        hipLaunchKernelGGL(shift_copy_kernel, dim3(nblk((long)b.len * b.len)), dim3(256), 0, s, B, lda,
+                           bt.X + (long)i * ll, (long)L, b.len, mk<double>(sr, 0), mk<double>(1, 0));
+        RSRR_LAUNCH_CHECK();
+      }
+      RSRR_HIP(hipMemcpyAsync(bt.lens_dev, bt.lens.data(), cnt * sizeof(int), hipMemcpyHostToDevice, s));
+      RSRR_TRY(pad_identity(bt.X, bt, s));
+      std::vector<int> ok;
+      int its = 0;
+      RSRR_TRY(newton_sign_batched(bt, s, &ok, &its));
+      std::vector<int> ks(cnt, 0);
+      for (size_t i = 0; i < cnt; ++i)
+        if (ok[i]) {
+          hipLaunchKernelGGL(projector_kernel, dim3(nblk((long)bt.lens[i] * bt.lens[i])), dim3(256), 0, s,
+                             bt.X + (long)i * ll, (long)L, bt.lens[i], bt.diag + (long)i * L);
+          RSRR_LAUNCH_CHECK();
+        }
+      std::vector<c128> pd(cnt * (size_t)L);
+      RSRR_HIP(hipMemcpyAsync(pd.data(), bt.diag, pd.size() * sizeof(c128), hipMemcpyDeviceToHost, s));
+      RSRR_HIP(hipStreamSynchronize(s));
+      for (size_t i = 0; i < cnt; ++i) {
+        if (!ok[i]) continue;
+        double tr = 0;
+        for (int q = 0; q < bt.lens[i]; ++q) tr += pd[i * (size_t)L + q].re;
+        ks[i] = (int)std::lround(tr);
+      }
+      vlog("dc level batch: %d blocks up to %d, %d newton its", (int)cnt, L, its);
+      // successful splits first: their projectors live in bt.X
+      for (size_t i = 0; i < cnt; ++i) {
+        const Blk& b = big[g0 + i];
+        if (ks[i] <= 0 || ks[i] >= b.len) continue;
+        RSRR_TRY(bases_from_projector(bt.X + (long)i * ll, L, b.len, ks[i], w.Q, w.LU, w, ws, s));
+        RSRR_TRY(finish_split(b, ks[i], next));
+      }
+      // the others: one block at a time, from the horizontal line on
+      for (size_t i = 0; i < cnt; ++i) {
+        const Blk& b = big[g0 + i];
+        if (ks[i] > 0 && ks[i] < b.len) continue;
+        int k = 0;
+        RSRR_TRY(split_block(A + b.off + (long)b.off * lda, lda, b.len, w, ws, s, &k, 1));
+        if (k <= 0 || k >= b.len) {
+          if (b.len > 512) return set_error(ST_ENOTCONV, "divide and conquer: no split of a %d block", b.len);
+          leaves.push_back(b);
+          continue;
+        }
+        RSRR_TRY(finish_split(b, k, next));
+      }
+      g0 += cnt;
+    }
+    level.swap(next);
   }
   // ---- leaves: Schur forms of the diagonal blocks, all at once
   const int nl = (int)leaves.size();
