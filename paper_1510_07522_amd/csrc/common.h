@@ -86,4 +86,28 @@ __device__ inline void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// Pivot searches.  A non-negative magnitude is compared through the bits of a
+// non-negative float (exact) or the high word of a non-negative double (a
+// pivot within a relative 2^-20 of the column maximum, which keeps the growth
+// bound of partial pivoting).  Maxima over a wave use DPP moves inside rows of
+// 16 lanes (quad xor 1, quad xor 2, half-row mirror, row mirror) and the four
+// row results by readlane: no LDS round trips.
+__device__ inline unsigned mag_bits(float v) { return __float_as_uint(v); }
+__device__ inline unsigned mag_bits(double v) {
+  return (unsigned)((unsigned long long)__double_as_longlong(v) >> 32);
+}
+__device__ inline unsigned row16_umax_all(unsigned v) {
+  v = max(v, (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0xB1, 0xF, 0xF, false));
+  v = max(v, (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0x4E, 0xF, 0xF, false));
+  v = max(v, (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0x141, 0xF, 0xF, false));
+  v = max(v, (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0x140, 0xF, 0xF, false));
+  return v;
+}
+__device__ inline unsigned wave_umax(unsigned v) {
+  v = row16_umax_all(v);
+  const unsigned a = __builtin_amdgcn_readlane((int)v, 0), b = __builtin_amdgcn_readlane((int)v, 16);
+  const unsigned c = __builtin_amdgcn_readlane((int)v, 32), d = __builtin_amdgcn_readlane((int)v, 48);
+  return max(max(a, b), max(c, d));
+}
+
 }  // namespace rsrr

@@ -19,55 +19,63 @@
 namespace rsrr {
 
 constexpr int PCT = 1024;     // threads of the pivoted-Cholesky panel kernel
-constexpr int PBS = 64;       // block size
+constexpr int PBS = 64;       // block size of the triangular solves
+constexpr int PCB = 16;       // columns per pivoted-Cholesky panel
+constexpr int PMAX = 8192;    // largest Gram matrix (the Schur-complement diagonal lives in LDS)
 
 // One block of the right-looking pivoted Cholesky, in place on G (m x m, both
 // triangles stored).  Columns j0 .. j0+jb-1 of L are written to the lower part
-// of G.  d holds the diagonal of the current Schur complement, perm the
-// symmetric permutation.  Stops at the first pivot <= tol (rank -> *rank).
+// of G.  d holds the diagonal of the current Schur complement (kept in LDS
+// while the block is factored), perm the symmetric permutation.  Stops at the
+// first pivot <= tol (rank -> *rank).  The pivot is the largest remaining
+// diagonal entry (compared through the high word of the double, so within a
+// relative 2^-20 of the maximum), found with DPP wave maxima.
 __global__ __launch_bounds__(PCT) void pchol_panel_kernel(c128* G, long ldg, int m, int j0, int jb,
                                                           int* perm, double* d, double tol,
                                                           int pivot, int* rank) {
-  __shared__ double s_v[16];
-  __shared__ int s_i[16];
-  __shared__ c128 s_lj[PBS];
+  __shared__ double s_d[PMAX];
+  __shared__ unsigned s_val[16];
+  __shared__ int s_row[16];
+  __shared__ c128 s_lj[PCB];
   __shared__ int s_stop;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   if (j0 == 0) {
     for (int i = tid; i < m; i += PCT) {
-      d[i] = G[i + (long)i * ldg].re;
+      s_d[i] = G[i + (long)i * ldg].re;
       perm[i] = i;
     }
-    __syncthreads();
+  } else {
+    for (int i = j0 + tid; i < m; i += PCT) s_d[i] = d[i];
   }
   if (tid == 0) s_stop = 0;
+  __syncthreads();
+  int jdone = jb;
   for (int jj = 0; jj < jb; ++jj) {
     const int j = j0 + jj;
     int p = j;
-    double best = d[j];
+    double best = s_d[j];
     if (pivot) {
-      best = -1.0;
-      int bi = 0x7fffffff;
+      unsigned bv = 0;
+      int brow = -1;
       for (int i = j + tid; i < m; i += PCT) {
-        const double v = d[i];
-        if (v > best) { best = v; bi = i; }
+        const unsigned v = mag_bits(fmax(s_d[i], 0.0));
+        if (brow < 0 || v > bv) { bv = v; brow = i; }
       }
-      for (int off = 32; off >= 1; off >>= 1) {
-        const double ob = __shfl_xor(best, off);
-        const int oi = __shfl_xor(bi, off);
-        if (ob > best || (ob == best && oi < bi)) { best = ob; bi = oi; }
-      }
-      if (lane == 0) { s_v[wave] = best; s_i[wave] = bi; }
+      const unsigned wm = wave_umax(bv);
+      const unsigned long long hw = __ballot(brow >= 0 && bv == wm);
+      const int wrow = hw ? __builtin_amdgcn_readlane(brow, __ffsll((long long)hw) - 1) : -1;
+      if (lane == 0) { s_val[wave] = wm; s_row[wave] = wrow; }
       __syncthreads();
-      best = s_v[0];
-      bi = s_i[0];
-      for (int q = 1; q < 16; ++q)
-        if (s_v[q] > best || (s_v[q] == best && s_i[q] < bi)) { best = s_v[q]; bi = s_i[q]; }
-      p = bi;
+      const unsigned vq = (lane < 16) ? s_val[lane] : 0u;
+      const int rq = (lane < 16) ? s_row[lane] : -1;
+      const unsigned gm = (unsigned)__builtin_amdgcn_readlane((int)row16_umax_all(vq), 0);
+      const unsigned long long hq = __ballot(rq >= 0 && vq == gm);
+      p = __builtin_amdgcn_readlane(rq, __ffsll((long long)hq) - 1);
+      best = s_d[p];
     }
-    if (!(best > tol)) {                       // rank found
+    if (!(best > tol)) {                       // rank found (uniform decision)
       if (tid == 0) { *rank = j; s_stop = 1; }
-      __syncthreads();
+      jdone = jj;
       break;
     }
     if (p != j) {
@@ -83,28 +91,30 @@ __global__ __launch_bounds__(PCT) void pchol_panel_kernel(c128* G, long ldg, int
         G[r + (long)p * ldg] = a;
       }
       if (tid == 0) {
-        const double t = d[j]; d[j] = d[p]; d[p] = t;
+        const double t = s_d[j]; s_d[j] = s_d[p]; s_d[p] = t;
         const int q = perm[j]; perm[j] = perm[p]; perm[p] = q;
       }
       __syncthreads();
     }
-    const double ljj = sqrt(d[j]);
-    for (int l = tid; l < jj; l += PCT) s_lj[l] = G[j + (long)(j0 + l) * ldg];
+    const double ljj = sqrt(s_d[j]);
+    if (tid < jj) s_lj[tid] = G[j + (long)(j0 + tid) * ldg];
     __syncthreads();
     for (int i = j + 1 + tid; i < m; i += PCT) {
       c128 v = G[i + (long)j * ldg];
       for (int l = 0; l < jj; ++l) v = v - mulc(G[i + (long)(j0 + l) * ldg], s_lj[l]);
       v = (1.0 / ljj) * v;
       G[i + (long)j * ldg] = v;
-      d[i] -= abs2(v);
+      s_d[i] -= abs2(v);
     }
     if (tid == 0) {
       G[j + (long)j * ldg] = mk<double>(ljj, 0);
-      d[j] = 0.0;
+      s_d[j] = 0.0;
     }
     __syncthreads();
   }
-  if (tid == 0 && !s_stop) *rank = j0 + jb;
+  __syncthreads();
+  for (int i = j0 + tid; i < m; i += PCT) d[i] = s_d[i];
+  if (tid == 0 && !s_stop) *rank = j0 + jdone;
 }
 
 // Inverts the diagonal blocks (bs x bs, lower triangular, non-unit) of L, one
@@ -233,9 +243,10 @@ static int pchol(c128* G, long ldg, int m, int maxrank, double tol, bool pivot, 
   int* rk = nullptr;
   RSRR_TRY(ws.get<double>("pc_d", m, &d));
   RSRR_TRY(ws.get<int>("pc_rank", 1, &rk));
+  if (m > PMAX) return set_error(ST_EINVAL, "pivoted Cholesky: Gram matrix of order %d > %d", m, PMAX);
   int rank = 0;
-  for (int j0 = 0; j0 < maxrank; j0 += PBS) {
-    const int jb = std::min(PBS, maxrank - j0);
+  for (int j0 = 0; j0 < maxrank; j0 += PCB) {
+    const int jb = std::min(PCB, maxrank - j0);
     KernelTimer kt("pchol_panel", s, 8.0 * (double)m * jb * jb / 2, 16.0 * 4 * (double)m * jb);
     hipLaunchKernelGGL(pchol_panel_kernel, dim3(1), dim3(PCT), 0, s, G, ldg, m, j0, jb, perm, d,
                        tol, pivot ? 1 : 0, rk);
