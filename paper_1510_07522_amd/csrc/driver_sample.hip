@@ -150,6 +150,7 @@ int sample_impl(rsrr_problem* p, const rsrr_contour* c, const rsrr_params* prm, 
     w.n = n; w.nb = nb; w.batch = N; w.lda = n; w.sA = nn; w.A = T;
     w.ipiv = ipiv; w.dinv = dinv; w.info = infod;
     w.tag = "sample_lu_c64";
+    w.gauss3m = true;          // errors are removed by the fp64 refinement
     RSRR_TRY(lu_factor<float>(w, s));
     RSRR_TRY(check_info(infod, N, s, z));
     // Y0 = T~^{-1} U in complex64, widened to fp64

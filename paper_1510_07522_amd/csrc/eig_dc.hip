@@ -148,6 +148,7 @@ static int newton_sign(int len, DcWork& w, Arena& ws, hipStream_t s, int* iters)
   lw.n = len; lw.nb = 32; lw.batch = 1; lw.lda = len; lw.sA = ll;
   lw.ipiv = w.ipiv; lw.dinv = w.dinv; lw.info = w.info;
   lw.tag = "dc_lu";
+  lw.gauss3m = true;
   bool scaling = true, schulz = false;
   double prev_r = 1e300;
   for (int it = 0; it < 100; ++it) {
@@ -304,6 +305,7 @@ static int newton_sign_batched(DcBatch& bt, hipStream_t s, std::vector<int>* ok,
   lw.n = L; lw.nb = 32; lw.batch = nbk; lw.lda = L; lw.sA = ll;
   lw.ipiv = bt.ipiv; lw.dinv = bt.dinv; lw.info = bt.info;
   lw.tag = "dc_lu";
+  lw.gauss3m = true;
   GemmBatch<double> g;
   g.tag = "dc_gemm";
   g.M = g.N = g.K = L;

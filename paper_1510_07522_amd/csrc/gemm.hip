@@ -5,7 +5,8 @@
 // Complex products are split into real MFMA products on interleaved data:
 //   4M:  Cr += Ar Br - Ai Bi,  Ci += Ar Bi + Ai Br          (4 MFMA / k-quad)
 //   3M:  P1 += Ar Br, P2 += Ai Bi, P3 += (Ar+Ai)(Br+Bi);    (3 MFMA / k-quad)
-//        Cr = P1 - P2, Ci = P3 - P1 - P2                    (fp32 only)
+//        Cr = P1 - P2, Ci = P3 - P1 - P2 (normwise stable; used where the
+//        result is refined or self-correcting)
 // A may be real (fp64/fp32 values), which halves the products.
 //
 // Tiling: 64x64 C tile per 256-thread workgroup, 4 waves in a 2x2 layout,
@@ -31,11 +32,18 @@ __device__ inline f4 mfma16(float a, float b, f4 c) {
   return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
 }
 
-constexpr int BM = 64, BN = 64, BK = 16, PAD = 16, NT = 256;
+constexpr int BM = 64, BN = 64, BK = 16, PAD = 16;
+// threads per workgroup: 512 for complex128 (8 waves of 32x16, so that the
+// accumulators and the register staging of one wave fit 4 waves per SIMD),
+// 256 for complex64 (4 waves of 32x32)
+template <typename R> constexpr int gemm_threads() { return sizeof(R) == 8 ? 512 : 256; }
 
 template <typename R, int OPA, int OPB, bool AREAL, bool G3M>
-__global__ __launch_bounds__(NT) void gemm_kernel(GemmBatch<R> g) {
+__global__ __launch_bounds__(sizeof(R) == 8 ? 512 : 256) void gemm_kernel(GemmBatch<R> g) {
   typedef typename V4<R>::T acc_t;
+  constexpr int NT = gemm_threads<R>();
+  constexpr int WJ = NT == 512 ? 1 : 2;          // 16-column blocks per wave
+  constexpr int LP = BM * BK / NT;               // tile elements per thread and operand
   __shared__ R As_re[BK][BM + PAD];
   __shared__ R As_im[AREAL ? 1 : BK][BM + PAD];
   __shared__ R Bs_re[BK][BN + PAD];
@@ -45,31 +53,31 @@ __global__ __launch_bounds__(NT) void gemm_kernel(GemmBatch<R> g) {
   const int M = g.M, N = g.N, K = g.K;
   const int m0 = blockIdx.x * BM, n0 = blockIdx.y * BN;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int wm = wave & 1, wn = wave >> 1;
+  const int wm = wave & 1, wn = wave >> 1;       // 32-row half, 16*WJ-column slice
 
   const R* Ar = AREAL ? (const R*)g.A + (long)bz * g.sA : nullptr;
   const cplx<R>* Ac = AREAL ? nullptr : (const cplx<R>*)g.A + (long)bz * g.sA;
   const cplx<R>* Bp = g.B + (long)bz * g.sB;
   cplx<R>* Cp = g.C + (long)bz * g.sC;
 
-  acc_t acc0[2][2], acc1[2][2], acc2[2][2];
+  acc_t acc0[2][WJ], acc1[2][WJ], acc2[2][WJ];
 #pragma unroll
   for (int i = 0; i < 2; ++i)
 #pragma unroll
-    for (int j = 0; j < 2; ++j) {
+    for (int j = 0; j < WJ; ++j) {
       acc0[i][j] = acc_t{0, 0, 0, 0};
       acc1[i][j] = acc_t{0, 0, 0, 0};
       acc2[i][j] = acc_t{0, 0, 0, 0};
     }
 
-  // register staging of one A and one B tile (4 elements per thread each)
-  cplx<R> ra[4], rb[4];
+  // register staging of one A and one B tile (LP elements per thread each)
+  cplx<R> ra[LP], rb[LP];
   auto load_tiles = [&](int k0) {
 #pragma unroll
-    for (int p = 0; p < 4; ++p) {
+    for (int p = 0; p < LP; ++p) {
       int m, k;
-      if (OPA == OP_N) { m = tid & 63; k = (tid >> 6) + 4 * p; }
-      else             { k = tid & 15; m = (tid >> 4) + 16 * p; }
+      if (OPA == OP_N) { m = tid & 63; k = (tid >> 6) + (NT / 64) * p; }
+      else             { k = tid & 15; m = (tid >> 4) + (NT / 16) * p; }
       int gm = m0 + m, gk = k0 + k;
       cplx<R> v = mk<R>(0, 0);
       if (gm < M && gk < K) {
@@ -83,10 +91,10 @@ __global__ __launch_bounds__(NT) void gemm_kernel(GemmBatch<R> g) {
       ra[p] = v;
     }
 #pragma unroll
-    for (int p = 0; p < 4; ++p) {
+    for (int p = 0; p < LP; ++p) {
       int n, k;
-      if (OPB == OP_N) { k = tid & 15; n = (tid >> 4) + 16 * p; }
-      else             { n = tid & 63; k = (tid >> 6) + 4 * p; }
+      if (OPB == OP_N) { k = tid & 15; n = (tid >> 4) + (NT / 16) * p; }
+      else             { n = tid & 63; k = (tid >> 6) + (NT / 64) * p; }
       int gn = n0 + n, gk = k0 + k;
       cplx<R> v = mk<R>(0, 0);
       if (gn < N && gk < K) {
@@ -99,18 +107,18 @@ __global__ __launch_bounds__(NT) void gemm_kernel(GemmBatch<R> g) {
   };
   auto store_tiles = [&]() {
 #pragma unroll
-    for (int p = 0; p < 4; ++p) {
+    for (int p = 0; p < LP; ++p) {
       int m, k;
-      if (OPA == OP_N) { m = tid & 63; k = (tid >> 6) + 4 * p; }
-      else             { k = tid & 15; m = (tid >> 4) + 16 * p; }
+      if (OPA == OP_N) { m = tid & 63; k = (tid >> 6) + (NT / 64) * p; }
+      else             { k = tid & 15; m = (tid >> 4) + (NT / 16) * p; }
       As_re[k][m] = ra[p].re;
       if (!AREAL) As_im[k][m] = ra[p].im;
     }
 #pragma unroll
-    for (int p = 0; p < 4; ++p) {
+    for (int p = 0; p < LP; ++p) {
       int n, k;
-      if (OPB == OP_N) { k = tid & 15; n = (tid >> 4) + 16 * p; }
-      else             { n = tid & 63; k = (tid >> 6) + 4 * p; }
+      if (OPB == OP_N) { k = tid & 15; n = (tid >> 4) + (NT / 16) * p; }
+      else             { n = tid & 63; k = (tid >> 6) + (NT / 64) * p; }
       Bs_re[k][n] = rb[p].re;
       Bs_im[k][n] = rb[p].im;
     }
@@ -125,7 +133,7 @@ __global__ __launch_bounds__(NT) void gemm_kernel(GemmBatch<R> g) {
 #pragma unroll
     for (int kq = 0; kq < BK / 4; ++kq) {
       const int kk = kq * 4 + (lane >> 4);
-      R ar[2], ai[2], br[2], bi[2];
+      R ar[2], ai[2], br[WJ], bi[WJ];
 #pragma unroll
       for (int i = 0; i < 2; ++i) {
         int mm = wm * 32 + i * 16 + (lane & 15);
@@ -133,15 +141,15 @@ __global__ __launch_bounds__(NT) void gemm_kernel(GemmBatch<R> g) {
         ai[i] = AREAL ? R(0) : As_im[kk][mm];
       }
 #pragma unroll
-      for (int j = 0; j < 2; ++j) {
-        int nn = wn * 32 + j * 16 + (lane & 15);
+      for (int j = 0; j < WJ; ++j) {
+        int nn = wn * 16 * WJ + j * 16 + (lane & 15);
         br[j] = Bs_re[kk][nn];
         bi[j] = Bs_im[kk][nn];
       }
 #pragma unroll
       for (int i = 0; i < 2; ++i)
 #pragma unroll
-        for (int j = 0; j < 2; ++j) {
+        for (int j = 0; j < WJ; ++j) {
           if (AREAL) {
             acc0[i][j] = mfma16(ar[i], br[j], acc0[i][j]);
             acc1[i][j] = mfma16(ar[i], bi[j], acc1[i][j]);
@@ -167,8 +175,8 @@ __global__ __launch_bounds__(NT) void gemm_kernel(GemmBatch<R> g) {
 #pragma unroll
   for (int i = 0; i < 2; ++i)
 #pragma unroll
-    for (int j = 0; j < 2; ++j) {
-      int col = n0 + wn * 32 + j * 16 + (lane & 15);
+    for (int j = 0; j < WJ; ++j) {
+      int col = n0 + wn * 16 * WJ + j * 16 + (lane & 15);
       if (col >= N) continue;
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
@@ -198,7 +206,7 @@ static int launch_one(const GemmBatch<R>& g, hipStream_t s) {
                                   es * (double)g.M * g.N *
                                       ((g.beta.re != R(0) || g.beta.im != R(0)) ? 2.0 : 1.0));
   KernelTimer kt(g.tag, s, flops, bytes);
-  hipLaunchKernelGGL((gemm_kernel<R, OPA, OPB, AREAL, G3M>), grid, dim3(NT), 0, s, g);
+  hipLaunchKernelGGL((gemm_kernel<R, OPA, OPB, AREAL, G3M>), grid, dim3(gemm_threads<R>()), 0, s, g);
   RSRR_LAUNCH_CHECK();
   return ST_OK;
 }
@@ -220,7 +228,7 @@ int gemm_batched(const GemmBatch<R>& g, hipStream_t s) {
   if (g.M == 0 || g.N == 0 || g.batch == 0) return ST_OK;
   if (g.a_real && g.opA == OP_C) return set_error(ST_EINVAL, "gemm: real A with conj op");
   if (g.a_real) return launch_ops<R, true, false>(g, s);
-  if (g.gauss3m && sizeof(R) == 4) return launch_ops<R, false, true>(g, s);
+  if (g.gauss3m) return launch_ops<R, false, true>(g, s);
   return launch_ops<R, false, false>(g, s);
 }
 

@@ -16,7 +16,7 @@ template <typename R> struct GemmBatch {
   cplx<R>* C = nullptr; long ldc = 0, sC = 0;
   int batch = 1;
   bool a_real = false;
-  bool gauss3m = false;   // 3-multiplication complex product (fp32 only)
+  bool gauss3m = false;   // 3-multiplication complex product (normwise stable)
   const char* tag = "gemm";   // kernel-timer class
 };
 template <typename R> int gemm_batched(const GemmBatch<R>& g, hipStream_t s);
@@ -38,6 +38,7 @@ template <typename R> struct LUWork {
   cplx<R>* dinv = nullptr;   // batch * npanel * 2 * nb * nb
   int* info = nullptr;       // batch
   const char* tag = "lu";    // kernel-timer class prefix (<tag>_panel, <tag>_update, ...)
+  bool gauss3m = false;      // update and solve products with 3 real multiplications
   int npanel() const { return (n + nb - 1) / nb; }
   static size_t dinv_elems(int n, int nb, int batch) {
     return (size_t)batch * ((n + nb - 1) / nb) * 2 * nb * nb;

@@ -442,6 +442,7 @@ int lu_factor(const LUWork<R>& w, hipStream_t s) {
     g.C = w.A + k + (long)(k + nbe) * w.lda; g.ldc = w.lda; g.sC = w.sA;
     g.batch = w.batch;
     g.tag = t_trsm.c_str();
+    g.gauss3m = w.gauss3m;
     RSRR_TRY(gemm_batched<R>(g, s));
     GemmBatch<R> u;                       // A22 -= L21 U12
     u.M = rest; u.N = rest; u.K = nbe;
@@ -451,6 +452,7 @@ int lu_factor(const LUWork<R>& w, hipStream_t s) {
     u.C = w.A + (k + nbe) + (long)(k + nbe) * w.lda; u.ldc = w.lda; u.sC = w.sA;
     u.batch = w.batch;
     u.tag = t_upd.c_str();
+    u.gauss3m = w.gauss3m;
     RSRR_TRY(gemm_batched<R>(u, s));
   }
   return ST_OK;
@@ -472,6 +474,7 @@ int lu_solve(const LUWork<R>& w, cplx<R>* B, long ldb, long sB, int nrhs, hipStr
     g.C = B + k; g.ldc = ldb; g.sC = sB;
     g.batch = w.batch;
     g.tag = t_solve.c_str();
+    g.gauss3m = w.gauss3m;
     RSRR_TRY(gemm_batched<R>(g, s));
     const int rest = n - k - nbe;
     if (rest > 0) {
@@ -483,6 +486,7 @@ int lu_solve(const LUWork<R>& w, cplx<R>* B, long ldb, long sB, int nrhs, hipStr
       u.C = B + k + nbe; u.ldc = ldb; u.sC = sB;
       u.batch = w.batch;
       u.tag = t_solve.c_str();
+      u.gauss3m = w.gauss3m;
       RSRR_TRY(gemm_batched<R>(u, s));
     }
   }
@@ -495,6 +499,7 @@ int lu_solve(const LUWork<R>& w, cplx<R>* B, long ldb, long sB, int nrhs, hipStr
     g.C = B + k; g.ldc = ldb; g.sC = sB;
     g.batch = w.batch;
     g.tag = t_solve.c_str();
+    g.gauss3m = w.gauss3m;
     RSRR_TRY(gemm_batched<R>(g, s));
     if (k > 0) {
       GemmBatch<R> u;
@@ -505,6 +510,7 @@ int lu_solve(const LUWork<R>& w, cplx<R>* B, long ldb, long sB, int nrhs, hipStr
       u.C = B; u.ldc = ldb; u.sC = sB;
       u.batch = w.batch;
       u.tag = t_solve.c_str();
+      u.gauss3m = w.gauss3m;
       RSRR_TRY(gemm_batched<R>(u, s));
     }
   }
