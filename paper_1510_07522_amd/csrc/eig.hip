@@ -39,13 +39,22 @@ __device__ inline int pair_col(int round, int nbk, int i, int j) {
 }
 
 // Partial Gram X^H X of block pair i = blockIdx.x over row slice ks = blockIdx.y.
+// Each wave takes a quarter of every LDS chunk of rows; lane t accumulates the
+// 4x4 block (rows 4*(t/8).., columns 4*(t%8)..) of the 32x32 Gram; the four
+// wave partials are added in LDS in a fixed order.
 __global__ __launch_bounds__(256) void bj_gram_kernel(const c128* H, long ldh, int rows, int cols, int nbk,
                                                       int round, int rows_per, c128* part) {
   __shared__ c128 X[JCH][J2 + 1];
+  __shared__ c128 R[J2][J2 + 1];
   const int i = blockIdx.x, ks = blockIdx.y, tid = threadIdx.x;
-  const int gi = tid / 8, gj0 = (tid % 8) * 4;
+  const int wave = tid >> 6, t = tid & 63;
+  const int bi = 4 * (t >> 3), bj = 4 * (t & 7);
   const int r_begin = ks * rows_per, r_end = min(rows, r_begin + rows_per);
-  c128 acc[4] = {mk<double>(0, 0), mk<double>(0, 0), mk<double>(0, 0), mk<double>(0, 0)};
+  c128 acc[4][4];
+#pragma unroll
+  for (int p = 0; p < 4; ++p)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) acc[p][q] = mk<double>(0, 0);
   for (int r0 = r_begin; r0 < r_end; r0 += JCH) {
     for (int e = tid; e < JCH * J2; e += 256) {
       const int rr = e % JCH, j = e / JCH;
@@ -53,16 +62,29 @@ __global__ __launch_bounds__(256) void bj_gram_kernel(const c128* H, long ldh, i
       X[rr][j] = (r < r_end && c < cols) ? H[r + (long)c * ldh] : mk<double>(0, 0);
     }
     __syncthreads();
-    for (int rr = 0; rr < JCH; ++rr) {
-      const c128 xi = X[rr][gi];
+    for (int rr = wave; rr < JCH; rr += 4) {
+      c128 xa[4], xb[4];
 #pragma unroll
-      for (int q = 0; q < 4; ++q) acc[q] = acc[q] + cmul(xi, X[rr][gj0 + q]);
+      for (int p = 0; p < 4; ++p) { xa[p] = X[rr][bi + p]; xb[p] = X[rr][bj + p]; }
+#pragma unroll
+      for (int p = 0; p < 4; ++p)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) acc[p][q] = acc[p][q] + cmul(xa[p], xb[q]);
+    }
+    __syncthreads();
+  }
+  // wave partials added in the order 0, 1, 2, 3
+  for (int w = 0; w < 4; ++w) {
+    if (wave == w) {
+#pragma unroll
+      for (int p = 0; p < 4; ++p)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) R[bi + p][bj + q] = (w == 0) ? acc[p][q] : R[bi + p][bj + q] + acc[p][q];
     }
     __syncthreads();
   }
   c128* out = part + ((long)i * gridDim.y + ks) * (J2 * J2);
-#pragma unroll
-  for (int q = 0; q < 4; ++q) out[gi + (gj0 + q) * J2] = acc[q];
+  for (int e = tid; e < J2 * J2; e += 256) out[e] = R[e % J2][e / J2];
 }
 
 // Gram of block pair i (slices added in a fixed order), convergence test and
