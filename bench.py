@@ -32,48 +32,37 @@ if ROOT not in sys.path:
 
 PEAK = {"fp32_mfma": 157.3e12, "fp64_mfma": 78.6e12, "fp64_valu": 78.6e12, "hbm": 8.0e12}
 
-# Which roofline bounds each timed kernel class (the tags the library's HIP-event
-# timers use), and the source file that holds it (for the traffic record).
-KERNEL_SRC = {"_panel": "lu.hip", "pchol_panel": "ortho.hip", "jacobi_": "eig.hip", "lu_permute": "lu.hip",
-              "assemble": "assemble.hip", "gemm": "gemm.hip", "_update": "gemm.hip", "_trsm": "gemm.hip",
-              "_solve": "gemm.hip"}
-
-
-def kernel_bound(tag: str):
-    """(bound, peak) for a kernel class, or None if it has no model."""
-    if tag.endswith("_panel"):
-        return "hbm", PEAK["hbm"]          # latency bound in practice; priced on its bytes
-    if tag.startswith("jacobi_gram") or tag.startswith("jacobi_apply"):
+def kernel_bound(sym: str):
+    """(bound, peak) for a kernel function, or None if it has no model."""
+    if sym.startswith("gemm_kernel<double"):
+        return "mfma", PEAK["fp64_mfma"]
+    if sym.startswith("gemm_kernel<float"):
+        return "mfma", PEAK["fp32_mfma"]
+    if sym.startswith(("bj_gram_kernel", "bj_apply_kernel")):
         return "alu", PEAK["fp64_valu"]
-    if tag in ("lu_permute", "assemble_coeff"):
-        return "hbm", PEAK["hbm"]
-    if tag.endswith(("_update", "_trsm", "_solve", "gemm")):
-        return "mfma", PEAK["fp32_mfma"] if "c64" in tag else PEAK["fp64_mfma"]
+    if sym.startswith(("lu_panel_kernel", "pchol_panel_kernel", "lu_permute_kernel")):
+        return "hbm", PEAK["hbm"]          # panels are latency bound; priced on their bytes
     return None
 
 
-def source_of(tag: str) -> str:
-    for k, v in KERNEL_SRC.items():
-        if k in tag:
-            return v
-    return ""
 
-
-def traffic_record(tag: str):
+def traffic_record(sym: str):
     """HBM bytes per launch from the committed counter summary of this kernel
-    class, if the kernel's source file is unchanged since it was taken."""
-    path = os.path.join(ROOT, "profiles", f"traffic_{tag}.json")
+    function, if its source file is unchanged since the counters were taken."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(path):
         return None
-    rec = json.load(open(path))
+    rec = json.load(open(path)).get(sym)
+    if not rec:
+        return None
     src = os.path.join(ROOT, "paper_1510_07522_amd", "csrc", rec.get("source", ""))
     if not os.path.exists(src) or hashlib.sha256(open(src, "rb").read()).hexdigest() != rec.get("source_sha256"):
         return None
     return rec.get("hbm_bytes_per_launch")
 
 
-def roofline_of(tag: str, t: dict, steps: int):
-    bp = kernel_bound(tag)
+def roofline_of(sym: str, t: dict, steps: int):
+    bp = kernel_bound(sym)
     if bp is None or t["launches"] == 0:
         return None
     bound, peak = bp
@@ -85,16 +74,18 @@ def roofline_of(tag: str, t: dict, steps: int):
     if work <= 0:
         return None
     ach = work / avg_s
-    return {"kernel": tag, "bound": bound, "achieved": ach / scale, "peak": peak / scale, "unit": unit,
-            "frac": ach / peak, "traffic": traffic_record(tag), "algorithmic_per_launch": work,
+    return {"kernel": sym, "bound": bound, "achieved": ach / scale, "peak": peak / scale, "unit": unit,
+            "frac": ach / peak, "traffic": traffic_record(sym), "algorithmic_per_launch": work,
+            "algorithmic_bytes_per_launch": t["bytes"] / t["launches"],
             "launches_per_step": t["launches"] / steps, "avg_launch_ms": avg_s * 1e3,
             "ms_per_step": t["ms"] / steps}
 
 
 def kernel_roofline(timers: dict, steps: int):
-    """Roofline of the modelled kernel class with the most device time, and of
-    the next few classes."""
-    rows = [r for r in (roofline_of(k, v, steps) for k, v in timers.items()) if r is not None]
+    """Roofline of the kernel function with the most device time (HIP events
+    around each of its launches), and of the next few."""
+    rows = [r for r in (roofline_of(k[4:], v, steps) for k, v in timers.items() if k.startswith("sym:"))
+            if r is not None]
     rows.sort(key=lambda r: -r["ms_per_step"])
     if not rows:
         return None, []
@@ -217,11 +208,12 @@ def main():
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t_start
     P.timers_enable(False)
-    timers = P.timers_read()
+    timers_all = P.timers_read()
+    timers = {k: v for k, v in timers_all.items() if not k.startswith("sym:")}
     ms_step = elapsed / a.steps * 1e3
     samples_s = N * a.steps / elapsed
     eig_s = sum(n_eig) / elapsed
-    roof, roof_next = kernel_roofline(timers, a.steps)
+    roof, roof_next = kernel_roofline(timers_all, a.steps)
     dev_ms = sum(t["ms"] for t in timers.values()) / a.steps
     if roof is not None:
         roof["share_of_timed_device_ms"] = roof["ms_per_step"] / max(dev_ms, 1e-9)

@@ -209,7 +209,10 @@ int rsrr_gesv_batched(int precision, int n, int nrhs, void* A, int lda, long lon
  * by HIP events on the stream they are launched on.  Reading synchronises
  * those events.  Each class accumulates launches, total milliseconds and the
  * algorithmic flops and bytes of its launches (real flops, one complex
- * multiply-add = 8).  Process-wide; not for concurrent use with solves.
+ * multiply-add = 8).  Launches of the main kernel functions are also
+ * accumulated per function, under "sym:<name as a profiler lists it>" (for
+ * example "sym:gemm_kernel<double, 0, 0, false, true>").  Process-wide; not
+ * for concurrent use with solves.
  * ---------------------------------------------------------------------- */
 void rsrr_timers_enable(int on);
 void rsrr_timers_reset(void);

@@ -345,13 +345,14 @@ int jacobi_svd(c128* X, long ldx, int rows, int cols, c128* U, long ldu, c128* W
       // (Gram, apply) and of W once, and writes both once
       for (int r = 0; r < nbk - 1; ++r) {
         {
-          KernelTimer kt("jacobi_gram", s, 8.0 * np * J2 * J2 * (double)rows, np * J2 * (double)rows * sizeof(c128));
+          KernelTimer kt("jacobi_gram", s, 8.0 * np * J2 * J2 * (double)rows, np * J2 * (double)rows * sizeof(c128),
+                         "bj_gram_kernel");
           hipLaunchKernelGGL(bj_gram_kernel, dim3(np, nks), dim3(256), 0, s, Xc, ldc, rows, cols, nbk, r, rows_per,
                              part);
           RSRR_LAUNCH_CHECK();
         }
         {
-          KernelTimer kt("jacobi_rotate", s);
+          KernelTimer kt("jacobi_rotate", s, 0.0, 0.0, "bj_rotate_kernel");
           hipLaunchKernelGGL(bj_rotate_kernel, dim3(np), dim3(256), 0, s, part, nks, tol, gfloor, nfloor, Vr, flg,
                              cnt + (sweep % 64));
           RSRR_LAUNCH_CHECK();
@@ -359,7 +360,7 @@ int jacobi_svd(c128* X, long ldx, int rows, int cols, c128* U, long ldu, c128* W
         {
           // upper bound: every pair rotated (skipped pairs cost nothing)
           KernelTimer kt("jacobi_apply", s, 8.0 * np * J2 * J2 * (double)(rows + cols),
-                         2.0 * np * J2 * (double)(rows + cols) * sizeof(c128));
+                         2.0 * np * J2 * (double)(rows + cols) * sizeof(c128), "bj_apply_kernel");
           hipLaunchKernelGGL(bj_apply_kernel, dim3(np, nks, 2), dim3(256), 0, s, Xc, ldc, rows, Wc, (long)cols,
                              cols, cols, nbk, r, rows_per, Vr, flg);
           RSRR_LAUNCH_CHECK();

@@ -205,7 +205,11 @@ static int launch_one(const GemmBatch<R>& g, hipStream_t s) {
   const double bytes = g.batch * ((AREAL ? es / 2 : es) * (double)g.M * g.K + es * (double)g.K * g.N +
                                   es * (double)g.M * g.N *
                                       ((g.beta.re != R(0) || g.beta.im != R(0)) ? 2.0 : 1.0));
-  KernelTimer kt(g.tag, s, flops, bytes);
+  KernelTimer kt(g.tag, s, flops, bytes,
+                 timers_on() ? std::string("gemm_kernel<") + (sizeof(R) == 8 ? "double" : "float") + ", " +
+                                   std::to_string(OPA) + ", " + std::to_string(OPB) + ", " +
+                                   (AREAL ? "true" : "false") + ", " + (G3M ? "true" : "false") + ">"
+                             : std::string());
   hipLaunchKernelGGL((gemm_kernel<R, OPA, OPB, AREAL, G3M>), grid, dim3(gemm_threads<R>()), 0, s, g);
   RSRR_LAUNCH_CHECK();
   return ST_OK;

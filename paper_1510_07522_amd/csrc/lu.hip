@@ -379,7 +379,9 @@ static int launch_permute(cplx<R>* X, long ldx, long sX, int ncols, const int* i
                           int ipiv_stride, int k, int nbe, int batch, hipStream_t s) {
   if (ncols <= 0) return ST_OK;
   dim3 grid((unsigned)cdivl(ncols, SwCols<R>::v), (unsigned)batch);
-  KernelTimer kt("lu_permute", s, 0.0, 4.0 * sizeof(cplx<R>) * nbe * (double)ncols * batch);
+  KernelTimer kt("lu_permute", s, 0.0, 4.0 * sizeof(cplx<R>) * nbe * (double)ncols * batch,
+                 timers_on() ? std::string("lu_permute_kernel<") + (sizeof(R) == 8 ? "double" : "float") + ">"
+                             : std::string());
   hipLaunchKernelGGL((lu_permute_kernel<R>), grid, dim3(256), 0, s, X, ldx, sX, ncols, ipiv,
                      ipiv_stride, k, nbe);
   RSRR_LAUNCH_CHECK();
@@ -401,7 +403,10 @@ static int launch_panel_rows(const LUWork<R>& w, int k, int nbe, hipStream_t s) 
   cplx<R>* dslot = w.dinv + (long)(k / w.nb) * 2 * w.nb * w.nb;
   const std::string tn = std::string(w.tag) + "_panel";
   KernelTimer kt(tn.c_str(), s, 8.0 * nbe * nbe * (w.n - k) * w.batch / 2.0,
-                 2.0 * sizeof(cplx<R>) * (double)(w.n - k) * nbe * w.batch);
+                 2.0 * sizeof(cplx<R>) * (double)(w.n - k) * nbe * w.batch,
+                 timers_on() ? std::string("lu_panel_kernel<") + (sizeof(R) == 8 ? "double" : "float") + ", " +
+                                   std::to_string(ROWS) + ", " + std::to_string(W) + ">"
+                             : std::string());
   hipLaunchKernelGGL((lu_panel_kernel<R, ROWS, W>), dim3(w.batch), dim3(PNT), 0, s, w.A, w.lda,
                      w.sA, w.n, k, nbe, w.nb, w.ipiv, dslot, sD, w.info);
   RSRR_LAUNCH_CHECK();

@@ -247,7 +247,8 @@ static int pchol(c128* G, long ldg, int m, int maxrank, double tol, bool pivot, 
   int rank = 0;
   for (int j0 = 0; j0 < maxrank; j0 += PCB) {
     const int jb = std::min(PCB, maxrank - j0);
-    KernelTimer kt("pchol_panel", s, 8.0 * (double)m * jb * jb / 2, 16.0 * 4 * (double)m * jb);
+    KernelTimer kt("pchol_panel", s, 8.0 * (double)m * jb * jb / 2, 16.0 * 4 * (double)m * jb,
+                   "pchol_panel_kernel");
     hipLaunchKernelGGL(pchol_panel_kernel, dim3(1), dim3(PCT), 0, s, G, ldg, m, j0, jb, perm, d,
                        tol, pivot ? 1 : 0, rk);
     RSRR_LAUNCH_CHECK();

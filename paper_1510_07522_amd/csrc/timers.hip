@@ -10,7 +10,7 @@
 namespace rsrr {
 
 namespace {
-struct Rec { hipEvent_t a, b; double flops, bytes; };
+struct Rec { hipEvent_t a, b; double flops, bytes; std::string sym; };
 struct Acc { long launches = 0; double ms = 0, flops = 0, bytes = 0; };
 std::mutex g_mu;
 bool g_on = false;
@@ -36,6 +36,13 @@ void drain() {   // caller holds g_mu
         acc.ms += ms;
         acc.flops += r.flops;
         acc.bytes += r.bytes;
+        if (!r.sym.empty()) {
+          Acc& as = g_acc["sym:" + r.sym];
+          as.launches += 1;
+          as.ms += ms;
+          as.flops += r.flops;
+          as.bytes += r.bytes;
+        }
       }
       if (r.a) g_pool.push_back(r.a);
       if (r.b) g_pool.push_back(r.b);
@@ -47,8 +54,8 @@ void drain() {   // caller holds g_mu
 
 bool timers_on() { return g_on; }
 
-KernelTimer::KernelTimer(const char* n, hipStream_t st, double fl, double by)
-    : name(n), s(st), flops(fl), bytes(by) {
+KernelTimer::KernelTimer(const char* n, hipStream_t st, double fl, double by, std::string symbol)
+    : name(n), s(st), flops(fl), bytes(by), sym(std::move(symbol)) {
   if (!g_on) return;
   std::lock_guard<std::mutex> lk(g_mu);
   a = take();
@@ -60,7 +67,7 @@ KernelTimer::~KernelTimer() {
   std::lock_guard<std::mutex> lk(g_mu);
   hipEvent_t b = take();
   if (b) (void)hipEventRecord(b, s);
-  g_pending[name].push_back(Rec{a, b, flops, bytes});
+  g_pending[name].push_back(Rec{a, b, flops, bytes, sym});
 }
 
 }  // namespace rsrr
