@@ -61,9 +61,31 @@ int Arena::get(const char* name, size_t bytes, void** out) {
   return ST_OK;
 }
 
+int Arena::aux_stream(hipStream_t* s, hipEvent_t* ev_main, hipEvent_t* ev_aux) {
+  if (!aux) {
+    if (hipStreamCreateWithFlags(&aux, hipStreamNonBlocking) != hipSuccess) {
+      aux = nullptr;
+      return set_error(ST_EHIP, "cannot create the look-ahead stream");
+    }
+    for (auto& e : ev)
+      if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) {
+        e = nullptr;
+        return set_error(ST_EHIP, "cannot create the look-ahead events");
+      }
+  }
+  *s = aux;
+  *ev_main = ev[0];
+  *ev_aux = ev[1];
+  return ST_OK;
+}
+
 void Arena::release() {
+  if (aux) (void)hipStreamSynchronize(aux);
   for (auto& kv : bufs) (void)hipFree(kv.second.first);
   bufs.clear();
+  for (auto& e : ev)
+    if (e) { (void)hipEventDestroy(e); e = nullptr; }
+  if (aux) { (void)hipStreamDestroy(aux); aux = nullptr; }
 }
 
 void eval_fn(const rsrr_fn& f, cd z, cd* val, cd* der) {

@@ -17,10 +17,15 @@ typedef std::complex<double> cd;
 // not overlap, so a buffer is reused across calls without re-allocation.
 struct Arena {
   std::map<std::string, std::pair<void*, size_t>> bufs;
+  // second stream (default priority) and two events for the look-ahead of
+  // the LU factorisations, created on first use
+  hipStream_t aux = nullptr;
+  hipEvent_t ev[2] = {nullptr, nullptr};
   int get(const char* name, size_t bytes, void** out);
   template <typename T> int get(const char* name, size_t count, T** out) {
     return get(name, count * sizeof(T), (void**)out);
   }
+  int aux_stream(hipStream_t* s, hipEvent_t* ev_main, hipEvent_t* ev_aux);
   void release();
   ~Arena() { release(); }
 };

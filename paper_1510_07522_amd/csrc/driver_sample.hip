@@ -62,6 +62,30 @@ static int check_info(const int* info_dev, int batch, hipStream_t s, const std::
 }
 
 // Residual R = U - T(z_j) Y_j (fp64) for all nodes; P is scratch for A_k Y.
+// dst[:, q*L + c] = src[:, idx[q]*L + c]   (the columns of the listed nodes)
+__global__ __launch_bounds__(256) void gather_node_cols_kernel(const c128* src, long lds, int rows, int L,
+                                                               const int* idx, int count, c128* dst, long ldd) {
+  const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= (long)rows * L * count) return;
+  const int r = (int)(e % rows);
+  const long col = e / rows;
+  const int q = (int)(col / L), c = (int)(col % L);
+  dst[r + col * ldd] = src[r + ((long)idx[q] * L + c) * lds];
+}
+
+// dst[:, idx[q]*L + c] = (complex64) src[:, q*L + c]
+__global__ __launch_bounds__(256) void scatter_node_cols_c64_kernel(const c128* src, long lds, int rows, int L,
+                                                                    const int* idx, int count, c64* dst,
+                                                                    long ldd) {
+  const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= (long)rows * L * count) return;
+  const int r = (int)(e % rows);
+  const long col = e / rows;
+  const int q = (int)(col / L), c = (int)(col % L);
+  const c128 v = src[r + col * lds];
+  dst[r + ((long)idx[q] * L + c) * ldd] = mk<float>((float)v.re, (float)v.im);
+}
+
 static int residual_fp64(rsrr_problem* p, int N, int L, const c128* f_dev, const c128* z_dev,
                          const c128* U, long ldu, const c128* Y, long ldy, c128* Rb, hipStream_t s) {
   const int n = p->n;
@@ -129,6 +153,7 @@ int sample_impl(rsrr_problem* p, const rsrr_contour* c, const rsrr_params* prm, 
     w.n = n; w.nb = nb; w.batch = N; w.lda = n; w.sA = nn; w.A = T;
     w.ipiv = ipiv; w.dinv = dinv; w.info = infod;
     w.tag = "sample_lu_c128";
+    RSRR_TRY(p->ws.aux_stream(&w.aux, &w.ev_main, &w.ev_aux));
     RSRR_TRY(lu_factor<double>(w, s));
     RSRR_TRY(check_info(infod, N, s, z));
     RSRR_TRY(replicate<double>(U, ldu, S, lds, (long)L * lds, n, L, N, s));
@@ -150,6 +175,7 @@ int sample_impl(rsrr_problem* p, const rsrr_contour* c, const rsrr_params* prm, 
     w.n = n; w.nb = nb; w.batch = N; w.lda = n; w.sA = nn; w.A = T;
     w.ipiv = ipiv; w.dinv = dinv; w.info = infod;
     w.tag = "sample_lu_c64";
+    RSRR_TRY(p->ws.aux_stream(&w.aux, &w.ev_main, &w.ev_aux));
     w.gauss3m = true;          // errors are removed by the fp64 refinement
     RSRR_TRY(lu_factor<float>(w, s));
     RSRR_TRY(check_info(infod, N, s, z));
@@ -171,24 +197,94 @@ int sample_impl(rsrr_problem* p, const rsrr_contour* c, const rsrr_params* prm, 
     RSRR_HIP(hipMemcpyAsync(u2.data(), nrm + 3 * N, sizeof(double), hipMemcpyDeviceToHost, s));
     std::vector<int> active(N, 1);
     std::vector<double> r2(N), y2(N);
+    // after the first sweep only the nodes still above ir_tol are refined:
+    // their columns are gathered for the fp64 residual, and the solves skip
+    // the others
+    int *idx_dev = nullptr;
+    c128 *Sa = nullptr, *Ra = nullptr, *fa_dev = nullptr, *za_dev = nullptr;
+    RSRR_TRY(p->ws.get<int>("s_idx", N, &idx_dev));
+    std::vector<int> idx;
+    int nact = N;
     for (int it = 0;; ++it) {
-      RSRR_TRY(residual_fp64(p, N, L, f_dev, z_dev, U, ldu, S, lds, Rb, s));
-      RSRR_TRY(block_fro2(Rb, n, (long)L * n, n, L, N, nrm, s));
-      RSRR_TRY(block_fro2(S, lds, (long)L * lds, n, L, N, nrm + N, s));
-      RSRR_HIP(hipMemcpyAsync(r2.data(), nrm, N * sizeof(double), hipMemcpyDeviceToHost, s));
-      RSRR_HIP(hipMemcpyAsync(y2.data(), nrm + N, N * sizeof(double), hipMemcpyDeviceToHost, s));
-      RSRR_HIP(hipStreamSynchronize(s));
-      int nact = 0;
+      // residuals of the nodes corrected in the last sweep (all in the first)
+      const bool res_full = (nact == N);
+      if (res_full) {
+        RSRR_TRY(residual_fp64(p, N, L, f_dev, z_dev, U, ldu, S, lds, Rb, s));
+        RSRR_TRY(block_fro2(Rb, n, (long)L * n, n, L, N, nrm, s));
+        RSRR_TRY(block_fro2(S, lds, (long)L * lds, n, L, N, nrm + N, s));
+        RSRR_HIP(hipMemcpyAsync(r2.data(), nrm, N * sizeof(double), hipMemcpyDeviceToHost, s));
+        RSRR_HIP(hipMemcpyAsync(y2.data(), nrm + N, N * sizeof(double), hipMemcpyDeviceToHost, s));
+        RSRR_HIP(hipStreamSynchronize(s));
+      } else {
+        const int na = (int)idx.size();
+        const long ca = (long)na * L;
+        RSRR_TRY(p->ws.get<c128>("s_Sa", (size_t)n * ca, &Sa));
+        RSRR_TRY(p->ws.get<c128>("s_Ra", (size_t)n * ca, &Ra));
+        std::vector<c128> fa(p->bem ? 0 : (size_t)na * p->J), za(na);
+        for (int q = 0; q < na; ++q) {
+          za[q] = zc[idx[q]];
+          if (!p->bem)
+            for (int k = 0; k < p->J; ++k) fa[(size_t)q * p->J + k] = f[(size_t)idx[q] * p->J + k];
+        }
+        RSRR_TRY(p->ws.get<c128>("s_fa", std::max<size_t>(1, fa.size()), &fa_dev));
+        RSRR_TRY(p->ws.get<c128>("s_za", na, &za_dev));
+        if (!fa.empty())
+          RSRR_HIP(hipMemcpyAsync(fa_dev, fa.data(), fa.size() * sizeof(c128), hipMemcpyHostToDevice, s));
+        RSRR_HIP(hipMemcpyAsync(za_dev, za.data(), na * sizeof(c128), hipMemcpyHostToDevice, s));
+        RSRR_HIP(hipMemcpyAsync(idx_dev, idx.data(), na * sizeof(int), hipMemcpyHostToDevice, s));
+        hipLaunchKernelGGL(gather_node_cols_kernel, dim3((unsigned)cdivl((long)n * ca, 256)), dim3(256), 0, s, S,
+                           lds, n, L, idx_dev, na, Sa, (long)n);
+        RSRR_LAUNCH_CHECK();
+        RSRR_TRY(residual_fp64(p, na, L, fa_dev, za_dev, U, ldu, Sa, n, Ra, s));
+        RSRR_TRY(block_fro2(Ra, n, (long)L * n, n, L, na, nrm, s));
+        RSRR_TRY(block_fro2(Sa, n, (long)L * n, n, L, na, nrm + N, s));
+        std::vector<double> ra(na), ya(na);
+        RSRR_HIP(hipMemcpyAsync(ra.data(), nrm, na * sizeof(double), hipMemcpyDeviceToHost, s));
+        RSRR_HIP(hipMemcpyAsync(ya.data(), nrm + N, na * sizeof(double), hipMemcpyDeviceToHost, s));
+        RSRR_HIP(hipStreamSynchronize(s));
+        for (int q = 0; q < na; ++q) { r2[idx[q]] = ra[q]; y2[idx[q]] = ya[q]; }
+      }
+      // only the nodes tested in this sweep can stay active
+      const std::vector<int> was(active);
+      nact = 0;
+      double emax = 0;
       for (int j = 0; j < N; ++j) {
         const double eta = sqrt(r2[j]) / (sqrt(fro2[j]) * sqrt(y2[j]) + sqrt(u2[0]));
-        active[j] = (eta > prm->ir_tol) || !(eta == eta);
+        active[j] = was[j] && ((eta > prm->ir_tol) || !(eta == eta));
         nact += active[j];
+        emax = std::max(emax, eta);
       }
+      vlog("refinement sweep %d: %d of %d nodes above ir_tol, max eta %.2e", it, nact, N, emax);
       if (nact == 0 || it >= prm->ir_max_iter) break;
       ir_iters = it + 1;
+      const std::vector<int> tested(idx);
+      idx.clear();
+      for (int j = 0; j < N; ++j) if (active[j]) idx.push_back(j);
       RSRR_HIP(hipMemcpyAsync(active_dev, active.data(), N * sizeof(int), hipMemcpyHostToDevice, s));
-      RSRR_TRY((convert<float, double>(Rb, n, (long)L * n, Y32, n, (long)L * n, n, L, N, s)));
-      RSRR_TRY(lu_solve<float>(w, Y32, n, (long)L * n, L, s));
+      if (nact == N) {
+        RSRR_TRY((convert<float, double>(Rb, n, (long)L * n, Y32, n, (long)L * n, n, L, N, s)));
+        RSRR_TRY(lu_solve<float>(w, Y32, n, (long)L * n, L, s));
+      } else {
+        // residual columns of the active nodes, compacted into Rk in the order of idx
+        std::vector<int> src;
+        if (res_full) {
+          src = idx;
+        } else {
+          for (size_t q = 0; q < tested.size(); ++q) if (active[tested[q]]) src.push_back((int)q);
+        }
+        const long ck = (long)src.size() * L;
+        c128* Rk = nullptr;
+        RSRR_TRY(p->ws.get<c128>("s_Rk", (size_t)n * ck, &Rk));
+        RSRR_HIP(hipMemcpyAsync(idx_dev, src.data(), src.size() * sizeof(int), hipMemcpyHostToDevice, s));
+        hipLaunchKernelGGL(gather_node_cols_kernel, dim3((unsigned)cdivl((long)n * ck, 256)), dim3(256), 0, s,
+                           res_full ? Rb : Ra, (long)n, n, L, idx_dev, (int)src.size(), Rk, (long)n);
+        RSRR_LAUNCH_CHECK();
+        RSRR_HIP(hipMemcpyAsync(idx_dev, idx.data(), idx.size() * sizeof(int), hipMemcpyHostToDevice, s));
+        hipLaunchKernelGGL(scatter_node_cols_c64_kernel, dim3((unsigned)cdivl((long)n * ck, 256)), dim3(256), 0, s,
+                           Rk, (long)n, n, L, idx_dev, (int)idx.size(), Y32, (long)n);
+        RSRR_LAUNCH_CHECK();
+        RSRR_TRY(lu_solve<float>(w, Y32, n, (long)L * n, L, s, active_dev));
+      }
       RSRR_TRY(add_correction(S, lds, (long)L * lds, Y32, n, (long)L * n, n, L, N, active_dev, s));
     }
     // complex128 fallback for the nodes that did not converge
@@ -215,6 +311,7 @@ int sample_impl(rsrr_problem* p, const rsrr_contour* c, const rsrr_params* prm, 
       wb.n = n; wb.nb = nb; wb.batch = nbad; wb.lda = n; wb.sA = nn; wb.A = Tb;
       wb.ipiv = ipiv; wb.dinv = dinvb; wb.info = infod;
       wb.tag = "fallback_lu_c128";
+      RSRR_TRY(p->ws.aux_stream(&wb.aux, &wb.ev_main, &wb.ev_aux));
       RSRR_TRY(lu_factor<double>(wb, s));
       RSRR_TRY(check_info(infod, nbad, s, zb));
       RSRR_TRY(replicate<double>(U, ldu, Yb, n, (long)n * L, n, L, nbad, s));

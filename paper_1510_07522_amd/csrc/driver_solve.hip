@@ -184,6 +184,7 @@ int solve_impl(rsrr_problem* p, const rsrr_contour* c, const rsrr_params* prm, c
     w.n = kS; w.nb = prm->nb; w.batch = cnt; w.lda = kS; w.sA = kk; w.A = TS;
     w.ipiv = ipiv; w.dinv = dinv; w.info = linfo;
     w.tag = "reduced_lu_c128";
+    RSRR_TRY(ws.aux_stream(&w.aux, &w.ev_main, &w.ev_aux));
     w.gauss3m = true;
     RSRR_TRY(lu_factor<double>(w, s));
     RSRR_TRY(replicate<double>(Iden, kS, X, kS, kk, kS, kS, cnt, s));

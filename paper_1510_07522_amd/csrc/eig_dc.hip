@@ -13,6 +13,7 @@
 // Inversions use the batched LU of the sampling step; bases use the pivoted
 // Cholesky / Cholesky-QR routines of the orthonormalisation step.
 #include <algorithm>
+#include <complex>
 #include <cmath>
 #include <vector>
 
@@ -149,6 +150,7 @@ static int newton_sign(int len, DcWork& w, Arena& ws, hipStream_t s, int* iters)
   lw.ipiv = w.ipiv; lw.dinv = w.dinv; lw.info = w.info;
   lw.tag = "dc_lu";
   lw.gauss3m = true;
+  RSRR_TRY(ws.aux_stream(&lw.aux, &lw.ev_main, &lw.ev_aux));
   bool scaling = true, schulz = false;
   double prev_r = 1e300;
   for (int it = 0; it < 100; ++it) {
@@ -294,11 +296,61 @@ static int pad_identity(c128* X, DcBatch& bt, hipStream_t s) {
   return ST_OK;
 }
 
+// Principal Pade iteration of order 2m for the sign function in partial
+// fractions: r_m(x) = tanh(2m artanh x) = sum_j w_j x / (x^2 + beta_j^2),
+// beta_j = tan(pi (2j-1) / (4m)), w_j from the residues at x = i beta_j.  One
+// step X <- sum_j w_j Z_j with (X^2 + beta_j^2 I) Z_j = X needs m independent
+// LU solves (one batch) and gains a factor 2m per step near the split line,
+// where Newton gains 2.
+constexpr int PADE_M = 4;
+struct PadeCoef { double b2[PADE_M]; double w[PADE_M]; };
+
+static PadeCoef pade_coefficients() {
+  PadeCoef pc;
+  const int p = 2 * PADE_M;
+  for (int j = 0; j < PADE_M; ++j) {
+    const double beta = tan(M_PI * (2 * j + 1) / (2.0 * p));
+    const cd x(0.0, beta);
+    const cd num = std::pow(1.0 + x, p) - std::pow(1.0 - x, p);
+    const cd dden = (double)p * (std::pow(1.0 + x, p - 1) - std::pow(1.0 - x, p - 1));
+    pc.b2[j] = beta * beta;
+    pc.w[j] = (2.0 * num / dden).real();
+  }
+  return pc;
+}
+
+// slot q = j * nbk + b:  LU_q = X2_b + beta_j^2 I,  Z_q = X_b
+__global__ __launch_bounds__(256) void pade_setup_kernel(const c128* X2, const c128* X, int nbk, int L,
+                                                         PadeCoef pc, c128* LU, c128* Z) {
+  const long ll = (long)L * L;
+  const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= ll) return;
+  const int q = blockIdx.y, j = q / nbk, b = q % nbk;
+  c128 v = X2[(long)b * ll + e];
+  if (e % L == e / L) v.re += pc.b2[j];
+  LU[(long)q * ll + e] = v;
+  Z[(long)q * ll + e] = X[(long)b * ll + e];
+}
+
+// Y_b = sum_j w_j Z_{j * nbk + b}
+__global__ __launch_bounds__(256) void pade_combine_kernel(const c128* Z, int nbk, int L, PadeCoef pc, c128* Y) {
+  const long ll = (long)L * L;
+  const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= ll) return;
+  const int b = blockIdx.y;
+  c128 acc = mk<double>(0, 0);
+#pragma unroll
+  for (int j = 0; j < PADE_M; ++j) acc = acc + pc.w[j] * Z[((long)j * nbk + b) * ll + e];
+  Y[(long)b * ll + e] = acc;
+}
+
 // Sign functions of the nbk matrices in bt.X (destroyed; results in bt.X),
-// the iteration of newton_sign run on all of them in lock step with a scaling
-// factor per matrix.  ok[b] = 0 if matrix b became singular or did not
-// converge (its slot is reset to the identity so it stays inert).
-static int newton_sign_batched(DcBatch& bt, hipStream_t s, std::vector<int>* ok, int* iters) {
+// run on all of them in lock step: one Newton step with a scaling factor per
+// matrix, then Pade steps of order 2*PADE_M until the relative change is below
+// 1e-2, then Newton-Schulz to convergence.  ok[b] = 0 if matrix b became
+// singular or did not converge (its slot is reset to the identity so it stays
+// inert).
+static int newton_sign_batched(DcBatch& bt, Arena& ws, hipStream_t s, std::vector<int>* ok, int* iters) {
   const int nbk = bt.nbk, L = bt.Lmax;
   const long ll = (long)L * L;
   LUWork<double> lw;
@@ -306,6 +358,7 @@ static int newton_sign_batched(DcBatch& bt, hipStream_t s, std::vector<int>* ok,
   lw.ipiv = bt.ipiv; lw.dinv = bt.dinv; lw.info = bt.info;
   lw.tag = "dc_lu";
   lw.gauss3m = true;
+  RSRR_TRY(ws.aux_stream(&lw.aux, &lw.ev_main, &lw.ev_aux));
   GemmBatch<double> g;
   g.tag = "dc_gemm";
   g.M = g.N = g.K = L;
@@ -316,6 +369,18 @@ static int newton_sign_batched(DcBatch& bt, hipStream_t s, std::vector<int>* ok,
   std::vector<int> done(nbk, 0);
   std::vector<double> prev(nbk, 1e300), coef(2 * nbk), fx, fy, fn, fd;
   bool scaling = true, schulz = false;
+  int n_newton = 0, n_schulz = 0, n_pade = 0;
+  const PadeCoef pc = pade_coefficients();
+  const int nq = PADE_M * nbk;
+  c128 *LUp = nullptr, *Zp = nullptr, *dinvp = nullptr;
+  int *ipivp = nullptr, *infop = nullptr;
+  RSRR_TRY(ws.get<c128>("dcp_LU", (size_t)nq * ll, &LUp));
+  RSRR_TRY(ws.get<c128>("dcp_Z", (size_t)nq * ll, &Zp));
+  RSRR_TRY(ws.get<c128>("dcp_dinv", LUWork<double>::dinv_elems(L, 32, nq), &dinvp));
+  RSRR_TRY(ws.get<int>("dcp_ipiv", (size_t)nq * L, &ipivp));
+  RSRR_TRY(ws.get<int>("dcp_info", nq, &infop));
+  LUWork<double> lwp = lw;
+  lwp.batch = nq; lwp.A = LUp; lwp.ipiv = ipivp; lwp.dinv = dinvp; lwp.info = infop;
   auto reset = [&](int b) -> int {
     (*ok)[b] = 0;
     done[b] = 1;
@@ -338,20 +403,56 @@ static int newton_sign_batched(DcBatch& bt, hipStream_t s, std::vector<int>* ok,
         all = false;
         if (!(r < 0.5)) back = true;
       }
-      if (all) { *iters = it; return ST_OK; }
+      if (all) {
+        *iters = it;
+        vlog("dc sign batch of %d (len %d): %d newton + %d pade + %d schulz steps", nbk, L, n_newton, n_pade, n_schulz);
+        return ST_OK;
+      }
       if (back) {
         schulz = false;
         std::fill(prev.begin(), prev.end(), 1e300);
         continue;
       }
       g.A = bt.X; g.B = bt.Y; g.C = bt.LU;
+      ++n_schulz;
       RSRR_TRY(gemm_batched<double>(g, s));                         // X^3
       for (int b = 0; b < nbk; ++b) { coef[2 * b] = -0.5; coef[2 * b + 1] = 1.5; }
       RSRR_TRY(axpby_batched(bt.LU, bt.X, bt, coef, s));           // X <- 1.5 X - 0.5 X^3
       RSRR_TRY(pad_identity(bt.X, bt, s));
       continue;
     }
+    if (it > 0) {                // Pade step
+      g.alpha = ONE; g.beta = ZERO;
+      g.A = bt.X; g.B = bt.X; g.C = bt.Y;
+      RSRR_TRY(gemm_batched<double>(g, s));                         // X^2
+      hipLaunchKernelGGL(pade_setup_kernel, dim3(nblk(ll), nq), dim3(256), 0, s, bt.Y, bt.X, nbk, L, pc, LUp, Zp);
+      RSRR_LAUNCH_CHECK();
+      RSRR_TRY(lu_factor<double>(lwp, s));
+      std::vector<int> infq(nq);
+      RSRR_HIP(hipMemcpyAsync(infq.data(), infop, nq * sizeof(int), hipMemcpyDeviceToHost, s));
+      RSRR_TRY(lu_solve<double>(lwp, Zp, L, ll, L, s));
+      hipLaunchKernelGGL(pade_combine_kernel, dim3(nblk(ll), nbk), dim3(256), 0, s, Zp, nbk, L, pc, bt.Y);
+      RSRR_LAUNCH_CHECK();
+      RSRR_TRY(pad_identity(bt.Y, bt, s));
+      RSRR_TRY(fro_batched(bt.Y, bt.X, bt, s, &fn, &fd));
+      std::swap(bt.X, bt.Y);
+      ++n_pade;
+      bool all = true, any = false;
+      for (int b = 0; b < nbk; ++b) {
+        if (done[b]) continue;
+        int sing = 0;
+        for (int j = 0; j < PADE_M; ++j) sing |= infq[j * nbk + b];
+        const double rel = sqrt(fd[b] / std::max(fn[b], 1e-300));
+        if (sing || !(rel == rel)) { RSRR_TRY(reset(b)); continue; }
+        if (!(rel < 1e-2)) all = false;
+      }
+      if (all) { schulz = true; std::fill(prev.begin(), prev.end(), 1e300); }
+      for (int b = 0; b < nbk; ++b) any = any || !done[b];
+      if (!any) { *iters = it; return ST_OK; }
+      continue;
+    }
     RSRR_HIP(hipMemcpyAsync(bt.LU, bt.X, (size_t)nbk * ll * sizeof(c128), hipMemcpyDeviceToDevice, s));
+    ++n_newton;
     lw.A = bt.LU;
     for (int b = 0; b < nbk; ++b) RSRR_TRY(set_identity(bt.Y + (long)b * ll, L, L, s));
     RSRR_TRY(lu_factor<double>(lw, s));
@@ -493,6 +594,7 @@ int eig_dc(c128* A, long lda, int m, std::vector<cd>* lam, c128* V, long ldv, Ar
   RSRR_TRY(set_identity(Z, m, m, s));
   struct Blk { int off, len; };
   std::vector<Blk> level{{0, m}}, leaves;
+  const double t_dc = now_s();
   // block b of T split into k + (len - k) with the bases in w.Q
   auto finish_split = [&](const Blk& b, int k, std::vector<Blk>& next) -> int {
     c128* B = A + b.off + (long)b.off * lda;
@@ -562,7 +664,7 @@ int eig_dc(c128* A, long lda, int m, std::vector<cd>* lam, c128* V, long ldv, Ar
       RSRR_TRY(pad_identity(bt.X, bt, s));
       std::vector<int> ok;
       int its = 0;
-      RSRR_TRY(newton_sign_batched(bt, s, &ok, &its));
+      RSRR_TRY(newton_sign_batched(bt, ws, s, &ok, &its));
       std::vector<int> ks(cnt, 0);
       for (size_t i = 0; i < cnt; ++i)
         if (ok[i]) {
@@ -579,7 +681,7 @@ int eig_dc(c128* A, long lda, int m, std::vector<cd>* lam, c128* V, long ldv, Ar
         for (int q = 0; q < bt.lens[i]; ++q) tr += pd[i * (size_t)L + q].re;
         ks[i] = (int)std::lround(tr);
       }
-      vlog("dc level batch: %d blocks up to %d, %d newton its", (int)cnt, L, its);
+      vlog("dc level batch: %d blocks up to %d, %d iterations, sign done at %.3fs", (int)cnt, L, its, now_s() - t_dc);
       // successful splits first: their projectors live in bt.X
       for (size_t i = 0; i < cnt; ++i) {
         const Blk& b = big[g0 + i];
@@ -601,6 +703,8 @@ int eig_dc(c128* A, long lda, int m, std::vector<cd>* lam, c128* V, long ldv, Ar
         RSRR_TRY(finish_split(b, k, next));
       }
       g0 += cnt;
+      RSRR_HIP(hipStreamSynchronize(s));
+      vlog("dc level batch done at %.3fs", now_s() - t_dc);
     }
     level.swap(next);
   }
@@ -641,7 +745,7 @@ int eig_dc(c128* A, long lda, int m, std::vector<cd>* lam, c128* V, long ldv, Ar
     RSRR_TRY((convert<double, double>(hH[i], b.len, 0, A + b.off + (long)b.off * lda, lda, 0, b.len,
                                       b.len, 1, s)));
   }
-  vlog("dc: %d leaves", nl);
+  vlog("dc: %d leaves, at %.3fs", nl, now_s() - t_dc);
   // ---- eigenvalues and eigenvectors of the Schur form
   c128* X = nullptr;
   RSRR_TRY(ws.get<c128>("dc_Xv", mm, &X));

@@ -50,6 +50,7 @@ __global__ __launch_bounds__(sizeof(R) == 8 ? 512 : 256) void gemm_kernel(GemmBa
   __shared__ R Bs_im[BK][BN + PAD];
 
   const int bz = blockIdx.z;
+  if (g.active && !g.active[bz]) return;
   const int M = g.M, N = g.N, K = g.K;
   const int m0 = blockIdx.x * BM, n0 = blockIdx.y * BN;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;

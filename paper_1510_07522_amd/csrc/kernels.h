@@ -17,6 +17,7 @@ template <typename R> struct GemmBatch {
   int batch = 1;
   bool a_real = false;
   bool gauss3m = false;   // 3-multiplication complex product (normwise stable)
+  const int* active = nullptr;   // optional: batch entries with active[b] == 0 are skipped
   const char* tag = "gemm";   // kernel-timer class
 };
 template <typename R> int gemm_batched(const GemmBatch<R>& g, hipStream_t s);
@@ -39,6 +40,10 @@ template <typename R> struct LUWork {
   int* info = nullptr;       // batch
   const char* tag = "lu";    // kernel-timer class prefix (<tag>_panel, <tag>_update, ...)
   bool gauss3m = false;      // update and solve products with 3 real multiplications
+  // look-ahead (optional): the trailing update beyond the next panel runs on
+  // `aux` while the next panel is factored; ev_main / ev_aux order the two
+  hipStream_t aux = nullptr;
+  hipEvent_t ev_main = nullptr, ev_aux = nullptr;
   int npanel() const { return (n + nb - 1) / nb; }
   static size_t dinv_elems(int n, int nb, int batch) {
     return (size_t)batch * ((n + nb - 1) / nb) * 2 * nb * nb;
@@ -46,8 +51,9 @@ template <typename R> struct LUWork {
 };
 template <typename R> int lu_factor(const LUWork<R>& w, hipStream_t s);
 // Solves A_b X_b = B_b in place for nrhs columns (B leading dim ldb, stride sB).
+// active (optional, device): systems b with active[b] == 0 are left untouched.
 template <typename R> int lu_solve(const LUWork<R>& w, cplx<R>* B, long ldb, long sB,
-                                   int nrhs, hipStream_t s);
+                                   int nrhs, hipStream_t s, const int* active = nullptr);
 
 // ----------------------------------------------------------------- assembly
 // Coefficient form: T_j = sum_k f[j*J + k] * A_k for j < nz, written to

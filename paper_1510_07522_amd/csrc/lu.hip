@@ -205,22 +205,17 @@ __global__ __launch_bounds__(PNT) void lu_panel_kernel(cplx<R>* A, long lda, lon
         for (int j = 0; j < W; ++j) s_L[tid][j] = a[0][j];
       }
       __syncthreads();
-      // U rows of the micro-panel: unit-lower solve, one column per thread
+      // U rows of the micro-panel: unit-lower solve in LDS, one column per thread
       if (tid < ncols) {
         const int cc = rc0 + tid;
-        cplx<R> x[W];
 #pragma unroll
         for (int j = 0; j < W; ++j)
-          x[j] = (j < w) ? Ab[c + j + (long)cc * lda] : mk<R>(0, 0);
-#pragma unroll
-        for (int j = 1; j < W; ++j)
-#pragma unroll
-          for (int l = 0; l < j; ++l)
-            if (j < w) x[j] = x[j] - s_L[j][l] * x[l];
-#pragma unroll
-        for (int j = 0; j < W; ++j) {
-          s_U[j][tid] = x[j];
-          if (j < w) Ab[c + j + (long)cc * lda] = x[j];
+          s_U[j][tid] = (j < w) ? Ab[c + j + (long)cc * lda] : mk<R>(0, 0);
+        for (int j = 1; j < w; ++j) {
+          cplx<R> v = s_U[j][tid];
+          for (int l = 0; l < j; ++l) v = v - s_L[j][l] * s_U[l][tid];
+          s_U[j][tid] = v;
+          Ab[c + j + (long)cc * lda] = v;
         }
       }
       __syncthreads();
@@ -319,12 +314,13 @@ template <typename R> struct SwCols { static constexpr int v = 8 * 16 / (int)siz
 template <typename R>
 __global__ __launch_bounds__(256) void lu_permute_kernel(cplx<R>* X, long ldx, long sX, int ncols,
                                                          const int* ipiv, int ipiv_stride, int k,
-                                                         int nbe) {
+                                                         int nbe, const int* active) {
   __shared__ int t_row[2 * MAXNB], t_src[2 * MAXNB];
   __shared__ int s_cnt;
   constexpr int SWC = SwCols<R>::v;
   __shared__ cplx<R> vals[2 * MAXNB][SWC];
   const int b = blockIdx.y;
+  if (active && !active[b]) return;
   const int tid = threadIdx.x;
   const int* pv = ipiv + (long)b * ipiv_stride;
   cplx<R>* Xb = X + (long)b * sX;
@@ -376,14 +372,15 @@ __global__ __launch_bounds__(256) void lu_permute_kernel(cplx<R>* X, long ldx, l
 
 template <typename R>
 static int launch_permute(cplx<R>* X, long ldx, long sX, int ncols, const int* ipiv,
-                          int ipiv_stride, int k, int nbe, int batch, hipStream_t s) {
+                          int ipiv_stride, int k, int nbe, int batch, hipStream_t s,
+                          const int* active = nullptr) {
   if (ncols <= 0) return ST_OK;
   dim3 grid((unsigned)cdivl(ncols, SwCols<R>::v), (unsigned)batch);
   KernelTimer kt("lu_permute", s, 0.0, 4.0 * sizeof(cplx<R>) * nbe * (double)ncols * batch,
                  timers_on() ? std::string("lu_permute_kernel<") + (sizeof(R) == 8 ? "double" : "float") + ">"
                              : std::string());
   hipLaunchKernelGGL((lu_permute_kernel<R>), grid, dim3(256), 0, s, X, ldx, sX, ncols, ipiv,
-                     ipiv_stride, k, nbe);
+                     ipiv_stride, k, nbe, active);
   RSRR_LAUNCH_CHECK();
   return ST_OK;
 }
@@ -433,45 +430,80 @@ int lu_factor(const LUWork<R>& w, hipStream_t s) {
   const int n = w.n, nb = w.nb;
   const long sD = (long)w.npanel() * 2 * nb * nb;
   const std::string t_trsm = std::string(w.tag) + "_trsm", t_upd = std::string(w.tag) + "_update";
-  for (int k = 0; k < n; k += nb) {
-    const int nbe = min(nb, n - k);
-    RSRR_TRY(launch_panel<R>(w, k, nbe, s));
-    const int rest = n - k - nbe;
-    if (rest <= 0) continue;
-    RSRR_TRY(launch_permute<R>(w.A + (long)(k + nbe) * w.lda, w.lda, w.sA, rest, w.ipiv, n, k,
-                               nbe, w.batch, s));
-    GemmBatch<R> g;                       // U12 = inv(L11) A12 (in place)
-    g.M = nbe; g.N = rest; g.K = nbe;
+  // U12 = inv(L11) A12 on columns [c0, c0 + nc) (in place)
+  auto trsm = [&](int k, int nbe, int c0, int nc, hipStream_t st) -> int {
+    GemmBatch<R> g;
+    g.M = nbe; g.N = nc; g.K = nbe;
     g.A = w.dinv + (long)(k / nb) * 2 * nb * nb; g.lda = nb; g.sA = sD;
-    g.B = w.A + k + (long)(k + nbe) * w.lda; g.ldb = w.lda; g.sB = w.sA;
-    g.C = w.A + k + (long)(k + nbe) * w.lda; g.ldc = w.lda; g.sC = w.sA;
+    g.B = w.A + k + (long)c0 * w.lda; g.ldb = w.lda; g.sB = w.sA;
+    g.C = w.A + k + (long)c0 * w.lda; g.ldc = w.lda; g.sC = w.sA;
     g.batch = w.batch;
     g.tag = t_trsm.c_str();
     g.gauss3m = w.gauss3m;
-    RSRR_TRY(gemm_batched<R>(g, s));
-    GemmBatch<R> u;                       // A22 -= L21 U12
-    u.M = rest; u.N = rest; u.K = nbe;
+    return gemm_batched<R>(g, st);
+  };
+  // A22 -= L21 U12 on columns [c0, c0 + nc)
+  auto update = [&](int k, int nbe, int c0, int nc, hipStream_t st) -> int {
+    GemmBatch<R> u;
+    u.M = n - k - nbe; u.N = nc; u.K = nbe;
     u.alpha = mk<R>(-1, 0); u.beta = mk<R>(1, 0);
     u.A = w.A + (k + nbe) + (long)k * w.lda; u.lda = w.lda; u.sA = w.sA;
-    u.B = w.A + k + (long)(k + nbe) * w.lda; u.ldb = w.lda; u.sB = w.sA;
-    u.C = w.A + (k + nbe) + (long)(k + nbe) * w.lda; u.ldc = w.lda; u.sC = w.sA;
+    u.B = w.A + k + (long)c0 * w.lda; u.ldb = w.lda; u.sB = w.sA;
+    u.C = w.A + (k + nbe) + (long)c0 * w.lda; u.ldc = w.lda; u.sC = w.sA;
     u.batch = w.batch;
     u.tag = t_upd.c_str();
     u.gauss3m = w.gauss3m;
-    RSRR_TRY(gemm_batched<R>(u, s));
+    return gemm_batched<R>(u, st);
+  };
+  // With look-ahead, step k updates the next panel's columns on s and starts
+  // the next panel at once, while the columns beyond it are updated on aux:
+  //   s:   [wait aux(k-1)] next-panel permute/trsm/update, panel k+1, record main
+  //   aux: wait main(panel k), far permute/trsm/update, record aux
+  const bool la = (w.aux != nullptr && w.ev_main != nullptr && w.ev_aux != nullptr);
+  bool aux_busy = false;
+  RSRR_TRY(launch_panel<R>(w, 0, min(nb, n), s));
+  if (la) RSRR_HIP(hipEventRecord(w.ev_main, s));
+  for (int k = 0; k < n; k += nb) {
+    const int nbe = min(nb, n - k);
+    const int rest = n - k - nbe;
+    if (rest <= 0) break;
+    const int c1 = k + nbe;
+    const int nxt = la ? min(nb, rest) : rest;
+    const int far = rest - nxt;
+    if (aux_busy) {              // the next panel's columns had step k-1's far update
+      RSRR_HIP(hipStreamWaitEvent(s, w.ev_aux, 0));
+      aux_busy = false;
+    }
+    if (far > 0) {
+      RSRR_HIP(hipStreamWaitEvent(w.aux, w.ev_main, 0));
+      RSRR_TRY(launch_permute<R>(w.A + (long)(c1 + nxt) * w.lda, w.lda, w.sA, far, w.ipiv, n, k, nbe,
+                                 w.batch, w.aux));
+      RSRR_TRY(trsm(k, nbe, c1 + nxt, far, w.aux));
+      RSRR_TRY(update(k, nbe, c1 + nxt, far, w.aux));
+      RSRR_HIP(hipEventRecord(w.ev_aux, w.aux));
+      aux_busy = true;
+    }
+    RSRR_TRY(launch_permute<R>(w.A + (long)c1 * w.lda, w.lda, w.sA, nxt, w.ipiv, n, k, nbe, w.batch, s));
+    RSRR_TRY(trsm(k, nbe, c1, nxt, s));
+    RSRR_TRY(update(k, nbe, c1, nxt, s));
+    if (c1 < n) {
+      RSRR_TRY(launch_panel<R>(w, c1, min(nb, n - c1), s));
+      if (la) RSRR_HIP(hipEventRecord(w.ev_main, s));
+    }
   }
+  if (aux_busy) RSRR_HIP(hipStreamWaitEvent(s, w.ev_aux, 0));
   return ST_OK;
 }
 
 template <typename R>
-int lu_solve(const LUWork<R>& w, cplx<R>* B, long ldb, long sB, int nrhs, hipStream_t s) {
+int lu_solve(const LUWork<R>& w, cplx<R>* B, long ldb, long sB, int nrhs, hipStream_t s, const int* active) {
   if (w.n <= 0 || w.batch <= 0 || nrhs <= 0) return ST_OK;
   const int n = w.n, nb = w.nb;
   const std::string t_solve = std::string(w.tag) + "_solve";
   const long sD = (long)w.npanel() * 2 * nb * nb;
   for (int k = 0; k < n; k += nb) {                      // forward: L
     const int nbe = min(nb, n - k);
-    RSRR_TRY(launch_permute<R>(B, ldb, sB, nrhs, w.ipiv, n, k, nbe, w.batch, s));
+    RSRR_TRY(launch_permute<R>(B, ldb, sB, nrhs, w.ipiv, n, k, nbe, w.batch, s, active));
     GemmBatch<R> g;
     g.M = nbe; g.N = nrhs; g.K = nbe;
     g.A = w.dinv + (long)(k / nb) * 2 * nb * nb; g.lda = nb; g.sA = sD;
@@ -480,6 +512,7 @@ int lu_solve(const LUWork<R>& w, cplx<R>* B, long ldb, long sB, int nrhs, hipStr
     g.batch = w.batch;
     g.tag = t_solve.c_str();
     g.gauss3m = w.gauss3m;
+    g.active = active;
     RSRR_TRY(gemm_batched<R>(g, s));
     const int rest = n - k - nbe;
     if (rest > 0) {
@@ -492,6 +525,7 @@ int lu_solve(const LUWork<R>& w, cplx<R>* B, long ldb, long sB, int nrhs, hipStr
       u.batch = w.batch;
       u.tag = t_solve.c_str();
       u.gauss3m = w.gauss3m;
+      u.active = active;
       RSRR_TRY(gemm_batched<R>(u, s));
     }
   }
@@ -505,6 +539,7 @@ int lu_solve(const LUWork<R>& w, cplx<R>* B, long ldb, long sB, int nrhs, hipStr
     g.batch = w.batch;
     g.tag = t_solve.c_str();
     g.gauss3m = w.gauss3m;
+    g.active = active;
     RSRR_TRY(gemm_batched<R>(g, s));
     if (k > 0) {
       GemmBatch<R> u;
@@ -516,6 +551,7 @@ int lu_solve(const LUWork<R>& w, cplx<R>* B, long ldb, long sB, int nrhs, hipStr
       u.batch = w.batch;
       u.tag = t_solve.c_str();
       u.gauss3m = w.gauss3m;
+      u.active = active;
       RSRR_TRY(gemm_batched<R>(u, s));
     }
   }
@@ -524,7 +560,7 @@ int lu_solve(const LUWork<R>& w, cplx<R>* B, long ldb, long sB, int nrhs, hipStr
 
 template int lu_factor<double>(const LUWork<double>&, hipStream_t);
 template int lu_factor<float>(const LUWork<float>&, hipStream_t);
-template int lu_solve<double>(const LUWork<double>&, c128*, long, long, int, hipStream_t);
-template int lu_solve<float>(const LUWork<float>&, c64*, long, long, int, hipStream_t);
+template int lu_solve<double>(const LUWork<double>&, c128*, long, long, int, hipStream_t, const int*);
+template int lu_solve<float>(const LUWork<float>&, c64*, long, long, int, hipStream_t, const int*);
 
 }  // namespace rsrr

@@ -151,6 +151,46 @@ __global__ __launch_bounds__(64) void tri_inv_lower_blocks(const c128* L, long l
   }
 }
 
+// Cholesky of the jb x jb diagonal block at (j0, j0) of G (Hermitian, the
+// lower triangle is used), right-looking in LDS; L11 overwrites the lower
+// triangle.  *bad is set to 1 if a pivot is not positive.
+__global__ __launch_bounds__(256) void chol_diag_kernel(c128* G, long ldg, int j0, int jb, int* bad) {
+  __shared__ c128 a[PBS][PBS + 1];
+  const int tid = threadIdx.x;
+  c128* B = G + j0 + (long)j0 * ldg;
+  for (int e = tid; e < jb * jb; e += 256) {
+    const int r = e % jb, c = e / jb;
+    a[r][c] = (r >= c) ? B[r + (long)c * ldg] : mk<double>(0, 0);
+  }
+  __syncthreads();
+  int done = jb;
+  for (int k = 0; k < jb; ++k) {
+    const double d = a[k][k].re;
+    if (!(d > 0.0)) { done = k; break; }      // same value in every thread: uniform
+    const double lkk = sqrt(d), rl = 1.0 / lkk;
+    __syncthreads();
+    for (int i = k + 1 + tid; i < jb; i += 256) a[i][k] = rl * a[i][k];
+    if (tid == 0) a[k][k] = mk<double>(lkk, 0);
+    __syncthreads();
+    const int t = jb - k - 1;
+    for (int e = tid; e < t * t; e += 256) {
+      const int i = k + 1 + e % t, j = k + 1 + e / t;
+      if (i >= j) a[i][j] = a[i][j] - a[i][k] * conj(a[j][k]);
+    }
+    __syncthreads();
+  }
+  if (done < jb) {
+    if (tid == 0) *bad = 1;
+    return;
+  }
+  for (int e = tid; e < jb * jb; e += 256) {
+    const int r = e % jb, c = e / jb;
+    if (r >= c) B[r + (long)c * ldg] = a[r][c];
+  }
+}
+
+__global__ void set_int_kernel(int* p, int v) { *p = v; }
+
 __global__ __launch_bounds__(256) void gather_cols_kernel(const c128* S, long lds, const int* perm,
                                                           int rows, int k, c128* out, long ldo) {
   const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -287,16 +327,50 @@ static int trsm_right_lh(const c128* L, long ldl, int k, c128* X, long ldx, int 
   return ST_OK;
 }
 
+// Unpivoted blocked Cholesky of the Hermitian positive definite G (m x m, L
+// in the lower triangle): per block of PBS columns the diagonal block in LDS,
+// L21 = G21 L11^{-H} and G22 -= L21 L21^H as matrix-core GEMMs.
+static int chol_blocked(c128* G, long ldg, int m, Arena& ws, hipStream_t s, bool* ok) {
+  int* bad = nullptr;
+  c128 *inv = nullptr, *tmp = nullptr;
+  RSRR_TRY(ws.get<int>("ch_bad", 1, &bad));
+  RSRR_TRY(ws.get<c128>("ch_inv", (size_t)PBS * PBS, &inv));
+  RSRR_TRY(ws.get<c128>("ch_tmp", (size_t)std::max(1, m) * PBS, &tmp));
+  hipLaunchKernelGGL(set_int_kernel, dim3(1), dim3(1), 0, s, bad, 0);
+  RSRR_LAUNCH_CHECK();
+  for (int j0 = 0; j0 < m; j0 += PBS) {
+    const int jb = std::min(PBS, m - j0);
+    {
+      KernelTimer kt("chol_diag", s, 8.0 * (double)jb * jb * jb / 6, 32.0 * (double)jb * jb, "chol_diag_kernel");
+      hipLaunchKernelGGL(chol_diag_kernel, dim3(1), dim3(256), 0, s, G, ldg, j0, jb, bad);
+      RSRR_LAUNCH_CHECK();
+    }
+    const int rest = m - j0 - jb;
+    if (rest <= 0) break;
+    hipLaunchKernelGGL(tri_inv_lower_blocks, dim3(1), dim3(64), 0, s, G + j0 + (long)j0 * ldg, ldg, jb, PBS, inv);
+    RSRR_LAUNCH_CHECK();
+    c128* L21 = G + (j0 + jb) + (long)j0 * ldg;
+    RSRR_TRY(gemm_z(OP_N, OP_C, rest, jb, jb, ONE, L21, ldg, inv, PBS, ZERO, tmp, rest, s));
+    RSRR_TRY((convert<double, double>(tmp, rest, 0, L21, ldg, 0, rest, jb, 1, s)));
+    RSRR_TRY(gemm_z(OP_N, OP_C, rest, rest, jb, MONE, L21, ldg, L21, ldg, ONE, G + (j0 + jb) + (long)(j0 + jb) * ldg,
+                    ldg, s));
+  }
+  int hb = 0;
+  RSRR_HIP(hipMemcpyAsync(&hb, bad, sizeof(int), hipMemcpyDeviceToHost, s));
+  RSRR_HIP(hipStreamSynchronize(s));
+  *ok = (hb == 0);
+  return ST_OK;
+}
+
 // One Cholesky-QR pass on X (rows x k, in place): X <- X chol(X^H X)^{-H}.
 static int cholqr_pass(c128* X, long ldx, int rows, int k, Arena& ws, hipStream_t s, bool* ok) {
   c128* G = nullptr;
   int* perm = nullptr;
   RSRR_TRY(ws.get<c128>("cq_G", (size_t)k * k, &G));
   RSRR_TRY(ws.get<int>("cq_perm", k, &perm));
+  (void)perm;
   RSRR_TRY(gemm_z(OP_C, OP_N, k, k, rows, ONE, X, ldx, X, ldx, ZERO, G, k, s));
-  int r = 0;
-  RSRR_TRY(pchol(G, k, k, k, 0.0, false, perm, ws, s, &r));
-  *ok = (r == k);
+  RSRR_TRY(chol_blocked(G, k, k, ws, s, ok));
   if (!*ok) return ST_OK;
   return trsm_right_lh(G, k, k, X, ldx, rows, ws, s);
 }
