@@ -61,6 +61,65 @@ def traffic_record(sym: str):
     return rec.get("hbm_bytes_per_launch")
 
 
+def _pmc_rows(folder: str):
+    import csv
+    import glob
+    files = glob.glob(os.path.join(folder, "**", "*counter_collection.csv"), recursive=True)
+    if len(files) != 1:
+        raise SystemExit(f"{folder}: expected one counter_collection.csv, found {len(files)}")
+    return list(csv.DictReader(open(files[0])))
+
+
+def _kernel_sym(name: str) -> str:
+    """Kernel function as the library's timers name it: no return type,
+    namespace or argument list."""
+    name = name.replace("void ", "", 1).replace("rsrr::", "")
+    depth = 0
+    for i, ch in enumerate(name):
+        depth += ch == "<"
+        depth -= ch == ">"
+        if ch == "(" and depth == 0:
+            return name[:i]
+    return name
+
+
+def write_traffic(dirs, sym: str, source: str, copy_mib: int):
+    """HBM bytes per launch of one kernel function from FETCH_SIZE and
+    WRITE_SIZE (KiB per dispatch), each scaled by what the same counter reads
+    for a plain device copy of copy_mib MiB (the copy reads and writes exactly
+    that many bytes)."""
+    f_dir, w_dir, cf_dir, cw_dir = dirs
+    per = {}
+    for tag, folder in (("fetch", f_dir), ("write", w_dir)):
+        vals = [float(r["Counter_Value"]) * 1024.0 for r in _pmc_rows(folder)
+                if _kernel_sym(r["Kernel_Name"]) == sym]
+        if not vals:
+            raise SystemExit(f"{folder}: no dispatch of {sym}")
+        per[tag] = (sum(vals) / len(vals), len(vals))
+    true_bytes = float(copy_mib) * (1 << 20)
+    scale = {}
+    for tag, folder in (("fetch", cf_dir), ("write", cw_dir)):
+        vals = [float(r["Counter_Value"]) * 1024.0 for r in _pmc_rows(folder)
+                if "copyBuffer" in r["Kernel_Name"]]
+        if not vals:
+            raise SystemExit(f"{folder}: no copy dispatch")
+        scale[tag] = true_bytes / (sum(vals) / len(vals))
+    src = os.path.join(ROOT, "paper_1510_07522_amd", "csrc", source)
+    fetch = per["fetch"][0] * scale["fetch"]
+    write = per["write"][0] * scale["write"]
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    rec = json.load(open(path)) if os.path.exists(path) else {}
+    rec[sym] = {"source": source,
+                "source_sha256": hashlib.sha256(open(src, "rb").read()).hexdigest(),
+                "hbm_bytes_per_launch": fetch + write, "fetch_bytes_per_launch": fetch,
+                "write_bytes_per_launch": write, "launches": per["fetch"][1],
+                "fetch_scale": scale["fetch"], "write_scale": scale["write"],
+                "workload": "delay NEP n=2048, N=48, L=48, complex64+IR, one solve "
+                            "(bench.py --steps 1 --warmup 0 --no-cpu --sample-compare 0)"}
+    json.dump(rec, open(path, "w"), indent=1)
+    print(json.dumps(rec[sym], indent=1))
+
+
 def roofline_of(sym: str, t: dict, steps: int):
     bp = kernel_bound(sym)
     if bp is None or t["launches"] == 0:
@@ -157,7 +216,16 @@ def main():
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of this many MiB 5 times (reference "
                          "for scaling the FETCH_SIZE / WRITE_SIZE counters) and exit")
+    ap.add_argument("--traffic-from", nargs=4, default=None,
+                    metavar=("FETCH_DIR", "WRITE_DIR", "COPY_FETCH_DIR", "COPY_WRITE_DIR"),
+                    help="write profiles/traffic.json from four rocprofv3 --pmc output folders "
+                         "(FETCH_SIZE / WRITE_SIZE of the kernel, then of the copy calibration) and exit")
+    ap.add_argument("--traffic-kernel", default="gemm_kernel<double, 0, 0, false, true>")
+    ap.add_argument("--traffic-source", default="gemm.hip")
     a = ap.parse_args()
+    if a.traffic_from:
+        write_traffic(a.traffic_from, a.traffic_kernel, a.traffic_source, a.copy_calibration or 1024)
+        return
     if a.gpus != 1:
         print(json.dumps({"error": "this build runs on exactly one GPU; --gpus must be 1"}))
         sys.exit(2)

@@ -9,9 +9,12 @@
 //        result is refined or self-correcting)
 // A may be real (fp64/fp32 values), which halves the products.
 //
-// Tiling: 64x64 C tile per 256-thread workgroup, 4 waves in a 2x2 layout,
-// each wave owns 32x32 = 2x2 blocks of the 16x16x4 MFMA.  K is staged through
-// LDS 16 at a time with one register-prefetched tile in flight.
+// Tiling: 64x64 C tile per workgroup; complex128 uses 8 waves of 32x16,
+// complex64 4 waves of 32x32 (blocks of the 16x16x4 MFMA).  K is staged
+// through LDS 16 at a time with one register-prefetched tile in flight.  The
+// LDS tiles are stored [k][m ^ (k & 15)]: a store with k running across lanes
+// (column-major B, or A^T / A^H) then hits 16 different banks instead of one,
+// and the MFMA operand reads stay conflict-free.
 #include "common.h"
 #include "kernels.h"
 #include "timers.h"
@@ -112,16 +115,16 @@ __global__ __launch_bounds__(sizeof(R) == 8 ? 512 : 256) void gemm_kernel(GemmBa
       int m, k;
       if (OPA == OP_N) { m = tid & 63; k = (tid >> 6) + (NT / 64) * p; }
       else             { k = tid & 15; m = (tid >> 4) + (NT / 16) * p; }
-      As_re[k][m] = ra[p].re;
-      if (!AREAL) As_im[k][m] = ra[p].im;
+      As_re[k][m ^ (k & 15)] = ra[p].re;
+      if (!AREAL) As_im[k][m ^ (k & 15)] = ra[p].im;
     }
 #pragma unroll
     for (int p = 0; p < LP; ++p) {
       int n, k;
       if (OPB == OP_N) { k = tid & 15; n = (tid >> 4) + (NT / 16) * p; }
       else             { n = tid & 63; k = (tid >> 6) + (NT / 64) * p; }
-      Bs_re[k][n] = rb[p].re;
-      Bs_im[k][n] = rb[p].im;
+      Bs_re[k][n ^ (k & 15)] = rb[p].re;
+      Bs_im[k][n ^ (k & 15)] = rb[p].im;
     }
   };
 
@@ -134,16 +137,17 @@ __global__ __launch_bounds__(sizeof(R) == 8 ? 512 : 256) void gemm_kernel(GemmBa
 #pragma unroll
     for (int kq = 0; kq < BK / 4; ++kq) {
       const int kk = kq * 4 + (lane >> 4);
+      const int sw = (lane & 15) ^ (kk & 15);      // swizzled column within a 16-block
       R ar[2], ai[2], br[WJ], bi[WJ];
 #pragma unroll
       for (int i = 0; i < 2; ++i) {
-        int mm = wm * 32 + i * 16 + (lane & 15);
+        int mm = wm * 32 + i * 16 + sw;
         ar[i] = As_re[kk][mm];
         ai[i] = AREAL ? R(0) : As_im[kk][mm];
       }
 #pragma unroll
       for (int j = 0; j < WJ; ++j) {
-        int nn = wn * 16 * WJ + j * 16 + (lane & 15);
+        int nn = wn * 16 * WJ + j * 16 + sw;
         br[j] = Bs_re[kk][nn];
         bi[j] = Bs_im[kk][nn];
       }
