@@ -68,17 +68,40 @@ typedef struct {
   rsrr_complex t;    /* exponent rate (EXP) or pole (RAT); unused for POW */
 } rsrr_fn;
 
-/* Ellipse phi(theta) = center + a cos(theta) + i b sin(theta) (eq.
- * eq-contour); a is the semi-axis along the real direction, b along the
- * imaginary one (a = b = r for a circle).  Interior = strictly inside. */
-typedef struct { rsrr_complex center; double a, b; } rsrr_contour;
+/* Closed contour C of Alg. 2 Step 1 and Alg. 1 Step 1; interior = strictly
+ * inside.  The same contour gives the sampling nodes (N of them) and the
+ * moment quadrature of the reduced problem (NS nodes).
+ *
+ * RSRR_CONTOUR_ELLIPSE (kind 0, the zero-initialised default):
+ *   phi(theta) = center + a cos(theta) + i b sin(theta) (eq. eq-contour), a the
+ *   semi-axis along the real direction, b along the imaginary one (a = b = r
+ *   for a circle); trapezoid angles theta_j = 2 pi (j + 1/2)/N.
+ * RSRR_CONTOUR_RECT (kind 1): the rectangle center + [-a, a] x i[-b, b] (a, b
+ *   the half-sides), with Gauss-Legendre nodes on each of its four sides
+ *   (the paper's rectangular contours, numerical examples of Sec. 7),
+ *   counter-clockwise from the lower-left corner: bottom, right, top, left.
+ *   n_h nodes on each horizontal side and n_v on each vertical side for the
+ *   sampling nodes, so N = 2 (n_h + n_v) (the paper's "10-5" split is n_h = 10,
+ *   n_v = 5 for a wide rectangle).  n_h = n_v = 0 splits N (even, >= 4) in
+ *   proportion to the side lengths: n_h = round(N/2 * a/(a+b)) clamped to
+ *   [1, N/2 - 1]; the NS moment nodes are always split that way (NS even).
+ * Moments and the winding count use rho = max(a, b) and the quadrature
+ * weights dz_j / (2 pi i) of the contour integral (for the ellipse this is
+ * eq. eq-Ap-num). */
+enum { RSRR_CONTOUR_ELLIPSE = 0, RSRR_CONTOUR_RECT = 1 };
+typedef struct {
+  rsrr_complex center;
+  double a, b;
+  int kind;           /* RSRR_CONTOUR_* */
+  int n_h, n_v;       /* RECT only: sampling nodes per horizontal / vertical side, or 0, 0 */
+} rsrr_contour;
 
 enum { RSRR_PREC_C128 = 0, RSRR_PREC_C64_IR = 1 };
 
 typedef struct {
-  int N;              /* sampling nodes on the contour (trapezoid angles 2 pi (j+1/2)/N) */
+  int N;              /* sampling nodes on the contour (see rsrr_contour) */
   int L;              /* probing vectors (columns of U) */
-  int NS;             /* trapezoid nodes of the reduced problem (eq. eq-Ap-num), default 512 */
+  int NS;             /* quadrature nodes of the reduced problem (eq. eq-Ap-num), default 512 */
   int K;              /* Hankel blocks (eq. eq-HH), default 2 */
   double delta;       /* basis truncation: keep singular directions above delta*sigma_1, default 1e-14 */
   double tol_gap;     /* singular-value gap threshold (eq. eq-gap), default 1e3 */

@@ -42,13 +42,18 @@ __all__ = [
 
 @dataclasses.dataclass
 class Contour:
-    """Ellipse phi(t) = center + a cos t + i b sin t (eq. eq-contour).
-
-    a is the semi-axis along the real direction, b along the imaginary one; a
-    circle of radius r has a = b = r."""
+    """Closed contour.  kind "ellipse": phi(t) = center + a cos t + i b sin t
+    (eq. eq-contour), a the semi-axis along the real direction, b along the
+    imaginary one (a circle of radius r has a = b = r).  kind "rect": the
+    rectangle center + [-a, a] x i[-b, b] with nh sampling nodes on each
+    horizontal side and nv on each vertical side (0, 0: split in proportion to
+    the side lengths)."""
     center: complex
     a: float
     b: float
+    kind: str = "ellipse"
+    nh: int = 0
+    nv: int = 0
 
 
 @dataclasses.dataclass

@@ -11,7 +11,7 @@ Method (Xiao, Meng, Zhang, Zheng, "Resolvent sampling based Rayleigh-Ritz
 method for large-scale nonlinear eigenvalue problems", arXiv 1510.07522):
 
   Alg. 2 (RSRR)
-    Step 1  contour, N, L, random U, sampling nodes z_i            contour_nodes
+    Step 1  contour, N, L, random U, sampling nodes z_i            contour_quadrature
     Step 2  Y_i = T(z_i)^{-1} U                                     sample_resolvent
     Step 3  S_hat = [Y_0 ... Y_{N-1}] (eq. eq-hatS), truncated SVD  truncated_basis
     Step 4  T_S(z) = S^H T(z) S (eq. eq-Ts-NEP, eq-Zs-expr)         project_coefficients
@@ -43,6 +43,14 @@ design notes with its reason):
       ||T(l) v||_2 / ||v||_2 is reported too.
   R8  eigenvectors are scaled to unit 2-norm with the entry of largest modulus
       real and positive.
+  R12 rectangular contours (the paper's Sec. 7 examples): Gauss-Legendre
+      nodes on each side, counter-clockwise from the lower-left corner
+      (bottom, right, top, left); the sampling split (nh per horizontal side,
+      nv per vertical side) is given, or N/2 is split in proportion to the
+      side lengths, nh = round(N/2 a/(a+b)) clamped to [1, N/2-1]; the moment
+      nodes are always split that way.  Moments and the winding number use
+      the quadrature weights dz/(2 pi i) and rho = max(a, b) as for the
+      ellipse.
 """
 from __future__ import annotations
 
@@ -143,11 +151,71 @@ def contour_nodes(c: Contour, N: int):
     return theta, z.astype(np.complex128), dz.astype(np.complex128)
 
 
+def gauss_legendre(n: int):
+    """n-point Gauss-Legendre rule on [-1, 1]: the nodes are the eigenvalues of
+    the symmetric tridiagonal Jacobi matrix of the Legendre polynomials
+    (off-diagonal k / sqrt(4k^2 - 1)), polished by two Newton steps on P_n;
+    the weights are 2 / ((1 - x^2) P_n'(x)^2)."""
+    if n == 1:
+        return np.zeros(1), np.full(1, 2.0)
+    k = np.arange(1, n)
+    x = sla.eigvalsh_tridiagonal(np.zeros(n), k / np.sqrt(4.0 * k * k - 1.0))
+
+    def p_and_dp(t):
+        p_prev, p = np.ones_like(t), t.copy()
+        for j in range(2, n + 1):
+            p_prev, p = p, ((2 * j - 1) * t * p - (j - 1) * p_prev) / j
+        return p, n * (t * p - p_prev) / (t * t - 1.0)
+
+    for _ in range(2):
+        p, dp = p_and_dp(x)
+        x = x - p / dp
+    x = np.sort(x)
+    x = 0.5 * (x - x[::-1])                       # exact symmetry
+    _, dp = p_and_dp(x)
+    w = 2.0 / ((1.0 - x) * (1.0 + x) * dp * dp)
+    w = 0.5 * (w + w[::-1])
+    return x, w
+
+
+def rect_split(c: Contour, N: int, sampling: bool):
+    """Nodes per horizontal and per vertical side of a rectangle (R12)."""
+    if sampling and (c.nh or c.nv):
+        assert c.nh > 0 and c.nv > 0 and N == 2 * (c.nh + c.nv), "N = 2 (nh + nv)"
+        return c.nh, c.nv
+    assert N >= 4 and N % 2 == 0, "rectangle needs an even node count >= 4"
+    half = N // 2
+    nh = min(max(int(math.floor(half * c.a / (c.a + c.b) + 0.5)), 1), half - 1)
+    return nh, half - nh
+
+
+def contour_quadrature(c: Contour, N: int, sampling: bool = True):
+    """Nodes z_j and weights dz_j with  integral of g(z) dz ~ sum_j dz_j g(z_j).
+    Ellipse: trapezoid rule in theta, dz_j = (2 pi / N) phi'(theta_j).
+    Rectangle: Gauss-Legendre on each side (R12)."""
+    if c.kind == "ellipse":
+        _, z, dphi = contour_nodes(c, N)
+        return z, (2.0 * math.pi / N) * dphi
+    assert c.kind == "rect"
+    nh, nv = rect_split(c, N, sampling)
+    g, a, b = complex(c.center), c.a, c.b
+    z, dz = [], []
+    # (midpoint, half-side vector) of bottom, right, top, left, counter-clockwise
+    for mid, half, cnt in ((g - 1j * b, a, nh), (g + a, 1j * b, nv),
+                           (g + 1j * b, -a, nh), (g - a, -1j * b, nv)):
+        x, w = gauss_legendre(cnt)
+        z.append(mid + half * x)
+        dz.append(half * w)
+    return np.concatenate(z).astype(np.complex128), np.concatenate(dz).astype(np.complex128)
+
+
 def inside(c: Contour, lam) -> np.ndarray:
     lam = np.asarray(lam, np.complex128)
-    q = ((lam.real - np.real(c.center)) / c.a) ** 2 + \
-        ((lam.imag - np.imag(c.center)) / c.b) ** 2
-    return q < 1.0
+    xr = (lam.real - np.real(c.center)) / c.a
+    xi = (lam.imag - np.imag(c.center)) / c.b
+    if c.kind == "rect":
+        return (np.abs(xr) < 1.0) & (np.abs(xi) < 1.0)
+    return xr ** 2 + xi ** 2 < 1.0
 
 
 # --------------------------------------------------------------------------
@@ -264,9 +332,10 @@ def reduced_from_chebyshev(prob, S, center: float, a: float, d: int) -> ReducedN
 # Alg. 1: modified block SS for the reduced NEP.
 # --------------------------------------------------------------------------
 def reduced_moments(red: ReducedNEP, c: Contour, NS: int, K: int):
-    """Moments A_alpha, alpha < 2K, of T_S^{-1} by the N_S-point trapezoid
-    rule (eq. eq-Ap-num) and the winding-number count (eq. eq-ncs)."""
-    theta, zeta, dzeta = contour_nodes(c, NS)
+    """Moments A_alpha, alpha < 2K, of T_S^{-1} by the N_S-point quadrature of
+    the contour (trapezoid rule on the ellipse = eq. eq-Ap-num; Gauss-Legendre
+    on a rectangle, R12) and the winding-number count (eq. eq-ncs)."""
+    zeta, dz = contour_quadrature(c, NS, sampling=False)
     rho = max(c.a, c.b)
     k = red.k
     A = [np.zeros((k, k), np.complex128) for _ in range(2 * K)]
@@ -275,7 +344,7 @@ def reduced_moments(red: ReducedNEP, c: Contour, NS: int, K: int):
     for m in range(NS):
         X = sla.solve(red.T(zeta[m]), I)            # T_S(zeta_m)^{-1}
         s = (zeta[m] - c.center) / rho
-        w = dzeta[m] / (1j * NS)
+        w = dz[m] / (2j * math.pi)
         for alpha in range(2 * K):
             A[alpha] += (w * s ** alpha) * X
         # tr(X T_S') = sum_ij X_ij T_S'_ji
@@ -369,7 +438,7 @@ def rsrr(prob, c: Contour, N: int, L: int, U: np.ndarray, NS: int = 512,
     residual <= tol_res, sorted by (Re, Im), their eigenvectors and residuals,
     plus every intermediate the GPU path is compared against."""
     assert U.shape == (prob.n, L)
-    theta, z, dz = contour_nodes(c, N)
+    z, _ = contour_quadrature(c, N, sampling=True)
     S_hat = sample_resolvent(prob, z, U)
     S, sig_S, kS = truncated_basis(S_hat, delta)
     if isinstance(prob, BemProblem):

@@ -31,7 +31,11 @@ class fn_t(C.Structure):
 
 
 class contour_t(C.Structure):
-    _fields_ = [("center", cplx), ("a", C.c_double), ("b", C.c_double)]
+    _fields_ = [("center", cplx), ("a", C.c_double), ("b", C.c_double), ("kind", C.c_int),
+                ("n_h", C.c_int), ("n_v", C.c_int)]
+
+
+CONTOUR_KIND = {"ellipse": 0, "rect": 1}
 
 
 class params_t(C.Structure):
@@ -167,10 +171,15 @@ def default_params(**kw) -> params_t:
     return p
 
 
-def contour(center: complex, a: float, b: float) -> contour_t:
+def contour(center: complex, a: float, b: float, kind: str = "ellipse", n_h: int = 0,
+            n_v: int = 0) -> contour_t:
+    """Ellipse (semi-axes a, b) or rectangle (half-sides a, b; n_h / n_v
+    sampling nodes per horizontal / vertical side, 0 = split by length)."""
     c = contour_t()
     c.center = cplx(float(np.real(center)), float(np.imag(center)))
     c.a, c.b = float(a), float(b)
+    c.kind = CONTOUR_KIND[kind]
+    c.n_h, c.n_v = int(n_h), int(n_v)
     return c
 
 

@@ -115,15 +115,93 @@ void eval_fn(const rsrr_fn& f, cd z, cd* val, cd* der) {
   }
 }
 
-void contour_nodes(const rsrr_contour* c, int N, std::vector<cd>* z, std::vector<cd>* dz) {
+void gauss_legendre(int n, std::vector<double>* x, std::vector<double>* w) {
+  // roots of P_n by Newton's method from Tricomi's initial guesses; P_n and
+  // P_{n-1} by the three-term recurrence k P_k = (2k-1) x P_{k-1} - (k-1) P_{k-2};
+  // P_n'(x) = n (x P_n - P_{n-1}) / (x^2 - 1); w = 2 / ((1 - x^2) P_n'(x)^2)
+  x->assign(n, 0.0);
+  w->assign(n, 0.0);
+  // P_n(t) and P_n'(t)
+  auto legendre = [n](double t, double* pn, double* dpn) {
+    double p0 = 1.0, p1 = t;
+    for (int k = 2; k <= n; ++k) {
+      const double p2 = ((2.0 * k - 1.0) * t * p1 - (k - 1.0) * p0) / k;
+      p0 = p1;
+      p1 = p2;
+    }
+    *pn = p1;
+    *dpn = n * (t * p1 - p0) / (t * t - 1.0);
+  };
+  for (int i = 0; i < (n + 1) / 2; ++i) {
+    double t = cos(M_PI * (i + 0.75) / (n + 0.5)), pn, dp;
+    for (int it = 0; it < 50; ++it) {           // quadratic convergence: a few steps
+      legendre(t, &pn, &dp);
+      const double dt = pn / dp;
+      t -= dt;
+      if (fabs(dt) < 1e-15) break;
+    }
+    legendre(t, &pn, &dp);
+    t -= pn / dp;                                // one more step at full accuracy
+    legendre(t, &pn, &dp);
+    const double wi = 2.0 / ((1.0 - t * t) * dp * dp);
+    // t is the i-th largest root; store ascending with exact symmetry
+    (*x)[n - 1 - i] = t;
+    (*x)[i] = -t;
+    (*w)[n - 1 - i] = wi;
+    (*w)[i] = wi;
+  }
+  if (n % 2 == 1) (*x)[n / 2] = 0.0;
+}
+
+bool rect_split(const rsrr_contour* c, int N, bool sampling, int* nh, int* nv) {
+  if (sampling && (c->n_h > 0 || c->n_v > 0)) {
+    *nh = c->n_h;
+    *nv = c->n_v;
+    return c->n_h > 0 && c->n_v > 0 && N == 2 * (c->n_h + c->n_v);
+  }
+  if (N < 4 || N % 2) return false;
+  const int half = N / 2;
+  int h = (int)std::lround(half * c->a / (c->a + c->b));
+  h = std::min(std::max(h, 1), half - 1);
+  *nh = h;
+  *nv = half - h;
+  return true;
+}
+
+void contour_nodes(const rsrr_contour* c, int N, bool sampling, std::vector<cd>* z, std::vector<cd>* dz) {
   z->resize(N);
   if (dz) dz->resize(N);
   const cd g(c->center.re, c->center.im);
+  if (c->kind == RSRR_CONTOUR_RECT) {
+    int nh = 0, nv = 0;
+    if (!rect_split(c, N, sampling, &nh, &nv)) return;   // rejected by the parameter check
+    const double a = c->a, b = c->b;
+    // side j: z = p0 + h x, x in [-1, 1], dz = h dx; counter-clockwise
+    const cd p0[4] = {g + cd(0, -b), g + cd(a, 0), g + cd(0, b), g + cd(-a, 0)};
+    const cd hv[4] = {cd(a, 0), cd(0, b), cd(-a, 0), cd(0, -b)};
+    const int cnt[4] = {nh, nv, nh, nv};
+    std::vector<double> x, w;
+    int j = 0;
+    for (int side = 0; side < 4; ++side) {
+      gauss_legendre(cnt[side], &x, &w);
+      for (int k = 0; k < cnt[side]; ++k, ++j) {
+        (*z)[j] = p0[side] + hv[side] * x[k];
+        if (dz) (*dz)[j] = hv[side] * w[k];
+      }
+    }
+    return;
+  }
   for (int j = 0; j < N; ++j) {
     const double th = 2.0 * M_PI * (j + 0.5) / N;
     (*z)[j] = g + cd(c->a * cos(th), c->b * sin(th));
-    if (dz) (*dz)[j] = cd(-c->a * sin(th), c->b * cos(th));
+    if (dz) (*dz)[j] = (2.0 * M_PI / N) * cd(-c->a * sin(th), c->b * cos(th));
   }
+}
+
+bool contour_inside(const rsrr_contour* c, cd lam) {
+  const double xr = (lam.real() - c->center.re) / c->a, xi = (lam.imag() - c->center.im) / c->b;
+  if (c->kind == RSRR_CONTOUR_RECT) return fabs(xr) < 1.0 && fabs(xi) < 1.0;
+  return xr * xr + xi * xi < 1.0;
 }
 
 }  // namespace rsrr
@@ -254,6 +332,16 @@ static int check_params(const rsrr_problem* p, const rsrr_contour* c, const rsrr
   if (!p || !c || !prm) return set_error(ST_EINVAL, "null argument");
   if (prm->N < 1 || prm->L < 1) return set_error(ST_EINVAL, "N and L must be >= 1");
   if (!(c->a > 0) || !(c->b > 0)) return set_error(ST_EINVAL, "contour semi-axes must be > 0");
+  if (c->kind != RSRR_CONTOUR_ELLIPSE && c->kind != RSRR_CONTOUR_RECT)
+    return set_error(ST_EINVAL, "unknown contour kind %d", c->kind);
+  if (c->kind == RSRR_CONTOUR_RECT) {
+    int nh, nv;
+    if (!rect_split(c, prm->N, true, &nh, &nv))
+      return set_error(ST_EINVAL, "rectangle: N=%d does not match n_h=%d, n_v=%d (N = 2(n_h+n_v), or "
+                       "n_h = n_v = 0 and N even >= 4)", prm->N, c->n_h, c->n_v);
+    if (!rect_split(c, prm->NS, false, &nh, &nv))
+      return set_error(ST_EINVAL, "rectangle: NS=%d must be even and >= 4", prm->NS);
+  }
   if (prm->nb < 1 || prm->nb > 64) return set_error(ST_EINVAL, "nb must be in [1, 64]");
   if (prm->precision != RSRR_PREC_C128 && prm->precision != RSRR_PREC_C64_IR)
     return set_error(ST_EINVAL, "unknown precision %d", prm->precision);

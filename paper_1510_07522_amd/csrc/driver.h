@@ -67,7 +67,18 @@ int project_impl(rsrr_problem* p, const rsrr_contour* c, const rsrr_params* prm,
                  long ldq, int kS, c128* B, int* J_out);
 int solve_impl(rsrr_problem* p, const rsrr_contour* c, const rsrr_params* prm, const c128* U,
                rsrr_result* res);
-void contour_nodes(const rsrr_contour* c, int N, std::vector<cd>* z, std::vector<cd>* dz);
+// Gauss-Legendre nodes x (ascending) and weights w of the n-point rule on [-1, 1].
+void gauss_legendre(int n, std::vector<double>* x, std::vector<double>* w);
+// Per-side node counts of a rectangular contour for N nodes in total: the
+// contour's own (n_h, n_v) when `sampling` and they are set, else the split
+// in proportion to the side lengths.  Returns false if N cannot be split.
+bool rect_split(const rsrr_contour* c, int N, bool sampling, int* nh, int* nv);
+// Quadrature of the contour integral with N nodes: integral of g(z) dz ~=
+// sum_j dz[j] g(z[j]).  Sampling nodes when `sampling` (rectangles then use
+// the contour's own per-side counts), moment nodes otherwise.
+void contour_nodes(const rsrr_contour* c, int N, bool sampling, std::vector<cd>* z, std::vector<cd>* dz);
+// lambda strictly inside the contour.
+bool contour_inside(const rsrr_contour* c, cd lam);
 double now_s();
 // Progress line on stderr when RSRR_VERBOSE=1 (stage boundaries of long solves).
 void vlog(const char* fmt, ...);

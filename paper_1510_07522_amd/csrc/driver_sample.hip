@@ -129,7 +129,7 @@ int sample_impl(rsrr_problem* p, const rsrr_contour* c, const rsrr_params* prm, 
   const int n = p->n, N = prm->N, L = prm->L, nb = prm->nb;
   const long nn = (long)n * n;
   std::vector<cd> z;
-  contour_nodes(c, N, &z, nullptr);
+  contour_nodes(c, N, true, &z, nullptr);
   std::vector<c128> f, zc(N);
   for (int j = 0; j < N; ++j) zc[j] = mk<double>(z[j].real(), z[j].imag());
   if (!p->bem) node_coefs(p, z, &f);

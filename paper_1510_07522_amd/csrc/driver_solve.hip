@@ -2,10 +2,12 @@
 // block Sakurai-Sugiura method on the reduced problem (Alg. 1), eigenvector
 // recovery, and the residual filter.
 //
-//   moments   A_a = 1/(i NS) sum_m ((zeta_m - gamma)/rho)^a zeta'_m T_S(zeta_m)^{-1}
-//             (eq. eq-Ap-num), a < 2K, as one GEMM per chunk of nodes over the
-//             batched inverses;
-//   winding   n = 1/(i NS) sum_m zeta'_m tr(T_S(zeta_m)^{-1} T_S'(zeta_m)) (eq. eq-ncs);
+//   moments   A_a = 1/(2 pi i) sum_m dz_m ((zeta_m - gamma)/rho)^a T_S(zeta_m)^{-1},
+//             a < 2K, with the contour's quadrature weights dz_m (ellipse:
+//             dz_m = (2 pi/NS) phi'(theta_m), which is eq. eq-Ap-num;
+//             rectangle: Gauss-Legendre on each side), as one GEMM per chunk of
+//             nodes over the batched inverses;
+//   winding   n = 1/(2 pi i) sum_m dz_m tr(T_S(zeta_m)^{-1} T_S'(zeta_m)) (eq. eq-ncs);
 //   Hankel    H = [A_{i+j}], H^< = [A_{i+j+1}] (eq. eq-HH); SVD of H (eq. eq-svdH);
 //   gap       argmax sigma_j / sigma_{j+1} if >= tol_gap (eq. eq-gap);
 //   extract   A = V0^H H^< W0 S0^{-1} (eq. eq-A), lambda = rho l' + gamma,
@@ -135,7 +137,7 @@ int solve_impl(rsrr_problem* p, const rsrr_contour* c, const rsrr_params* prm, c
   // ---- Alg. 1: moments of T_S^{-1} and the winding number
   t0 = now_s();
   std::vector<cd> zeta, dzeta;
-  contour_nodes(c, NS, &zeta, &dzeta);
+  contour_nodes(c, NS, false, &zeta, &dzeta);
   const double cx = c->center.re, ax = c->a;
   const size_t per = (size_t)kk * sizeof(c128) * 2;
   const int ch = (int)std::max<size_t>(1, std::min<size_t>(NS, (size_t)8e9 / per));
@@ -165,7 +167,7 @@ int solve_impl(rsrr_problem* p, const rsrr_contour* c, const rsrr_params* prm, c
         hg[(size_t)q * J + k] = mk<double>(g[k].real(), g[k].imag());
         hdg[(size_t)q * J + k] = mk<double>(dg[k].real(), dg[k].imag());
       }
-      const cd w = dzeta[m0 + q] / (cd(0, 1) * (double)NS);
+      const cd w = dzeta[m0 + q] / cd(0, 2.0 * M_PI);
       const cd sm = (zeta[m0 + q] - gamma) / rho;
       cd pw(1, 0);
       for (int a = 0; a < 2 * K; ++a) {
@@ -204,7 +206,7 @@ int solve_impl(rsrr_problem* p, const rsrr_contour* c, const rsrr_params* prm, c
     for (int q = 0; q < cnt; ++q) {
       cd tr(0, 0);
       for (int t = 0; t < nchunk; ++t) tr += cd(hpart[(size_t)q * nchunk + t].re, hpart[(size_t)q * nchunk + t].im);
-      wind += dzeta[m0 + q] / (cd(0, 1) * (double)NS) * tr;
+      wind += dzeta[m0 + q] / cd(0, 2.0 * M_PI) * tr;
     }
   }
   info.wind_re = wind.real();
@@ -279,8 +281,7 @@ int solve_impl(rsrr_problem* p, const rsrr_contour* c, const rsrr_params* prm, c
   std::vector<int> inside;
   for (int j = 0; j < m; ++j) {
     lam[j] = rho * lamp[j] + gamma;
-    const double xr = (lam[j].real() - c->center.re) / c->a, xi = (lam[j].imag() - c->center.im) / c->b;
-    if (xr * xr + xi * xi < 1.0) inside.push_back(j);
+    if (contour_inside(c, lam[j])) inside.push_back(j);
   }
   const int nin = (int)inside.size();
   info.n_candidates = nin;

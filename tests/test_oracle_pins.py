@@ -77,6 +77,46 @@ def test_contour_nodes_integrate_cauchy_kernel():
     assert np.allclose(((z - 0.5j) / 1.5) ** 17, -1.0, atol=1e-12)
 
 
+def test_gauss_legendre_closed_forms_and_error_constant():
+    # 2- and 3-point rules in closed form
+    x, w = R.gauss_legendre(2)
+    assert np.allclose(x, [-1 / math.sqrt(3), 1 / math.sqrt(3)], rtol=0, atol=1e-15)
+    assert np.allclose(w, [1.0, 1.0], rtol=0, atol=1e-15)
+    x, w = R.gauss_legendre(3)
+    assert np.allclose(x, [-math.sqrt(0.6), 0.0, math.sqrt(0.6)], rtol=0, atol=1e-15)
+    assert np.allclose(w, [5 / 9, 8 / 9, 5 / 9], rtol=0, atol=1e-15)
+    # an n-point Gauss rule integrates x^k exactly for k <= 2n-1; for x^(2n) it
+    # misses by 2^(2n+1) (n!)^4 / ((2n+1) ((2n)!)^2)
+    for n in (1, 2, 4, 7, 12):
+        x, w = R.gauss_legendre(n)
+        for k in range(2 * n):
+            exact = 2.0 / (k + 1) if k % 2 == 0 else 0.0
+            assert abs(np.sum(w * x ** k) - exact) < 1e-14
+        err = 2.0 / (2 * n + 1) - np.sum(w * x ** (2 * n))
+        E = 2.0 ** (2 * n + 1) * math.factorial(n) ** 4 / ((2 * n + 1) * math.factorial(2 * n) ** 2)
+        assert abs(err - E) <= 1e-14 + 1e-9 * E
+
+
+def test_rect_quadrature_area_polynomials_and_cauchy_kernel():
+    # the paper's "10-5" split: 10 nodes on each long side, 5 on each short one
+    c = ni.Contour(1 + 2j, 1.5, 0.4, kind="rect", nh=10, nv=5)
+    z, dz = R.contour_quadrature(c, 30)
+    assert len(z) == 30
+    assert np.allclose(z[:10].imag, 1.6) and np.allclose(z[10:15].real, 2.5)    # bottom, right
+    assert np.allclose(z[15:25].imag, 2.4) and np.allclose(z[25:].real, -0.5)   # top, left
+    # Green: oint conj(z) dz = 2 i * area (the integrand is linear on each side)
+    assert abs(np.sum(np.conj(z) * dz) - 2j * (3.0 * 0.8)) < 1e-13
+    # Cauchy: oint z^k dz = 0 (each side's rule is exact up to degree 9)
+    for k in range(10):
+        assert abs(np.sum(z ** k * dz)) < 1e-12 * 3.0 ** k
+    # (1/2 pi i) oint dz/(z - p): 1 inside, 0 outside (moment nodes, split by length)
+    z, dz = R.contour_quadrature(c, 256, sampling=False)
+    w = dz / (2j * math.pi)
+    assert abs(np.sum(w / (z - (1.3 + 2.1j))) - 1) < 1e-10
+    assert abs(np.sum(w / (z - (3.5 + 2j)))) < 1e-10
+    assert list(R.inside(c, [1.3 + 2.1j, 2.6 + 2j, 1 + 2.5j, -0.4 + 1.7j])) == [True, False, False, True]
+
+
 # ------------------------------------------------- Step 2: the samples
 def test_sample_diagonal_closed_form():
     rng = np.random.default_rng(3)
@@ -235,6 +275,25 @@ def test_rsrr_diagonal_qep_matches_quadratic_formula():
     ref = lam_all[R.inside(c, lam_all)]
     assert len(out["lam"]) == len(ref) > 3
     assert match_sets(out["lam"], ref) <= 1e-10 * max(np.max(np.abs(ref)), 1.2)
+    assert out["n_wind"] == len(ref)
+    assert np.all(out["res"] < 1e-12)
+
+
+def test_rsrr_rectangle_diagonal_qep_matches_quadratic_formula():
+    # rectangular contour with Gauss-Legendre sides (the paper's Sec. 7 form)
+    rng = np.random.default_rng(33)
+    n = 40
+    m, cc, k = np.ones(n), rng.uniform(0.0, 0.4, n), rng.uniform(1, 30, n)
+    lam_all = quad_roots(m, cc, k)
+    c = ni.Contour(3j, 1.5, 1.0, kind="rect", nh=8, nv=4)
+    xr, xi = np.abs(lam_all.real / 1.5), np.abs((lam_all.imag - 3.0) / 1.0)
+    assert np.min(np.minimum(np.abs(xr - 1), np.abs(xi - 1))) > 0.02
+    p = ni.qep_diag(m, cc, k)
+    U = ni.probing_matrix(n, 4, seed=34)
+    out = R.rsrr(p, c, 24, 4, U, NS=256, K=2)
+    ref = lam_all[(xr < 1) & (xi < 1)]
+    assert len(out["lam"]) == len(ref) > 5
+    assert match_sets(out["lam"], ref) <= 1e-10 * 4.0
     assert out["n_wind"] == len(ref)
     assert np.all(out["res"] < 1e-12)
 
