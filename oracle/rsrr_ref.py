@@ -51,6 +51,12 @@ design notes with its reason):
       nodes are always split that way.  Moments and the winding number use
       the quadrature weights dz/(2 pi i) and rho = max(a, b) as for the
       ellipse.
+  R13 the moment scheme (SSRR, Sec. 3.1-3.2) uses the shifted and scaled
+      monomials s^alpha, s = (z - gamma)/rho, as the paper's own moment
+      formula eq. eq-Ap-num does; over alpha < K' they span the same
+      polynomials as z^alpha, so span(M_hat) is unchanged in exact arithmetic.
+      The weights are the contour's dz/(2 pi i); K' = N by default (the
+      paper's comparisons use K' = N).
 """
 from __future__ import annotations
 
@@ -229,6 +235,23 @@ def sample_resolvent(prob, z_nodes, U: np.ndarray) -> np.ndarray:
     for i, zi in enumerate(z_nodes):
         S_hat[:, i * L:(i + 1) * L] = sla.solve(T_matrix(prob, zi), U)
     return S_hat
+
+
+def moment_matrix(S_hat: np.ndarray, c: Contour, N: int, L: int, Kp: int) -> np.ndarray:
+    """Moment scheme (SSRR): M_hat = [M_0 ... M_{K'-1}] with
+    M_alpha = sum_i w_i s_i^alpha T(z_i)^{-1} U (eq. eq-malpha-qud, eq-hatM),
+    w_i = dz_i / (2 pi i), s_i = (z_i - gamma)/rho (R13); the same matrix as
+    S_hat D Z (eq. eq-hatMS)."""
+    z, dz = contour_quadrature(c, N, sampling=True)
+    rho = max(c.a, c.b)
+    w = dz / (2j * math.pi)
+    s = (z - c.center) / rho
+    n = S_hat.shape[0]
+    M = np.zeros((n, Kp * L), np.complex128, order="F")
+    for alpha in range(Kp):
+        for i in range(N):
+            M[:, alpha * L:(alpha + 1) * L] += (w[i] * s[i] ** alpha) * S_hat[:, i * L:(i + 1) * L]
+    return M
 
 
 # --------------------------------------------------------------------------
@@ -433,14 +456,22 @@ def solve_reduced(red: ReducedNEP, c: Contour, NS: int, K: int,
 def rsrr(prob, c: Contour, N: int, L: int, U: np.ndarray, NS: int = 512,
          K: int = 2, delta: float = 1e-14, tol_gap: float = 1e3,
          tol_res: float = 1e-10, hankel_tol: float = 1e-13,
-         cheb_degree: int = 40) -> Dict:
+         cheb_degree: int = 40, scheme: str = "sampling", Kp: int = 0) -> Dict:
     """Alg. 2 end to end.  Returns eigenvalues strictly inside the contour with
     residual <= tol_res, sorted by (Re, Im), their eigenvectors and residuals,
-    plus every intermediate the GPU path is compared against."""
+    plus every intermediate the GPU path is compared against.  scheme
+    "moment" replaces S_hat by the moment matrix M_hat in Step 3 (SSRR; K'
+    moments, 0 = N)."""
     assert U.shape == (prob.n, L)
     z, _ = contour_quadrature(c, N, sampling=True)
     S_hat = sample_resolvent(prob, z, U)
-    S, sig_S, kS = truncated_basis(S_hat, delta)
+    M_hat = None
+    if scheme == "moment":
+        M_hat = moment_matrix(S_hat, c, N, L, Kp if Kp > 0 else N)
+        S, sig_S, kS = truncated_basis(M_hat, delta)
+    else:
+        assert scheme == "sampling"
+        S, sig_S, kS = truncated_basis(S_hat, delta)
     if isinstance(prob, BemProblem):
         red = reduced_from_chebyshev(prob, S, float(np.real(c.center)), c.a, cheb_degree)
     else:
@@ -456,6 +487,6 @@ def rsrr(prob, c: Contour, N: int, L: int, U: np.ndarray, NS: int = 512,
     order = np.lexsort((lam.imag, lam.real))
     return dict(lam=lam[order], V=V[:, order], res=rel[order], res_paper=raw[order],
                 n_wind=out["n_wind"], wind=out["wind"], n_gap=out["n_gap"],
-                gmax=out["gmax"], m=out["m"], kS=kS, sigma_S=sig_S, S_hat=S_hat,
+                gmax=out["gmax"], m=out["m"], kS=kS, sigma_S=sig_S, S_hat=S_hat, M_hat=M_hat,
                 S=S, nodes=z, hankel_sigma=out["hankel_sigma"],
                 n_inside_candidates=int(keep.sum()))

@@ -224,6 +224,65 @@ def test_moments_equal_trapezoid_rational_filter():
     assert abs(wind - np.sum(1 / (1 + s ** NS))) < 1e-12
 
 
+def test_moment_matrix_equals_trapezoid_rational_filter():
+    # SSRR moments of T(z) = z I - diag(d) on a circle: the N-point trapezoid
+    # rule gives M_alpha = diag(s^alpha / (1 + s^N)) U, s = (d - gamma)/rho
+    rng = np.random.default_rng(5)
+    d = rng.uniform(-2, 2, 11) + 1j * rng.uniform(-2, 2, 11)
+    p = linear_diag_problem(d)
+    c = ni.Contour(0.3 - 0.2j, 1.8, 1.8)
+    N, L, Kp = 20, 3, 7
+    U = ni.probing_matrix(11, L, seed=6)
+    z, _ = R.contour_quadrature(c, N)
+    M = R.moment_matrix(R.sample_resolvent(p, z, U), c, N, L, Kp)
+    s = (d - c.center) / 1.8
+    for alpha in range(Kp):
+        want = (s ** alpha / (1 + s ** N))[:, None] * U
+        assert np.allclose(M[:, alpha * L:(alpha + 1) * L], want, rtol=0, atol=1e-13)
+
+
+def test_moment_span_inside_sampling_span():
+    # eq. eq-setsMS: span(M_hat) within span(S_hat); with K' = N and M_hat of
+    # full rank the two spans coincide
+    p, c, N, L, U = ni.config_small_qep(n=48, seed=7)
+    z, _ = R.contour_quadrature(c, N)
+    S = R.sample_resolvent(p, z, U)
+    Q, _ = np.linalg.qr(S)
+    for Kp in (3, N):
+        M = R.moment_matrix(S, c, N, L, Kp)
+        assert np.linalg.norm(M - Q @ (Q.conj().T @ M)) <= 1e-12 * np.linalg.norm(M)
+    # 4 nodes, one probe, n = 10: S_hat and M_hat = S_hat D Z are 10 x 4 of full
+    # rank (D Z is an invertible Vandermonde-times-diagonal matrix)
+    rng = np.random.default_rng(9)
+    p2 = linear_diag_problem(rng.uniform(-3, 3, 10) + 1j * rng.uniform(-3, 3, 10))
+    c2 = ni.Contour(0.2, 1.0, 1.0)
+    U2 = ni.probing_matrix(10, 1, seed=3)
+    z2, _ = R.contour_quadrature(c2, 4)
+    S2 = R.sample_resolvent(p2, z2, U2)
+    M2 = R.moment_matrix(S2, c2, 4, 1, 4)
+    assert np.linalg.matrix_rank(M2) == np.linalg.matrix_rank(S2) == 4
+    for A, B in ((M2, S2), (S2, M2)):
+        Qb, _ = np.linalg.qr(B)
+        assert np.linalg.norm(A - Qb @ (Qb.conj().T @ A)) <= 1e-12 * np.linalg.norm(A)
+
+
+def test_moment_scheme_loses_eigenpairs_on_acoustic_1d_with_one_probe():
+    # the paper's comparison on Acoustic-1D with L = 1: the sampling scheme
+    # still returns the 40 eigenpairs accurately, the moment scheme (K' = N)
+    # about 32, most of them wrong
+    g, g1 = GOLD["acoustic_1d"], GOLD["acoustic_1d_L1"]
+    p = ni.acoustic_1d(g["n"])
+    c = ni.Contour(complex(*g["center"]), g["a"], g["b"])
+    U = ni.probing_matrix(g["n"], g1["L"], seed=10)
+    kw = dict(NS=g["NS"], K=g["K"], tol_res=1.0)
+    rs = R.rsrr(p, c, g["N"], g1["L"], U, **kw)
+    mo = R.rsrr(p, c, g["N"], g1["L"], U, scheme="moment", **kw)
+    assert len(rs["lam"]) == g1["rsrr_count"] and np.all(rs["res"] <= 1e-10)
+    assert abs(len(mo["lam"]) - g1["ssrr_count"]) <= 5 and len(mo["lam"]) < g1["rsrr_count"]
+    assert np.sum(mo["res"] <= 1e-8) < len(mo["lam"]) / 2
+    assert mo["kS"] < rs["kS"]
+
+
 def test_hankel_extraction_recovers_linear_spectrum():
     rng = np.random.default_rng(8)
     d = rng.uniform(-2, 2, 14) + 1j * rng.uniform(-1, 1, 14)
