@@ -208,6 +208,10 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="c1")
     ap.add_argument("--precision", default="c64_ir", choices=["c64_ir", "c128"])
+    ap.add_argument("--scheme", default="sampling", choices=["sampling", "moment"],
+                    help="subspace of Alg. 2 Step 3: sampling matrix (RSRR) or moment matrix (SSRR, K' = N)")
+    ap.add_argument("--contour", default="ellipse", choices=["ellipse", "rect"],
+                    help="rect: the square inscribed in the workload's circle, Gauss-Legendre sides")
     ap.add_argument("--cpu-nodes", type=int, default=4)
     ap.add_argument("--cpu-budget", type=float, default=20.0)
     ap.add_argument("--no-cpu", action="store_true")
@@ -245,11 +249,18 @@ def main():
 
     w = workload(a.workload)
     prob, c, N, L = w["prob"], w["contour"], w["N"], w["L"]
+    if a.contour == "rect":
+        r = min(c.a, c.b) / np.sqrt(2.0)
+        w["desc"] += f"; contour: inscribed square, half-side {r:.4f}, Gauss-Legendre sides"
+        ct = P.contour(c.center, r, r, kind="rect")
+    else:
+        ct = P.contour(c.center, c.a, c.b)
+    if a.scheme == "moment":
+        w["desc"] += "; moment scheme (SSRR), K' = N"
     log(f"workload {a.workload}: {w['desc']}")
     h = P.Problem(prob)
     U = P.to_device(w["U"])
-    ct = P.contour(c.center, c.a, c.b)
-    prm = P.default_params(N=N, L=L, precision=a.precision)
+    prm = P.default_params(N=N, L=L, precision=a.precision, scheme=a.scheme)
 
     for i in range(a.warmup):
         t0 = time.perf_counter()
@@ -325,7 +336,8 @@ def main():
         "dtype": "c64+f64" if a.precision == "c64_ir" else "c128",
         "data": "synthetic (seeded)",
         "config": {"workload": a.workload, "description": w["desc"], "n": prob.n, "N": N, "L": L,
-                   "NS": prm.NS, "K": prm.K, "precision": a.precision, "parallelism": "single GPU"},
+                   "NS": prm.NS, "K": prm.K, "precision": a.precision, "scheme": a.scheme,
+                   "contour": a.contour, "parallelism": "single GPU"},
         "eigenpairs_per_s": eig_s,
         "n_eig": n_eig[-1],
         "latency_s": {"p50": float(np.percentile(lat_s, 50)), "p99": float(np.percentile(lat_s, 99))},

@@ -98,6 +98,12 @@ typedef struct {
 
 enum { RSRR_PREC_C128 = 0, RSRR_PREC_C64_IR = 1 };
 
+/* How Alg. 2 Step 3 builds its subspace: from the sampling matrix S_hat
+ * (eq. eq-hatS, the resolvent sampling scheme; default) or from the moment
+ * matrix M_hat = S_hat D Z (eq. eq-hatMS, the moment scheme of SSRR,
+ * Sec. 3.1; see rsrr_moment_matrix). */
+enum { RSRR_SCHEME_SAMPLING = 0, RSRR_SCHEME_MOMENT = 1 };
+
 typedef struct {
   int N;              /* sampling nodes on the contour (see rsrr_contour) */
   int L;              /* probing vectors (columns of U) */
@@ -113,6 +119,8 @@ typedef struct {
   int cheb_degree;    /* BEM only: Chebyshev degree d (eq. eq-T-interp), default 40 */
   int nb;             /* LU panel width (1..64), default 64 */
   uint64_t seed;      /* seed of the probing matrix when U is not supplied */
+  int scheme;         /* RSRR_SCHEME_SAMPLING (default) or RSRR_SCHEME_MOMENT */
+  int Kp;             /* moment scheme: number of moments K' (0 = N, as in the paper's comparisons) */
 } rsrr_params;
 
 /* Diagnostics of one solve. */
@@ -162,6 +170,19 @@ void rsrr_destroy(rsrr_problem* p);
  * info (may be NULL) receives ir_iters / ir_fallback / t_sample. */
 int rsrr_sample(rsrr_problem* p, const rsrr_contour* c, const rsrr_params* prm,
                 const rsrr_complex* U, int ldu, rsrr_complex* S, int lds, rsrr_info* info);
+
+/* Moment scheme (SSRR, Sec. 3.1-3.2): from the sampling matrix S_hat of
+ * rsrr_sample (device, n x N*L, leading dim lds, block i = T(z_i)^{-1} U), the
+ * moment matrix M_hat = [M_0 ... M_{K'-1}] (eq. eq-hatM; device, n x K'*L,
+ * leading dim ldm, block alpha = M_alpha) with
+ *   M_alpha = sum_i w_i s_i^alpha T(z_i)^{-1} U   (eq. eq-malpha-qud),
+ * w_i = dz_i / (2 pi i) the contour's quadrature weights at the sampling
+ * nodes, s_i = (z_i - center) / max(a, b) and K' = prm->Kp (0 = N); this is
+ * M_hat = S_hat D Z of eq. eq-hatMS.  S is not modified; M must not overlap
+ * it.  Runs on the problem's stream and returns after it completes.
+ * Errors: RSRR_EINVAL for bad arguments (lds, ldm < n, null buffers). */
+int rsrr_moment_matrix(rsrr_problem* p, const rsrr_contour* c, const rsrr_params* prm,
+                       const rsrr_complex* S, int lds, rsrr_complex* M, int ldm);
 
 /* Alg. 2 Step 3: orthonormal basis Q of the columns of S_hat (device, rows x
  * cols, leading dim lds; not modified) spanning its singular directions above

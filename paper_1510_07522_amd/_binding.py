@@ -43,7 +43,7 @@ class params_t(C.Structure):
                 ("delta", C.c_double), ("tol_gap", C.c_double), ("tol_res", C.c_double),
                 ("hankel_tol", C.c_double), ("precision", C.c_int), ("ir_max_iter", C.c_int),
                 ("ir_tol", C.c_double), ("cheb_degree", C.c_int), ("nb", C.c_int),
-                ("seed", C.c_uint64)]
+                ("seed", C.c_uint64), ("scheme", C.c_int), ("Kp", C.c_int)]
 
 
 class info_t(C.Structure):
@@ -59,6 +59,7 @@ class info_t(C.Structure):
 
 
 PREC_C128, PREC_C64_IR = 0, 1
+SCHEME = {"sampling": 0, "moment": 1}
 MAT_KIND = {"identity": 0, "diag": 1, "real": 2, "dense": 3}
 FN_KIND = {"pow": 0, "exp": 1, "rat": 2}
 WARN_RANK_SATURATED, WARN_COUNT_MISMATCH, WARN_IR_FALLBACK = 1, 2, 4
@@ -72,6 +73,7 @@ SIGNATURES = {
     "rsrr_destroy": (None, [_vp]),
     "rsrr_sample": (_i, [_vp, C.POINTER(contour_t), C.POINTER(params_t), _vp, _i, _vp, _i,
                          C.POINTER(info_t)]),
+    "rsrr_moment_matrix": (_i, [_vp, C.POINTER(contour_t), C.POINTER(params_t), _vp, _i, _vp, _i]),
     "rsrr_orthonormalize": (_i, [_i, _i, _vp, _i, _d, _vp, _i, C.POINTER(_i), _vp]),
     "rsrr_project": (_i, [_vp, C.POINTER(contour_t), C.POINTER(params_t), _vp, _i, _i, _vp,
                           C.POINTER(_i)]),
@@ -167,6 +169,8 @@ def default_params(**kw) -> params_t:
     for k, v in kw.items():
         if k == "precision" and isinstance(v, str):
             v = {"c128": PREC_C128, "c64_ir": PREC_C64_IR}[v]
+        if k == "scheme" and isinstance(v, str):
+            v = SCHEME[v]
         setattr(p, k, v)
     return p
 
@@ -252,6 +256,16 @@ class Problem:
         st = check(load().rsrr_sample(self.handle, C.byref(c), C.byref(prm), _ptr(U), n, _ptr(S),
                                       n, C.byref(info)))
         return S, info, st
+
+    def moment_matrix(self, c: contour_t, prm: params_t, S, M=None):
+        """M_hat = [M_0 ... M_{K'-1}] of the moment scheme from S_hat, as a
+        column-major device tensor (K'L, n)."""
+        Kp = prm.Kp if prm.Kp > 0 else prm.N
+        if M is None:
+            M = empty_device(self.n, Kp * prm.L)
+        check(load().rsrr_moment_matrix(self.handle, C.byref(c), C.byref(prm), _ptr(S), self.n,
+                                        _ptr(M), self.n))
+        return M
 
     def project(self, c: contour_t, prm: params_t, Q, kS: int, J_max: int = 64):
         torch = _torch()

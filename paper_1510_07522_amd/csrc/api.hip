@@ -347,6 +347,10 @@ static int check_params(const rsrr_problem* p, const rsrr_contour* c, const rsrr
     return set_error(ST_EINVAL, "unknown precision %d", prm->precision);
   if (prm->NS < 2 || prm->K < 1) return set_error(ST_EINVAL, "NS >= 2 and K >= 1 required");
   if ((long)prm->N * prm->L > (1L << 20)) return set_error(ST_EINVAL, "N*L too large");
+  if (prm->scheme != RSRR_SCHEME_SAMPLING && prm->scheme != RSRR_SCHEME_MOMENT)
+    return set_error(ST_EINVAL, "unknown scheme %d", prm->scheme);
+  if (prm->Kp < 0 || (long)prm->Kp * prm->L > (1L << 20))
+    return set_error(ST_EINVAL, "Kp=%d outside [0, 2^20/L]", prm->Kp);
   return ST_OK;
 }
 
@@ -355,6 +359,13 @@ int rsrr_sample(rsrr_problem* p, const rsrr_contour* c, const rsrr_params* prm,
   RSRR_TRY(check_params(p, c, prm));
   if (!U || !S || ldu < p->n || lds < p->n) return set_error(ST_EINVAL, "rsrr_sample: bad buffers");
   return sample_impl(p, c, prm, (const c128*)U, ldu, (c128*)S, lds, info);
+}
+
+int rsrr_moment_matrix(rsrr_problem* p, const rsrr_contour* c, const rsrr_params* prm,
+                       const rsrr_complex* S, int lds, rsrr_complex* M, int ldm) {
+  RSRR_TRY(check_params(p, c, prm));
+  if (!S || !M || lds < p->n || ldm < p->n) return set_error(ST_EINVAL, "rsrr_moment_matrix: bad buffers");
+  return moment_impl(p, c, prm, (const c128*)S, lds, (c128*)M, ldm);
 }
 
 int rsrr_orthonormalize(int rows, int cols, const rsrr_complex* S, int lds, double delta,

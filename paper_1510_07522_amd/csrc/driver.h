@@ -59,6 +59,9 @@ namespace rsrr {
 // Stage implementations (driver_*.hip).
 int sample_impl(rsrr_problem* p, const rsrr_contour* c, const rsrr_params* prm,
                 const c128* U, long ldu, c128* S, long lds, rsrr_info* info);
+// Moment matrix M_hat of the SSRR moment scheme from S_hat (eq. eq-hatMS).
+int moment_impl(rsrr_problem* p, const rsrr_contour* c, const rsrr_params* prm, const c128* S, long lds,
+                c128* M, long ldm);
 int ortho_impl(int rows, int cols, const c128* S, long lds, double delta, c128* Q, long ldq,
                int* k_S, Arena& ws, hipStream_t s);
 int basis_of_columns(const c128* X, long ldx, int rows, int cols, int rank, c128* Q, long ldq,

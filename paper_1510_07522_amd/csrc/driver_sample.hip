@@ -122,6 +122,42 @@ static int residual_fp64(rsrr_problem* p, int N, int L, const c128* f_dev, const
   return combine_residual(U, ldu, P.data(), p->J, f_dev, n, L, N, Rb, n, s);
 }
 
+// M_alpha = sum_i w_i s_i^alpha Y_i (eq. eq-malpha-qud).  For each probe column
+// l, [M_0(:,l) ... M_{K'-1}(:,l)] = [Y_0(:,l) ... Y_{N-1}(:,l)] C with
+// C[i][alpha] = w_i s_i^alpha: an n x N by N x K' product, batched over l
+// (column l of block i sits at S + (i L + l) lds).
+int moment_impl(rsrr_problem* p, const rsrr_contour* c, const rsrr_params* prm, const c128* S, long lds,
+                c128* M, long ldm) {
+  hipStream_t s = p->stream;
+  const int n = p->n, N = prm->N, L = prm->L, Kp = prm->Kp > 0 ? prm->Kp : prm->N;
+  std::vector<cd> z, dz;
+  contour_nodes(c, N, true, &z, &dz);
+  const cd gamma(c->center.re, c->center.im);
+  const double rho = std::max(c->a, c->b);
+  std::vector<c128> hC((size_t)N * Kp);
+  for (int i = 0; i < N; ++i) {
+    const cd si = (z[i] - gamma) / rho;
+    cd v = dz[i] / cd(0, 2.0 * M_PI);
+    for (int a = 0; a < Kp; ++a) {
+      hC[i + (size_t)a * N] = mk<double>(v.real(), v.imag());
+      v *= si;
+    }
+  }
+  c128* dC = nullptr;
+  RSRR_TRY(p->ws.get<c128>("mm_C", hC.size(), &dC));
+  RSRR_HIP(hipMemcpyAsync(dC, hC.data(), hC.size() * sizeof(c128), hipMemcpyHostToDevice, s));
+  GemmBatch<double> g;
+  g.tag = "moment_gemm";
+  g.M = n; g.N = Kp; g.K = N;
+  g.A = S; g.lda = (long)L * lds; g.sA = lds;
+  g.B = dC; g.ldb = N; g.sB = 0;
+  g.C = M; g.ldc = (long)L * ldm; g.sC = ldm;
+  g.batch = L;
+  RSRR_TRY(gemm_batched<double>(g, s));
+  RSRR_HIP(hipStreamSynchronize(s));
+  return ST_OK;
+}
+
 int sample_impl(rsrr_problem* p, const rsrr_contour* c, const rsrr_params* prm, const c128* U,
                 long ldu, c128* S, long lds, rsrr_info* info) {
   const double t0 = now_s();

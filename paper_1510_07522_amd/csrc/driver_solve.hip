@@ -107,19 +107,29 @@ int solve_impl(rsrr_problem* p, const rsrr_contour* c, const rsrr_params* prm, c
   if (st < 0) return st;
   warn |= st;
 
-  // ---- Step 3: orthonormal basis
+  // ---- Step 3: orthonormal basis of S_hat, or of the moment matrix M_hat
+  // (SSRR moment scheme: S_hat replaced by M_hat = S_hat D Z)
   double t0 = now_s();
-  const int kmax = (int)std::min<long>(n, NL);
+  const c128* Sbase = Shat;
+  long ncols = NL;
+  if (prm->scheme == RSRR_SCHEME_MOMENT) {
+    ncols = (long)(prm->Kp > 0 ? prm->Kp : N) * L;
+    c128* Mhat = nullptr;
+    RSRR_TRY(ws.get<c128>("sv_Mhat", (size_t)n * ncols, &Mhat));
+    RSRR_TRY(moment_impl(p, c, prm, Shat, n, Mhat, n));
+    Sbase = Mhat;
+  }
+  const int kmax = (int)std::min<long>(n, ncols);
   c128* Q = nullptr;
   RSRR_TRY(ws.get<c128>("sv_Q", (size_t)n * kmax, &Q));
   int kS = 0;
-  RSRR_TRY(ortho_impl(n, (int)NL, Shat, n, prm->delta, Q, n, &kS, ws, s));
+  RSRR_TRY(ortho_impl(n, (int)ncols, Sbase, n, prm->delta, Q, n, &kS, ws, s));
   info.k_S = kS;
   info.t_basis = now_s() - t0;
   vlog("sample %.3fs (ir %d, fallback %d), basis k_S=%d %.3fs", info.t_sample, info.ir_iters,
        info.ir_fallback, kS, info.t_basis);
   if (kS == 0) return set_error(ST_ENOTCONV, "sampling matrix is numerically zero");
-  if (kS == NL && NL < n) warn |= RSRR_WARN_RANK_SATURATED;
+  if (kS == ncols && ncols < n) warn |= RSRR_WARN_RANK_SATURATED;
 
   // ---- Step 4: reduced coefficients
   t0 = now_s();

@@ -26,7 +26,7 @@ def test_header_declares_the_boundary():
     for required in ["rsrr_create", "rsrr_create_bem", "rsrr_sample", "rsrr_orthonormalize",
                      "rsrr_project", "rsrr_solve", "rsrr_result_info", "rsrr_result_copy",
                      "rsrr_result_free", "rsrr_destroy", "rsrr_last_error",
-                     "rsrr_default_params"]:
+                     "rsrr_default_params", "rsrr_moment_matrix"]:
         assert required in names
 
 
