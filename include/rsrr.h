@@ -137,6 +137,7 @@ typedef struct {
   int status;         /* the status the solve returned */
   double wind_re, wind_im;   /* unrounded winding integral */
   double t_sample, t_basis, t_project, t_reduced, t_residual;  /* seconds per stage */
+  double ws_bytes;    /* device workspace held by the handle (or server slot) after the call */
 } rsrr_info;
 
 typedef struct rsrr_problem rsrr_problem;
@@ -205,6 +206,43 @@ int rsrr_project(rsrr_problem* p, const rsrr_contour* c, const rsrr_params* prm,
  * (leading dim n) or NULL to draw a complex Gaussian U from prm->seed. */
 int rsrr_solve(rsrr_problem* p, const rsrr_contour* c, const rsrr_params* prm,
                const rsrr_complex* U, rsrr_result** out);
+
+/* Upper bound of the device workspace one rsrr_solve of p with prm allocates
+ * (bytes), from n, J, N, L, NS, K, nb, the precision and the scheme: the
+ * admission figure of the serving loop below.  The handle's coefficients are
+ * not included. */
+int rsrr_workspace_bound(const rsrr_problem* p, const rsrr_contour* c, const rsrr_params* prm,
+                         size_t* bytes);
+
+/* Serving: continuous batching of rsrr_solve requests on the current device
+ * (the request loop the method needs when many eigenproblems arrive over time;
+ * the sampling nodes of different requests are independent, Sec. 1 and 5).
+ * A server has max_slots (1..16) slots; each is one host worker thread with its
+ * own non-blocking, default-priority HIP stream and device workspace, so up to
+ * max_slots solves run on the device at once.  Requests are admitted in
+ * submission order as soon as a slot is free and
+ *   (workspace held by the other slots) + rsrr_workspace_bound(request)
+ * fits hbm_budget_bytes; idle slots give their workspace back when the head of
+ * the queue waits for memory.  Results are bit-identical to a solve of the same
+ * request alone (every kernel is deterministic).
+ *   submit: validates like rsrr_solve, copies c, prm and U_host (host, n x L
+ *           column-major, or NULL to draw U from prm->seed) and returns a ticket
+ *           at once; RSRR_EBUSY if the request's bound alone exceeds the budget.
+ *           p must stay alive until the request has been waited for.
+ *   wait:   blocks until the request has finished; *out receives its result
+ *           (free with rsrr_result_free; NULL on error) and *latency_s (may be
+ *           NULL) the time from submission to completion; returns the solve's
+ *           status.  Each ticket can be waited for once.
+ *   pending: requests queued and running.
+ *   destroy: finishes every submitted request, frees results nobody waited
+ *           for, and releases the slots. */
+typedef struct rsrr_server rsrr_server;
+int rsrr_server_create(rsrr_server** out, size_t hbm_budget_bytes, int max_slots);
+int rsrr_server_submit(rsrr_server* srv, rsrr_problem* p, const rsrr_contour* c, const rsrr_params* prm,
+                       const rsrr_complex* U_host, uint64_t* ticket);
+int rsrr_server_wait(rsrr_server* srv, uint64_t ticket, rsrr_result** out, double* latency_s);
+int rsrr_server_pending(rsrr_server* srv, int* queued, int* running);
+void rsrr_server_destroy(rsrr_server* srv);
 
 int rsrr_result_info(const rsrr_result* r, rsrr_info* info);
 /* Host copies; any pointer may be NULL.  lambda: n_eig; V: n x n_eig

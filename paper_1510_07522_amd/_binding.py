@@ -52,7 +52,7 @@ class info_t(C.Structure):
                 ("n_candidates", C.c_int), ("ir_iters", C.c_int), ("ir_fallback", C.c_int),
                 ("status", C.c_int), ("wind_re", C.c_double), ("wind_im", C.c_double),
                 ("t_sample", C.c_double), ("t_basis", C.c_double), ("t_project", C.c_double),
-                ("t_reduced", C.c_double), ("t_residual", C.c_double)]
+                ("t_reduced", C.c_double), ("t_residual", C.c_double), ("ws_bytes", C.c_double)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -78,6 +78,13 @@ SIGNATURES = {
     "rsrr_project": (_i, [_vp, C.POINTER(contour_t), C.POINTER(params_t), _vp, _i, _i, _vp,
                           C.POINTER(_i)]),
     "rsrr_solve": (_i, [_vp, C.POINTER(contour_t), C.POINTER(params_t), _vp, C.POINTER(_vp)]),
+    "rsrr_workspace_bound": (_i, [_vp, C.POINTER(contour_t), C.POINTER(params_t), C.POINTER(C.c_size_t)]),
+    "rsrr_server_create": (_i, [C.POINTER(_vp), C.c_size_t, _i]),
+    "rsrr_server_submit": (_i, [_vp, _vp, C.POINTER(contour_t), C.POINTER(params_t), _vp,
+                                C.POINTER(C.c_uint64)]),
+    "rsrr_server_wait": (_i, [_vp, C.c_uint64, C.POINTER(_vp), C.POINTER(_d)]),
+    "rsrr_server_pending": (_i, [_vp, C.POINTER(_i), C.POINTER(_i)]),
+    "rsrr_server_destroy": (None, [_vp]),
     "rsrr_result_info": (_i, [_vp, C.POINTER(info_t)]),
     "rsrr_result_copy": (_i, [_vp, _vp, _vp, _vp, _vp, _vp]),
     "rsrr_result_free": (None, [_vp]),
@@ -280,21 +287,75 @@ class Problem:
         r = C.c_void_p()
         st = check(lib.rsrr_solve(self.handle, C.byref(c), C.byref(prm),
                                   _ptr(U) if U is not None else None, C.byref(r)))
+        return _take_result(r, self.n, prm, st)
+
+    def workspace_bound(self, c: contour_t, prm: params_t) -> int:
+        b = C.c_size_t(0)
+        check(load().rsrr_workspace_bound(self.handle, C.byref(c), C.byref(prm), C.byref(b)))
+        return b.value
+
+
+def _take_result(r, n: int, prm: params_t, st: int) -> dict:
+    """Copies a library result object to host arrays and frees it."""
+    lib = load()
+    try:
+        info = info_t()
+        check(lib.rsrr_result_info(r, C.byref(info)))
+        ne = info.n_eig
+        lam = np.zeros(ne, np.complex128)
+        V = np.zeros((ne, n), np.complex128)
+        res = np.zeros(ne)
+        resp = np.zeros(ne)
+        hs = np.zeros(max(1, prm.K * info.k_S))
+        check(lib.rsrr_result_copy(r, lam.ctypes.data, V.ctypes.data, res.ctypes.data,
+                                   resp.ctypes.data, hs.ctypes.data))
+    finally:
+        lib.rsrr_result_free(r)
+    return dict(lam=lam, V=V.T, res=res, res_paper=resp, hankel_sigma=hs[: prm.K * info.k_S],
+                info=info.as_dict(), status=st)
+
+
+class Server:
+    """Continuous-batching request loop (rsrr_server_*): submit solves of any
+    problems; each runs in one of max_slots concurrent slots once it fits the
+    device-memory budget."""
+
+    def __init__(self, hbm_budget_bytes: int, max_slots: int):
+        self.handle = C.c_void_p()
+        check(load().rsrr_server_create(C.byref(self.handle), int(hbm_budget_bytes), int(max_slots)))
+        self._req = {}
+
+    def submit(self, prob: "Problem", c: contour_t, prm: params_t, U: np.ndarray | None = None) -> int:
+        t = C.c_uint64(0)
+        Uh = None if U is None else np.asfortranarray(U, dtype=np.complex128)
+        check(load().rsrr_server_submit(self.handle, prob.handle, C.byref(c), C.byref(prm),
+                                        None if Uh is None else Uh.ctypes.data, C.byref(t)))
+        self._req[t.value] = (prob.n, prm)
+        return t.value
+
+    def wait(self, ticket: int):
+        """(result dict as Problem.solve returns it, latency in seconds)."""
+        n, prm = self._req.pop(ticket)
+        r = C.c_void_p()
+        lat = C.c_double(0)
+        st = check(load().rsrr_server_wait(self.handle, C.c_uint64(ticket), C.byref(r), C.byref(lat)))
+        return _take_result(r, n, prm, st), lat.value
+
+    def pending(self):
+        q, r = C.c_int(0), C.c_int(0)
+        check(load().rsrr_server_pending(self.handle, C.byref(q), C.byref(r)))
+        return q.value, r.value
+
+    def close(self):
+        if self.handle:
+            load().rsrr_server_destroy(self.handle)
+            self.handle = C.c_void_p()
+
+    def __del__(self):
         try:
-            info = info_t()
-            check(lib.rsrr_result_info(r, C.byref(info)))
-            ne = info.n_eig
-            lam = np.zeros(ne, np.complex128)
-            V = np.zeros((ne, self.n), np.complex128)
-            res = np.zeros(ne)
-            resp = np.zeros(ne)
-            hs = np.zeros(max(1, prm.K * info.k_S))
-            check(lib.rsrr_result_copy(r, lam.ctypes.data, V.ctypes.data, res.ctypes.data,
-                                       resp.ctypes.data, hs.ctypes.data))
-        finally:
-            lib.rsrr_result_free(r)
-        return dict(lam=lam, V=V.T, res=res, res_paper=resp, hankel_sigma=hs[: prm.K * info.k_S],
-                    info=info.as_dict(), status=st)
+            self.close()
+        except Exception:
+            pass
 
 
 def orthonormalize(S, rows: int, cols: int, delta: float = 1e-14):

@@ -204,6 +204,32 @@ bool contour_inside(const rsrr_contour* c, cd lam) {
   return xr * xr + xi * xi < 1.0;
 }
 
+int check_params(const rsrr_problem* p, const rsrr_contour* c, const rsrr_params* prm) {
+  if (!p || !c || !prm) return set_error(ST_EINVAL, "null argument");
+  if (prm->N < 1 || prm->L < 1) return set_error(ST_EINVAL, "N and L must be >= 1");
+  if (!(c->a > 0) || !(c->b > 0)) return set_error(ST_EINVAL, "contour semi-axes must be > 0");
+  if (c->kind != RSRR_CONTOUR_ELLIPSE && c->kind != RSRR_CONTOUR_RECT)
+    return set_error(ST_EINVAL, "unknown contour kind %d", c->kind);
+  if (c->kind == RSRR_CONTOUR_RECT) {
+    int nh, nv;
+    if (!rect_split(c, prm->N, true, &nh, &nv))
+      return set_error(ST_EINVAL, "rectangle: N=%d does not match n_h=%d, n_v=%d (N = 2(n_h+n_v), or "
+                       "n_h = n_v = 0 and N even >= 4)", prm->N, c->n_h, c->n_v);
+    if (!rect_split(c, prm->NS, false, &nh, &nv))
+      return set_error(ST_EINVAL, "rectangle: NS=%d must be even and >= 4", prm->NS);
+  }
+  if (prm->nb < 1 || prm->nb > 64) return set_error(ST_EINVAL, "nb must be in [1, 64]");
+  if (prm->precision != RSRR_PREC_C128 && prm->precision != RSRR_PREC_C64_IR)
+    return set_error(ST_EINVAL, "unknown precision %d", prm->precision);
+  if (prm->NS < 2 || prm->K < 1) return set_error(ST_EINVAL, "NS >= 2 and K >= 1 required");
+  if ((long)prm->N * prm->L > (1L << 20)) return set_error(ST_EINVAL, "N*L too large");
+  if (prm->scheme != RSRR_SCHEME_SAMPLING && prm->scheme != RSRR_SCHEME_MOMENT)
+    return set_error(ST_EINVAL, "unknown scheme %d", prm->scheme);
+  if (prm->Kp < 0 || (long)prm->Kp * prm->L > (1L << 20))
+    return set_error(ST_EINVAL, "Kp=%d outside [0, 2^20/L]", prm->Kp);
+  return ST_OK;
+}
+
 }  // namespace rsrr
 
 using namespace rsrr;
@@ -328,37 +354,20 @@ void rsrr_destroy(rsrr_problem* p) {
   delete p;
 }
 
-static int check_params(const rsrr_problem* p, const rsrr_contour* c, const rsrr_params* prm) {
-  if (!p || !c || !prm) return set_error(ST_EINVAL, "null argument");
-  if (prm->N < 1 || prm->L < 1) return set_error(ST_EINVAL, "N and L must be >= 1");
-  if (!(c->a > 0) || !(c->b > 0)) return set_error(ST_EINVAL, "contour semi-axes must be > 0");
-  if (c->kind != RSRR_CONTOUR_ELLIPSE && c->kind != RSRR_CONTOUR_RECT)
-    return set_error(ST_EINVAL, "unknown contour kind %d", c->kind);
-  if (c->kind == RSRR_CONTOUR_RECT) {
-    int nh, nv;
-    if (!rect_split(c, prm->N, true, &nh, &nv))
-      return set_error(ST_EINVAL, "rectangle: N=%d does not match n_h=%d, n_v=%d (N = 2(n_h+n_v), or "
-                       "n_h = n_v = 0 and N even >= 4)", prm->N, c->n_h, c->n_v);
-    if (!rect_split(c, prm->NS, false, &nh, &nv))
-      return set_error(ST_EINVAL, "rectangle: NS=%d must be even and >= 4", prm->NS);
-  }
-  if (prm->nb < 1 || prm->nb > 64) return set_error(ST_EINVAL, "nb must be in [1, 64]");
-  if (prm->precision != RSRR_PREC_C128 && prm->precision != RSRR_PREC_C64_IR)
-    return set_error(ST_EINVAL, "unknown precision %d", prm->precision);
-  if (prm->NS < 2 || prm->K < 1) return set_error(ST_EINVAL, "NS >= 2 and K >= 1 required");
-  if ((long)prm->N * prm->L > (1L << 20)) return set_error(ST_EINVAL, "N*L too large");
-  if (prm->scheme != RSRR_SCHEME_SAMPLING && prm->scheme != RSRR_SCHEME_MOMENT)
-    return set_error(ST_EINVAL, "unknown scheme %d", prm->scheme);
-  if (prm->Kp < 0 || (long)prm->Kp * prm->L > (1L << 20))
-    return set_error(ST_EINVAL, "Kp=%d outside [0, 2^20/L]", prm->Kp);
-  return ST_OK;
-}
 
 int rsrr_sample(rsrr_problem* p, const rsrr_contour* c, const rsrr_params* prm,
                 const rsrr_complex* U, int ldu, rsrr_complex* S, int lds, rsrr_info* info) {
   RSRR_TRY(check_params(p, c, prm));
   if (!U || !S || ldu < p->n || lds < p->n) return set_error(ST_EINVAL, "rsrr_sample: bad buffers");
   return sample_impl(p, c, prm, (const c128*)U, ldu, (c128*)S, lds, info);
+}
+
+int rsrr_workspace_bound(const rsrr_problem* p, const rsrr_contour* c, const rsrr_params* prm,
+                         size_t* bytes) {
+  if (!bytes) return set_error(ST_EINVAL, "rsrr_workspace_bound: null output");
+  RSRR_TRY(check_params(p, c, prm));
+  *bytes = solve_workspace_bound(p, prm);
+  return ST_OK;
 }
 
 int rsrr_moment_matrix(rsrr_problem* p, const rsrr_contour* c, const rsrr_params* prm,

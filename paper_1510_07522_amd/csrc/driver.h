@@ -26,6 +26,7 @@ struct Arena {
     return get(name, count * sizeof(T), (void**)out);
   }
   int aux_stream(hipStream_t* s, hipEvent_t* ev_main, hipEvent_t* ev_aux);
+  size_t bytes() const;   // device memory held
   void release();
   ~Arena() { release(); }
 };
@@ -70,6 +71,9 @@ int project_impl(rsrr_problem* p, const rsrr_contour* c, const rsrr_params* prm,
                  long ldq, int kS, c128* B, int* J_out);
 int solve_impl(rsrr_problem* p, const rsrr_contour* c, const rsrr_params* prm, const c128* U,
                rsrr_result* res);
+// Upper bound of the device workspace one solve of p with prm allocates.
+size_t solve_workspace_bound(const rsrr_problem* p, const rsrr_params* prm);
+int check_params(const rsrr_problem* p, const rsrr_contour* c, const rsrr_params* prm);
 // Gauss-Legendre nodes x (ascending) and weights w of the n-point rule on [-1, 1].
 void gauss_legendre(int n, std::vector<double>* x, std::vector<double>* w);
 // Per-side node counts of a rectangular contour for N nodes in total: the

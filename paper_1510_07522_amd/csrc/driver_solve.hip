@@ -79,6 +79,43 @@ static void reduced_scalars(const rsrr_problem* p, int J, double cx, double a, c
   for (int j = 0; j < J; ++j) (*dg)[j] /= a;
 }
 
+size_t solve_workspace_bound(const rsrr_problem* p, const rsrr_params* prm) {
+  const double z = 16.0;   // bytes of a complex128
+  const double n = p->n, N = prm->N, L = prm->L, NS = prm->NS, K = prm->K, nb = prm->nb;
+  const double NL = N * L;
+  const double cols = prm->scheme == RSRR_SCHEME_MOMENT ? (prm->Kp > 0 ? prm->Kp : prm->N) * L : NL;
+  const double kS = std::min(n, cols), kk = kS * kS, M = K * kS;   // m <= M
+  const double J = p->bem ? (prm->cheb_degree > 0 ? prm->cheb_degree : 40) + 1 : p->J;
+  // sampling: complex128 factors and diagonal-block inverses (the precision, or
+  // the fallback of every node), complex64 factors, solutions and residuals
+  double samp = N * n * n * z + 2 * N * n * nb * z + (J + 10) * n * NL * z;
+  if (prm->precision == RSRR_PREC_C64_IR) samp += N * n * n * 8 + 2 * N * n * nb * 8;
+  if (p->bem) samp += N * n * 8;
+  // basis: S_hat or M_hat, Q and the Gram matrices of the two levels
+  const double basis = (cols + kS) * n * z + 8 * cols * cols * z;
+  // projection (BEM: Chebyshev samples in chunks of at most 8 GB)
+  double proj = 2 * J * kk * z + n * kS * z;
+  if (p->bem) {   // Chebyshev samples T(x_k) and T(x_k) Q in chunks of at most 8 GB
+    const double chb = std::max(1.0, std::min(J, std::floor(8e9 / (n * n * z))));
+    proj += chb * (n * n + n * kS) * z + J * J * z + J * kk * z;
+  }
+  // moments: a chunk of T_S(zeta) and inverses sized to at most 8 GB
+  const double ch = std::max(1.0, std::min(NS, std::floor(8e9 / (kk * z * 2))));
+  const double red = 2 * ch * kk * z + (2 * K + 1) * kk * z + 2 * ch * kS * nb * z + ch * (kS + 64) * z;
+  // Hankel matrices, SVD (basis, Jacobi copies), extraction, eigen-solve
+  const double hank = 18 * M * M * z + (kS + n) * M * z;
+  const double eig = 24 * M * M * z;
+  // residual filter
+  const double resid = (J + 4) * n * M * z;
+  return (size_t)(1.1 * (samp + basis + proj + red + hank + eig + resid)) + ((size_t)64 << 20);
+}
+
+size_t Arena::bytes() const {
+  size_t b = 0;
+  for (const auto& kv : bufs) b += kv.second.second;
+  return b;
+}
+
 int solve_impl(rsrr_problem* p, const rsrr_contour* c, const rsrr_params* prm, const c128* Uin,
                rsrr_result* res) {
   hipStream_t s = p->stream;
@@ -207,10 +244,10 @@ int solve_impl(rsrr_problem* p, const rsrr_contour* c, const rsrr_params* prm, c
     RSRR_TRY(zgemm(OP_N, OP_N, (int)kk, cnt, J, ONE, BT, kk, gdev + (size_t)ch * J, J, ZERO, TS, kk, s));
     RSRR_TRY(dot_partials(X, TS, kk, cnt, nchunk, part, s));
     hpart.resize((size_t)cnt * nchunk);
-    RSRR_HIP(hipMemcpyAsync(hpart.data(), part, hpart.size() * sizeof(c128), hipMemcpyDeviceToHost, s));
-    RSRR_HIP(hipStreamSynchronize(s));
     std::vector<int> hinfo(cnt);
-    RSRR_HIP(hipMemcpy(hinfo.data(), linfo, cnt * sizeof(int), hipMemcpyDeviceToHost));
+    RSRR_HIP(hipMemcpyAsync(hpart.data(), part, hpart.size() * sizeof(c128), hipMemcpyDeviceToHost, s));
+    RSRR_HIP(hipMemcpyAsync(hinfo.data(), linfo, cnt * sizeof(int), hipMemcpyDeviceToHost, s));
+    RSRR_HIP(hipStreamSynchronize(s));
     for (int q = 0; q < cnt; ++q)
       if (hinfo[q]) return set_error(ST_ESINGULAR, "reduced matrix singular at node %d", m0 + q);
     for (int q = 0; q < cnt; ++q) {
@@ -400,6 +437,7 @@ int solve_impl(rsrr_problem* p, const rsrr_contour* c, const rsrr_params* prm, c
   }
   RSRR_HIP(hipStreamSynchronize(s));
   info.t_residual = now_s() - t0;
+  info.ws_bytes = (double)ws.bytes();
   if (ne != info.n_wind) warn |= RSRR_WARN_COUNT_MISMATCH;
   return warn;
 }
