@@ -254,6 +254,45 @@ def config_c2(count: int = 16, nmin: int = 512, nmax: int = 4096):
     return out
 
 
+def config_c4(count: int = 600, rate: float = 20.0, seed: int = 1004):
+    """Request stream of the serving workload: Poisson arrivals (exponential
+    gaps, `rate` per second); family uniform over
+      QEP   n ~ U{256..4096}, N = 32, k ~ U[1,100], centre i U[2,9], radius U[0.5,2]
+      delay n ~ U{512..2048}, N = 48, centre uniform in |c| <= 1, radius U[0.5,1.5]
+      BEM   n ~ U{1024..4096}, N = 40, centre U[2.5,4.0] (real), radius U[0.3,0.8]
+    and L uniform in {16, 32, 64}.  Returns dicts with the arrival time, the
+    family, n, a problem seed, the contour, N, L and the seed of U; problems
+    are built by the caller (build_c4_problem) so that they can be cached."""
+    rng = np.random.default_rng(seed)
+    t = 0.0
+    out = []
+    for i in range(count):
+        t += rng.exponential(1.0 / rate)
+        fam = ("qep", "delay", "bem")[int(rng.integers(0, 3))]
+        L = int((16, 32, 64)[int(rng.integers(0, 3))])
+        if fam == "qep":
+            n, N = int(rng.integers(256, 4097)), 32
+            c = Contour(1j * rng.uniform(2.0, 9.0), *([rng.uniform(0.5, 2.0)] * 2))
+        elif fam == "delay":
+            n, N = int(rng.integers(512, 2049)), 48
+            rad, ang = math.sqrt(rng.uniform()), rng.uniform(0, 2 * math.pi)
+            c = Contour(rad * complex(math.cos(ang), math.sin(ang)), *([rng.uniform(0.5, 1.5)] * 2))
+        else:
+            n, N = int(rng.integers(1024, 4097)), 40
+            c = Contour(complex(rng.uniform(2.5, 4.0)), *([rng.uniform(0.3, 0.8)] * 2))
+        out.append(dict(t=t, family=fam, n=n, pseed=5000 + i, contour=c, N=N, L=L, useed=6000 + i))
+    return out
+
+
+def build_c4_problem(req):
+    """The problem of one serving request (see config_c4)."""
+    if req["family"] == "qep":
+        return qep_dense(req["n"], 100.0, seed=req["pseed"])
+    if req["family"] == "delay":
+        return delay_dense(req["n"], seed=req["pseed"])
+    return bem_sphere(req["n"])
+
+
 def config_c3(n: int = 8192):
     """Helmholtz single-layer BEM on a Fibonacci sphere, ellipse centre 3,
     semi-axes 1.5 and 0.3, N=40, L=64."""

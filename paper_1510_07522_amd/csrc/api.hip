@@ -283,11 +283,13 @@ int rsrr_create(rsrr_problem** out, int n, int J, const int* kinds, const void* 
     else if (kinds[k] == RSRR_MAT_REAL) bytes = nn * sizeof(double);
     else if (kinds[k] == RSRR_MAT_DENSE) bytes = nn * sizeof(c128);
     if (!bytes) continue;
-    if (hipMalloc(&p->mats[k], bytes) != hipSuccess ||
-        hipMemcpy(p->mats[k], A[k], bytes, hipMemcpyHostToDevice) != hipSuccess) {
+    hipError_t e = hipMalloc(&p->mats[k], bytes);
+    if (e == hipSuccess) e = hipMemcpy(p->mats[k], A[k], bytes, hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
       (void)hipGetLastError();
       rsrr_destroy(p);
-      return set_error(ST_ENOMEM, "rsrr_create: cannot upload coefficient %d", k);
+      return set_error(ST_ENOMEM, "rsrr_create: cannot upload coefficient %d (%zu bytes): %s", k, bytes,
+                       hipGetErrorString(e));
     }
   }
   // Gram of the coefficients, gram[k,l] = sum_ij conj(A_k)_ij (A_l)_ij, so that
@@ -334,11 +336,12 @@ int rsrr_create_bem(rsrr_problem** out, int n, const double* xyz, double h, void
   p->bem = true;
   p->h = h;
   p->stream = (hipStream_t)stream;
-  if (hipMalloc(&p->xyz, (size_t)n * 3 * sizeof(double)) != hipSuccess ||
-      hipMemcpy(p->xyz, xyz, (size_t)n * 3 * sizeof(double), hipMemcpyHostToDevice) != hipSuccess) {
+  hipError_t e = hipMalloc(&p->xyz, (size_t)n * 3 * sizeof(double));
+  if (e == hipSuccess) e = hipMemcpy(p->xyz, xyz, (size_t)n * 3 * sizeof(double), hipMemcpyHostToDevice);
+  if (e != hipSuccess) {
     (void)hipGetLastError();
     rsrr_destroy(p);
-    return set_error(ST_ENOMEM, "rsrr_create_bem: cannot upload points");
+    return set_error(ST_ENOMEM, "rsrr_create_bem: cannot upload points: %s", hipGetErrorString(e));
   }
   *out = p;
   return ST_OK;

@@ -123,6 +123,8 @@ void worker(rsrr_server* srv, Slot* sl) {
     srv->queue.pop_front();
     sl->busy = true;
     sl->held = std::max(r.need, own);
+    ++srv->gen;                                          // the head changed: others look again
+    srv->cv.notify_all();
     lk.unlock();
 
     bind_view(&sl->view, r.p, sl->stream);
