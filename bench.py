@@ -281,6 +281,8 @@ def main():
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of this many MiB 5 times (reference "
                          "for scaling the FETCH_SIZE / WRITE_SIZE counters) and exit")
+    ap.add_argument("--chunk-gib", type=float, default=None,
+                    help="device memory per batch of reduced-problem inverses (library default if unset)")
     ap.add_argument("--requests", type=int, default=24, help="serving workload (c4): requests")
     ap.add_argument("--slots", type=int, default=4, help="serving workload (c4): concurrent slots")
     ap.add_argument("--budget-gib", type=float, default=200.0, help="serving workload (c4): HBM budget")
@@ -328,6 +330,8 @@ def main():
     h = P.Problem(prob)
     U = P.to_device(w["U"])
     prm = P.default_params(N=N, L=L, precision=a.precision, scheme=a.scheme)
+    if a.chunk_gib is not None:
+        prm.chunk_gib = a.chunk_gib
 
     for i in range(a.warmup):
         t0 = time.perf_counter()

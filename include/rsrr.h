@@ -121,6 +121,8 @@ typedef struct {
   uint64_t seed;      /* seed of the probing matrix when U is not supplied */
   int scheme;         /* RSRR_SCHEME_SAMPLING (default) or RSRR_SCHEME_MOMENT */
   int Kp;             /* moment scheme: number of moments K' (0 = N, as in the paper's comparisons) */
+  double chunk_gib;   /* device memory for one batch of T_S(zeta_m) and their inverses in the
+                         reduced moments (and of BEM Chebyshev samples), GiB; default 24 */
 } rsrr_params;
 
 /* Diagnostics of one solve. */

@@ -43,7 +43,7 @@ class params_t(C.Structure):
                 ("delta", C.c_double), ("tol_gap", C.c_double), ("tol_res", C.c_double),
                 ("hankel_tol", C.c_double), ("precision", C.c_int), ("ir_max_iter", C.c_int),
                 ("ir_tol", C.c_double), ("cheb_degree", C.c_int), ("nb", C.c_int),
-                ("seed", C.c_uint64), ("scheme", C.c_int), ("Kp", C.c_int)]
+                ("seed", C.c_uint64), ("scheme", C.c_int), ("Kp", C.c_int), ("chunk_gib", C.c_double)]
 
 
 class info_t(C.Structure):

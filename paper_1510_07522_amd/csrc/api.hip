@@ -225,6 +225,8 @@ int check_params(const rsrr_problem* p, const rsrr_contour* c, const rsrr_params
   if ((long)prm->N * prm->L > (1L << 20)) return set_error(ST_EINVAL, "N*L too large");
   if (prm->scheme != RSRR_SCHEME_SAMPLING && prm->scheme != RSRR_SCHEME_MOMENT)
     return set_error(ST_EINVAL, "unknown scheme %d", prm->scheme);
+  if (!(prm->chunk_gib >= 0.0625) || prm->chunk_gib > 256.0)
+    return set_error(ST_EINVAL, "chunk_gib=%g outside [1/16, 256]", prm->chunk_gib);
   if (prm->Kp < 0 || (long)prm->Kp * prm->L > (1L << 20))
     return set_error(ST_EINVAL, "Kp=%d outside [0, 2^20/L]", prm->Kp);
   return ST_OK;
@@ -255,6 +257,7 @@ void rsrr_default_params(rsrr_params* p) {
   p->cheb_degree = 40;
   p->nb = 64;
   p->seed = 1;
+  p->chunk_gib = 24.0;
 }
 
 int rsrr_create(rsrr_problem** out, int n, int J, const int* kinds, const void* const* A,

@@ -63,7 +63,7 @@ int project_impl(rsrr_problem* p, const rsrr_contour* c, const rsrr_params* prm,
     xk[k] = mk<double>(cx + a * cos(theta[k]), 0.0);
   }
   const size_t per = (size_t)n * n * sizeof(c128);
-  const int ch = (int)std::max<size_t>(1, std::min<size_t>(nd, (size_t)8e9 / per));
+  const int ch = (int)std::max<size_t>(1, std::min<size_t>(nd, (size_t)(prm->chunk_gib * 1073741824.0) / per));
   c128 *T = nullptr, *Mk = nullptr, *zd = nullptr, *Cw = nullptr;
   RSRR_TRY(p->ws.get<c128>("pj_T", (size_t)ch * n * n, &T));
   RSRR_TRY(p->ws.get<c128>("pj_W", (size_t)ch * n * kS, &W));

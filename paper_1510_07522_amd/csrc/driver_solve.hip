@@ -79,8 +79,18 @@ static void reduced_scalars(const rsrr_problem* p, int J, double cx, double a, c
   for (int j = 0; j < J; ++j) (*dg)[j] /= a;
 }
 
+// (number of batches, nodes per batch) for NS nodes of `per` bytes each in
+// chunk_gib GiB: the fewest batches that fit, with the nodes spread evenly.
+static std::pair<int, int> chunk_count(int NS, size_t per, double chunk_gib) {
+  const size_t cap = (size_t)(chunk_gib * 1073741824.0);
+  const int fit = (int)std::max<size_t>(1, std::min<size_t>(NS, cap / std::max<size_t>(per, 1)));
+  const int nb = (NS + fit - 1) / fit;
+  return {nb, (NS + nb - 1) / nb};
+}
+
 size_t solve_workspace_bound(const rsrr_problem* p, const rsrr_params* prm) {
   const double z = 16.0;   // bytes of a complex128
+  const double cap = prm->chunk_gib * 1073741824.0;
   const double n = p->n, N = prm->N, L = prm->L, NS = prm->NS, K = prm->K, nb = prm->nb;
   const double NL = N * L;
   const double cols = prm->scheme == RSRR_SCHEME_MOMENT ? (prm->Kp > 0 ? prm->Kp : prm->N) * L : NL;
@@ -96,11 +106,11 @@ size_t solve_workspace_bound(const rsrr_problem* p, const rsrr_params* prm) {
   // projection (BEM: Chebyshev samples in chunks of at most 8 GB)
   double proj = 2 * J * kk * z + n * kS * z;
   if (p->bem) {   // Chebyshev samples T(x_k) and T(x_k) Q in chunks of at most 8 GB
-    const double chb = std::max(1.0, std::min(J, std::floor(8e9 / (n * n * z))));
+    const double chb = std::max(1.0, std::min(J, std::floor(cap / (n * n * z))));
     proj += chb * (n * n + n * kS) * z + J * J * z + J * kk * z;
   }
   // moments: a chunk of T_S(zeta) and inverses sized to at most 8 GB
-  const double ch = std::max(1.0, std::min(NS, std::floor(8e9 / (kk * z * 2))));
+  const double ch = chunk_count(prm->NS, (size_t)(kk * z * 2), prm->chunk_gib).second;
   const double red = 2 * ch * kk * z + (2 * K + 1) * kk * z + 2 * ch * kS * nb * z + ch * (kS + 64) * z;
   // Hankel matrices, SVD (basis, Jacobi copies), extraction, eigen-solve
   const double hank = 18 * M * M * z + (kS + n) * M * z;
@@ -187,7 +197,8 @@ int solve_impl(rsrr_problem* p, const rsrr_contour* c, const rsrr_params* prm, c
   contour_nodes(c, NS, false, &zeta, &dzeta);
   const double cx = c->center.re, ax = c->a;
   const size_t per = (size_t)kk * sizeof(c128) * 2;
-  const int ch = (int)std::max<size_t>(1, std::min<size_t>(NS, (size_t)8e9 / per));
+  // nodes per batch: as many as the chunk memory holds, balanced over the batches
+  const int ch = chunk_count(NS, per, prm->chunk_gib).second;
   c128 *TS = nullptr, *X = nullptr, *Amom = nullptr, *gdev = nullptr, *cw = nullptr, *dinv = nullptr,
        *part = nullptr, *Iden = nullptr;
   int *ipiv = nullptr, *linfo = nullptr;

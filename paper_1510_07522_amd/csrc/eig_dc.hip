@@ -345,11 +345,17 @@ __global__ __launch_bounds__(256) void pade_combine_kernel(const c128* Z, int nb
 }
 
 // Sign functions of the nbk matrices in bt.X (destroyed; results in bt.X),
-// run on all of them in lock step: one Newton step with a scaling factor per
-// matrix, then Pade steps of order 2*PADE_M until the relative change is below
-// 1e-2, then Newton-Schulz to convergence.  ok[b] = 0 if matrix b became
+// run on all of them in lock step: DC_NEWTON_STEPS Newton steps with a scaling
+// factor per matrix, then Pade steps of order 2*PADE_M until ||X^2 - I||_F / sqrt(len) <
+// 0.3 for every block (or the relative change is below 1e-2), then
+// Newton-Schulz to convergence.  ok[b] = 0 if matrix b became
 // singular or did not converge (its slot is reset to the identity so it stays
 // inert).
+// scaled Newton steps before the Pade steps (each is one LU and inverse per
+// block; they move the spectrum towards +-1 faster per unit of work than a
+// Pade step while it is far from converged)
+constexpr int DC_NEWTON_STEPS = 2;
+
 static int newton_sign_batched(DcBatch& bt, Arena& ws, hipStream_t s, std::vector<int>* ok, int* iters) {
   const int nbk = bt.nbk, L = bt.Lmax;
   const long ll = (long)L * L;
@@ -421,10 +427,24 @@ static int newton_sign_batched(DcBatch& bt, Arena& ws, hipStream_t s, std::vecto
       RSRR_TRY(pad_identity(bt.X, bt, s));
       continue;
     }
-    if (it > 0) {                // Pade step
+    if (it >= DC_NEWTON_STEPS) {  // Pade step
       g.alpha = ONE; g.beta = ZERO;
       g.A = bt.X; g.B = bt.X; g.C = bt.Y;
       RSRR_TRY(gemm_batched<double>(g, s));                         // X^2
+      {
+        // once every block is close to an involution, Newton-Schulz (two
+        // products per step, quadratic) finishes faster than another Pade step
+        std::vector<double> r2;
+        RSRR_TRY(fro_batched(bt.Y, nullptr, bt, s, &r2, nullptr, 1));
+        bool close = true;
+        for (int b = 0; b < nbk && close; ++b)
+          if (!done[b] && !(sqrt(r2[b] / bt.lens[b]) < 0.3)) close = false;
+        if (close) {
+          schulz = true;
+          std::fill(prev.begin(), prev.end(), 1e300);
+          continue;
+        }
+      }
       hipLaunchKernelGGL(pade_setup_kernel, dim3(nblk(ll), nq), dim3(256), 0, s, bt.Y, bt.X, nbk, L, pc, LUp, Zp);
       RSRR_LAUNCH_CHECK();
       RSRR_TRY(lu_factor<double>(lwp, s));
