@@ -19,6 +19,7 @@ namespace rsrr {
 
 constexpr int PNT = 1024;           // panel workgroup size (16 waves)
 constexpr int MAXNB = 64;
+constexpr int LU_SB = 4;            // panels per group of the triangular solves
 
 template <typename R> __device__ inline cplx<R> shfl_c(cplx<R> v, int src) {
   return mk<R>(__shfl(v.re, src), __shfl(v.im, src));
@@ -492,68 +493,71 @@ int lu_factor(const LUWork<R>& w, hipStream_t s) {
     }
   }
   if (aux_busy) RSRR_HIP(hipStreamWaitEvent(s, w.ev_aux, 0));
+  // Within every group of LU_SB panels, the interchanges of a panel are also
+  // applied to the L columns of the group's earlier panels, so that all L
+  // columns of a group share one row order (that after its last panel) and
+  // the solver can update the rows below a group with one product.  Rows of a
+  // panel's own diagonal block are never touched, so L stays unit lower
+  // triangular and dinv is unchanged.
+  const int np = w.npanel();
+  for (int q = 1; q < np; ++q) {
+    if (q % LU_SB == 0) continue;
+    const int k = q * nb, c0 = (q / LU_SB) * LU_SB * nb;
+    RSRR_TRY(launch_permute<R>(w.A + (long)c0 * w.lda, w.lda, w.sA, k - c0, w.ipiv, n, k, min(nb, n - k),
+                               w.batch, s));
+  }
   return ST_OK;
 }
 
 template <typename R>
 int lu_solve(const LUWork<R>& w, cplx<R>* B, long ldb, long sB, int nrhs, hipStream_t s, const int* active) {
   if (w.n <= 0 || w.batch <= 0 || nrhs <= 0) return ST_OK;
-  const int n = w.n, nb = w.nb;
+  const int n = w.n, nb = w.nb, np = w.npanel();
   const std::string t_solve = std::string(w.tag) + "_solve";
-  const long sD = (long)w.npanel() * 2 * nb * nb;
-  for (int k = 0; k < n; k += nb) {                      // forward: L
-    const int nbe = min(nb, n - k);
-    RSRR_TRY(launch_permute<R>(B, ldb, sB, nrhs, w.ipiv, n, k, nbe, w.batch, s, active));
+  const long sD = (long)np * 2 * nb * nb;
+  // C[rows] = alpha A B + beta C on the batch (A from the factors or dinv)
+  auto mm = [&](int M, int K, const cplx<R>* A, long lda, long sA, const cplx<R>* Bp, cplx<R>* Cp, bool acc) {
     GemmBatch<R> g;
-    g.M = nbe; g.N = nrhs; g.K = nbe;
-    g.A = w.dinv + (long)(k / nb) * 2 * nb * nb; g.lda = nb; g.sA = sD;
-    g.B = B + k; g.ldb = ldb; g.sB = sB;
-    g.C = B + k; g.ldc = ldb; g.sC = sB;
+    g.M = M; g.N = nrhs; g.K = K;
+    if (acc) { g.alpha = mk<R>(-1, 0); g.beta = mk<R>(1, 0); }
+    g.A = A; g.lda = lda; g.sA = sA;
+    g.B = Bp; g.ldb = ldb; g.sB = sB;
+    g.C = Cp; g.ldc = ldb; g.sC = sB;
     g.batch = w.batch;
     g.tag = t_solve.c_str();
     g.gauss3m = w.gauss3m;
     g.active = active;
-    RSRR_TRY(gemm_batched<R>(g, s));
-    const int rest = n - k - nbe;
-    if (rest > 0) {
-      GemmBatch<R> u;
-      u.M = rest; u.N = nrhs; u.K = nbe;
-      u.alpha = mk<R>(-1, 0); u.beta = mk<R>(1, 0);
-      u.A = w.A + (k + nbe) + (long)k * w.lda; u.lda = w.lda; u.sA = w.sA;
-      u.B = B + k; u.ldb = ldb; u.sB = sB;
-      u.C = B + k + nbe; u.ldc = ldb; u.sC = sB;
-      u.batch = w.batch;
-      u.tag = t_solve.c_str();
-      u.gauss3m = w.gauss3m;
-      u.active = active;
-      RSRR_TRY(gemm_batched<R>(u, s));
+    return gemm_batched<R>(g, s);
+  };
+  // forward, L: per group of LU_SB panels (the row order lu_factor gives its L
+  // columns): the group's interchanges on B, the triangular solves with the
+  // diagonal-block inverses and updates inside the group, then the rows below
+  // the group in one product with K = the group's width
+  for (int p0 = 0; p0 < np; p0 += LU_SB) {
+    const int p1 = min(np, p0 + LU_SB);
+    const int k0 = p0 * nb, k1 = min(n, p1 * nb);
+    for (int p = p0; p < p1; ++p)
+      RSRR_TRY(launch_permute<R>(B, ldb, sB, nrhs, w.ipiv, n, p * nb, min(nb, n - p * nb), w.batch, s, active));
+    for (int p = p0; p < p1; ++p) {
+      const int k = p * nb, nbe = min(nb, n - k);
+      // in place: one workgroup row (M <= 64) reads all of B_k before writing it
+      RSRR_TRY(mm(nbe, nbe, w.dinv + (long)p * 2 * nb * nb, nb, sD, B + k, B + k, false));
+      if (k + nbe < k1)
+        RSRR_TRY(mm(k1 - k - nbe, nbe, w.A + (k + nbe) + (long)k * w.lda, w.lda, w.sA, B + k, B + k + nbe, true));
     }
+    if (k1 < n) RSRR_TRY(mm(n - k1, k1 - k0, w.A + k1 + (long)k0 * w.lda, w.lda, w.sA, B + k0, B + k1, true));
   }
-  for (int p = w.npanel() - 1; p >= 0; --p) {          // backward: U
-    const int k = p * nb, nbe = min(nb, n - k);
-    GemmBatch<R> g;
-    g.M = nbe; g.N = nrhs; g.K = nbe;
-    g.A = w.dinv + (long)p * 2 * nb * nb + (long)nb * nb; g.lda = nb; g.sA = sD;
-    g.B = B + k; g.ldb = ldb; g.sB = sB;
-    g.C = B + k; g.ldc = ldb; g.sC = sB;
-    g.batch = w.batch;
-    g.tag = t_solve.c_str();
-    g.gauss3m = w.gauss3m;
-    g.active = active;
-    RSRR_TRY(gemm_batched<R>(g, s));
-    if (k > 0) {
-      GemmBatch<R> u;
-      u.M = k; u.N = nrhs; u.K = nbe;
-      u.alpha = mk<R>(-1, 0); u.beta = mk<R>(1, 0);
-      u.A = w.A + (long)k * w.lda; u.lda = w.lda; u.sA = w.sA;
-      u.B = B + k; u.ldb = ldb; u.sB = sB;
-      u.C = B; u.ldc = ldb; u.sC = sB;
-      u.batch = w.batch;
-      u.tag = t_solve.c_str();
-      u.gauss3m = w.gauss3m;
-      u.active = active;
-      RSRR_TRY(gemm_batched<R>(u, s));
+  // backward, U: per group from the last, solves and updates inside the
+  // group, then the rows above it in one product
+  for (int p0 = ((np - 1) / LU_SB) * LU_SB; p0 >= 0; p0 -= LU_SB) {
+    const int p1 = min(np, p0 + LU_SB);
+    const int k0 = p0 * nb, k1 = min(n, p1 * nb);
+    for (int p = p1 - 1; p >= p0; --p) {
+      const int k = p * nb, nbe = min(nb, n - k);
+      RSRR_TRY(mm(nbe, nbe, w.dinv + (long)p * 2 * nb * nb + (long)nb * nb, nb, sD, B + k, B + k, false));
+      if (k > k0) RSRR_TRY(mm(k - k0, nbe, w.A + k0 + (long)k * w.lda, w.lda, w.sA, B + k, B + k0, true));
     }
+    if (k0 > 0) RSRR_TRY(mm(k0, k1 - k0, w.A + (long)k0 * w.lda, w.lda, w.sA, B + k0, B, true));
   }
   return ST_OK;
 }
