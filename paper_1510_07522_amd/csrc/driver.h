@@ -65,6 +65,9 @@ int moment_impl(rsrr_problem* p, const rsrr_contour* c, const rsrr_params* prm, 
                 c128* M, long ldm);
 int ortho_impl(int rows, int cols, const c128* S, long lds, double delta, c128* Q, long ldq,
                int* k_S, Arena& ws, hipStream_t s);
+// One Cholesky-QR pass, X <- X chol(X^H X)^{-H} in place (ok = false if the
+// Cholesky factorisation breaks down).
+int cholqr(c128* X, long ldx, int rows, int k, Arena& ws, hipStream_t s, bool* ok);
 int basis_of_columns(const c128* X, long ldx, int rows, int cols, int rank, c128* Q, long ldq,
                      Arena& ws, hipStream_t s);
 int project_impl(rsrr_problem* p, const rsrr_contour* c, const rsrr_params* prm, const c128* Q,

@@ -509,6 +509,52 @@ static int newton_sign_batched(DcBatch& bt, Arena& ws, hipStream_t s, std::vecto
   return ST_OK;
 }
 
+// Deterministic complex Gaussian entries (x + iy)/sqrt(2): splitmix64 of the
+// element index and the seed, two uniforms per entry, Box-Muller.
+__device__ inline uint64_t mix64(uint64_t z) {
+  z += 0x9E3779B97F4A7C15ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+__global__ __launch_bounds__(256) void gauss_fill_kernel(c128* X, long ldx, int rows, int cols, uint64_t seed) {
+  const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= (long)rows * cols) return;
+  const uint64_t a = mix64(seed ^ (2 * (uint64_t)e)), b = mix64(seed ^ (2 * (uint64_t)e + 1));
+  const double u1 = ((a >> 11) + 1.0) * (1.0 / 9007199254740993.0);
+  const double u2 = (b >> 11) * (1.0 / 9007199254740992.0);
+  const double r = sqrt(-2.0 * log(u1)) * 0.7071067811865476;
+  double sn, cs;
+  sincos(6.283185307179586 * u2, &sn, &cs);
+  X[(e % rows) + (long)(e / rows) * ldx] = mk<double>(r * cs, r * sn);
+}
+
+// Q2 (len x (len-k)): an orthonormal basis of the orthogonal complement of
+// range(Q1) from a seeded Gaussian block, projected against Q1 twice and
+// orthonormalised by Cholesky-QR, then projected and orthonormalised once
+// more.  A Gaussian block restricted to the complement is well conditioned
+// with high probability; *ok = false if a Cholesky factorisation breaks down.
+static int complement_basis(const c128* Q1, int len, int k, c128* Q2, DcWork& w, Arena& ws, hipStream_t s,
+                            bool* ok) {
+  const int r = len - k;
+  *ok = false;
+  hipLaunchKernelGGL(gauss_fill_kernel, dim3(nblk((long)len * r)), dim3(256), 0, s, Q2, (long)len, len, r,
+                     0x5DEECE66Dull * (uint64_t)len + (uint64_t)k);
+  RSRR_LAUNCH_CHECK();
+  for (int pass = 0; pass < 3; ++pass) {
+    RSRR_TRY(zg(OP_C, OP_N, k, r, len, ONE, Q1, len, Q2, len, ZERO, w.tmp, k, s));
+    RSRR_TRY(zg(OP_N, OP_N, len, r, k, MONE, Q1, len, w.tmp, k, ONE, Q2, len, s));
+    if (pass >= 1) {
+      bool good = false;
+      RSRR_TRY(cholqr(Q2, len, len, r, ws, s, &good));
+      if (!good) return ST_OK;
+    }
+  }
+  *ok = true;
+  return ST_OK;
+}
+
 // Q = [Q1 Q2] (len x len, ld len): Q1 an orthonormal basis of range(P) (rank
 // k, P len x len with leading dimension ldp), Q2 of its orthogonal complement.
 // scratch: len x len, distinct from P and w.Q.
@@ -517,6 +563,10 @@ static int bases_from_projector(const c128* P, long ldp, int len, int k, c128* Q
   c128* Q1 = Q;
   c128* Q2 = Q + (long)k * len;
   RSRR_TRY(basis_of_columns(P, ldp, len, len, k, Q1, len, ws, s));
+  bool ok = false;
+  RSRR_TRY(complement_basis(Q1, len, k, Q2, w, ws, s, &ok));
+  if (ok) return ST_OK;
+  // fallback: pivoted basis of range(I - Q1 Q1^H)
   RSRR_TRY(set_identity(scratch, len, len, s));
   RSRR_TRY(zg(OP_N, OP_C, len, len, k, MONE, Q1, len, Q1, len, ONE, scratch, len, s));
   RSRR_TRY(basis_of_columns(scratch, len, len, len, len - k, Q2, len, ws, s));

@@ -314,15 +314,26 @@ static int trsm_right_lh(const c128* L, long ldl, int k, c128* X, long ldx, int 
   RSRR_TRY(ws.get<c128>("tr_tmp", (size_t)rows * PBS, &tmp));
   hipLaunchKernelGGL(tri_inv_lower_blocks, dim3(nblk), dim3(64), 0, s, L, ldl, k, PBS, inv);
   RSRR_LAUNCH_CHECK();
-  for (int b = 0; b < nblk; ++b) {
-    const int j = b * PBS, be = std::min(PBS, k - j);
-    if (j > 0)   // X_b -= X[:, :j] (L[b, :j])^H
-      RSRR_TRY(gemm_z(OP_N, OP_C, rows, be, j, MONE, X, ldx, L + j, ldl, ONE, X + (long)j * ldx,
-                      ldx, s));
-    // X_b <- X_b inv(L_bb)^H
-    RSRR_TRY(gemm_z(OP_N, OP_C, rows, be, be, ONE, X + (long)j * ldx, ldx, inv + (long)b * PBS * PBS,
-                    PBS, ZERO, tmp, rows, s));
-    RSRR_TRY((convert<double, double>(tmp, rows, 0, X + (long)j * ldx, ldx, 0, rows, be, 1, s)));
+  // right-looking over groups of TRSM_G column blocks: inside a group each
+  // block is solved after the group's earlier blocks are subtracted, then the
+  // columns right of the group are updated with one product (K = group width)
+  constexpr int TRSM_G = 4;
+  for (int g0 = 0; g0 < nblk; g0 += TRSM_G) {
+    const int g1 = std::min(nblk, g0 + TRSM_G);
+    const int c0 = g0 * PBS, c1 = std::min(k, g1 * PBS);
+    for (int b = g0; b < g1; ++b) {
+      const int j = b * PBS, be = std::min(PBS, k - j);
+      if (j > c0)   // X_b -= X[:, c0:j] (L[b, c0:j])^H
+        RSRR_TRY(gemm_z(OP_N, OP_C, rows, be, j - c0, MONE, X + (long)c0 * ldx, ldx, L + j + (long)c0 * ldl, ldl,
+                        ONE, X + (long)j * ldx, ldx, s));
+      // X_b <- X_b inv(L_bb)^H
+      RSRR_TRY(gemm_z(OP_N, OP_C, rows, be, be, ONE, X + (long)j * ldx, ldx, inv + (long)b * PBS * PBS,
+                      PBS, ZERO, tmp, rows, s));
+      RSRR_TRY((convert<double, double>(tmp, rows, 0, X + (long)j * ldx, ldx, 0, rows, be, 1, s)));
+    }
+    if (c1 < k)     // X[:, c1:] -= X[:, c0:c1] (L[c1:, c0:c1])^H
+      RSRR_TRY(gemm_z(OP_N, OP_C, rows, k - c1, c1 - c0, MONE, X + (long)c0 * ldx, ldx, L + c1 + (long)c0 * ldl,
+                      ldl, ONE, X + (long)c1 * ldx, ldx, s));
   }
   return ST_OK;
 }
@@ -373,6 +384,10 @@ static int cholqr_pass(c128* X, long ldx, int rows, int k, Arena& ws, hipStream_
   RSRR_TRY(chol_blocked(G, k, k, ws, s, ok));
   if (!*ok) return ST_OK;
   return trsm_right_lh(G, k, k, X, ldx, rows, ws, s);
+}
+
+int cholqr(c128* X, long ldx, int rows, int k, Arena& ws, hipStream_t s, bool* ok) {
+  return cholqr_pass(X, ldx, rows, k, ws, s, ok);
 }
 
 // Orthonormal basis (rows x rank, into Q) of the span of the columns of X
