@@ -46,17 +46,26 @@ def kernel_bound(sym: str):
 
 
 
+def sources_sha256() -> str:
+    """Hash of every library source: the kernels and the drivers that decide
+    the launch mix a per-launch traffic figure averages over."""
+    d = os.path.join(ROOT, "paper_1510_07522_amd", "csrc")
+    h = hashlib.sha256()
+    for f in sorted(os.listdir(d)):
+        if f.endswith((".hip", ".h")):
+            h.update(f.encode())
+            h.update(open(os.path.join(d, f), "rb").read())
+    return h.hexdigest()
+
+
 def traffic_record(sym: str):
     """HBM bytes per launch from the committed counter summary of this kernel
-    function, if its source file is unchanged since the counters were taken."""
+    function, if no library source has changed since the counters were taken."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(path):
         return None
     rec = json.load(open(path)).get(sym)
-    if not rec:
-        return None
-    src = os.path.join(ROOT, "paper_1510_07522_amd", "csrc", rec.get("source", ""))
-    if not os.path.exists(src) or hashlib.sha256(open(src, "rb").read()).hexdigest() != rec.get("source_sha256"):
+    if not rec or rec.get("sources_sha256") != sources_sha256():
         return None
     return rec.get("hbm_bytes_per_launch")
 
@@ -83,7 +92,7 @@ def _kernel_sym(name: str) -> str:
     return name
 
 
-def write_traffic(dirs, sym: str, source: str, copy_mib: int):
+def write_traffic(dirs, sym: str, copy_mib: int):
     """HBM bytes per launch of one kernel function from FETCH_SIZE and
     WRITE_SIZE (KiB per dispatch), each scaled by what the same counter reads
     for a plain device copy of copy_mib MiB (the copy reads and writes exactly
@@ -104,13 +113,11 @@ def write_traffic(dirs, sym: str, source: str, copy_mib: int):
         if not vals:
             raise SystemExit(f"{folder}: no copy dispatch")
         scale[tag] = true_bytes / (sum(vals) / len(vals))
-    src = os.path.join(ROOT, "paper_1510_07522_amd", "csrc", source)
     fetch = per["fetch"][0] * scale["fetch"]
     write = per["write"][0] * scale["write"]
     path = os.path.join(ROOT, "profiles", "traffic.json")
     rec = json.load(open(path)) if os.path.exists(path) else {}
-    rec[sym] = {"source": source,
-                "source_sha256": hashlib.sha256(open(src, "rb").read()).hexdigest(),
+    rec[sym] = {"sources_sha256": sources_sha256(),
                 "hbm_bytes_per_launch": fetch + write, "fetch_bytes_per_launch": fetch,
                 "write_bytes_per_launch": write, "launches": per["fetch"][1],
                 "fetch_scale": scale["fetch"], "write_scale": scale["write"],
@@ -291,10 +298,9 @@ def main():
                     help="write profiles/traffic.json from four rocprofv3 --pmc output folders "
                          "(FETCH_SIZE / WRITE_SIZE of the kernel, then of the copy calibration) and exit")
     ap.add_argument("--traffic-kernel", default="gemm_kernel<double, 0, 0, false, true>")
-    ap.add_argument("--traffic-source", default="gemm.hip")
     a = ap.parse_args()
     if a.traffic_from:
-        write_traffic(a.traffic_from, a.traffic_kernel, a.traffic_source, a.copy_calibration or 1024)
+        write_traffic(a.traffic_from, a.traffic_kernel, a.copy_calibration or 1024)
         return
     if a.gpus != 1:
         print(json.dumps({"error": "this build runs on exactly one GPU; --gpus must be 1"}))

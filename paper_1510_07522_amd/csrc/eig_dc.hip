@@ -555,6 +555,26 @@ static int complement_basis(const c128* Q1, int len, int k, c128* Q2, DcWork& w,
   return ST_OK;
 }
 
+// Q1 (len x k): an orthonormal basis of range(P) (P a projector of rank k)
+// from P times a seeded Gaussian block, orthonormalised by two Cholesky-QR
+// passes; *ok = false if a factorisation breaks down (P Omega too ill
+// conditioned for Cholesky-QR).
+static int range_basis(const c128* P, long ldp, int len, int k, c128* Q1, DcWork& w, Arena& ws, hipStream_t s,
+                       bool* ok) {
+  *ok = false;
+  hipLaunchKernelGGL(gauss_fill_kernel, dim3(nblk((long)len * k)), dim3(256), 0, s, w.tmp, (long)len, len, k,
+                     0x2545F4914F6CDD1Dull * (uint64_t)len + (uint64_t)k);
+  RSRR_LAUNCH_CHECK();
+  RSRR_TRY(zg(OP_N, OP_N, len, k, len, ONE, P, ldp, w.tmp, len, ZERO, Q1, len, s));
+  for (int pass = 0; pass < 2; ++pass) {
+    bool good = false;
+    RSRR_TRY(cholqr(Q1, len, len, k, ws, s, &good));
+    if (!good) return ST_OK;
+  }
+  *ok = true;
+  return ST_OK;
+}
+
 // Q = [Q1 Q2] (len x len, ld len): Q1 an orthonormal basis of range(P) (rank
 // k, P len x len with leading dimension ldp), Q2 of its orthogonal complement.
 // scratch: len x len, distinct from P and w.Q.
@@ -562,8 +582,9 @@ static int bases_from_projector(const c128* P, long ldp, int len, int k, c128* Q
                                 Arena& ws, hipStream_t s) {
   c128* Q1 = Q;
   c128* Q2 = Q + (long)k * len;
-  RSRR_TRY(basis_of_columns(P, ldp, len, len, k, Q1, len, ws, s));
   bool ok = false;
+  RSRR_TRY(range_basis(P, ldp, len, k, Q1, w, ws, s, &ok));
+  if (!ok) RSRR_TRY(basis_of_columns(P, ldp, len, len, k, Q1, len, ws, s));
   RSRR_TRY(complement_basis(Q1, len, k, Q2, w, ws, s, &ok));
   if (ok) return ST_OK;
   // fallback: pivoted basis of range(I - Q1 Q1^H)
