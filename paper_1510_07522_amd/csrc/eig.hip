@@ -88,8 +88,10 @@ __global__ __launch_bounds__(256) void bj_gram_kernel(const c128* H, long ldh, i
 }
 
 // Gram of block pair i (slices added in a fixed order), convergence test and
-// diagonalisation by cyclic two-sided Jacobi (circle method over the 2*JB
-// indices, at most 3 sweeps per visit; the outer sweeps finish the job).
+// one sweep of cyclic two-sided Jacobi (circle method over the 2*JB indices)
+// per visit: the outer sweeps finish the job, and more inner sweeps do not
+// save outer ones (13 outer sweeps with one inner sweep or three on the
+// benchmark's Hankel matrix).
 // Writes V (2*JB x 2*JB, column-major) and flag[i] = 1 if V is to be applied.
 __global__ __launch_bounds__(256) void bj_rotate_kernel(const c128* part, int nks, double tol, double gfloor,
                                                         double nfloor, c128* Vout, int* flag, int* counter) {
@@ -122,7 +124,7 @@ __global__ __launch_bounds__(256) void bj_rotate_kernel(const c128* part, int nk
     if (need) atomicAdd(counter, 1);
   }
   if (!need) return;
-  for (int sweep = 0; sweep < 3; ++sweep) {
+  for (int sweep = 0; sweep < 1; ++sweep) {
     __syncthreads();
     if (tid == 0) s_flag = 0;
     __syncthreads();
