@@ -38,38 +38,65 @@ __device__ inline int pair_col(int round, int nbk, int i, int j) {
   return (j < JB) ? a * JB + j : cb * JB + (j - JB);
 }
 
-// Partial Gram X^H X of block pair i = blockIdx.x over row slice ks = blockIdx.y.
-// Each wave takes a quarter of every LDS chunk of rows; lane t accumulates the
-// 4x4 block (rows 4*(t/8).., columns 4*(t%8)..) of the 32x32 Gram; the four
-// wave partials are added in LDS in a fixed order.
+typedef double jd4 __attribute__((ext_vector_type(4)));
+__device__ inline jd4 jmfma(double a, double b, jd4 c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
+// Partial Gram X^H X of block pair i = blockIdx.x over row slice ks = blockIdx.y
+// on the matrix cores.  A chunk of JCH rows of the pair's 32 columns is staged
+// in LDS (real and imaginary parts apart); each wave takes two of the chunk's
+// eight 4-row steps and accumulates the blocks (0,0), (0,1), (1,1) of the
+// 32x32 Gram (16x16 MFMA blocks, four real products per complex block and
+// step; the A and B operands of a lane are the same LDS values).  The wave
+// partials are added in LDS in wave order and block (1,0) is the conjugate
+// transpose of block (0,1).  MFMA f64 16x16x4 lane layout: A[m][k] and
+// B[k][n] with m, n = lane % 16, k = lane / 16; accumulator element r holds
+// row lane / 16 + 4 r, column lane % 16.
 __global__ __launch_bounds__(256) void bj_gram_kernel(const c128* H, long ldh, int rows, int cols, int nbk,
                                                       int round, int rows_per, c128* part) {
-  __shared__ c128 X[JCH][J2 + 1];
+  __shared__ double Xr[JCH][J2 + 1], Xi[JCH][J2 + 1];
   __shared__ c128 R[J2][J2 + 1];
   const int i = blockIdx.x, ks = blockIdx.y, tid = threadIdx.x;
-  const int wave = tid >> 6, t = tid & 63;
-  const int bi = 4 * (t >> 3), bj = 4 * (t & 7);
+  const int wave = tid >> 6, lane = tid & 63;
   const int r_begin = ks * rows_per, r_end = min(rows, r_begin + rows_per);
-  c128 acc[4][4];
+  jd4 are[3], aim[3];
 #pragma unroll
-  for (int p = 0; p < 4; ++p)
+  for (int b = 0; b < 3; ++b) { are[b] = jd4{0, 0, 0, 0}; aim[b] = jd4{0, 0, 0, 0}; }
+  // element e = tid + 256 t of a chunk: row e % JCH, local column e / JCH;
+  // the next chunk is loaded into registers while this one is multiplied
+  constexpr int PER = JCH * J2 / 256;
+  int gcol[PER];
 #pragma unroll
-    for (int q = 0; q < 4; ++q) acc[p][q] = mk<double>(0, 0);
+  for (int t = 0; t < PER; ++t) gcol[t] = pair_col(round, nbk, i, (tid + 256 * t) / JCH);
+  c128 pf[PER];
+  auto load = [&](int r0) {
+#pragma unroll
+    for (int t = 0; t < PER; ++t) {
+      const int r = r0 + (tid + 256 * t) % JCH, c = gcol[t];
+      pf[t] = (r < r_end && c < cols) ? H[r + (long)c * ldh] : mk<double>(0, 0);
+    }
+  };
+  if (r_begin < r_end) load(r_begin);
   for (int r0 = r_begin; r0 < r_end; r0 += JCH) {
-    for (int e = tid; e < JCH * J2; e += 256) {
-      const int rr = e % JCH, j = e / JCH;
-      const int r = r0 + rr, c = pair_col(round, nbk, i, j);
-      X[rr][j] = (r < r_end && c < cols) ? H[r + (long)c * ldh] : mk<double>(0, 0);
+#pragma unroll
+    for (int t = 0; t < PER; ++t) {
+      const int e = tid + 256 * t;
+      Xr[e % JCH][e / JCH] = pf[t].re;
+      Xi[e % JCH][e / JCH] = pf[t].im;
     }
     __syncthreads();
-    for (int rr = wave; rr < JCH; rr += 4) {
-      c128 xa[4], xb[4];
-#pragma unroll
-      for (int p = 0; p < 4; ++p) { xa[p] = X[rr][bi + p]; xb[p] = X[rr][bj + p]; }
-#pragma unroll
-      for (int p = 0; p < 4; ++p)
-#pragma unroll
-        for (int q = 0; q < 4; ++q) acc[p][q] = acc[p][q] + cmul(xa[p], xb[q]);
+    if (r0 + JCH < r_end) load(r0 + JCH);
+    for (int q = wave; q < JCH / 4; q += 4) {
+      const int kk = q * 4 + (lane >> 4), n = lane & 15;
+      const double x0r = Xr[kk][n], x0i = Xi[kk][n], x1r = Xr[kk][16 + n], x1i = Xi[kk][16 + n];
+      // conj(x_a) x_b: re = xr_a xr_b + xi_a xi_b, im = xr_a xi_b - xi_a xr_b
+      are[0] = jmfma(x0r, x0r, are[0]); are[0] = jmfma(x0i, x0i, are[0]);
+      aim[0] = jmfma(x0r, x0i, aim[0]); aim[0] = jmfma(-x0i, x0r, aim[0]);
+      are[1] = jmfma(x0r, x1r, are[1]); are[1] = jmfma(x0i, x1i, are[1]);
+      aim[1] = jmfma(x0r, x1i, aim[1]); aim[1] = jmfma(-x0i, x1r, aim[1]);
+      are[2] = jmfma(x1r, x1r, are[2]); are[2] = jmfma(x1i, x1i, are[2]);
+      aim[2] = jmfma(x1r, x1i, aim[2]); aim[2] = jmfma(-x1i, x1r, aim[2]);
     }
     __syncthreads();
   }
@@ -77,12 +104,24 @@ __global__ __launch_bounds__(256) void bj_gram_kernel(const c128* H, long ldh, i
   for (int w = 0; w < 4; ++w) {
     if (wave == w) {
 #pragma unroll
-      for (int p = 0; p < 4; ++p)
-#pragma unroll
-        for (int q = 0; q < 4; ++q) R[bi + p][bj + q] = (w == 0) ? acc[p][q] : R[bi + p][bj + q] + acc[p][q];
+      for (int r = 0; r < 4; ++r) {
+        const int m = (lane >> 4) + 4 * r, n = lane & 15;
+        const c128 g0 = mk<double>(are[0][r], aim[0][r]), g1 = mk<double>(are[1][r], aim[1][r]),
+                   g2 = mk<double>(are[2][r], aim[2][r]);
+        if (w == 0) {
+          R[m][n] = g0; R[m][16 + n] = g1; R[16 + m][16 + n] = g2;
+        } else {
+          R[m][n] = R[m][n] + g0; R[m][16 + n] = R[m][16 + n] + g1; R[16 + m][16 + n] = R[16 + m][16 + n] + g2;
+        }
+      }
     }
     __syncthreads();
   }
+  {
+    const int m = tid % 16, n = tid / 16;          // 256 threads: the 16x16 block (1,0)
+    R[16 + m][n] = conj(R[n][16 + m]);
+  }
+  __syncthreads();
   c128* out = part + ((long)i * gridDim.y + ks) * (J2 * J2);
   for (int e = tid; e < J2 * J2; e += 256) out[e] = R[e % J2][e / J2];
 }
@@ -183,48 +222,88 @@ __global__ __launch_bounds__(256) void bj_rotate_kernel(const c128* part, int nk
   for (int e = tid; e < J2 * J2; e += 256) vo[e] = V[e % J2][e / J2];
 }
 
-// Columns of block pair i = blockIdx.x times its V over row slice
+// Columns of block pair i = blockIdx.x times its V (32x32) over row slice
 // ks = blockIdx.y, for H (blockIdx.z == 0, rowsH rows) or W (blockIdx.z == 1,
-// rowsW rows); both have `cols` columns.
+// rowsW rows); both have `cols` columns.  On the matrix cores: a chunk of JAR
+// rows of the pair's columns is staged in LDS column by column (real and
+// imaginary parts apart), each wave computes 16 rows x 32 columns (two 16x16
+// MFMA blocks, four real products per complex block and 4-column step), and
+// the result goes back through LDS so that the global stores run along rows.
+constexpr int JAR = 64;
 __global__ __launch_bounds__(256) void bj_apply_kernel(c128* H, long ldh, int rowsH, c128* W, long ldw,
                                                        int rowsW, int cols, int nbk, int round, int rows_per,
                                                        const c128* Vin, const int* flag) {
-  __shared__ c128 X[JCH][J2 + 1];
-  __shared__ c128 V[J2][J2 + 1];
+  __shared__ double Xr[J2][JAR + 1], Xi[J2][JAR + 1];
+  __shared__ double Vr[J2][J2 + 1], Vi[J2][J2 + 1];
+  __shared__ int s_gc[J2];
   const int i = blockIdx.x, ks = blockIdx.y, tid = threadIdx.x;
   if (!flag[i]) return;
   c128* Mx = blockIdx.z == 0 ? H : W;
   const long ld = blockIdx.z == 0 ? ldh : ldw;
   const int rows = blockIdx.z == 0 ? rowsH : rowsW;
-  for (int e = tid; e < J2 * J2; e += 256) V[e % J2][e / J2] = Vin[(long)i * (J2 * J2) + e];
+  const int wave = tid >> 6, lane = tid & 63;
+  for (int e = tid; e < J2 * J2; e += 256) {
+    const c128 v = Vin[(long)i * (J2 * J2) + e];
+    Vr[e % J2][e / J2] = v.re;
+    Vi[e % J2][e / J2] = v.im;
+  }
+  if (tid < J2) s_gc[tid] = pair_col(round, nbk, i, tid);
   const int r_begin = ks * rows_per, r_end = min(rows, r_begin + rows_per);
-  const int rr = tid / 8, j0 = (tid % 8) * 4;   // 4 outputs per thread (JCH * J2 = 4 * 256)
-  int gc[4];
+  // element e = tid + 256 t of a chunk: row e % JAR, local column e / JAR; the
+  // next chunk is loaded into registers while this one is multiplied
+  constexpr int PER = JAR * J2 / 256;
+  int gcol[PER];
 #pragma unroll
-  for (int q = 0; q < 4; ++q) gc[q] = pair_col(round, nbk, i, j0 + q);
-  for (int r0 = r_begin; r0 < r_end; r0 += JCH) {
-    __syncthreads();
-    for (int e = tid; e < JCH * J2; e += 256) {
-      const int q = e % JCH, j = e / JCH;
-      const int r = r0 + q, c = pair_col(round, nbk, i, j);
-      X[q][j] = (r < r_end && c < cols) ? Mx[r + (long)c * ld] : mk<double>(0, 0);
+  for (int t = 0; t < PER; ++t) gcol[t] = pair_col(round, nbk, i, (tid + 256 * t) / JAR);
+  c128 pf[PER];
+  auto load = [&](int r0) {
+#pragma unroll
+    for (int t = 0; t < PER; ++t) {
+      const int r = r0 + (tid + 256 * t) % JAR, c = gcol[t];
+      pf[t] = (r < r_end && c < cols) ? Mx[r + (long)c * ld] : mk<double>(0, 0);
+    }
+  };
+  if (r_begin < r_end) load(r_begin);
+  for (int r0 = r_begin; r0 < r_end; r0 += JAR) {
+    __syncthreads();                     // V, s_gc ready; the previous chunk's stores done
+#pragma unroll
+    for (int t = 0; t < PER; ++t) {
+      const int e = tid + 256 * t;
+      Xr[e / JAR][e % JAR] = pf[t].re;
+      Xi[e / JAR][e % JAR] = pf[t].im;
     }
     __syncthreads();
-    c128 v0 = mk<double>(0, 0), v1 = v0, v2 = v0, v3 = v0;
+    if (r0 + JAR < r_end) load(r0 + JAR);
+    jd4 yr[2], yi[2];
+#pragma unroll
+    for (int b = 0; b < 2; ++b) { yr[b] = jd4{0, 0, 0, 0}; yi[b] = jd4{0, 0, 0, 0}; }
+    const int m = 16 * wave + (lane & 15);
 #pragma unroll 4
-    for (int l = 0; l < J2; ++l) {
-      const c128 x = X[rr][l];
-      v0 = v0 + x * V[l][j0];
-      v1 = v1 + x * V[l][j0 + 1];
-      v2 = v2 + x * V[l][j0 + 2];
-      v3 = v3 + x * V[l][j0 + 3];
+    for (int kq = 0; kq < J2 / 4; ++kq) {
+      const int kk = kq * 4 + (lane >> 4);
+      const double ar = Xr[kk][m], ai = Xi[kk][m];
+#pragma unroll
+      for (int b = 0; b < 2; ++b) {
+        const double br = Vr[kk][16 * b + (lane & 15)], bi = Vi[kk][16 * b + (lane & 15)];
+        // (ar + i ai)(br + i bi) = ar br - ai bi + i (ar bi + ai br)
+        yr[b] = jmfma(ar, br, yr[b]); yr[b] = jmfma(-ai, bi, yr[b]);
+        yi[b] = jmfma(ar, bi, yi[b]); yi[b] = jmfma(ai, br, yi[b]);
+      }
     }
-    const int r = r0 + rr;
-    if (r < r_end) {
-      if (gc[0] < cols) Mx[r + (long)gc[0] * ld] = v0;
-      if (gc[1] < cols) Mx[r + (long)gc[1] * ld] = v1;
-      if (gc[2] < cols) Mx[r + (long)gc[2] * ld] = v2;
-      if (gc[3] < cols) Mx[r + (long)gc[3] * ld] = v3;
+    __syncthreads();                     // every wave has read the chunk
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = 16 * wave + (lane >> 4) + 4 * r, col = 16 * b + (lane & 15);
+        Xr[col][row] = yr[b][r];
+        Xi[col][row] = yi[b][r];
+      }
+    __syncthreads();
+    for (int e = tid; e < JAR * J2; e += 256) {
+      const int rr = e % JAR, j = e / JAR;
+      const int r = r0 + rr, c = s_gc[j];
+      if (r < r_end && c < cols) Mx[r + (long)c * ld] = mk<double>(Xr[j][rr], Xi[j][rr]);
     }
   }
 }
