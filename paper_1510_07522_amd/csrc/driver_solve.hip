@@ -200,7 +200,7 @@ int solve_impl(rsrr_problem* p, const rsrr_contour* c, const rsrr_params* prm, c
   // nodes per batch: as many as the chunk memory holds, balanced over the batches
   const int ch = chunk_count(NS, per, prm->chunk_gib).second;
   c128 *TS = nullptr, *X = nullptr, *Amom = nullptr, *gdev = nullptr, *cw = nullptr, *dinv = nullptr,
-       *part = nullptr, *Iden = nullptr;
+       *part = nullptr;
   int *ipiv = nullptr, *linfo = nullptr;
   const int nchunk = 64;
   RSRR_TRY(ws.get<c128>("rd_TS", (size_t)ch * kk, &TS));
@@ -210,10 +210,10 @@ int solve_impl(rsrr_problem* p, const rsrr_contour* c, const rsrr_params* prm, c
   RSRR_TRY(ws.get<c128>("rd_cw", (size_t)ch * 2 * K, &cw));
   RSRR_TRY(ws.get<c128>("rd_dinv", LUWork<double>::dinv_elems(kS, prm->nb, ch), &dinv));
   RSRR_TRY(ws.get<c128>("rd_part", (size_t)ch * nchunk, &part));
-  RSRR_TRY(ws.get<c128>("rd_I", (size_t)kk, &Iden));
   RSRR_TRY(ws.get<int>("rd_ipiv", (size_t)ch * kS, &ipiv));
+  int* iperm = nullptr;
+  RSRR_TRY(ws.get<int>("rd_perm", (size_t)ch * kS, &iperm));
   RSRR_TRY(ws.get<int>("rd_info", ch, &linfo));
-  RSRR_TRY(set_identity(Iden, kS, kS, s));
   cd wind(0, 0);
   std::vector<cd> g, dg;
   std::vector<c128> hg((size_t)ch * J), hdg((size_t)ch * J), hcw((size_t)ch * 2 * K), hpart;
@@ -246,14 +246,16 @@ int solve_impl(rsrr_problem* p, const rsrr_contour* c, const rsrr_params* prm, c
     w.tag = "reduced_lu_c128";
     RSRR_TRY(ws.aux_stream(&w.aux, &w.ev_main, &w.ev_aux));
     w.gauss3m = true;
+    w.full_swap = true;
     RSRR_TRY(lu_factor<double>(w, s));
-    RSRR_TRY(replicate<double>(Iden, kS, X, kS, kk, kS, kS, cnt, s));
-    RSRR_TRY(lu_solve<double>(w, X, kS, kk, kS, s));
-    // moments: [A_0 .. A_{2K-1}] += [X_m] cw   (kk x cnt) (cnt x 2K)
-    RSRR_TRY(zgemm(OP_N, OP_N, (int)kk, 2 * K, cnt, ONE, X, kk, cw, cnt, m0 == 0 ? ZERO : ONE, Amom, kk, s));
-    // winding: tr(X_m T_S'(zeta_m)) = sum_e X_m[e] (T_S'(zeta_m)^T)[e]
-    RSRR_TRY(zgemm(OP_N, OP_N, (int)kk, cnt, J, ONE, BT, kk, gdev + (size_t)ch * J, J, ZERO, TS, kk, s));
-    RSRR_TRY(dot_partials(X, TS, kk, cnt, nchunk, part, s));
+    // the inverses replace the factors in TS once the solves are done; X is
+    // the work space of the solves
+    RSRR_TRY(lu_inverse<double>(w, X, TS, kS, kk, iperm, s));
+    // moments: [A_0 .. A_{2K-1}] += [X_m] cw   (kk x cnt) (cnt x 2K), X_m in TS
+    RSRR_TRY(zgemm(OP_N, OP_N, (int)kk, 2 * K, cnt, ONE, TS, kk, cw, cnt, m0 == 0 ? ZERO : ONE, Amom, kk, s));
+    // winding: tr(X_m T_S'(zeta_m)) = sum_e X_m[e] (T_S'(zeta_m)^T)[e], T_S' into X
+    RSRR_TRY(zgemm(OP_N, OP_N, (int)kk, cnt, J, ONE, BT, kk, gdev + (size_t)ch * J, J, ZERO, X, kk, s));
+    RSRR_TRY(dot_partials(TS, X, kk, cnt, nchunk, part, s));
     hpart.resize((size_t)cnt * nchunk);
     std::vector<int> hinfo(cnt);
     RSRR_HIP(hipMemcpyAsync(hpart.data(), part, hpart.size() * sizeof(c128), hipMemcpyDeviceToHost, s));

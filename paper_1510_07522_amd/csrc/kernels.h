@@ -40,6 +40,10 @@ template <typename R> struct LUWork {
   int* info = nullptr;       // batch
   const char* tag = "lu";    // kernel-timer class prefix (<tag>_panel, <tag>_update, ...)
   bool gauss3m = false;      // update and solve products with 3 real multiplications
+  // every panel's interchanges also applied to all earlier L columns, so that
+  // P A = L U with one row order (needed by lu_inverse); otherwise only within
+  // the groups of panels the solver uses
+  bool full_swap = false;
   // look-ahead (optional): the trailing update beyond the next panel runs on
   // `aux` while the next panel is factored; ev_main / ev_aux order the two
   hipStream_t aux = nullptr;
@@ -54,6 +58,14 @@ template <typename R> int lu_factor(const LUWork<R>& w, hipStream_t s);
 // active (optional, device): systems b with active[b] == 0 are left untouched.
 template <typename R> int lu_solve(const LUWork<R>& w, cplx<R>* B, long ldb, long sB,
                                    int nrhs, hipStream_t s, const int* active = nullptr);
+// Inverses of factors computed with full_swap: out_b = A_b^{-1} (n x n,
+// leading dim ldo, stride sO).  X (n x n per matrix, ld n, stride n*n) is
+// work space: U^{-1} L^{-1} is formed there (the forward solve on the identity
+// skips the zero upper part of L^{-1}) and its columns are scattered to out by
+// the row permutation of the factorisation (A^{-1} = U^{-1} L^{-1} P).
+// perm: batch * n ints of work space.  out must not overlap X or the factors.
+template <typename R> int lu_inverse(const LUWork<R>& w, cplx<R>* X, cplx<R>* out, long ldo, long sO,
+                                     int* perm, hipStream_t s);
 
 // ----------------------------------------------------------------- assembly
 // Coefficient form: T_j = sum_k f[j*J + k] * A_k for j < nz, written to

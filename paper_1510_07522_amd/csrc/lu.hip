@@ -501,8 +501,8 @@ int lu_factor(const LUWork<R>& w, hipStream_t s) {
   // triangular and dinv is unchanged.
   const int np = w.npanel();
   for (int q = 1; q < np; ++q) {
-    if (q % LU_SB == 0) continue;
-    const int k = q * nb, c0 = (q / LU_SB) * LU_SB * nb;
+    if (!w.full_swap && q % LU_SB == 0) continue;
+    const int k = q * nb, c0 = w.full_swap ? 0 : (q / LU_SB) * LU_SB * nb;
     RSRR_TRY(launch_permute<R>(w.A + (long)c0 * w.lda, w.lda, w.sA, k - c0, w.ipiv, n, k, min(nb, n - k),
                                w.batch, s));
   }
@@ -562,9 +562,103 @@ int lu_solve(const LUWork<R>& w, cplx<R>* B, long ldb, long sB, int nrhs, hipStr
   return ST_OK;
 }
 
+// perm_b: the row order of P A = L U, composed from the interchanges
+// (row i of P A is row perm[i] of A); one thread per matrix.
+__global__ void lu_perm_kernel(const int* ipiv, int n, int batch, int* perm) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= batch) return;
+  const int* pv = ipiv + (long)b * n;
+  int* pm = perm + (long)b * n;
+  for (int i = 0; i < n; ++i) pm[i] = i;
+  for (int i = 0; i < n; ++i) {
+    const int p = pv[i];
+    if (p != i) { const int t = pm[i]; pm[i] = pm[p]; pm[p] = t; }
+  }
+}
+
+// out_b[:, perm_b[k]] = X_b[:, k]: column k of U^{-1} L^{-1} is column perm[k]
+// of A^{-1}.  One workgroup per (column, matrix).
+template <typename R>
+__global__ __launch_bounds__(256) void scatter_cols_kernel(const cplx<R>* X, int n, const int* perm, cplx<R>* out,
+                                                           long ldo, long sO) {
+  const int k = blockIdx.x, b = blockIdx.y;
+  const cplx<R>* src = X + (long)b * n * n + (long)k * n;
+  cplx<R>* dst = out + (long)b * sO + (long)perm[(long)b * n + k] * ldo;
+  for (int i = threadIdx.x; i < n; i += 256) dst[i] = src[i];
+}
+
+__global__ __launch_bounds__(256) void identity_batch_kernel(double* X, int n, long total_re) {
+  const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;   // over batch * n * n complex
+  if (e >= total_re) return;
+  const long nn = (long)n * n, q = e % nn;
+  X[2 * e] = (q % n == q / n) ? 1.0 : 0.0;
+  X[2 * e + 1] = 0.0;
+}
+
+template <typename R>
+int lu_inverse(const LUWork<R>& w, cplx<R>* X, cplx<R>* out, long ldo, long sO, int* perm, hipStream_t s) {
+  static_assert(sizeof(R) == 8, "complex128 only");
+  if (w.n <= 0 || w.batch <= 0) return ST_OK;
+  if (!w.full_swap) return set_error(ST_EINVAL, "lu_inverse needs factors computed with full_swap");
+  const int n = w.n, nb = w.nb, np = w.npanel();
+  const long nn = (long)n * n;
+  const std::string t_solve = std::string(w.tag) + "_solve";
+  const long sD = (long)np * 2 * nb * nb;
+  {
+    const long tot = nn * w.batch;
+    hipLaunchKernelGGL(identity_batch_kernel, dim3((unsigned)cdivl(tot, 256)), dim3(256), 0, s, (double*)X, n, tot);
+    RSRR_LAUNCH_CHECK();
+  }
+  // C[rows, 0:N) = alpha A B + beta C on the batch, X with ld n
+  auto mm = [&](int M, int N, int K, const cplx<R>* A, long lda, long sA, const cplx<R>* Bp, cplx<R>* Cp,
+                bool acc) {
+    GemmBatch<R> g;
+    g.M = M; g.N = N; g.K = K;
+    if (acc) { g.alpha = mk<R>(-1, 0); g.beta = mk<R>(1, 0); }
+    g.A = A; g.lda = lda; g.sA = sA;
+    g.B = Bp; g.ldb = n; g.sB = nn;
+    g.C = Cp; g.ldc = n; g.sC = nn;
+    g.batch = w.batch;
+    g.tag = t_solve.c_str();
+    g.gauss3m = w.gauss3m;
+    return gemm_batched<R>(g, s);
+  };
+  // forward, L Y = I: rows of panel p of Y vanish beyond column p*nb + nbe
+  // (L^{-1} is lower triangular), so every product stops at that column
+  for (int p0 = 0; p0 < np; p0 += LU_SB) {
+    const int p1 = min(np, p0 + LU_SB);
+    const int k0 = p0 * nb, k1 = min(n, p1 * nb);
+    for (int p = p0; p < p1; ++p) {
+      const int k = p * nb, nbe = min(nb, n - k);
+      RSRR_TRY(mm(nbe, k + nbe, nbe, w.dinv + (long)p * 2 * nb * nb, nb, sD, X + k, X + k, false));
+      if (k + nbe < k1)
+        RSRR_TRY(mm(k1 - k - nbe, k + nbe, nbe, w.A + (k + nbe) + (long)k * w.lda, w.lda, w.sA, X + k,
+                    X + k + nbe, true));
+    }
+    if (k1 < n) RSRR_TRY(mm(n - k1, k1, k1 - k0, w.A + k1 + (long)k0 * w.lda, w.lda, w.sA, X + k0, X + k1, true));
+  }
+  // backward, U Z = Y (dense)
+  for (int p0 = ((np - 1) / LU_SB) * LU_SB; p0 >= 0; p0 -= LU_SB) {
+    const int p1 = min(np, p0 + LU_SB);
+    const int k0 = p0 * nb, k1 = min(n, p1 * nb);
+    for (int p = p1 - 1; p >= p0; --p) {
+      const int k = p * nb, nbe = min(nb, n - k);
+      RSRR_TRY(mm(nbe, n, nbe, w.dinv + (long)p * 2 * nb * nb + (long)nb * nb, nb, sD, X + k, X + k, false));
+      if (k > k0) RSRR_TRY(mm(k - k0, n, nbe, w.A + k0 + (long)k * w.lda, w.lda, w.sA, X + k, X + k0, true));
+    }
+    if (k0 > 0) RSRR_TRY(mm(k0, n, k1 - k0, w.A + (long)k0 * w.lda, w.lda, w.sA, X + k0, X, true));
+  }
+  hipLaunchKernelGGL(lu_perm_kernel, dim3((unsigned)cdivl(w.batch, 64)), dim3(64), 0, s, w.ipiv, n, w.batch, perm);
+  RSRR_LAUNCH_CHECK();
+  hipLaunchKernelGGL((scatter_cols_kernel<R>), dim3(n, w.batch), dim3(256), 0, s, X, n, perm, out, ldo, sO);
+  RSRR_LAUNCH_CHECK();
+  return ST_OK;
+}
+
 template int lu_factor<double>(const LUWork<double>&, hipStream_t);
 template int lu_factor<float>(const LUWork<float>&, hipStream_t);
 template int lu_solve<double>(const LUWork<double>&, c128*, long, long, int, hipStream_t, const int*);
 template int lu_solve<float>(const LUWork<float>&, c64*, long, long, int, hipStream_t, const int*);
+template int lu_inverse<double>(const LUWork<double>&, c128*, c128*, long, long, int*, hipStream_t);
 
 }  // namespace rsrr
