@@ -386,6 +386,9 @@ static int newton_sign_batched(DcBatch& bt, Arena& ws, hipStream_t s, std::vecto
   RSRR_TRY(ws.get<int>("dcp_ipiv", (size_t)nq * L, &ipivp));
   RSRR_TRY(ws.get<int>("dcp_info", nq, &infop));
   LUWork<double> lwp = lw;
+  lw.full_swap = true;           // the Newton steps invert (lu_inverse)
+  int* nperm = nullptr;
+  RSRR_TRY(ws.get<int>("dcp_perm", (size_t)nbk * L, &nperm));
   lwp.batch = nq; lwp.A = LUp; lwp.ipiv = ipivp; lwp.dinv = dinvp; lwp.info = infop;
   auto reset = [&](int b) -> int {
     (*ok)[b] = 0;
@@ -474,12 +477,11 @@ static int newton_sign_batched(DcBatch& bt, Arena& ws, hipStream_t s, std::vecto
     RSRR_HIP(hipMemcpyAsync(bt.LU, bt.X, (size_t)nbk * ll * sizeof(c128), hipMemcpyDeviceToDevice, s));
     ++n_newton;
     lw.A = bt.LU;
-    for (int b = 0; b < nbk; ++b) RSRR_TRY(set_identity(bt.Y + (long)b * ll, L, L, s));
     RSRR_TRY(lu_factor<double>(lw, s));
     std::vector<int> info(nbk);
     RSRR_HIP(hipMemcpyAsync(info.data(), bt.info, nbk * sizeof(int), hipMemcpyDeviceToHost, s));
     RSRR_HIP(hipStreamSynchronize(s));
-    RSRR_TRY(lu_solve<double>(lw, bt.Y, L, ll, L, s));
+    RSRR_TRY(lu_inverse<double>(lw, Zp, bt.Y, L, ll, nperm, s));   // Y = X^{-1}; Zp is work space
     RSRR_TRY(fro_batched(bt.X, nullptr, bt, s, &fx, nullptr));
     RSRR_TRY(fro_batched(bt.Y, nullptr, bt, s, &fy, nullptr));
     for (int b = 0; b < nbk; ++b) {
