@@ -32,6 +32,7 @@ static int zg(int opA, int opB, int M, int N, int K, c128 alpha, const c128* A, 
   g.alpha = alpha; g.beta = beta;
   g.A = A; g.lda = lda; g.B = B; g.ldb = ldb; g.C = C; g.ldc = ldc;
   g.tag = "dc_gemm";
+  g.gauss3m = true;
   return gemm_batched<double>(g, s);
 }
 
@@ -367,6 +368,7 @@ static int newton_sign_batched(DcBatch& bt, Arena& ws, hipStream_t s, std::vecto
   RSRR_TRY(ws.aux_stream(&lw.aux, &lw.ev_main, &lw.ev_aux));
   GemmBatch<double> g;
   g.tag = "dc_gemm";
+  g.gauss3m = true;
   g.M = g.N = g.K = L;
   g.lda = g.ldb = g.ldc = L;
   g.sA = g.sB = g.sC = ll;
