@@ -19,7 +19,9 @@ namespace rsrr {
 
 constexpr int PNT = 1024;           // panel workgroup size (16 waves)
 constexpr int MAXNB = 64;
-constexpr int LU_SB = 4;            // panels per group of the triangular solves
+// panels per group of the triangular solves (and of the row order lu_factor
+// gives the L columns): groups of 256 columns
+__host__ __device__ constexpr int lu_group(int nb) { return nb >= 256 ? 1 : 256 / nb; }
 
 template <typename R> __device__ inline cplx<R> shfl_c(cplx<R> v, int src) {
   return mk<R>(__shfl(v.re, src), __shfl(v.im, src));
@@ -493,16 +495,16 @@ int lu_factor(const LUWork<R>& w, hipStream_t s) {
     }
   }
   if (aux_busy) RSRR_HIP(hipStreamWaitEvent(s, w.ev_aux, 0));
-  // Within every group of LU_SB panels, the interchanges of a panel are also
+  // Within every group of lu_group(nb) panels, the interchanges of a panel are also
   // applied to the L columns of the group's earlier panels, so that all L
   // columns of a group share one row order (that after its last panel) and
   // the solver can update the rows below a group with one product.  Rows of a
   // panel's own diagonal block are never touched, so L stays unit lower
   // triangular and dinv is unchanged.
-  const int np = w.npanel();
+  const int np = w.npanel(), SB = lu_group(nb);
   for (int q = 1; q < np; ++q) {
-    if (!w.full_swap && q % LU_SB == 0) continue;
-    const int k = q * nb, c0 = w.full_swap ? 0 : (q / LU_SB) * LU_SB * nb;
+    if (!w.full_swap && q % SB == 0) continue;
+    const int k = q * nb, c0 = w.full_swap ? 0 : (q / SB) * SB * nb;
     RSRR_TRY(launch_permute<R>(w.A + (long)c0 * w.lda, w.lda, w.sA, k - c0, w.ipiv, n, k, min(nb, n - k),
                                w.batch, s));
   }
@@ -512,7 +514,7 @@ int lu_factor(const LUWork<R>& w, hipStream_t s) {
 template <typename R>
 int lu_solve(const LUWork<R>& w, cplx<R>* B, long ldb, long sB, int nrhs, hipStream_t s, const int* active) {
   if (w.n <= 0 || w.batch <= 0 || nrhs <= 0) return ST_OK;
-  const int n = w.n, nb = w.nb, np = w.npanel();
+  const int n = w.n, nb = w.nb, np = w.npanel(), SB = lu_group(nb);
   const std::string t_solve = std::string(w.tag) + "_solve";
   const long sD = (long)np * 2 * nb * nb;
   // C[rows] = alpha A B + beta C on the batch (A from the factors or dinv)
@@ -529,12 +531,12 @@ int lu_solve(const LUWork<R>& w, cplx<R>* B, long ldb, long sB, int nrhs, hipStr
     g.active = active;
     return gemm_batched<R>(g, s);
   };
-  // forward, L: per group of LU_SB panels (the row order lu_factor gives its L
+  // forward, L: per group of lu_group(nb) panels (the row order lu_factor gives its L
   // columns): the group's interchanges on B, the triangular solves with the
   // diagonal-block inverses and updates inside the group, then the rows below
   // the group in one product with K = the group's width
-  for (int p0 = 0; p0 < np; p0 += LU_SB) {
-    const int p1 = min(np, p0 + LU_SB);
+  for (int p0 = 0; p0 < np; p0 += SB) {
+    const int p1 = min(np, p0 + SB);
     const int k0 = p0 * nb, k1 = min(n, p1 * nb);
     for (int p = p0; p < p1; ++p)
       RSRR_TRY(launch_permute<R>(B, ldb, sB, nrhs, w.ipiv, n, p * nb, min(nb, n - p * nb), w.batch, s, active));
@@ -549,8 +551,8 @@ int lu_solve(const LUWork<R>& w, cplx<R>* B, long ldb, long sB, int nrhs, hipStr
   }
   // backward, U: per group from the last, solves and updates inside the
   // group, then the rows above it in one product
-  for (int p0 = ((np - 1) / LU_SB) * LU_SB; p0 >= 0; p0 -= LU_SB) {
-    const int p1 = min(np, p0 + LU_SB);
+  for (int p0 = ((np - 1) / SB) * SB; p0 >= 0; p0 -= SB) {
+    const int p1 = min(np, p0 + SB);
     const int k0 = p0 * nb, k1 = min(n, p1 * nb);
     for (int p = p1 - 1; p >= p0; --p) {
       const int k = p * nb, nbe = min(nb, n - k);
@@ -600,7 +602,7 @@ int lu_inverse(const LUWork<R>& w, cplx<R>* X, cplx<R>* out, long ldo, long sO, 
   static_assert(sizeof(R) == 8, "complex128 only");
   if (w.n <= 0 || w.batch <= 0) return ST_OK;
   if (!w.full_swap) return set_error(ST_EINVAL, "lu_inverse needs factors computed with full_swap");
-  const int n = w.n, nb = w.nb, np = w.npanel();
+  const int n = w.n, nb = w.nb, np = w.npanel(), SB = lu_group(nb);
   const long nn = (long)n * n;
   const std::string t_solve = std::string(w.tag) + "_solve";
   const long sD = (long)np * 2 * nb * nb;
@@ -625,8 +627,8 @@ int lu_inverse(const LUWork<R>& w, cplx<R>* X, cplx<R>* out, long ldo, long sO, 
   };
   // forward, L Y = I: rows of panel p of Y vanish beyond column p*nb + nbe
   // (L^{-1} is lower triangular), so every product stops at that column
-  for (int p0 = 0; p0 < np; p0 += LU_SB) {
-    const int p1 = min(np, p0 + LU_SB);
+  for (int p0 = 0; p0 < np; p0 += SB) {
+    const int p1 = min(np, p0 + SB);
     const int k0 = p0 * nb, k1 = min(n, p1 * nb);
     for (int p = p0; p < p1; ++p) {
       const int k = p * nb, nbe = min(nb, n - k);
@@ -638,8 +640,8 @@ int lu_inverse(const LUWork<R>& w, cplx<R>* X, cplx<R>* out, long ldo, long sO, 
     if (k1 < n) RSRR_TRY(mm(n - k1, k1, k1 - k0, w.A + k1 + (long)k0 * w.lda, w.lda, w.sA, X + k0, X + k1, true));
   }
   // backward, U Z = Y (dense)
-  for (int p0 = ((np - 1) / LU_SB) * LU_SB; p0 >= 0; p0 -= LU_SB) {
-    const int p1 = min(np, p0 + LU_SB);
+  for (int p0 = ((np - 1) / SB) * SB; p0 >= 0; p0 -= SB) {
+    const int p1 = min(np, p0 + SB);
     const int k0 = p0 * nb, k1 = min(n, p1 * nb);
     for (int p = p1 - 1; p >= p0; --p) {
       const int k = p * nb, nbe = min(nb, n - k);
