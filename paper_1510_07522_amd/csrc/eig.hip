@@ -188,31 +188,41 @@ __global__ __launch_bounds__(256) void bj_rotate_kernel(const c128* part, int nk
         s_pp[tid] = p; s_qq[tid] = q; s_rc[tid] = c; s_rs[tid] = sn; s_ph[tid] = phc;
       }
       __syncthreads();
-      // columns: [g_p, g_q] <- [c g_p - s phc g_q, s g_p + c phc g_q]  (same for V)
-      for (int e = tid; e < (J2 / 2) * J2; e += 256) {
-        const int k = e / J2, r = e % J2;
-        if (s_rs[k] == 0.0) continue;
-        const int p = s_pp[k], q = s_qq[k];
-        const double c = s_rc[k], sn = s_rs[k];
-        const c128 ph = s_ph[k];
-        c128 x = G[r][p], y = G[r][q] * ph;
-        G[r][p] = mk<double>(c * x.re - sn * y.re, c * x.im - sn * y.im);
-        G[r][q] = mk<double>(sn * x.re + c * y.re, sn * x.im + c * y.im);
-        x = V[r][p]; y = V[r][q] * ph;
-        V[r][p] = mk<double>(c * x.re - sn * y.re, c * x.im - sn * y.im);
-        V[r][q] = mk<double>(sn * x.re + c * y.re, sn * x.im + c * y.im);
-      }
-      __syncthreads();
-      // rows: [g_p; g_q] <- J^H [g_p; g_q]
-      for (int e = tid; e < (J2 / 2) * J2; e += 256) {
-        const int k = e / J2, cc = e % J2;
-        if (s_rs[k] == 0.0) continue;
-        const int p = s_pp[k], q = s_qq[k];
-        const double c = s_rc[k], sn = s_rs[k];
-        const c128 phb = conj(s_ph[k]);
-        const c128 x = G[p][cc], y = G[q][cc] * phb;
-        G[p][cc] = mk<double>(c * x.re - sn * y.re, c * x.im - sn * y.im);
-        G[q][cc] = mk<double>(sn * x.re + c * y.re, sn * x.im + c * y.im);
+      // The step's pairs are disjoint and cover every index, so G <- J^H G J
+      // acts on each 2x2 block (rows of pair k, columns of pair l) on its own:
+      // with M = [[c, s], [-s phc, c phc]] per pair, block <- M_k^H block M_l;
+      // V <- V J acts on each row's 2-vector of pair l.  One phase, no thread
+      // reads what another writes.
+      for (int e = tid; e < (J2 / 2) * (J2 / 2) + J2 * (J2 / 2); e += 256) {
+        if (e < (J2 / 2) * (J2 / 2)) {
+          const int k = e % (J2 / 2), l = e / (J2 / 2);
+          if (s_rs[k] == 0.0 && s_rs[l] == 0.0) continue;
+          const int pk = s_pp[k], qk = s_qq[k], pl = s_pp[l], ql = s_qq[l];
+          // columns of the block: [x, y] <- [c x - s ph y, s x + c ph y] with pair l
+          const double cl = s_rc[l], sl = s_rs[l];
+          const c128 phl = s_ph[l];
+          c128 a0 = G[pk][pl], a1 = G[pk][ql] * phl, b0 = G[qk][pl], b1 = G[qk][ql] * phl;
+          c128 u0 = cl * a0 - sl * a1, u1 = sl * a0 + cl * a1;    // row pk
+          c128 w0 = cl * b0 - sl * b1, w1 = sl * b0 + cl * b1;    // row qk
+          // rows: [x; y] <- [c x - s conj(ph) y; s x + c conj(ph) y] with pair k
+          const double ck = s_rc[k], sk = s_rs[k];
+          const c128 phb = conj(s_ph[k]);
+          w0 = w0 * phb;
+          w1 = w1 * phb;
+          G[pk][pl] = ck * u0 - sk * w0;
+          G[pk][ql] = ck * u1 - sk * w1;
+          G[qk][pl] = sk * u0 + ck * w0;
+          G[qk][ql] = sk * u1 + ck * w1;
+        } else {
+          const int f = e - (J2 / 2) * (J2 / 2);
+          const int l = f / J2, r = f % J2;
+          if (s_rs[l] == 0.0) continue;
+          const int p = s_pp[l], q = s_qq[l];
+          const double c = s_rc[l], sn = s_rs[l];
+          const c128 x = V[r][p], y = V[r][q] * s_ph[l];
+          V[r][p] = c * x - sn * y;
+          V[r][q] = sn * x + c * y;
+        }
       }
       __syncthreads();
     }
