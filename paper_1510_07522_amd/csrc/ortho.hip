@@ -117,37 +117,58 @@ __global__ __launch_bounds__(PCT) void pchol_panel_kernel(c128* G, long ldg, int
   if (tid == 0 && !s_stop) *rank = j0 + jdone;
 }
 
-// Inverts the diagonal blocks (bs x bs, lower triangular, non-unit) of L, one
-// wave per block, in place in LDS by a row sweep:
-//   X[i][i] = 1/L[i][i],  X[i][j] = -(sum_{l=j}^{i-1} L[i][l] X[l][j]) / L[i][i].
-__global__ __launch_bounds__(64) void tri_inv_lower_blocks(const c128* L, long ldl, int k, int bs,
-                                                           c128* out) {
-  __shared__ c128 s[PBS][PBS + 1];
-  const int blk = blockIdx.x;
+// Inverses of the diagonal blocks (bs <= 64) of a lower-triangular L, one
+// 256-thread workgroup per block, right-looking: step i finishes row i of
+// X = L^{-1} (X[i][j] = (delta_ij - acc[i][j]) / L[i][i]) and every later row
+// r adds L[r][i] X[i][j] to its accumulators.  Thread t keeps row t / 4,
+// columns t % 4 + 4q, in registers; one barrier per step.
+__global__ __launch_bounds__(256) void tri_inv_lower_blocks(const c128* L, long ldl, int k, int bs,
+                                                            c128* out) {
+  __shared__ c128 s[PBS][PBS + 1];     // the block of L; row i becomes row i of X at step i
+  __shared__ c128 rd[PBS];
+  __shared__ c128 xrow[2][PBS];
+  const int blk = blockIdx.x, tid = threadIdx.x;
   const int b0 = blk * bs, be = min(bs, k - b0);
-  const int j = threadIdx.x;
-  for (int e = j; e < be * be; e += 64) {
+  for (int e = tid; e < be * be; e += 256) {
     const int r = e % be, c = e / be;
     s[r][c] = (r >= c) ? L[b0 + r + (long)(b0 + c) * ldl] : mk<double>(0, 0);
   }
   __syncthreads();
+  if (tid < be) rd[tid] = crecip(s[tid][tid]);
+  const int r = tid >> 2, j0 = tid & 3;
+  c128 acc[PBS / 4];
+#pragma unroll
+  for (int q = 0; q < PBS / 4; ++q) acc[q] = mk<double>(0, 0);
+  __syncthreads();
   for (int i = 0; i < be; ++i) {
-    const c128 dii = s[i][i];
-    c128 v = mk<double>(0, 0);
-    if (j < i) {
-      for (int l = j; l < i; ++l) v = v + s[i][l] * s[l][j];
-      v = cdiv(mk<double>(-v.re, -v.im), dii);
+    const int par = i & 1;
+    if (r == i) {
+      const c128 d = rd[i];
+#pragma unroll
+      for (int q = 0; q < PBS / 4; ++q) {
+        const int j = j0 + 4 * q;
+        if (j <= i) {
+          const c128 x = (mk<double>(j == i ? 1.0 : 0.0, 0) - acc[q]) * d;
+          xrow[par][j] = x;
+          s[i][j] = x;
+        }
+      }
     }
-    wave_sync();
-    if (j < i) s[i][j] = v;
-    if (j == i) s[i][i] = crecip(dii);
-    wave_sync();
+    __syncthreads();
+    if (r > i && r < be) {
+      const c128 lri = s[r][i];
+#pragma unroll
+      for (int q = 0; q < PBS / 4; ++q) {
+        const int j = j0 + 4 * q;
+        if (j <= i) acc[q] = acc[q] + lri * xrow[par][j];
+      }
+    }
   }
   __syncthreads();
   c128* o = out + (long)blk * bs * bs;
-  for (int e = j; e < bs * bs; e += 64) {
-    const int r = e % bs, c = e / bs;
-    o[e] = (r < be && c < be && r >= c) ? s[r][c] : mk<double>(0, 0);
+  for (int e = tid; e < bs * bs; e += 256) {
+    const int rr = e % bs, c = e / bs;
+    o[e] = (rr < be && c < be && rr >= c) ? s[rr][c] : mk<double>(0, 0);
   }
 }
 
@@ -312,7 +333,7 @@ static int trsm_right_lh(const c128* L, long ldl, int k, c128* X, long ldx, int 
   c128* tmp = nullptr;
   RSRR_TRY(ws.get<c128>("tr_inv", (size_t)nblk * PBS * PBS, &inv));
   RSRR_TRY(ws.get<c128>("tr_tmp", (size_t)rows * PBS, &tmp));
-  hipLaunchKernelGGL(tri_inv_lower_blocks, dim3(nblk), dim3(64), 0, s, L, ldl, k, PBS, inv);
+  hipLaunchKernelGGL(tri_inv_lower_blocks, dim3(nblk), dim3(256), 0, s, L, ldl, k, PBS, inv);
   RSRR_LAUNCH_CHECK();
   // right-looking over groups of TRSM_G column blocks: inside a group each
   // block is solved after the group's earlier blocks are subtracted, then the
@@ -358,7 +379,7 @@ static int chol_blocked(c128* G, long ldg, int m, Arena& ws, hipStream_t s, bool
     }
     const int rest = m - j0 - jb;
     if (rest <= 0) break;
-    hipLaunchKernelGGL(tri_inv_lower_blocks, dim3(1), dim3(64), 0, s, G + j0 + (long)j0 * ldg, ldg, jb, PBS, inv);
+    hipLaunchKernelGGL(tri_inv_lower_blocks, dim3(1), dim3(256), 0, s, G + j0 + (long)j0 * ldg, ldg, jb, PBS, inv);
     RSRR_LAUNCH_CHECK();
     c128* L21 = G + (j0 + jb) + (long)j0 * ldg;
     RSRR_TRY(gemm_z(OP_N, OP_C, rest, jb, jb, ONE, L21, ldg, inv, PBS, ZERO, tmp, rest, s));

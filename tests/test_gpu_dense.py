@@ -59,8 +59,12 @@ def test_gemm_matches_numpy(P, opA, opB, prec):
         assert err < tol, (b, err)
 
 
+# 24- and 32-column panels (those of the divide-and-conquer inverses), also
+# with a batch of 50
 @pytest.mark.parametrize("n,nrhs,batch,nb", [(1, 3, 2, 64), (37, 5, 3, 16), (200, 20, 4, 64),
-                                             (333, 7, 2, 64), (1100, 9, 2, 64), (2100, 4, 1, 64)])
+                                             (333, 7, 2, 64), (1100, 9, 2, 64), (2100, 4, 1, 64),
+                                             (300, 6, 5, 32), (777, 3, 3, 24), (2600, 5, 2, 32),
+                                             (600, 3, 50, 32)])
 @pytest.mark.parametrize("prec", ["c128", "c64"])
 def test_batched_lu_solve(P, n, nrhs, batch, nb, prec):
     import torch
