@@ -111,7 +111,8 @@ size_t solve_workspace_bound(const rsrr_problem* p, const rsrr_params* prm) {
   }
   // moments: a chunk of T_S(zeta) and inverses sized to at most 8 GB
   const double ch = chunk_count(prm->NS, (size_t)(kk * z * 2), prm->chunk_gib).second;
-  const double red = 2 * ch * kk * z + (2 * K + 1) * kk * z + 2 * ch * kS * nb * z + ch * (kS + 64) * z;
+  const double red = 2 * ch * kk * z + (2 * K + 1) * kk * z + 2 * ch * kS * nb * z + ch * (kS + 64) * z +
+                     (double)moments_wind_parts((long)kk, (int)ch, (int)std::min(J, 4.0)) * z;
   // Hankel matrices, SVD (basis, Jacobi copies), extraction, eigen-solve
   const double hank = 18 * M * M * z + (kS + n) * M * z;
   const double eig = 24 * M * M * z;
@@ -210,6 +211,11 @@ int solve_impl(rsrr_problem* p, const rsrr_contour* c, const rsrr_params* prm, c
   RSRR_TRY(ws.get<c128>("rd_cw", (size_t)ch * 2 * K, &cw));
   RSRR_TRY(ws.get<c128>("rd_dinv", LUWork<double>::dinv_elems(kS, prm->nb, ch), &dinv));
   RSRR_TRY(ws.get<c128>("rd_part", (size_t)ch * nchunk, &part));
+  // moments and winding traces in one pass over the inverses when the sizes
+  // allow it (2K <= 8, J <= 4, the batch's wave sums in LDS)
+  const bool fused = 2 * K <= 8 && J <= 4 && (size_t)4 * ch * J * sizeof(c128) <= 60 * 1024;
+  c128* dpart = nullptr;
+  if (fused) RSRR_TRY(ws.get<c128>("rd_dpart", (size_t)moments_wind_parts(kk, ch, J), &dpart));
   RSRR_TRY(ws.get<int>("rd_ipiv", (size_t)ch * kS, &ipiv));
   int* iperm = nullptr;
   RSRR_TRY(ws.get<int>("rd_perm", (size_t)ch * kS, &iperm));
@@ -251,21 +257,34 @@ int solve_impl(rsrr_problem* p, const rsrr_contour* c, const rsrr_params* prm, c
     // the inverses replace the factors in TS once the solves are done; X is
     // the work space of the solves
     RSRR_TRY(lu_inverse<double>(w, X, TS, kS, kk, iperm, s));
-    // moments: [A_0 .. A_{2K-1}] += [X_m] cw   (kk x cnt) (cnt x 2K), X_m in TS
-    RSRR_TRY(zgemm(OP_N, OP_N, (int)kk, 2 * K, cnt, ONE, TS, kk, cw, cnt, m0 == 0 ? ZERO : ONE, Amom, kk, s));
-    // winding: tr(X_m T_S'(zeta_m)) = sum_e X_m[e] (T_S'(zeta_m)^T)[e], T_S' into X
-    RSRR_TRY(zgemm(OP_N, OP_N, (int)kk, cnt, J, ONE, BT, kk, gdev + (size_t)ch * J, J, ZERO, X, kk, s));
-    RSRR_TRY(dot_partials(TS, X, kk, cnt, nchunk, part, s));
-    hpart.resize((size_t)cnt * nchunk);
+    // moments: [A_0 .. A_{2K-1}] += [X_m] cw   (kk x cnt) (cnt x 2K), X_m in TS;
+    // winding: tr(X_m T_S'(zeta_m)) = sum_k g_k'(zeta_m) sum_e X_m[e] (B_k^T)[e]
     std::vector<int> hinfo(cnt);
-    RSRR_HIP(hipMemcpyAsync(hpart.data(), part, hpart.size() * sizeof(c128), hipMemcpyDeviceToHost, s));
+    if (fused) {
+      RSRR_TRY(moments_wind(TS, kk, cnt, cw, 2 * K, BT, J, Amom, m0 != 0, dpart, part, s));
+      hpart.resize((size_t)cnt * J);
+      RSRR_HIP(hipMemcpyAsync(hpart.data(), part, hpart.size() * sizeof(c128), hipMemcpyDeviceToHost, s));
+    } else {
+      RSRR_TRY(zgemm(OP_N, OP_N, (int)kk, 2 * K, cnt, ONE, TS, kk, cw, cnt, m0 == 0 ? ZERO : ONE, Amom, kk, s));
+      // T_S'(zeta_m) into X, then sum_e X_m[e] (T_S'(zeta_m)^T)[e] in chunks
+      RSRR_TRY(zgemm(OP_N, OP_N, (int)kk, cnt, J, ONE, BT, kk, gdev + (size_t)ch * J, J, ZERO, X, kk, s));
+      RSRR_TRY(dot_partials(TS, X, kk, cnt, nchunk, part, s));
+      hpart.resize((size_t)cnt * nchunk);
+      RSRR_HIP(hipMemcpyAsync(hpart.data(), part, hpart.size() * sizeof(c128), hipMemcpyDeviceToHost, s));
+    }
     RSRR_HIP(hipMemcpyAsync(hinfo.data(), linfo, cnt * sizeof(int), hipMemcpyDeviceToHost, s));
     RSRR_HIP(hipStreamSynchronize(s));
     for (int q = 0; q < cnt; ++q)
       if (hinfo[q]) return set_error(ST_ESINGULAR, "reduced matrix singular at node %d", m0 + q);
     for (int q = 0; q < cnt; ++q) {
       cd tr(0, 0);
-      for (int t = 0; t < nchunk; ++t) tr += cd(hpart[(size_t)q * nchunk + t].re, hpart[(size_t)q * nchunk + t].im);
+      if (fused) {
+        for (int k = 0; k < J; ++k)
+          tr += cd(hdg[(size_t)q * J + k].re, hdg[(size_t)q * J + k].im) *
+                cd(hpart[(size_t)q * J + k].re, hpart[(size_t)q * J + k].im);
+      } else {
+        for (int t = 0; t < nchunk; ++t) tr += cd(hpart[(size_t)q * nchunk + t].re, hpart[(size_t)q * nchunk + t].im);
+      }
       wind += dzeta[m0 + q] / cd(0, 2.0 * M_PI) * tr;
     }
   }

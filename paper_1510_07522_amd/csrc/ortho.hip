@@ -159,6 +159,7 @@ __global__ __launch_bounds__(256) void tri_inv_lower_blocks(const c128* L, long 
       const c128 lri = s[r][i];
 #pragma unroll
       for (int q = 0; q < PBS / 4; ++q) {
+        if (4 * q > i) break;                   // columns right of i (uniform)
         const int j = j0 + 4 * q;
         if (j <= i) acc[q] = acc[q] + lri * xrow[par][j];
       }
@@ -173,40 +174,62 @@ __global__ __launch_bounds__(256) void tri_inv_lower_blocks(const c128* L, long 
 }
 
 // Cholesky of the jb x jb diagonal block at (j0, j0) of G (Hermitian, the
-// lower triangle is used), right-looking in LDS; L11 overwrites the lower
-// triangle.  *bad is set to 1 if a pivot is not positive.
+// lower triangle is used), right-looking; L11 overwrites the lower triangle.
+// *bad is set to 1 if a pivot is not positive.  Thread t keeps row t / 4,
+// columns t % 4 + 4q, in registers; per column k the owners post column k
+// (not yet scaled) to LDS, and after one barrier every thread scales by
+// 1 / sqrt(a_kk) itself and updates its entries.
 __global__ __launch_bounds__(256) void chol_diag_kernel(c128* G, long ldg, int j0, int jb, int* bad) {
-  __shared__ c128 a[PBS][PBS + 1];
-  const int tid = threadIdx.x;
+  __shared__ c128 lo[PBS][PBS + 1];   // staging of the block, then L
+  __shared__ c128 col[2][PBS];
+  const int tid = threadIdx.x, r = tid >> 2, c0 = tid & 3;
   c128* B = G + j0 + (long)j0 * ldg;
   for (int e = tid; e < jb * jb; e += 256) {
-    const int r = e % jb, c = e / jb;
-    a[r][c] = (r >= c) ? B[r + (long)c * ldg] : mk<double>(0, 0);
+    const int i = e % jb, c = e / jb;
+    lo[i][c] = (i >= c) ? B[i + (long)c * ldg] : mk<double>(0, 0);
+  }
+  __syncthreads();
+  c128 a[PBS / 4];
+#pragma unroll
+  for (int q = 0; q < PBS / 4; ++q) {
+    const int j = c0 + 4 * q;
+    a[q] = (r < jb && j < jb && r >= j) ? lo[r][j] : mk<double>(0, 0);
   }
   __syncthreads();
   int done = jb;
   for (int k = 0; k < jb; ++k) {
-    const double d = a[k][k].re;
-    if (!(d > 0.0)) { done = k; break; }      // same value in every thread: uniform
-    const double lkk = sqrt(d), rl = 1.0 / lkk;
-    __syncthreads();
-    for (int i = k + 1 + tid; i < jb; i += 256) a[i][k] = rl * a[i][k];
-    if (tid == 0) a[k][k] = mk<double>(lkk, 0);
-    __syncthreads();
-    const int t = jb - k - 1;
-    for (int e = tid; e < t * t; e += 256) {
-      const int i = k + 1 + e % t, j = k + 1 + e / t;
-      if (i >= j) a[i][j] = a[i][j] - a[i][k] * conj(a[j][k]);
+    const int par = k & 1;
+    const bool owner = c0 == (k & 3) && r >= k && r < jb;
+    if (owner) {
+      c128 v = a[0];
+#pragma unroll
+      for (int q = 1; q < PBS / 4; ++q)
+        if (q == (k >> 2)) v = a[q];
+      col[par][r] = v;
     }
     __syncthreads();
+    const double d = col[par][k].re;
+    if (!(d > 0.0)) { done = k; break; }      // same value in every thread: uniform
+    const double lkk = sqrt(d), rl = 1.0 / lkk;
+    if (owner) lo[r][k] = (r == k) ? mk<double>(lkk, 0) : rl * col[par][r];
+    if (r > k && r < jb) {
+      const c128 lr = rl * col[par][r];
+#pragma unroll
+      for (int q = 0; q < PBS / 4; ++q) {
+        if (4 * q + 3 <= k) continue;           // columns left of k (uniform)
+        const int j = c0 + 4 * q;
+        if (j > k && j <= r) a[q] = a[q] - lr * conj(rl * col[par][j]);
+      }
+    }
   }
   if (done < jb) {
     if (tid == 0) *bad = 1;
     return;
   }
+  __syncthreads();
   for (int e = tid; e < jb * jb; e += 256) {
-    const int r = e % jb, c = e / jb;
-    if (r >= c) B[r + (long)c * ldg] = a[r][c];
+    const int i = e % jb, c = e / jb;
+    if (i >= c) B[i + (long)c * ldg] = lo[i][c];
   }
 }
 

@@ -1,6 +1,7 @@
 // Small kernels of the reduced problem (Alg. 1) and of the final eigenpairs.
 #include "driver.h"
 #include "reduced.h"
+#include "timers.h"
 
 namespace rsrr {
 
@@ -76,6 +77,137 @@ int dot_partials(const c128* X, const c128* Y, long len, int batch, int nchunk, 
   const long chunk = cdivl(len, nchunk);
   hipLaunchKernelGGL(dot_partial_kernel, dim3(nchunk, batch), dim3(256), 0, s, X, Y, len, chunk,
                      nchunk, partial);
+  RSRR_LAUNCH_CHECK();
+  return ST_OK;
+}
+
+// Moments and winding partials in one pass over the inverses.  Each thread
+// takes MWE elements (consecutive threads on consecutive elements) and runs
+// over the nodes in order: the P moment sums of its elements stay in
+// registers; the J products X_m[e] BT_k[e] are summed over the wave by a
+// fixed butterfly and the four wave sums of node m are added in wave order at
+// the end.  Block partials go to Dpart[blk][m][k].
+constexpr int MWE = 4, MWB = 256 * MWE;
+
+template <int P, int JJ>
+__global__ __launch_bounds__(256) void moments_wind_kernel(const c128* X, long kk, int cnt, const c128* cw,
+                                                           const c128* BT, c128* A, int accumulate,
+                                                           c128* Dpart, int cmax) {
+  extern __shared__ c128 s_w[];          // [4][cmax][JJ] wave sums
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const long e0 = (long)blockIdx.x * MWB + tid;
+  c128 acc[MWE][P], bt[MWE][JJ];
+#pragma unroll
+  for (int i = 0; i < MWE; ++i) {
+    const long e = e0 + 256L * i;
+#pragma unroll
+    for (int p = 0; p < P; ++p) acc[i][p] = mk<double>(0, 0);
+#pragma unroll
+    for (int k = 0; k < JJ; ++k) bt[i][k] = e < kk ? BT[e + (long)k * kk] : mk<double>(0, 0);
+  }
+  for (int m = 0; m < cnt; ++m) {
+    c128 x[MWE];
+#pragma unroll
+    for (int i = 0; i < MWE; ++i) {
+      const long e = e0 + 256L * i;
+      x[i] = e < kk ? X[(long)m * kk + e] : mk<double>(0, 0);
+    }
+    c128 w[P];
+#pragma unroll
+    for (int p = 0; p < P; ++p) w[p] = cw[m + (long)p * cnt];
+    c128 d[JJ];
+#pragma unroll
+    for (int k = 0; k < JJ; ++k) d[k] = mk<double>(0, 0);
+#pragma unroll
+    for (int i = 0; i < MWE; ++i) {
+#pragma unroll
+      for (int p = 0; p < P; ++p) acc[i][p] = acc[i][p] + x[i] * w[p];
+#pragma unroll
+      for (int k = 0; k < JJ; ++k) d[k] = d[k] + x[i] * bt[i][k];
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1)
+#pragma unroll
+      for (int k = 0; k < JJ; ++k) {
+        d[k].re += __shfl_xor(d[k].re, off);
+        d[k].im += __shfl_xor(d[k].im, off);
+      }
+    if (lane == 0)
+#pragma unroll
+      for (int k = 0; k < JJ; ++k) s_w[((long)wave * cmax + m) * JJ + k] = d[k];
+  }
+#pragma unroll
+  for (int i = 0; i < MWE; ++i) {
+    const long e = e0 + 256L * i;
+    if (e < kk)
+#pragma unroll
+      for (int p = 0; p < P; ++p) {
+        const long o = e + (long)p * kk;
+        A[o] = accumulate ? A[o] + acc[i][p] : acc[i][p];
+      }
+  }
+  __syncthreads();
+  c128* out = Dpart + (long)blockIdx.x * cnt * JJ;
+  for (int o = tid; o < cnt * JJ; o += 256) {
+    const int m = o / JJ, k = o % JJ;
+    c128 v = s_w[((long)0 * cmax + m) * JJ + k];
+#pragma unroll
+    for (int q = 1; q < 4; ++q) v = v + s_w[((long)q * cmax + m) * JJ + k];
+    out[o] = v;
+  }
+}
+
+// D[o] = sum over blocks b (in order, per thread then a fixed tree) of Dpart[b][o]
+__global__ __launch_bounds__(256) void sum_parts_kernel(const c128* Dpart, int nblk, int ncol, c128* D) {
+  __shared__ double re_[256], im_[256];
+  const int o = blockIdx.x;
+  double ar = 0, ai = 0;
+  for (int b = threadIdx.x; b < nblk; b += 256) {
+    const c128 v = Dpart[(long)b * ncol + o];
+    ar += v.re;
+    ai += v.im;
+  }
+  re_[threadIdx.x] = ar;
+  im_[threadIdx.x] = ai;
+  __syncthreads();
+  for (int h = 128; h > 0; h >>= 1) {
+    if (threadIdx.x < h) { re_[threadIdx.x] += re_[threadIdx.x + h]; im_[threadIdx.x] += im_[threadIdx.x + h]; }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) D[o] = mk<double>(re_[0], im_[0]);
+}
+
+long moments_wind_parts(long kk, int cnt, int J) { return cdivl(kk, MWB) * (long)cnt * J; }
+
+template <int P, int JJ>
+static int launch_mw(const c128* X, long kk, int cnt, const c128* cw, const c128* BT, c128* A, bool accumulate,
+                     c128* Dpart, hipStream_t s) {
+  const long nblk = cdivl(kk, MWB);
+  const size_t lds = (size_t)4 * cnt * JJ * sizeof(c128);
+  if (lds > 60 * 1024) return set_error(ST_EINVAL, "moments: %d nodes per batch exceed the LDS of one pass", cnt);
+  KernelTimer kt("reduced_moments", s, 8.0 * (double)kk * cnt * (P + JJ), 16.0 * (double)kk * (cnt + JJ + P),
+                 "moments_wind_kernel");
+  hipLaunchKernelGGL((moments_wind_kernel<P, JJ>), dim3((unsigned)nblk), dim3(256), lds, s, X, kk, cnt, cw, BT, A,
+                     accumulate ? 1 : 0, Dpart, cnt);
+  RSRR_LAUNCH_CHECK();
+  return ST_OK;
+}
+
+int moments_wind(const c128* X, long kk, int cnt, const c128* cw, int P, const c128* BT, int J, c128* A,
+                 bool accumulate, c128* Dpart, c128* D, hipStream_t s) {
+  if (kk <= 0 || cnt <= 0) return ST_OK;
+  int st = ST_OK;
+  // instantiations: P in {2, 4, 6, 8}, J in 1..4
+#define RSRR_MW(PP, JV) \
+  if (P == PP && J == JV) st = launch_mw<PP, JV>(X, kk, cnt, cw, BT, A, accumulate, Dpart, s); else
+#define RSRR_MW_J(PP) RSRR_MW(PP, 1) RSRR_MW(PP, 2) RSRR_MW(PP, 3) RSRR_MW(PP, 4)
+  RSRR_MW_J(2) RSRR_MW_J(4) RSRR_MW_J(6) RSRR_MW_J(8)
+  return set_error(ST_EINVAL, "moments: P=%d, J=%d outside the one-pass kernel", P, J);
+#undef RSRR_MW_J
+#undef RSRR_MW
+  if (st < 0) return st;
+  const long nblk = cdivl(kk, MWB);
+  hipLaunchKernelGGL(sum_parts_kernel, dim3((unsigned)(cnt * J)), dim3(256), 0, s, Dpart, (int)nblk, cnt * J, D);
   RSRR_LAUNCH_CHECK();
   return ST_OK;
 }
