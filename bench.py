@@ -288,6 +288,8 @@ def main():
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of this many MiB 5 times (reference "
                          "for scaling the FETCH_SIZE / WRITE_SIZE counters) and exit")
+    ap.add_argument("--nb", type=int, default=None,
+                    help="LU panel width of the sampling and reduced-problem factorisations (default 64)")
     ap.add_argument("--chunk-gib", type=float, default=None,
                     help="device memory per batch of reduced-problem inverses (library default if unset)")
     ap.add_argument("--requests", type=int, default=24, help="serving workload (c4): requests")
@@ -338,6 +340,8 @@ def main():
     prm = P.default_params(N=N, L=L, precision=a.precision, scheme=a.scheme)
     if a.chunk_gib is not None:
         prm.chunk_gib = a.chunk_gib
+    if a.nb is not None:
+        prm.nb = a.nb
 
     for i in range(a.warmup):
         t0 = time.perf_counter()
@@ -415,7 +419,7 @@ def main():
         "data": "synthetic (seeded)",
         "config": {"workload": a.workload, "description": w["desc"], "n": prob.n, "N": N, "L": L,
                    "NS": prm.NS, "K": prm.K, "precision": a.precision, "scheme": a.scheme,
-                   "contour": a.contour, "parallelism": "single GPU"},
+                   "contour": a.contour, "nb": int(prm.nb), "parallelism": "single GPU"},
         "eigenpairs_per_s": eig_s,
         "n_eig": n_eig[-1],
         "latency_s": {"p50": float(np.percentile(lat_s, 50)), "p99": float(np.percentile(lat_s, 99))},
