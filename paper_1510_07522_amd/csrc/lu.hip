@@ -42,16 +42,14 @@ __global__ __launch_bounds__(PNT) void lu_panel_kernel(cplx<R>* A, long lda, lon
   __shared__ cplx<R> s_cand[2][16][W];
   __shared__ cplx<R> s_crow[2][W];
   __shared__ cplx<R> s_L[W][W];
-  __shared__ cplx<R> s_U[W][MAXNB];
+  __shared__ cplx<R> s_U[W][MAXNB];       // U rows of the micro-panel, one column per thread
+  // rows k .. k+nbe-1 of the panel as far as they are final (U rows and the
+  // micro-panels' L rows), then the diagonal block for its inverses
   __shared__ cplx<R> s_D[MAXNB][MAXNB + 1];
   __shared__ int s_piv[W];
   __shared__ int t_row[2 * W], t_src[2 * W];
   __shared__ int s_cnt;
   __shared__ cplx<R> s_mv[2 * W][MAXNB];
-  // columns per load batch of the rank-W update: ROWS * UB complex values
-  // in flight per thread (16 VGPRs, two batches in flight)
-  constexpr int UB0 = 16 * 4 / (ROWS * (int)sizeof(cplx<R>)) > 0 ? 16 * 4 / (ROWS * (int)sizeof(cplx<R>)) : 1;
-  constexpr int UB = UB0 < 128 / W ? (UB0 < 16 ? UB0 : 16) : 128 / W;
 
   const int b = blockIdx.x;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -60,14 +58,40 @@ __global__ __launch_bounds__(PNT) void lu_panel_kernel(cplx<R>* A, long lda, lon
   cplx<R> a[ROWS][W];
   int parity = 0;
 
+  // Left-looking (Crout) order inside the panel: a micro-panel receives the
+  // updates of the panel's earlier columns when it is loaded, and the U rows
+  // of each micro-panel are formed for the later columns of the panel right
+  // after it is factored, so the later columns are read and written once
+  // instead of after every micro-panel.
   for (int c = k; c < k + nbe; c += W) {
     const int w = min(W, k + nbe - c);
+    const int done = c - k;
 #pragma unroll
     for (int i = 0; i < ROWS; ++i) {
       const int r = c + tid + PNT * i;
 #pragma unroll
       for (int j = 0; j < W; ++j)
         a[i][j] = (r < n && j < w) ? Ab[r + (long)(c + j) * lda] : mk<R>(0, 0);
+    }
+    if (done > 0) {
+      // a -= L[rows, k..c) U[k..c, c..c+w), the U rows from s_D
+      // two iterations in flight for one or two rows per thread
+      constexpr int UA = ROWS >= 4 ? 1 : 2;
+#pragma unroll UA
+      for (int l = 0; l < done; ++l) {
+        cplx<R> lv[ROWS];
+#pragma unroll
+        for (int i = 0; i < ROWS; ++i) {
+          const int r = c + tid + PNT * i;
+          lv[i] = r < n ? Ab[r + (long)(k + l) * lda] : mk<R>(0, 0);
+        }
+#pragma unroll
+        for (int j = 0; j < W; ++j) {
+          const cplx<R> u = (j < w) ? s_D[l][done + j] : mk<R>(0, 0);
+#pragma unroll
+          for (int i = 0; i < ROWS; ++i) a[i][j] = a[i][j] - lv[i] * u;
+        }
+      }
     }
 #pragma unroll
     for (int jj = 0; jj < W; ++jj) {
@@ -201,72 +225,44 @@ __global__ __launch_bounds__(PNT) void lu_panel_kernel(cplx<R>* A, long lda, lon
         if (cc < c || cc >= c + w) Ab[t_row[q] + (long)cc * lda] = s_mv[q][cc - k];
       }
     }
+    // U rows of this micro-panel for the later columns of the panel: the
+    // earlier columns' terms, then the unit-lower solve with the micro-panel's
+    // diagonal block; one column per thread
     const int rc0 = c + w, ncols = k + nbe - rc0;
     if (ncols > 0) {
       if (tid < w) {
 #pragma unroll
         for (int j = 0; j < W; ++j) s_L[tid][j] = a[0][j];
       }
+      __syncthreads();                   // the interchanges above are written
+      // the micro-panel's rows are final in columns k..c-1 (L) from here on
+      for (int e = tid; e < W * done; e += PNT) {
+        const int jj = e % W, l = e / W;
+        if (jj < w) s_D[done + jj][l] = Ab[c + jj + (long)(k + l) * lda];
+      }
       __syncthreads();
-      // U rows of the micro-panel: unit-lower solve in LDS, one column per thread
       if (tid < ncols) {
-        const int cc = rc0 + tid;
+        const int cc = rc0 + tid, cl = cc - k;
+        cplx<R> v[W];
 #pragma unroll
-        for (int j = 0; j < W; ++j)
-          s_U[j][tid] = (j < w) ? Ab[c + j + (long)cc * lda] : mk<R>(0, 0);
+        for (int j = 0; j < W; ++j) v[j] = (j < w) ? Ab[c + j + (long)cc * lda] : mk<R>(0, 0);
+        for (int l = 0; l < done; ++l) {
+          const cplx<R> u = s_D[l][cl];
+#pragma unroll
+          for (int j = 0; j < W; ++j)
+            if (j < w) v[j] = v[j] - s_D[done + j][l] * u;
+        }
+#pragma unroll
+        for (int j = 0; j < W; ++j) s_U[j][tid] = v[j];
         for (int j = 1; j < w; ++j) {
-          cplx<R> v = s_U[j][tid];
-          for (int l = 0; l < j; ++l) v = v - s_L[j][l] * s_U[l][tid];
-          s_U[j][tid] = v;
-          Ab[c + j + (long)cc * lda] = v;
+          cplx<R> x = s_U[j][tid];
+          for (int l = 0; l < j; ++l) x = x - s_L[j][l] * s_U[l][tid];
+          s_U[j][tid] = x;
         }
-      }
-      __syncthreads();
-      // rank-w update of the remaining panel columns: UB columns of all ROWS
-      // rows per load batch, the next batch loaded while this one is updated
-      cplx<R> nxt[ROWS][UB];
-#pragma unroll
-      for (int i = 0; i < ROWS; ++i) {
-        const int r = c + tid + PNT * i;
-#pragma unroll
-        for (int u = 0; u < UB; ++u)
-          nxt[i][u] = (r >= rc0 && r < n && u < ncols) ? Ab[r + (long)(rc0 + u) * lda] : mk<R>(0, 0);
-      }
-      for (int t0 = 0; t0 < ncols; t0 += UB) {
-        cplx<R> acc[ROWS][UB];
-#pragma unroll
-        for (int i = 0; i < ROWS; ++i)
-#pragma unroll
-          for (int u = 0; u < UB; ++u) acc[i][u] = nxt[i][u];
-        if (t0 + UB < ncols) {
-#pragma unroll
-          for (int i = 0; i < ROWS; ++i) {
-            const int r = c + tid + PNT * i;
-#pragma unroll
-            for (int u = 0; u < UB; ++u)
-              if (r >= rc0 && r < n && t0 + UB + u < ncols) nxt[i][u] = Ab[r + (long)(rc0 + t0 + UB + u) * lda];
-          }
-        }
-#pragma unroll
-        for (int u = 0; u < UB; ++u) {
-          if (t0 + u < ncols) {
-            cplx<R> uc[W];
-#pragma unroll
-            for (int j = 0; j < W; ++j) uc[j] = s_U[j][t0 + u];
-#pragma unroll
-            for (int i = 0; i < ROWS; ++i) {
-#pragma unroll
-              for (int j = 0; j < W; ++j)
-                if (j < w) acc[i][u] = acc[i][u] - a[i][j] * uc[j];
-            }
-          }
-        }
-#pragma unroll
-        for (int i = 0; i < ROWS; ++i) {
-          const int r = c + tid + PNT * i;
-#pragma unroll
-          for (int u = 0; u < UB; ++u)
-            if (r >= rc0 && r < n && t0 + u < ncols) Ab[r + (long)(rc0 + t0 + u) * lda] = acc[i][u];
+        for (int j = 0; j < w; ++j) {
+          const cplx<R> x = s_U[j][tid];
+          s_D[done + j][cl] = x;
+          Ab[c + j + (long)cc * lda] = x;
         }
       }
     }
