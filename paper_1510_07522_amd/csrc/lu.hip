@@ -74,22 +74,31 @@ __global__ __launch_bounds__(PNT) void lu_panel_kernel(cplx<R>* A, long lda, lon
         a[i][j] = (r < n && j < w) ? Ab[r + (long)(c + j) * lda] : mk<R>(0, 0);
     }
     if (done > 0) {
-      // a -= L[rows, k..c) U[k..c, c..c+w), the U rows from s_D
-      // two iterations in flight for one or two rows per thread
-      constexpr int UA = ROWS >= 4 ? 1 : 2;
-#pragma unroll UA
-      for (int l = 0; l < done; ++l) {
-        cplx<R> lv[ROWS];
+      // a -= L[rows, k..c) U[k..c, c..c+w), the U rows from s_D; the L
+      // entries of CH columns are loaded together (one memory round trip per
+      // CH columns; 8 complex128 or 16 complex64 values per thread)
+      constexpr int CHV = sizeof(R) == 8 ? 8 : 16;
+      constexpr int CH = CHV / ROWS > 8 ? 8 : (CHV / ROWS < 1 ? 1 : CHV / ROWS);
+      for (int l0 = 0; l0 < done; l0 += CH) {
+        cplx<R> lv[CH][ROWS];
 #pragma unroll
-        for (int i = 0; i < ROWS; ++i) {
-          const int r = c + tid + PNT * i;
-          lv[i] = r < n ? Ab[r + (long)(k + l) * lda] : mk<R>(0, 0);
-        }
+        for (int t = 0; t < CH; ++t)
 #pragma unroll
-        for (int j = 0; j < W; ++j) {
-          const cplx<R> u = (j < w) ? s_D[l][done + j] : mk<R>(0, 0);
+          for (int i = 0; i < ROWS; ++i) {
+            const int r = c + tid + PNT * i, l = l0 + t;
+            lv[t][i] = (r < n && l < done) ? Ab[r + (long)(k + l) * lda] : mk<R>(0, 0);
+          }
 #pragma unroll
-          for (int i = 0; i < ROWS; ++i) a[i][j] = a[i][j] - lv[i] * u;
+        for (int t = 0; t < CH; ++t) {
+          const int l = l0 + t;
+          if (l < done) {
+#pragma unroll
+            for (int j = 0; j < W; ++j) {
+              const cplx<R> u = (j < w) ? s_D[l][done + j] : mk<R>(0, 0);
+#pragma unroll
+              for (int i = 0; i < ROWS; ++i) a[i][j] = a[i][j] - lv[t][i] * u;
+            }
+          }
         }
       }
     }
