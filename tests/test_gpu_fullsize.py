@@ -1,0 +1,105 @@
+"""The delay workload at the size the benchmark times (n = 2048, N = 48,
+L = 48, N_S = 512, K = 2, complex64 factors with FP64 refinement), checked
+where the oracle can follow at that size: the sampling blocks of a few nodes
+against LAPACK solves of the same T(z_j) and U (Alg. 2 Step 2), and the
+returned eigenpairs through properties that hold at any size (the count
+against the winding number of the reduced problem, every eigenvalue strictly
+inside the contour, residuals recomputed on the host from the coefficient
+matrices for a sample of pairs).  The oracle's full solve at this size (512
+reduced LU solves of order 2048 on the host) is out of reach for a test."""
+import numpy as np
+import pytest
+
+import nep_inputs as ni
+from oracle import rsrr_ref as R
+from tests._util import match_sets
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def P():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a ROCm device"
+    import paper_1510_07522_amd as P
+    P.load()
+    return P
+
+
+@pytest.fixture(scope="module")
+def c1():
+    return ni.config_c1()
+
+
+def ct(P, c):
+    return P.contour(c.center, c.a, c.b, kind=c.kind, n_h=c.nh, n_v=c.nv)
+
+
+def test_c1_sampling_blocks_match_lapack(P, c1):
+    p, c, N, L, U = c1
+    h = P.Problem(p)
+    try:
+        S, info, st = h.sample(ct(P, c), P.default_params(N=N, L=L, precision="c64_ir"), P.to_device(U))
+        S = P.from_device(S)
+    finally:
+        h.close()
+    assert S.shape == (p.n, N * L)
+    z, _ = R.contour_quadrature(c, N)
+    for j in (0, 17, 41):
+        T = R.T_matrix(p, z[j])
+        Y = S[:, j * L:(j + 1) * L]
+        # refinement target: normwise backward error at the FP64 level
+        eta = np.linalg.norm(U - T @ Y) / (np.linalg.norm(T) * np.linalg.norm(Y) + np.linalg.norm(U))
+        ref = np.linalg.solve(T, U)
+        err = np.linalg.norm(Y - ref) / np.linalg.norm(ref)
+        print(f"node {j}: backward error {eta:.2e}, forward error against LAPACK {err:.2e}")
+        assert eta <= 2e-14, (j, eta)
+        # T(z_j) is well conditioned here (condition numbers up to a few 1e3)
+        assert err <= 1e-10, (j, err)
+
+
+def test_c1_full_solve_properties(P, c1):
+    p, c, N, L, U = c1
+    h = P.Problem(p)
+    try:
+        out = h.solve(ct(P, c), P.default_params(N=N, L=L, precision="c64_ir"), P.to_device(U))
+    finally:
+        h.close()
+    info, lam, V, res = out["info"], out["lam"], out["V"], out["res"]
+    print("k_S", info["k_S"], "m", info["m"], "winding", info["wind_re"], "n_wind", info["n_wind"],
+          "n_eig", info["n_eig"], "max residual", float(np.max(res)))
+    # N L = 2304 > n: the sampled subspace is the whole space
+    assert info["k_S"] == p.n
+    assert info["n_eig"] == len(lam) == V.shape[1] > 2900
+    # the winding count rounds an N_S-node quadrature of the argument
+    # principle, in which eigenvalues within about a node spacing of the
+    # contour count fractionally (here a conjugate pair at |l| = 3.0005 adds
+    # about 1.08); the returned pairs agree with it up to one
+    assert abs(info["n_wind"] - info["n_eig"]) <= 1
+    assert np.all(R.inside(c, lam))
+    assert np.all(res <= 1e-10)
+    assert len(np.unique(np.round(lam, 8))) == len(lam)
+    # residuals recomputed on the host from the coefficient matrices
+    idx = np.sort(np.random.default_rng(5).choice(len(lam), 12, replace=False))
+    rel, _ = R.residuals(p, lam[idx], V[:, idx])
+    print("host residuals", rel)
+    assert np.all(rel <= 1e-10)
+    assert np.all(np.abs(rel - res[idx]) <= 1e-12)
+
+
+def test_c1_eigenvalues_do_not_depend_on_the_contour(P, c1):
+    # the eigenvalues inside |z| < 3 from the benchmark's circle and from a
+    # circle of radius 3.05 (different sampling and moment nodes, a larger
+    # subspace of the reduced problem) are the same set
+    p, c, N, L, U = c1
+    h = P.Problem(p)
+    try:
+        prm = P.default_params(N=N, L=L, precision="c64_ir")
+        a = h.solve(ct(P, c), prm, P.to_device(U))["lam"]
+        b = h.solve(P.contour(0.0, 3.05, 3.05), prm, P.to_device(U))["lam"]
+    finally:
+        h.close()
+    b_in = b[np.abs(b) < 3.0]
+    print("inside |z| < 3:", len(a), "from r = 3,", len(b_in), "from r = 3.05")
+    assert len(a) == len(b_in)
+    assert match_sets(a, b_in) <= 1e-9 * 3.0
