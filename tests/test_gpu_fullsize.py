@@ -103,3 +103,40 @@ def test_c1_eigenvalues_do_not_depend_on_the_contour(P, c1):
     print("inside |z| < 3:", len(a), "from r = 3,", len(b_in), "from r = 3.05")
     assert len(a) == len(b_in)
     assert match_sets(a, b_in) <= 1e-9 * 3.0
+
+
+def test_c3_bem_full_size_properties(P):
+    # the BEM workload at its full size (n = 8192, N = 40, L = 64, complex64 +
+    # refinement): two sampled blocks by their backward error against the
+    # oracle's T(z_j), the count against the winding number, and all returned
+    # pairs' residuals recomputed on the host.  The eigenvalues approach the
+    # Dirichlet eigenvalues of the unit ball in the wavenumber z as the
+    # discretisation refines: one near pi and a near-triple below 4.4934 (with
+    # small negative imaginary parts); that is context, the residuals certify
+    p, c, N, L, U = ni.config_c3()
+    h = P.Problem(p)
+    try:
+        prm = P.default_params(N=N, L=L, precision="c64_ir")
+        S, info_s, st = h.sample(ct(P, c), prm, P.to_device(U))
+        S = P.from_device(S)
+        out = h.solve(ct(P, c), prm, P.to_device(U))
+    finally:
+        h.close()
+    z, _ = R.contour_quadrature(c, N)
+    for j in (0, 23):
+        T = R.T_matrix(p, z[j])
+        Y = S[:, j * L:(j + 1) * L]
+        eta = np.linalg.norm(U - T @ Y) / (np.linalg.norm(T) * np.linalg.norm(Y) + np.linalg.norm(U))
+        print(f"node {j}: backward error {eta:.2e}")
+        assert eta <= 2e-14, (j, eta)
+        del T
+    info, lam, V, res = out["info"], out["lam"], out["V"], out["res"]
+    print("k_S", info["k_S"], "m", info["m"], "winding", info["wind_re"], "n_eig", info["n_eig"], "lam", lam)
+    assert info["n_eig"] == info["n_wind"] == 4
+    assert np.all(R.inside(c, lam))
+    rel, _ = R.residuals(p, lam, V)
+    print("host residuals", rel)
+    assert np.all(rel <= 1e-10) and np.all(res <= 1e-10)
+    lam = np.sort_complex(lam)
+    assert 2.9 < lam[0].real < 3.2 and np.all((lam[1:].real > 4.2) & (lam[1:].real < 4.5))
+    assert np.all((lam.imag < 0) & (lam.imag > -0.05))
