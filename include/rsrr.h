@@ -115,7 +115,7 @@ typedef struct {
   double hankel_tol;  /* Hankel truncation sigma_j > hankel_tol*sigma_1, default 1e-13 */
   int precision;      /* RSRR_PREC_C128 or RSRR_PREC_C64_IR (default) */
   int ir_max_iter;    /* refinement sweeps before the complex128 fallback, default 5 */
-  double ir_tol;      /* refinement stop: normwise backward error, default 1e-14 */
+  double ir_tol;      /* refinement acceptance: normwise backward error, default 1e-14 */
   int cheb_degree;    /* BEM only: Chebyshev degree d (eq. eq-T-interp), default 40 */
   int nb;             /* LU panel width (1..64), default 64 */
   uint64_t seed;      /* seed of the probing matrix when U is not supplied */
@@ -168,8 +168,10 @@ void rsrr_destroy(rsrr_problem* p);
  * (eq. eq-hatS).  U: device, n x L complex, leading dimension ldu >= n.
  * S: device, n x (N*L) complex, leading dimension lds >= n, block j = columns
  * [j*L, (j+1)*L).  With precision RSRR_PREC_C64_IR the factorisations are
- * complex64 and fp64 iterative refinement brings every block to a normwise
- * backward error <= ir_tol (else that node is redone in complex128).
+ * complex64 and fp64 iterative refinement runs until a block's normwise
+ * backward error reaches the fp64 floor (4 u) or a sweep no longer halves it,
+ * at most ir_max_iter sweeps; a block left above ir_tol is redone in
+ * complex128.
  * info (may be NULL) receives ir_iters / ir_fallback / t_sample. */
 int rsrr_sample(rsrr_problem* p, const rsrr_contour* c, const rsrr_params* prm,
                 const rsrr_complex* U, int ldu, rsrr_complex* S, int lds, rsrr_info* info);

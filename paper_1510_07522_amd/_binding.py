@@ -112,6 +112,10 @@ def load(path: str = LIB_PATH):
     if not os.path.exists(path):
         raise RuntimeError(f"{path} is missing: build it with `python -m paper_1510_07522_amd.build`"
                            " (there is no CPU fallback)")
+    # torch first: it brings its own HIP runtime (same soname), and the
+    # library must bind to that one, or the process holds two runtimes and
+    # torch's device memory and streams are foreign to the library's
+    _torch()
     lib = C.CDLL(path)
     for name, (res, args) in SIGNATURES.items():
         f = getattr(lib, name)

@@ -389,7 +389,7 @@ int rsrr_orthonormalize(int rows, int cols, const rsrr_complex* S, int lds, doub
     return set_error(ST_EINVAL, "rsrr_orthonormalize: bad arguments");
   Arena ws;
   int st = ortho_impl(rows, cols, (const c128*)S, lds, delta, (c128*)Q, ldq, k_S, ws,
-                      (hipStream_t)stream);
+                      (hipStream_t)stream, 3);
   (void)hipStreamSynchronize((hipStream_t)stream);
   return st;
 }

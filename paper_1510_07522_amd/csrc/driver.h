@@ -63,8 +63,11 @@ int sample_impl(rsrr_problem* p, const rsrr_contour* c, const rsrr_params* prm,
 // Moment matrix M_hat of the SSRR moment scheme from S_hat (eq. eq-hatMS).
 int moment_impl(rsrr_problem* p, const rsrr_contour* c, const rsrr_params* prm, const c128* S, long lds,
                 c128* M, long ldm);
+// Orthonormal basis Q (rows x k_S) of the columns of S above delta * sigma_1:
+// pivoted Cholesky of the Gram matrix and Cholesky-QR, then up to levels - 1
+// deflation levels for the directions one Gram matrix cannot resolve.
 int ortho_impl(int rows, int cols, const c128* S, long lds, double delta, c128* Q, long ldq,
-               int* k_S, Arena& ws, hipStream_t s);
+               int* k_S, Arena& ws, hipStream_t s, int levels = 2);
 // One Cholesky-QR pass, X <- X chol(X^H X)^{-H} in place (ok = false if the
 // Cholesky factorisation breaks down).
 int cholqr(c128* X, long ldx, int rows, int k, Arena& ws, hipStream_t s, bool* ok);

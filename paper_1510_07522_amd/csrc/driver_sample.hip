@@ -3,9 +3,12 @@
 // complex128 form: assemble T(z_j) for all j, one batched LU, one batched solve.
 // complex64 + refinement form: the same in complex64, then fp64 iterative
 // refinement  R_j = U - T(z_j) Y_j (fp64),  D_j = T~_j^{-1} R_j (complex64),
-// Y_j += D_j,  until eta_j = ||R_j||_F / (||T(z_j)||_F ||Y_j||_F + ||U||_F) <= ir_tol.
-// Nodes that do not reach ir_tol in ir_max_iter sweeps are factored again in
-// complex128.
+// Y_j += D_j, with eta_j = ||R_j||_F / (||T(z_j)||_F ||Y_j||_F + ||U||_F).  A node
+// is refined until eta_j reaches the fp64 floor (4 u) or stops falling (a sweep
+// that does not halve it), at most ir_max_iter sweeps: the sampled blocks carry
+// the accuracy a complex128 factorisation would give them, which clustered
+// eigenvalues of the reduced problem need.  Nodes left above ir_tol are
+// factored again in complex128.
 #include <algorithm>
 #include <cmath>
 
@@ -232,7 +235,8 @@ int sample_impl(rsrr_problem* p, const rsrr_contour* c, const rsrr_params* prm, 
     RSRR_TRY(block_fro2(U, ldu, 0, n, L, 1, nrm + 3 * N, s));
     RSRR_HIP(hipMemcpyAsync(u2.data(), nrm + 3 * N, sizeof(double), hipMemcpyDeviceToHost, s));
     std::vector<int> active(N, 1);
-    std::vector<double> r2(N), y2(N);
+    std::vector<double> r2(N), y2(N), eta_v(N, INFINITY);
+    const double eta_floor = 4 * 1.1102230246251565e-16;
     // after the first sweep only the nodes still above ir_tol are refined:
     // their columns are gathered for the fp64 residual, and the solves skip
     // the others
@@ -285,12 +289,15 @@ int sample_impl(rsrr_problem* p, const rsrr_contour* c, const rsrr_params* prm, 
       nact = 0;
       double emax = 0;
       for (int j = 0; j < N; ++j) {
+        if (!was[j]) continue;
         const double eta = sqrt(r2[j]) / (sqrt(fro2[j]) * sqrt(y2[j]) + sqrt(u2[0]));
-        active[j] = was[j] && ((eta > prm->ir_tol) || !(eta == eta));
+        const bool falling = !(eta > 0.5 * eta_v[j]);
+        active[j] = !(eta == eta) || (eta > eta_floor && falling);
+        eta_v[j] = eta;
         nact += active[j];
         emax = std::max(emax, eta);
       }
-      vlog("refinement sweep %d: %d of %d nodes above ir_tol, max eta %.2e", it, nact, N, emax);
+      vlog("refinement sweep %d: %d of %d nodes still refined, max eta %.2e", it, nact, N, emax);
       if (nact == 0 || it >= prm->ir_max_iter) break;
       ir_iters = it + 1;
       const std::vector<int> tested(idx);
@@ -323,9 +330,9 @@ int sample_impl(rsrr_problem* p, const rsrr_contour* c, const rsrr_params* prm, 
       }
       RSRR_TRY(add_correction(S, lds, (long)L * lds, Y32, n, (long)L * n, n, L, N, active_dev, s));
     }
-    // complex128 fallback for the nodes that did not converge
+    // complex128 fallback for the nodes left above ir_tol
     std::vector<int> bad;
-    for (int j = 0; j < N; ++j) if (active[j]) bad.push_back(j);
+    for (int j = 0; j < N; ++j) if (!(eta_v[j] <= prm->ir_tol)) bad.push_back(j);
     if (!bad.empty()) {
       fallback = (int)bad.size();
       warn |= RSRR_WARN_IR_FALLBACK;

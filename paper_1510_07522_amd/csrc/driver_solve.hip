@@ -171,7 +171,8 @@ int solve_impl(rsrr_problem* p, const rsrr_contour* c, const rsrr_params* prm, c
   c128* Q = nullptr;
   RSRR_TRY(ws.get<c128>("sv_Q", (size_t)n * kmax, &Q));
   int kS = 0;
-  RSRR_TRY(ortho_impl(n, (int)ncols, Sbase, n, prm->delta, Q, n, &kS, ws, s));
+  // three levels: the sampling matrix's singular values reach delta sigma_1
+  RSRR_TRY(ortho_impl(n, (int)ncols, Sbase, n, prm->delta, Q, n, &kS, ws, s, 3));
   info.k_S = kS;
   info.t_basis = now_s() - t0;
   vlog("sample %.3fs (ir %d, fallback %d), basis k_S=%d %.3fs", info.t_sample, info.ir_iters,

@@ -495,7 +495,7 @@ int jacobi_svd(c128* X, long ldx, int rows, int cols, c128* U, long ldu, c128* W
 
 // SVD of the M x M Hankel matrix H by one-sided Jacobi preconditioned with a
 // column-pivoted orthonormal basis Q1 of range(H) (H P = Q1 R; pivoted
-// Cholesky of H^H H with a second deflation level, the same basis routine as
+// Cholesky of H^H H with deflation levels (three at most), the same basis routine as
 // Alg. 2 Step 3):  Jacobi runs on X = H^H Q1 = P R^H, whose columns are far
 // closer to orthogonal than those of H, so far fewer sweeps are needed.
 // X J = Wh diag(sigma)  =>  H = (Q1 J) diag(sigma) Wh^H.
@@ -517,7 +517,7 @@ int hankel_svd(const c128* H, int M, double basis_tol, double trunc, c128* Vh, l
   c128 *Q1 = nullptr, *Xh = nullptr, *J = nullptr;
   RSRR_TRY(ws.get<c128>("hs_Q1", (size_t)M * M, &Q1));
   int r = 0;
-  RSRR_TRY(ortho_impl(M, M, H, M, basis_tol, Q1, M, &r, ws, s));
+  RSRR_TRY(ortho_impl(M, M, H, M, basis_tol, Q1, M, &r, ws, s, 3));
   if (r == 0) return ST_OK;
   RSRR_TRY(ws.get<c128>("hs_X", (size_t)M * r, &Xh));
   RSRR_TRY(ws.get<c128>("hs_J", (size_t)r * r, &J));

@@ -459,7 +459,7 @@ int basis_of_columns(const c128* X, long ldx, int rows, int cols, int rank, c128
 }
 
 int ortho_impl(int rows, int cols, const c128* S, long lds, double delta, c128* Q, long ldq,
-               int* k_S, Arena& ws, hipStream_t s) {
+               int* k_S, Arena& ws, hipStream_t s, int levels) {
   const int m = cols, kmax = std::min(rows, cols);
   c128* G = nullptr;
   int* perm = nullptr;
@@ -482,39 +482,52 @@ int ortho_impl(int rows, int cols, const c128* S, long lds, double delta, c128* 
   RSRR_TRY(cholqr_pass(Q, ldq, rows, k1, ws, s, &ok));
   if (!ok) return set_error(ST_ENOTCONV, "orthonormalize: second Cholesky-QR pass broke down");
   int kS = k1;
-  // ---- level 2: directions of S outside span(S1) above delta * sigma_1
-  if (k1 < kmax) {
+  // ---- levels 2, 3, ...: directions of S outside the span found so far,
+  // above delta * sigma_1.  Each level's Gram matrix resolves singular values
+  // down to its own rounding floor (rows * u times its largest column norm
+  // squared).  A level whose floor lies above delta sigma_1 leaves directions
+  // for the next one, which starts from that floor; a level whose threshold
+  // was delta sigma_1 itself is the last.
+  if (kS < kmax && levels > 1) {
     c128 *Rm = nullptr, *Cc = nullptr;
     RSRR_TRY(ws.get<c128>("or_R", (size_t)rows * m, &Rm));
-    RSRR_TRY(ws.get<c128>("or_C", (size_t)k1 * m, &Cc));
+    RSRR_TRY(ws.get<c128>("or_C", (size_t)kmax * m, &Cc));
+    // R = S - Q Q^H S (two passes); later levels remove only the columns
+    // they add, since R is already orthogonal to the earlier ones
     RSRR_TRY((convert<double, double>(S, lds, 0, Rm, rows, 0, rows, m, 1, s)));
-    for (int pass = 0; pass < 2; ++pass) {
-      RSRR_TRY(gemm_z(OP_C, OP_N, k1, m, rows, ONE, Q, ldq, Rm, rows, ZERO, Cc, k1, s));
-      RSRR_TRY(gemm_z(OP_N, OP_N, rows, m, k1, MONE, Q, ldq, Cc, k1, ONE, Rm, rows, s));
-    }
-    RSRR_TRY(gemm_z(OP_C, OP_N, m, m, rows, ONE, Rm, rows, Rm, rows, ZERO, G, m, s));
-    // stop at (delta sigma_1)^2, but not below the rounding floor of the Gram
-    // matrix of R: pivots under rows * u * max_i ||R_i||^2 are noise
-    double dmax = 0;
-    RSRR_TRY(max_real_diag(G, m, m, ws, s, &dmax));
-    const double tau2 = std::max(delta * delta * lam1, rows * 1.1102230246251565e-16 * dmax);
-    int k2 = 0;
-    RSRR_TRY(pchol(G, m, m, kmax - k1, tau2, true, perm, ws, s, &k2));
-    if (k2 > 0) {
-      c128* Q2 = Q + (long)k1 * ldq;
+    int k0 = 0, kn = kS;
+    for (int level = 2; level <= levels && kS < kmax; ++level) {
+      for (int pass = 0; pass < 2; ++pass) {
+        RSRR_TRY(gemm_z(OP_C, OP_N, kn, m, rows, ONE, Q + (long)k0 * ldq, ldq, Rm, rows, ZERO, Cc, kn, s));
+        RSRR_TRY(gemm_z(OP_N, OP_N, rows, m, kn, MONE, Q + (long)k0 * ldq, ldq, Cc, kn, ONE, Rm, rows, s));
+      }
+      RSRR_TRY(gemm_z(OP_C, OP_N, m, m, rows, ONE, Rm, rows, Rm, rows, ZERO, G, m, s));
+      // stop at (delta sigma_1)^2, but not below the rounding floor of the Gram
+      // matrix of R: pivots under rows * u * max_i ||R_i||^2 are noise
+      double dmax = 0;
+      RSRR_TRY(max_real_diag(G, m, m, ws, s, &dmax));
+      const double floor2 = rows * 1.1102230246251565e-16 * dmax;
+      const double tau2 = std::max(delta * delta * lam1, floor2);
+      int k2 = 0;
+      RSRR_TRY(pchol(G, m, m, kmax - kS, tau2, true, perm, ws, s, &k2));
+      if (k2 == 0) break;
+      c128* Q2 = Q + (long)kS * ldq;
       hipLaunchKernelGGL(gather_cols_kernel, dim3((unsigned)cdivl((long)rows * k2, 256)), dim3(256),
                          0, s, Rm, rows, perm, rows, k2, Q2, ldq);
       RSRR_LAUNCH_CHECK();
       RSRR_TRY(trsm_right_lh(G, m, k2, Q2, ldq, rows, ws, s));
       for (int pass = 0; pass < 2; ++pass) {
-        c128* C2 = Cc;
-        RSRR_TRY(gemm_z(OP_C, OP_N, k1, k2, rows, ONE, Q, ldq, Q2, ldq, ZERO, C2, k1, s));
-        RSRR_TRY(gemm_z(OP_N, OP_N, rows, k2, k1, MONE, Q, ldq, C2, k1, ONE, Q2, ldq, s));
+        RSRR_TRY(gemm_z(OP_C, OP_N, kS, k2, rows, ONE, Q, ldq, Q2, ldq, ZERO, Cc, kS, s));
+        RSRR_TRY(gemm_z(OP_N, OP_N, rows, k2, kS, MONE, Q, ldq, Cc, kS, ONE, Q2, ldq, s));
         bool ok2 = true;
         RSRR_TRY(cholqr_pass(Q2, ldq, rows, k2, ws, s, &ok2));
         if (!ok2) { k2 = 0; break; }
       }
+      if (k2 == 0) break;
+      k0 = kS;
+      kn = k2;
       kS += k2;
+      if (floor2 <= delta * delta * lam1) break;
     }
   }
   RSRR_HIP(hipStreamSynchronize(s));

@@ -55,3 +55,18 @@ def test_default_params_and_error_paths_without_gpu():
     st = lib.rsrr_create(ctypes.byref(h), 0, 1, None, None, None, None)
     assert st == -1
     assert b"null" in lib.rsrr_last_error() or b"n=" in lib.rsrr_last_error()
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="librsrr.so not built")
+def test_load_shares_torchs_hip_runtime():
+    # loading the library before torch is imported must not leave a second HIP
+    # runtime in the process (torch's memory and streams would be foreign to it)
+    import subprocess
+    import sys
+    code = ("import paper_1510_07522_amd as P; P.load(); import torch; "
+            "m = open('/proc/self/maps').read(); "
+            "print(len({l.split()[-1] for l in m.splitlines() if 'libamdhip64' in l}))")
+    out = subprocess.run([sys.executable, "-c", code], cwd=ROOT, capture_output=True, text=True,
+                         timeout=300)
+    assert out.returncode == 0, out.stderr
+    assert out.stdout.strip().splitlines()[-1] == "1"
