@@ -115,7 +115,7 @@ size_t solve_workspace_bound(const rsrr_problem* p, const rsrr_params* prm) {
                      (double)moments_wind_parts((long)kk, (int)ch, (int)std::min(J, 4.0)) * z;
   // Hankel matrices, SVD (basis, Jacobi copies), extraction, eigen-solve
   const double hank = 18 * M * M * z + (kS + n) * M * z;
-  const double eig = 24 * M * M * z;
+  const double eig = 26 * M * M * z;
   // residual filter
   const double resid = (J + 4) * n * M * z;
   return (size_t)(1.1 * (samp + basis + proj + red + hank + eig + resid)) + ((size_t)64 << 20);
@@ -346,7 +346,9 @@ int solve_impl(rsrr_problem* p, const rsrr_contour* c, const rsrr_params* prm, c
   RSRR_TRY(zgemm(OP_C, OP_N, m, m, M, ONE, Uh, M, T1, M, ZERO, Ar, m, s));
   std::vector<cd> lamp;
   vlog("extraction m=%d gap=%d", m, info.n_gap);
-  RSRR_TRY(eig_general(Ar, m, m, &lamp, Gp, m, ws, s));
+  // spectral splits whose dropped coupling could bring residuals within a
+  // tenth of the acceptance level are followed by a first-order correction
+  RSRR_TRY(eig_general(Ar, m, m, &lamp, Gp, m, ws, s, 0.1 * prm->tol_res));
   vlog("eig m=%d %.3fs", m, now_s() - t0);
   RSRR_TRY(zgemm(OP_N, OP_N, M, m, m, ONE, W0s, M, Gp, m, ZERO, T2, M, s));
   // H_r = [A_0 ... A_{K-1}] is the first block row of H: rows 0..kS-1 of the

@@ -22,9 +22,11 @@ int hankel_svd(const c128* H, int M, double basis_tol, double trunc, c128* Vh, l
                std::vector<double>* sigma, int* r_out, Arena& ws, hipStream_t s);
 
 // Eigenvalues lam and eigenvectors V (columns, not normalised) of the general
-// m x m matrix A (destroyed: it ends in Schur form).
+// m x m matrix A (destroyed: it ends in Schur form).  When spectral splits
+// drop a block larger than refine_above relative to its diagonal block, the
+// eigenpairs are corrected to first order in the dropped coupling.
 int eig_general(c128* A, long lda, int m, std::vector<cd>* lam, c128* V, long ldv, Arena& ws,
-                hipStream_t s);
+                hipStream_t s, double refine_above = 0.0);
 
 int set_identity(c128* X, long ldx, int m, hipStream_t s);
 
@@ -32,12 +34,18 @@ int set_identity(c128* X, long ldx, int m, hipStream_t s);
 // + single-shift QR); larger ones by spectral divide and conquer first.
 constexpr int DC_LEAF = 128;
 int eig_dc(c128* A, long lda, int m, std::vector<cd>* lam, c128* V, long ldv, Arena& ws,
-           hipStream_t s);
+           hipStream_t s, double refine_above = 0.0);
 // Schur forms of `count` independent small matrices (len <= 512), in place, with
 // their unitary factors Z_b (status_b = QR iterations, or -1 on failure).
 int leaf_schur_batched(c128* const* H_dev, c128* const* Z_dev, const int* len_dev, int count,
                        int* status_dev, hipStream_t s);
 // Eigenvectors X (columns) of the m x m upper-triangular T.
 int tri_eigvecs(const c128* T, long ldt, int m, c128* X, long ldx, hipStream_t s);
+// First-order correction of the eigenvectors X of T (from tri_eigvecs) for
+// T' = T + E, given P = T' X: X is updated in place, mu (device, m) receives
+// the eigenvalue corrections (0 where a correction was not applied).  D: m x m
+// work space.
+int tri_eigvecs_correct(const c128* T, long ldt, int m, const c128* P, long ldp, c128* X, long ldx,
+                        c128* D, c128* mu, hipStream_t s);
 
 }  // namespace rsrr

@@ -892,11 +892,111 @@ int tri_eigvecs(const c128* T, long ldt, int m, c128* X, long ldx, hipStream_t s
   return ST_OK;
 }
 
+// First-order correction of eigenvector i of the upper-triangular T when the
+// Schur form it came from is inexact: T' = T + E (E the coupling a spectral
+// split dropped), x = X[:, i] with T x = t x (x_i = 1), P[:, i] = T' x and
+// R = P - t x.  Solves (T - t I) d = mu x - R with d_i = 0 by one
+// back-substitution from the last row up (row i gives mu); then x + d and
+// t + mu satisfy T' (x + d) = (t + mu)(x + d) up to second-order terms.  The
+// correction is applied only if ||d|| <= ||x|| / 10 (else mu_out[i] = 0 and
+// x is kept), and only to eigenvectors with ||R|| > tau ||x|| (the others are
+// already backward stable).  D: m x m work space (column i holds d).  One
+// workgroup per eigenvector; r_acc[j] = sum_{k > j} T[j][k] d_k.
+__device__ inline void block_sum2(double& a, double& b, double (*s_red)[4]) {
+  for (int off = 32; off >= 1; off >>= 1) {
+    a += __shfl_xor(a, off);
+    b += __shfl_xor(b, off);
+  }
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) { s_red[0][threadIdx.x >> 6] = a; s_red[1][threadIdx.x >> 6] = b; }
+  __syncthreads();
+  a = s_red[0][0] + s_red[0][1] + s_red[0][2] + s_red[0][3];
+  b = s_red[1][0] + s_red[1][1] + s_red[1][2] + s_red[1][3];
+}
+
+__global__ __launch_bounds__(256) void evec_correct_kernel(const c128* T, long ldt, const c128* P, long ldp,
+                                                           int m, double small, double tau, c128* X, long ldx,
+                                                           c128* D, c128* mu_out) {
+  extern __shared__ c128 r_acc[];
+  __shared__ double s_red[2][4];
+  const int i = blockIdx.x, tid = threadIdx.x;
+  const c128 lam = T[i + (long)i * ldt];
+  c128* x = X + (long)i * ldx;
+  const c128* p = P + (long)i * ldp;
+  c128* d = D + (long)i * m;
+  {
+    double nr = 0, nx = 0;
+    for (int j = tid; j < m; j += 256) {
+      const c128 xj = (j <= i) ? x[j] : mk<double>(0, 0);
+      nr += abs2(p[j] - lam * xj);
+      nx += abs2(xj);
+    }
+    block_sum2(nr, nx, s_red);
+    if (nr <= tau * tau * nx) {                 // uniform
+      if (tid == 0) mu_out[i] = mk<double>(0, 0);
+      return;
+    }
+  }
+  for (int j = tid; j < m; j += 256) r_acc[j] = mk<double>(0, 0);
+  __syncthreads();
+  c128 mu = mk<double>(0, 0);
+  for (int l = m - 1; l >= 0; --l) {
+    // every thread forms d_l (the same value) from r_acc[l], final since the last barrier
+    const c128 xl = (l <= i) ? x[l] : mk<double>(0, 0);
+    const c128 rl = p[l] - lam * xl;
+    c128 dl = mk<double>(0, 0);
+    if (l == i) {
+      mu = cdiv(rl + r_acc[l], xl);
+    } else {
+      c128 dd = T[l + (long)l * ldt] - lam;
+      if (abs2(dd) < small * small) dd = mk<double>(small, 0);
+      c128 rhs = mk<double>(0, 0) - (rl + r_acc[l]);
+      if (l < i) rhs = rhs + mu * xl;
+      dl = cdiv(rhs, dd);
+    }
+    if (tid == 0) d[l] = dl;
+    for (int j = tid; j < l; j += 256) r_acc[j] = r_acc[j] + T[j + (long)l * ldt] * dl;
+    __syncthreads();
+  }
+  // apply if small against x
+  double nd = 0, nx = 0;
+  for (int j = tid; j < m; j += 256) {
+    nd += abs2(d[j]);
+    if (j <= i) nx += abs2(x[j]);
+  }
+  block_sum2(nd, nx, s_red);
+  const bool ok = (nd <= 0.01 * nx) && (nd == nd);
+  if (ok)
+    for (int j = tid; j < m; j += 256) x[j] = x[j] + d[j];
+  if (tid == 0) mu_out[i] = ok ? mu : mk<double>(0, 0);
+}
+
+int tri_eigvecs_correct(const c128* T, long ldt, int m, const c128* P, long ldp, c128* X, long ldx,
+                        c128* D, c128* mu, hipStream_t s) {
+  if (m <= 0) return ST_OK;
+  std::vector<c128> diag(m);
+  RSRR_HIP(hipMemcpy2DAsync(diag.data(), sizeof(c128), T, (ldt + 1) * sizeof(c128), sizeof(c128), m,
+                            hipMemcpyDeviceToHost, s));
+  RSRR_HIP(hipStreamSynchronize(s));
+  double tnorm = 0;
+  for (int j = 0; j < m; ++j) tnorm = std::max(tnorm, sqrt(abs2(diag[j])));
+  const double small = std::max(tnorm, 1e-300) * 2.220446049250313e-16;
+  const size_t shm = (size_t)m * sizeof(c128);
+  if (shm > 150 * 1024) return set_error(ST_EINVAL, "eigenvector correction: m=%d too large", m);
+  // residuals within 64 u ||T|| are at the rounding level of the Schur form
+  const double tau = 64 * 1.1102230246251565e-16 * std::max(tnorm, 1e-300);
+  KernelTimer kt("evec_correct", s, 8.0 * (double)m * m * m / 2, 16.0 * (double)m * m * m / 2);
+  hipLaunchKernelGGL(evec_correct_kernel, dim3(m), dim3(256), shm, s, T, ldt, P, ldp, m, small, tau, X, ldx,
+                     D, mu);
+  RSRR_LAUNCH_CHECK();
+  return ST_OK;
+}
+
 int eig_general(c128* A, long lda, int m, std::vector<cd>* lam, c128* V, long ldv, Arena& ws,
-                hipStream_t s) {
+                hipStream_t s, double refine_above) {
   lam->clear();
   if (m <= 0) return ST_OK;
-  if (m > DC_LEAF) return eig_dc(A, lda, m, lam, V, ldv, ws, s);
+  if (m > DC_LEAF) return eig_dc(A, lda, m, lam, V, ldv, ws, s, refine_above);
   c128 *Vh = nullptr, *Z = nullptr, *w = nullptr, *X = nullptr;
   int* skip = nullptr;
   RSRR_TRY(ws.get<c128>("eg_Vh", (size_t)m * m, &Vh));

@@ -670,7 +670,7 @@ static int apply_block(c128* T, long ldt, int m, c128* Z, long ldz, int off, int
 }
 
 int eig_dc(c128* A, long lda, int m, std::vector<cd>* lam, c128* V, long ldv, Arena& ws,
-           hipStream_t s) {
+           hipStream_t s, double refine_above) {
   const long mm = (long)m * m;
   DcWork w;
   c128* Z = nullptr;
@@ -686,10 +686,16 @@ int eig_dc(c128* A, long lda, int m, std::vector<cd>* lam, c128* V, long ldv, Ar
   RSRR_TRY(ws.get<int>("dc_ipiv", m, &w.ipiv));
   RSRR_TRY(ws.get<int>("dc_info", 1, &w.info));
   RSRR_TRY(ws.get<double>("dc_part", 2 * (size_t)(m / FCOLS + 2), &w.part));
+  c128 *A0 = nullptr, *Dc = nullptr, *mu = nullptr;
+  RSRR_TRY(ws.get<c128>("dc_A0", mm, &A0));
+  RSRR_TRY(ws.get<c128>("dc_D", mm, &Dc));
+  RSRR_TRY(ws.get<c128>("dc_mu", m, &mu));
+  RSRR_TRY((convert<double, double>(A, lda, 0, A0, m, 0, m, m, 1, s)));
   RSRR_TRY(set_identity(Z, m, m, s));
   struct Blk { int off, len; };
   std::vector<Blk> level{{0, m}}, leaves;
   const double t_dc = now_s();
+  double dropped = 0;         // largest ||B21|| / ||B|| over the splits
   // block b of T split into k + (len - k) with the bases in w.Q
   auto finish_split = [&](const Blk& b, int k, std::vector<Blk>& next) -> int {
     c128* B = A + b.off + (long)b.off * lda;
@@ -713,8 +719,9 @@ int eig_dc(c128* A, long lda, int m, std::vector<cd>* lam, c128* V, long ldv, Ar
       hipLaunchKernelGGL(zero_block_kernel, dim3(nblk((long)rows * k)), dim3(256), 0, s, Lo, lda, rows, k);
       RSRR_LAUNCH_CHECK();
     }
-    vlog("dc block off=%d len=%d -> %d + %d, ||B21||/||B|| = %.2e", b.off, b.len, k, b.len - k,
-         sqrt(f_low / std::max(f_all, 1e-300)));
+    const double ratio = sqrt(f_low / std::max(f_all, 1e-300));
+    dropped = std::max(dropped, ratio);
+    vlog("dc block off=%d len=%d -> %d + %d, ||B21||/||B|| = %.2e", b.off, b.len, k, b.len - k, ratio);
     next.push_back({b.off, k});
     next.push_back({b.off + k, b.len - k});
     return ST_OK;
@@ -845,11 +852,26 @@ int eig_dc(c128* A, long lda, int m, std::vector<cd>* lam, c128* V, long ldv, Ar
   c128* X = nullptr;
   RSRR_TRY(ws.get<c128>("dc_Xv", mm, &X));
   RSRR_TRY(tri_eigvecs(A, lda, m, X, m, s));
+  // the splits leave T' = Z^H A0 Z = T + E with E at the level of the sign
+  // function's error (well above rounding for eigenvalues near a split
+  // line); the residual of an eigenpair of T is about ||E|| ||x||, so when a
+  // dropped block exceeds refine_above the eigenvectors and eigenvalues are
+  // corrected to first order in E
+  std::vector<c128> d, dmu(m, mk<double>(0, 0));
+  const bool refine = dropped > refine_above;
+  vlog("dc: largest dropped block %.2e, eigenpair correction %s", dropped, refine ? "on" : "off");
+  if (refine) {
+    RSRR_TRY(zg(OP_N, OP_N, m, m, m, ONE, A0, m, Z, m, ZERO, w.tmp, m, s));
+    RSRR_TRY(zg(OP_C, OP_N, m, m, m, ONE, Z, m, w.tmp, m, ZERO, w.tmp2, m, s));
+    RSRR_TRY(zg(OP_N, OP_N, m, m, m, ONE, w.tmp2, m, X, m, ZERO, w.tmp, m, s));
+    RSRR_TRY(tri_eigvecs_correct(A, lda, m, w.tmp, m, X, m, Dc, mu, s));
+    RSRR_HIP(hipMemcpyAsync(dmu.data(), mu, m * sizeof(c128), hipMemcpyDeviceToHost, s));
+  }
   RSRR_TRY(zg(OP_N, OP_N, m, m, m, ONE, Z, m, X, m, ZERO, V, ldv, s));
-  std::vector<c128> d;
   RSRR_TRY(host_diag(A, lda, m, w, s, &d));
+  RSRR_HIP(hipStreamSynchronize(s));
   lam->resize(m);
-  for (int j = 0; j < m; ++j) (*lam)[j] = cd(d[j].re, d[j].im);
+  for (int j = 0; j < m; ++j) (*lam)[j] = cd(d[j].re + dmu[j].re, d[j].im + dmu[j].im);
   return ST_OK;
 }
 
