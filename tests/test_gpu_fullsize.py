@@ -202,3 +202,7 @@ def test_c2_uneven_qeps_full_size_through_the_server(P):
         print("n", p.n, "pairs", len(got), "companion pencil", len(exact), "max |dl|", err)
         assert len(got) == len(exact)
         assert err <= 1e-9 * scale
+        # divide-and-conquer splits near clusters drop couplings up to 4e-10
+        # here; the first-order correction brings the residuals back to the
+        # level of a backward-stable Schur form
+        assert np.max(outs[q]["res"]) <= 1e-12, np.max(outs[q]["res"])
