@@ -111,7 +111,9 @@ typedef struct {
   int K;              /* Hankel blocks (eq. eq-HH), default 2 */
   double delta;       /* basis truncation: keep singular directions above delta*sigma_1, default 1e-14 */
   double tol_gap;     /* singular-value gap threshold (eq. eq-gap), default 1e3 */
-  double tol_res;     /* returned pairs have ||T v||/(||T||_F ||v||) <= tol_res, default 1e-10 */
+  double tol_res;     /* returned pairs have ||T v||/(||T||_F ||v||) <= tol_res, default 1e-10;
+                         the reduced eigenpairs get a first-order correction when a spectral
+                         split of the reduced matrix drops a coupling above tol_res / 10 */
   double hankel_tol;  /* Hankel truncation sigma_j > hankel_tol*sigma_1, default 1e-13 */
   int precision;      /* RSRR_PREC_C128 or RSRR_PREC_C64_IR (default) */
   int ir_max_iter;    /* refinement sweeps before the complex128 fallback, default 5 */
