@@ -112,6 +112,7 @@ size_t solve_workspace_bound(const rsrr_problem* p, const rsrr_params* prm) {
   // moments: a chunk of T_S(zeta) and inverses sized to at most 8 GB
   const double ch = chunk_count(prm->NS, (size_t)(kk * z * 2), prm->chunk_gib).second;
   const double red = 2 * ch * kk * z + (2 * K + 1) * kk * z + 2 * ch * kS * nb * z + ch * (kS + 64) * z +
+                     ch * std::ceil(kS / nb) * kS * 4 +
                      (double)moments_wind_parts((long)kk, (int)ch, (int)std::min(J, 4.0)) * z;
   // Hankel matrices, SVD (basis, Jacobi copies), extraction, eigen-solve
   const double hank = 18 * M * M * z + (kS + n) * M * z;
@@ -220,6 +221,8 @@ int solve_impl(rsrr_problem* p, const rsrr_contour* c, const rsrr_params* prm, c
   RSRR_TRY(ws.get<int>("rd_ipiv", (size_t)ch * kS, &ipiv));
   int* iperm = nullptr;
   RSRR_TRY(ws.get<int>("rd_perm", (size_t)ch * kS, &iperm));
+  int* lperm = nullptr;
+  RSRR_TRY(ws.get<int>("rd_lperm", (size_t)ch * ((kS + prm->nb - 1) / prm->nb) * kS, &lperm));
   RSRR_TRY(ws.get<int>("rd_info", ch, &linfo));
   cd wind(0, 0);
   std::vector<cd> g, dg;
@@ -254,6 +257,7 @@ int solve_impl(rsrr_problem* p, const rsrr_contour* c, const rsrr_params* prm, c
     RSRR_TRY(ws.aux_stream(&w.aux, &w.ev_main, &w.ev_aux));
     w.gauss3m = true;
     w.full_swap = true;
+    w.lperm = lperm;
     RSRR_TRY(lu_factor<double>(w, s));
     // the inverses replace the factors in TS once the solves are done; X is
     // the work space of the solves

@@ -44,6 +44,10 @@ template <typename R> struct LUWork {
   // P A = L U with one row order (needed by lu_inverse); otherwise only within
   // the groups of panels the solver uses
   bool full_swap = false;
+  // full_swap only, optional: batch * npanel * n ints of work space; each
+  // panel's L columns are then moved once, by the composition of the later
+  // panels' interchanges, instead of once per later panel
+  int* lperm = nullptr;
   // look-ahead (optional): the trailing update beyond the next panel runs on
   // `aux` while the next panel is factored; ev_main / ev_aux order the two
   hipStream_t aux = nullptr;

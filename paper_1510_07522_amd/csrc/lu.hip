@@ -393,6 +393,71 @@ static int launch_permute(cplx<R>* X, long ldx, long sX, int ncols, const int* i
   return ST_OK;
 }
 
+// full_swap: the row order that the interchanges of panels p+1 .. np-1 give
+// the L columns of panel p, as a gather G[b][p][r] (r in [k_{p+1}, n)): the
+// entry that ends in row r comes from row G[b][p][r].  Built from the last
+// panel backwards, g_p = sigma_{p+1} o g_{p+1}, where sigma_q(x) is the row
+// found at x after panel q's swaps (ipiv[i] >= i, applied in order).  One
+// workgroup per matrix; LDS holds g and sigma (2 n ints) and the panel's pivots.
+__global__ __launch_bounds__(256) void lu_left_perm_kernel(const int* ipiv, int n, int nb, int* G) {
+  extern __shared__ int sh[];
+  __shared__ int s_pv[MAXNB];
+  int* g = sh;
+  int* sig = sh + n;
+  const int b = blockIdx.x, tid = threadIdx.x, np = (n + nb - 1) / nb;
+  const int* pv = ipiv + (long)b * n;
+  int* Gb = G + (long)b * np * n;
+  for (int r = tid; r < n; r += 256) g[r] = r;
+  for (int p = np - 2; p >= 0; --p) {
+    const int k = (p + 1) * nb, nbe = min(nb, n - k);
+    for (int x = k + tid; x < n; x += 256) sig[x] = x;
+    if (tid < nbe) s_pv[tid] = pv[k + tid];
+    __syncthreads();
+    if (tid == 0)
+      for (int e = 0; e < nbe; ++e) {
+        const int a = k + e, c = s_pv[e];
+        if (c != a) { const int t = sig[a]; sig[a] = sig[c]; sig[c] = t; }
+      }
+    __syncthreads();
+    for (int r = k + tid; r < n; r += 256) {
+      const int v = sig[g[r]];
+      g[r] = v;
+      Gb[(long)p * n + r] = v;
+    }
+    __syncthreads();
+  }
+}
+
+// Applies G to the L columns: column c of panel p = c / nb < np - 1, rows
+// [k_{p+1}, n), gathered through registers (every read before any write);
+// rows that keep their place are not touched.
+constexpr int LGT = 1024;               // threads per column
+constexpr int LGR = 4;                  // rows per thread: n - nb <= LGT * LGR
+template <typename R>
+__global__ __launch_bounds__(LGT) void lu_left_gather_kernel(cplx<R>* A, long lda, long sA, int n, int nb,
+                                                             const int* G) {
+  const int c = blockIdx.x, b = blockIdx.y, tid = threadIdx.x, np = (n + nb - 1) / nb;
+  const int p = c / nb;
+  if (p >= np - 1) return;
+  const int k1 = (p + 1) * nb;
+  cplx<R>* col = A + (long)b * sA + (long)c * lda;
+  const int* g = G + ((long)b * np + p) * n;
+  cplx<R> v[LGR];
+  int src[LGR];
+#pragma unroll
+  for (int i = 0; i < LGR; ++i) {
+    const int r = k1 + tid + LGT * i;
+    src[i] = (r < n) ? g[r] : r;
+    if (src[i] != r) v[i] = col[src[i]];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < LGR; ++i) {
+    const int r = k1 + tid + LGT * i;
+    if (src[i] != r) col[r] = v[i];
+  }
+}
+
 __global__ void zero_int_kernel(int* p, int count) {
   int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < count) p[i] = 0;
@@ -507,6 +572,22 @@ int lu_factor(const LUWork<R>& w, hipStream_t s) {
   // panel's own diagonal block are never touched, so L stays unit lower
   // triangular and dinv is unchanged.
   const int np = w.npanel(), SB = lu_group(nb);
+  if (w.full_swap && w.lperm && np > 1 && n - nb <= LGT * LGR && 2 * (size_t)n * sizeof(int) <= 64 * 1024) {
+    {
+      KernelTimer kt("lu_permute", s, 0.0, 4.0 * (double)np * n * w.batch, "lu_left_perm_kernel");
+      hipLaunchKernelGGL(lu_left_perm_kernel, dim3(w.batch), dim3(256), 2 * (size_t)n * sizeof(int), s, w.ipiv,
+                         n, nb, w.lperm);
+      RSRR_LAUNCH_CHECK();
+    }
+    const int lcols = (np - 1) * nb;
+    KernelTimer kt("lu_permute", s, 0.0, 2.0 * sizeof(cplx<R>) * 0.5 * (double)n * lcols * w.batch,
+                   timers_on() ? std::string("lu_left_gather_kernel<") + (sizeof(R) == 8 ? "double" : "float") + ">"
+                               : std::string());
+    hipLaunchKernelGGL((lu_left_gather_kernel<R>), dim3(lcols, w.batch), dim3(LGT), 0, s, w.A, w.lda, w.sA, n,
+                       nb, w.lperm);
+    RSRR_LAUNCH_CHECK();
+    return ST_OK;
+  }
   for (int q = 1; q < np; ++q) {
     if (!w.full_swap && q % SB == 0) continue;
     const int k = q * nb, c0 = w.full_swap ? 0 : (q / SB) * SB * nb;
