@@ -391,6 +391,7 @@ static int newton_sign_batched(DcBatch& bt, Arena& ws, hipStream_t s, std::vecto
   lw.full_swap = true;           // the Newton steps invert (lu_inverse)
   int* nperm = nullptr;
   RSRR_TRY(ws.get<int>("dcp_perm", (size_t)nbk * L, &nperm));
+  RSRR_TRY(ws.get<int>("dcn_lperm", (size_t)nbk * lw.npanel() * L, &lw.lperm));
   lwp.batch = nq; lwp.A = LUp; lwp.ipiv = ipivp; lwp.dinv = dinvp; lwp.info = infop;
   auto reset = [&](int b) -> int {
     (*ok)[b] = 0;
