@@ -478,3 +478,132 @@ def test_acoustic_1d_count_from_paper():
     out = R.rsrr(p, c, g["N"], g["L"], U, NS=g["NS"], K=g["K"], tol_res=1e-8)
     assert len(out["lam"]) == g["count"]
     assert out["n_wind"] == g["count"]
+
+
+# ------------------------------------- rational scalar functions (eq-Z-expr)
+def _cauchy_derivative(f, z0, r=1e-2, M=64):
+    """f'(z0) = (1/2 pi i) oint f(z)/(z - z0)^2 dz on a small circle (trapezoid
+    rule: geometric convergence for f analytic on the disk)."""
+    th = 2 * math.pi * np.arange(M) / M
+    e = np.exp(1j * th)
+    # z = z0 + r e^{i th}, dz = i r e^{i th} dth
+    return np.mean(f(z0 + r * e) / (r * e))
+
+
+def test_scalar_function_derivatives_by_cauchy_integral():
+    # every spec kind's derivative (which feeds the winding count, eq. eq-ncs)
+    # against the Cauchy integral of its value around the point
+    specs = [("pow", 1.5 - 0.5j, 3), ("pow", 2.0, 0), ("exp", 0.7 + 0.2j, 2, -1.0 + 0.3j),
+             ("exp", 1.0, 0, -1.0), ("rat", 2.0 + 1.0j, 1, 3.5), ("rat", -0.4, 2, 0.5 - 2j),
+             ("rat", 1.0, 0, -193.39)]
+    for spec in specs:
+        for z0 in (0.3 + 0.2j, -1.1 + 0.9j, 2.0 - 0.4j):
+            _, df = R.eval_scalar(spec, z0)
+            ref = _cauchy_derivative(lambda z: R.eval_scalar(spec, z)[0], z0)
+            assert abs(df - ref) <= 1e-10 * max(1.0, abs(ref)), (spec, z0, df, ref)
+
+
+def _rational_diag_problem(z_roots, c, b):
+    """T(z) = diag(a) + z/(z - b) diag(c) with a_i chosen so that row i
+    vanishes exactly at z_roots[i]: a_i + c_i z/(z - b) = 0 gives
+    z = a_i b / (a_i + c_i), i.e. a_i = c_i z_i / (b - z_i)."""
+    z_roots = np.asarray(z_roots, np.complex128)
+    c = np.asarray(c, np.complex128)
+    a = c * z_roots / (b - z_roots)
+    return ni.CoeffProblem(n=len(a), kinds=["diag", "diag"], mats=[a, c],
+                           fspecs=[("pow", 1.0, 0), ("rat", 1.0, 1, b)], name="rational_diag")
+
+
+RAT_ROOTS_IN = [0.3 + 0.2j, -1.1 + 0.5j, 1.2 - 0.7j, 0.0 - 1.5j, -0.5 - 0.4j]
+RAT_ROOTS_OUT = [2.6 + 0.1j, -2.4 + 1.0j, 0.1 + 2.5j, 3.0 - 1.0j, -1.8 - 1.9j]
+
+
+def test_rsrr_rational_diagonal_closed_form_roots_pole_outside():
+    # pole b = 3.5 outside |z| < 2: det T has exactly the five zeros inside,
+    # so the eigenvalues are the closed-form a_i b/(a_i + c_i) and the winding
+    # count (which uses the rational derivative) is 5
+    roots = RAT_ROOTS_IN + RAT_ROOTS_OUT
+    cc = 1.0 + 0.1j * np.arange(len(roots))
+    p = _rational_diag_problem(roots, cc, 3.5)
+    c = ni.Contour(0.0, 2.0, 2.0)
+    U = ni.probing_matrix(p.n, 4, seed=21)
+    out = R.rsrr(p, c, 32, 4, U, NS=256)
+    assert out["n_wind"] == 5 and abs(out["wind"] - 5) < 1e-8
+    assert len(out["lam"]) == 5
+    assert match_sets(out["lam"], RAT_ROOTS_IN) < 1e-11
+    assert np.all(out["res"] <= 1e-12)
+
+
+def test_rsrr_rational_diagonal_pole_inside_counts_zeros_minus_poles():
+    # pole b = 0.9 + 0.1i inside the circle: each of the ten rows has a simple
+    # pole there, so the argument principle gives (zeros - poles) = 5 - 10;
+    # T^{-1} is analytic at b, so the extracted eigenvalues are still the five
+    # closed-form zeros
+    roots = RAT_ROOTS_IN + RAT_ROOTS_OUT
+    cc = 1.0 + 0.1j * np.arange(len(roots))
+    b = 0.9 + 0.1j
+    p = _rational_diag_problem(roots, cc, b)
+    c = ni.Contour(0.0, 2.0, 2.0)
+    U = ni.probing_matrix(p.n, 4, seed=22)
+    out = R.rsrr(p, c, 32, 4, U, NS=256)
+    assert out["n_wind"] == -5 and abs(out["wind"] + 5) < 1e-8
+    assert match_sets(out["lam"], RAT_ROOTS_IN) < 1e-11
+
+
+# ------------------------------------------------ BEM entries (cf. eq-nyes)
+# Points (0,0,0), (1,0,0), (0,2,0) (r01 = 1, r02 = 2, r12 = sqrt 5), h = 0.5,
+# z = 1.5 + 0.2i: T_ij = exp(i z r)/(4 pi r), T_ii = i z/(4 pi) + 1/(2h), and
+# dT/dz: i exp(i z r)/(4 pi), i/(4 pi); values evaluated once at 30 digits with
+# mpmath and written out here.
+BEM3_T = {(0, 0): 0.98408450569081046642 + 0.11936620731892150183j,
+          (0, 1): 0.0046087071732430248735 + 0.064989315263442580004j,
+          (0, 2): -0.026404275198515193172 + 0.0037638381519302311319j,
+          (1, 2): -0.022243422511148017874 - 0.0047994001858654225898j}
+BEM3_DT = {(0, 0): 0.079577471545947667884j,
+           (0, 1): -0.064989315263442580004 + 0.0046087071732430248735j,
+           (0, 2): -0.0075276763038604622637 - 0.052808550397030386345j,
+           (1, 2): 0.010731785066820210246 - 0.049737804787176041659j}
+
+
+def test_bem_entries_literal_values():
+    p = ni.BemProblem(n=3, xyz=np.array([[0.0, 0, 0], [1.0, 0, 0], [0.0, 2.0, 0]]), h=0.5)
+    z = 1.5 + 0.2j
+    T = R.bem_matrix(p, z)
+    dT = R.bem_matrix(p, z, derivative=True)
+    for (i, j), v in BEM3_T.items():
+        assert abs(T[i, j] - v) < 1e-15 and abs(T[j, i] - v) < 1e-15, (i, j, T[i, j], v)
+    for i in range(3):
+        assert abs(T[i, i] - BEM3_T[(0, 0)]) < 1e-15
+        assert abs(dT[i, i] - BEM3_DT[(0, 0)]) < 1e-15
+    for (i, j), v in BEM3_DT.items():
+        assert abs(dT[i, j] - v) < 1e-15 and abs(dT[j, i] - v) < 1e-15, (i, j, dT[i, j], v)
+
+
+def test_bem_sphere_eigenvalues_approach_dirichlet_ball_eigenvalues():
+    # The single-layer operator on the unit sphere is singular where the
+    # interior Dirichlet problem of the ball has an eigenvalue: the zeros of
+    # the spherical Bessel functions j_l (multiplicity 2l + 1).  In the
+    # ellipse centre 3, semi-axes (1.5, 0.3) those are pi (j_0) and 4.4934
+    # (j_1, threefold).  As n doubles (h shrinks by about 1/sqrt 2) the
+    # discrete eigenvalues must move towards them, from below the real axis
+    # (outgoing waves: Im lambda < 0), with |Im lambda| shrinking.
+    from scipy.optimize import brentq
+    from scipy.special import spherical_jn
+    k0 = brentq(lambda x: spherical_jn(0, x), 3.0, 3.3)
+    k1 = brentq(lambda x: spherical_jn(1, x), 4.3, 4.6)
+    assert abs(k0 - math.pi) < 1e-12
+    c = ni.Contour(3.0, 1.5, 0.3)
+    d0, d1, im0 = [], [], []
+    for n in (128, 256, 512):
+        p = ni.bem_sphere(n)
+        U = ni.probing_matrix(n, 16, seed=9)
+        out = R.rsrr(p, c, 40, 16, U, NS=256, K=2, cheb_degree=40)
+        lam = np.sort_complex(out["lam"])
+        assert len(lam) == 4 and np.all(lam.imag < 0), lam
+        assert abs(lam[0].real - k0) < 0.3 and np.all(abs(lam[1:].real - k1) < 0.3)
+        d0.append(abs(lam[0] - k0))
+        d1.append(np.max(abs(lam[1:] - k1)))
+        im0.append(-lam[0].imag)
+    for d in (d0, d1, im0):
+        ratios = np.array(d[1:]) / np.array(d[:-1])
+        assert np.all((ratios > 0.4) & (ratios < 0.85)), (d, ratios)
