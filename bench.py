@@ -3,17 +3,21 @@
 A step is one full solve (Alg. 2 around Alg. 1: assembly, batched LU + solves
 with refinement, basis, projection, reduced problem, eigenpair recovery and
 residual filter) of one synthetic workload whose inputs are already resident
-in device memory.  The default workload is the dense delay eigenproblem
-T(z) = -z I + A0 + A1 exp(-z), n = 2048, circle |z| < 3, N = 48 nodes, L = 48
-probing vectors, complex64 factorisations with fp64 refinement.
+in device memory.  The default workload is the largest single-GPU
+configuration: the dense Helmholtz BEM matrix on a Fibonacci sphere, n = 8192,
+entries assembled on the fly at every node, ellipse centre 3 with semi-axes
+(1.5, 0.3), N = 40 nodes, L = 64 probing vectors, complex64 factorisations
+with fp64 refinement.
 
 Prints one JSON line.  `value` = resolvent samples per second of the whole
 step (N samples per solve); eigenpairs per second and per-step latency
-percentiles are reported beside it.  The roofline object covers the kernel
-class that takes most of the step's device time (HIP events on its stream,
-recorded inside the library during the timed steps).  `cpu_baseline` is the
-CPU oracle timed on a bounded sample of the same workload (a few of its
-sampling nodes).
+percentiles are reported beside it.  Kernel statistics come from one extra
+solve with every kernel timer on, outside the timed region; the timed steps
+record HIP events only around the launches of the kernel function that took
+most device time in that pass, and the roofline object is computed from
+those events.  `cpu_baseline` is the CPU oracle timed on a bounded sample of
+the same workload (a few of its sampling nodes), with the oracle's end-to-end
+time on the small QEP beside it.
 """
 from __future__ import annotations
 
@@ -30,7 +34,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
-PEAK = {"fp32_mfma": 157.3e12, "fp64_mfma": 78.6e12, "fp64_valu": 78.6e12, "hbm": 8.0e12}
+PEAK = {"fp32_mfma": 157.3e12, "fp64_mfma": 78.6e12, "hbm": 8.0e12}
 
 def kernel_bound(sym: str):
     """(bound, peak) for a kernel function, or None if it has no model."""
@@ -39,7 +43,7 @@ def kernel_bound(sym: str):
     if sym.startswith("gemm_kernel<float"):
         return "mfma", PEAK["fp32_mfma"]
     if sym.startswith(("bj_gram_kernel", "bj_apply_kernel")):
-        return "alu", PEAK["fp64_valu"]
+        return "mfma", PEAK["fp64_mfma"]    # FP64 MFMA 16x16x4 Gram and apply
     if sym.startswith(("lu_panel_kernel", "pchol_panel_kernel", "lu_permute_kernel")):
         return "hbm", PEAK["hbm"]          # panels are latency bound; priced on their bytes
     return None
@@ -92,7 +96,7 @@ def _kernel_sym(name: str) -> str:
     return name
 
 
-def write_traffic(dirs, sym: str, copy_mib: int):
+def write_traffic(dirs, sym: str, copy_mib: int, workload_desc: str):
     """HBM bytes per launch of one kernel function from FETCH_SIZE and
     WRITE_SIZE (KiB per dispatch), each scaled by what the same counter reads
     for a plain device copy of copy_mib MiB (the copy reads and writes exactly
@@ -121,8 +125,7 @@ def write_traffic(dirs, sym: str, copy_mib: int):
                 "hbm_bytes_per_launch": fetch + write, "fetch_bytes_per_launch": fetch,
                 "write_bytes_per_launch": write, "launches": per["fetch"][1],
                 "fetch_scale": scale["fetch"], "write_scale": scale["write"],
-                "workload": "delay NEP n=2048, N=48, L=48, complex64+IR, one solve "
-                            "(bench.py --steps 1 --warmup 0 --no-cpu --sample-compare 0)"}
+                "workload": workload_desc}
     json.dump(rec, open(path, "w"), indent=1)
     print(json.dumps(rec[sym], indent=1))
 
@@ -184,15 +187,25 @@ def workload(name: str):
     raise SystemExit(f"unknown workload {name}")
 
 
-def cpu_baseline(w, max_nodes: int, budget_s: float):
-    """Oracle (Alg. 2 Step 2: zgesv per node) on the host for a few nodes."""
-    from oracle import rsrr_ref as R
+def _blas_threads():
     try:
         from threadpoolctl import threadpool_info
-        cores = max([d.get("num_threads", 0) for d in threadpool_info()] + [1])
+        return max([d.get("num_threads", 0) for d in threadpool_info()] + [1])
     except Exception:
-        cores = os.cpu_count()
-    _, z, _ = R.contour_nodes(w["contour"], w["N"])
+        return os.cpu_count()
+
+
+def cpu_baseline(name: str, w, max_nodes: int, budget_s: float):
+    """The oracle on the host: (1) Alg. 2 Step 2 (LAPACK LU solve per node,
+    complex128) on as many of the workload's own nodes as fit the budget,
+    converted to samples/s (an upper bound on the oracle's end-to-end rate:
+    the basis, projection and reduced problem come on top); (2) the oracle
+    end to end on the small QEP (n = 200), timed here; (3) the oracle end to
+    end on this workload as recorded by tests/golden/make_oracle_golden.py
+    (host and thread count stated in the record)."""
+    import nep_inputs as ni
+    from oracle import rsrr_ref as R
+    z, _ = R.contour_quadrature(w["contour"], w["N"])
     t0 = time.perf_counter()
     done = 0
     for zj in z[:max_nodes]:
@@ -201,11 +214,28 @@ def cpu_baseline(w, max_nodes: int, budget_s: float):
         if time.perf_counter() - t0 > budget_s:
             break
     dt = time.perf_counter() - t0
-    return {"value": done / dt, "unit": "resolvent samples/s", "cores": cores, "kind": "oracle",
-            "sample": f"Alg. 2 Step 2 only (dense LU solve per node, complex128) on {done} of the "
-                      f"{w['N']} sampling nodes of the same workload; the oracle's full solve "
-                      f"(projection + reduced problem) is not included, so this is an upper bound "
-                      f"on its end-to-end samples/s"}
+    p0, c0, N0, L0, U0 = ni.config_c0()
+    t1 = time.perf_counter()
+    ref0 = R.rsrr(p0, c0, N0, L0, U0)
+    dt0 = time.perf_counter() - t1
+    out = {"value": done / dt, "unit": "resolvent samples/s", "cores": _blas_threads(),
+           "kind": "oracle",
+           "sample": f"Alg. 2 Step 2 only (LAPACK LU solve per node, complex128) on {done} of the "
+                     f"{w['N']} sampling nodes of this workload ({dt:.1f} s); the basis, projection "
+                     f"and reduced problem are not included, so this bounds the oracle's end-to-end "
+                     f"samples/s from above",
+           "end_to_end_c0": {"seconds": dt0, "resolvent_samples_per_s": N0 / dt0,
+                             "eigenpairs_per_s": len(ref0["lam"]) / dt0, "n_eig": len(ref0["lam"]),
+                             "what": "oracle end to end on the small QEP n=200, N=32, L=20, timed here"}}
+    gold = os.path.join(ROOT, "tests", "golden", f"oracle_{name}.json")
+    if os.path.exists(gold):
+        g = json.load(open(gold))
+        out["end_to_end_recorded"] = {
+            "seconds": g["oracle_seconds"], "resolvent_samples_per_s": g["N"] / g["oracle_seconds"],
+            "eigenpairs_per_s": g["count"] / g["oracle_seconds"], "n_eig": g["count"],
+            "host": g["host"], "what": "oracle end to end on this workload, recorded by "
+                                       "tests/golden/make_oracle_golden.py (not on this host)"}
+    return out
 
 
 def serve_bench(a, P):
@@ -237,8 +267,11 @@ def serve_bench(a, P):
     warn = collections.Counter()
     for (ts, t), r in zip(tickets, reqs):
         try:
-            out, l = srv.wait(t)
+            out, l = srv.wait(t, timeout_s=a.wait_timeout)
         except P.RsrrError as e:
+            if e.code == -7:            # bounded wait ended: the message carries the server state
+                log(f"request {r['family']} n={r['n']} not finished after {a.wait_timeout:.0f}s: {e}")
+                raise SystemExit(3)
             fails += 1
             log(f"request {r['family']} n={r['n']} failed: {e}")
             continue
@@ -274,13 +307,13 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=2)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="c1")
+    ap.add_argument("--workload", default="c3")
     ap.add_argument("--precision", default="c64_ir", choices=["c64_ir", "c128"])
     ap.add_argument("--scheme", default="sampling", choices=["sampling", "moment"],
                     help="subspace of Alg. 2 Step 3: sampling matrix (RSRR) or moment matrix (SSRR, K' = N)")
     ap.add_argument("--contour", default="ellipse", choices=["ellipse", "rect"],
                     help="rect: the square inscribed in the workload's circle, Gauss-Legendre sides")
-    ap.add_argument("--cpu-nodes", type=int, default=4)
+    ap.add_argument("--cpu-nodes", type=int, default=8)
     ap.add_argument("--cpu-budget", type=float, default=20.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--sample-compare", type=int, default=3,
@@ -292,7 +325,9 @@ def main():
                     help="LU panel width of the sampling and reduced-problem factorisations (default 64)")
     ap.add_argument("--chunk-gib", type=float, default=None,
                     help="device memory per batch of reduced-problem inverses (library default if unset)")
-    ap.add_argument("--requests", type=int, default=24, help="serving workload (c4): requests")
+    ap.add_argument("--requests", type=int, default=600, help="serving workload (c4): requests")
+    ap.add_argument("--wait-timeout", type=float, default=600.0,
+                    help="serving workload (c4): bound of each wait for a result, seconds")
     ap.add_argument("--slots", type=int, default=4, help="serving workload (c4): concurrent slots")
     ap.add_argument("--budget-gib", type=float, default=200.0, help="serving workload (c4): HBM budget")
     ap.add_argument("--traffic-from", nargs=4, default=None,
@@ -302,7 +337,9 @@ def main():
     ap.add_argument("--traffic-kernel", default="gemm_kernel<double, 0, 0, false, true>")
     a = ap.parse_args()
     if a.traffic_from:
-        write_traffic(a.traffic_from, a.traffic_kernel, a.copy_calibration or 1024)
+        write_traffic(a.traffic_from, a.traffic_kernel, a.copy_calibration or 1024,
+                      f"{a.workload}: one solve (bench.py --workload {a.workload} --steps 1 "
+                      f"--warmup 0 --no-cpu --sample-compare 0)")
         return
     if a.gpus != 1:
         print(json.dumps({"error": "this build runs on exactly one GPU; --gpus must be 1"}))
@@ -349,8 +386,26 @@ def main():
         torch.cuda.synchronize()
         log(f"warmup {i}: {time.perf_counter() - t0:.3f}s n_eig={out['info']['n_eig']}")
 
+    # kernel statistics: one solve with every kernel timer on (outside the
+    # timed region; the events cost a few percent of a step)
+    P.timers_only(None)
     P.timers_reset()
     P.timers_enable(True)
+    h.solve(ct, prm, U)
+    torch.cuda.synchronize()
+    P.timers_enable(False)
+    stats = P.timers_read()
+    classes = {k: v for k, v in stats.items() if not k.startswith("sym:")}
+    dev_ms = sum(t["ms"] for t in classes.values())
+    pre_roof, _ = kernel_roofline(stats, 1)
+    dominant = pre_roof["kernel"] if pre_roof else None
+    log(f"kernel statistics pass: {dev_ms:.1f} ms of timed device work; dominant kernel {dominant}")
+
+    # timed region: HIP events only around the dominant kernel function
+    P.timers_reset()
+    if dominant:
+        P.timers_only(dominant)
+        P.timers_enable(True)
     lat = []
     n_eig = []
     infos = []
@@ -368,15 +423,16 @@ def main():
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t_start
     P.timers_enable(False)
-    timers_all = P.timers_read()
-    timers = {k: v for k, v in timers_all.items() if not k.startswith("sym:")}
+    timed = P.timers_read()
+    P.timers_only(None)
     ms_step = elapsed / a.steps * 1e3
     samples_s = N * a.steps / elapsed
     eig_s = sum(n_eig) / elapsed
-    roof, roof_next = kernel_roofline(timers_all, a.steps)
-    dev_ms = sum(t["ms"] for t in timers.values()) / a.steps
+    roof, _ = kernel_roofline(timed, a.steps)
+    _, roof_next = kernel_roofline(stats, 1)
     if roof is not None:
-        roof["share_of_timed_device_ms"] = roof["ms_per_step"] / max(dev_ms, 1e-9)
+        roof["share_of_timed_device_ms"] = pre_roof["ms_per_step"] / max(dev_ms, 1e-9)
+        roof["events"] = "HIP events around each launch of this kernel function in the timed steps"
 
     # sampling stage alone, both precisions (the c64 + refinement vs complex128 comparison)
     ws_bound = h.workspace_bound(ct, prm)
@@ -401,7 +457,7 @@ def main():
     cpu = None
     if not a.no_cpu:
         log("cpu baseline (oracle) ...")
-        cpu = cpu_baseline(w, a.cpu_nodes, a.cpu_budget)
+        cpu = cpu_baseline(a.workload, w, a.cpu_nodes, a.cpu_budget)
 
     lat_s = np.array(lat)
     res = {
@@ -432,8 +488,9 @@ def main():
         "sampling_stage": stage,
         "sampling_c64ir_over_c128": (stage["c64_ir"]["samples_per_s"] / stage["c128"]["samples_per_s"]
                                      if len(stage) == 2 else None),
-        "kernel_ms_per_step": {k: v["ms"] / a.steps for k, v in sorted(
-            timers.items(), key=lambda kv: -kv[1]["ms"])},
+        "kernel_ms_per_step": {k: v["ms"] for k, v in sorted(
+            classes.items(), key=lambda kv: -kv[1]["ms"])},
+        "kernel_ms_source": "one solve with every kernel timer on, outside the timed steps",
         "roofline": roof,
         "roofline_next_kernels": roof_next,
         "cpu_baseline": cpu,

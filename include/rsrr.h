@@ -41,9 +41,13 @@ enum {
   RSRR_ESINGULAR = -4,   /* T(z_j) exactly singular at a sampling node */
   RSRR_EBUSY = -5,       /* request does not fit the memory budget */
   RSRR_ENOTCONV = -6,    /* an inner iteration (eigen / SVD) did not converge */
+  RSRR_ETIMEDOUT = -7,   /* a bounded wait ended before the request finished */
   RSRR_WARN_RANK_SATURATED = 1,  /* k_S == N*L < n: the sample space may be too small (eq. eq-rank-nc) */
   RSRR_WARN_COUNT_MISMATCH = 2,  /* final count differs from the winding count (eq. eq-ncs) */
-  RSRR_WARN_IR_FALLBACK = 4      /* some nodes needed the complex128 factorisation */
+  RSRR_WARN_IR_FALLBACK = 4,     /* some nodes needed the complex128 factorisation */
+  RSRR_WARN_HANKEL_FULL = 8,     /* every Hankel singular value was retained (m == K k_S): the rank
+                                    condition of Alg. 1 (eq. eq-ranks) may fail; raise K or L */
+  RSRR_WARN_NO_WINDING = 16      /* scalar-function callback without derivatives: no winding count */
 };
 
 /* Kinds of coefficient matrices A_k in T(z) = sum_k f_k(z) A_k (eq. eq-Z-expr). */
@@ -67,6 +71,21 @@ typedef struct {
   rsrr_complex c;    /* scale */
   rsrr_complex t;    /* exponent rate (EXP) or pole (RAT); unused for POW */
 } rsrr_fn;
+
+/* Scalar functions given by the caller instead of the menu above (the
+ * coefficient form allows any f_k, eq. eq-Z-expr).  The library calls
+ *   f(ctx, z, m, f_out, df_out)
+ * with m host nodes z[0..m-1] and expects f_k(z_q) in f_out[q*J + k] for every
+ * k < J, and, when df_out is not NULL, the derivatives f_k'(z_q) in
+ * df_out[q*J + k].  Calls come at the sampling nodes, the reduced-problem
+ * nodes (with derivatives, for the winding count of eq. eq-ncs) and the
+ * extracted eigenvalues, from the thread that runs the solve (a serving slot's
+ * worker thread for rsrr_server_submit).  Return 0 on success; return 1 when
+ * derivatives were asked for but are not available: the library then asks
+ * again with df_out = NULL, skips the winding count (n_wind = -1) and sets
+ * RSRR_WARN_NO_WINDING; any other value fails the call with RSRR_EINVAL. */
+typedef int (*rsrr_scalar_fn)(void* ctx, const rsrr_complex* z, size_t m, rsrr_complex* f_out,
+                              rsrr_complex* df_out);
 
 /* Closed contour C of Alg. 2 Step 1 and Alg. 1 Step 1; interior = strictly
  * inside.  The same contour gives the sampling nodes (N of them) and the
@@ -132,7 +151,8 @@ typedef struct {
   int n, N, L;
   int k_S;            /* dimension of the Rayleigh-Ritz basis (Alg. 2 Step 3) */
   int m;              /* retained Hankel singular values */
-  int n_wind;         /* eigenvalue count by the winding number (eq. eq-ncs), rounded */
+  int n_wind;         /* eigenvalue count by the winding number (eq. eq-ncs), rounded; -1 if not
+                         computed (callback without derivatives) */
   int n_gap;          /* count by the singular-value gap (eq. eq-gap); -1 if no gap >= tol_gap */
   int n_eig;          /* returned eigenpairs (inside, residual <= tol_res) */
   int n_candidates;   /* extracted eigenvalues inside the contour before the residual test */
@@ -156,6 +176,12 @@ void rsrr_default_params(rsrr_params* p);
  * 1 <= n <= 8192, 1 <= J <= 16.  stream: hipStream_t or NULL. */
 int rsrr_create(rsrr_problem** out, int n, int J, const int* kinds,
                 const void* const* A, const rsrr_fn* f, void* stream);
+
+/* The same coefficient form with the scalar functions supplied by a host
+ * callback (see rsrr_scalar_fn); f_ctx is passed back unchanged and must stay
+ * valid for the problem's lifetime.  Arguments and errors as rsrr_create. */
+int rsrr_create_fn(rsrr_problem** out, int n, int J, const int* kinds, const void* const* A,
+                   rsrr_scalar_fn f, void* f_ctx, void* stream);
 
 /* Helmholtz single-layer matrix on a point set (cf. eq. eq-nyes):
  * T_ij(z) = exp(i z r_ij)/(4 pi r_ij) for i != j, T_ii(z) = i z/(4 pi) + 1/(2h).
@@ -235,10 +261,18 @@ int rsrr_workspace_bound(const rsrr_problem* p, const rsrr_contour* c, const rsr
  *           column-major, or NULL to draw U from prm->seed) and returns a ticket
  *           at once; RSRR_EBUSY if the request's bound alone exceeds the budget.
  *           p must stay alive until the request has been waited for.
- *   wait:   blocks until the request has finished; *out receives its result
- *           (free with rsrr_result_free; NULL on error) and *latency_s (may be
- *           NULL) the time from submission to completion; returns the solve's
- *           status.  Each ticket can be waited for once.
+ *   wait:   blocks until the request has finished, or at most timeout_s
+ *           seconds when timeout_s > 0 (then RSRR_ETIMEDOUT, with the slot and
+ *           queue state in rsrr_last_error(); the ticket stays valid); *out
+ *           receives its result (free with rsrr_result_free; NULL on error)
+ *           and *latency_s (may be NULL) the time from submission to
+ *           completion; returns the solve's status.  Each ticket can be
+ *           waited for once.
+ * Slots run without the look-ahead stream of the LU factorisations (one
+ * stream per slot, no cross-stream waits).  When requests are pending and
+ * nothing has been admitted or finished for RSRR_SERVER_WATCHDOG_S seconds
+ * (environment, default 120, 0 = off), the slot and queue state is printed to
+ * stderr.
  *   pending: requests queued and running.
  *   destroy: finishes every submitted request, frees results nobody waited
  *           for, and releases the slots. */
@@ -246,7 +280,8 @@ typedef struct rsrr_server rsrr_server;
 int rsrr_server_create(rsrr_server** out, size_t hbm_budget_bytes, int max_slots);
 int rsrr_server_submit(rsrr_server* srv, rsrr_problem* p, const rsrr_contour* c, const rsrr_params* prm,
                        const rsrr_complex* U_host, uint64_t* ticket);
-int rsrr_server_wait(rsrr_server* srv, uint64_t ticket, rsrr_result** out, double* latency_s);
+int rsrr_server_wait(rsrr_server* srv, uint64_t ticket, double timeout_s, rsrr_result** out,
+                     double* latency_s);
 int rsrr_server_pending(rsrr_server* srv, int* queued, int* running);
 void rsrr_server_destroy(rsrr_server* srv);
 
@@ -303,6 +338,10 @@ int rsrr_gesv_batched(int precision, int n, int nrhs, void* A, int lda, long lon
  * for concurrent use with solves.
  * ---------------------------------------------------------------------- */
 void rsrr_timers_enable(int on);
+/* Restricts the timers to the launches of one kernel function (its "sym:"
+ * name without the prefix), so that a timed run pays for the events of that
+ * function only; NULL or "" times every class again. */
+void rsrr_timers_only(const char* sym);
 void rsrr_timers_reset(void);
 int rsrr_timers_count(void);
 int rsrr_timers_get(int index, char* name, int name_len, long long* launches, double* total_ms,

@@ -12,6 +12,8 @@ sides evaluate with their own code:
     ("pow",  c, p)          f(z) = c * z**p
     ("exp",  c, p, tau)     f(z) = c * z**p * exp(tau * z)
     ("rat",  c, p, b)       f(z) = c * z**p / (z - b)
+    ("callable", fn)        any f given by a Python function: fn(z) -> (f(z), f'(z))
+                            for a complex array z (f'(z) may be None: no derivative)
 
 Each A_k carries a storage kind: "dense" (complex128 n x n, column-major when
 flattened), "real" (float64 n x n), "identity" (no data) or "diag" (complex128
@@ -33,7 +35,7 @@ import numpy as np
 
 __all__ = [
     "CoeffProblem", "BemProblem", "Contour",
-    "probing_matrix", "qep_dense", "qep_diag", "delay_dense", "delay_diag",
+    "probing_matrix", "qep_dense", "qep_diag", "delay_dense", "delay_diag", "sqrt_coupled",
     "bem_sphere", "acoustic_1d", "loaded_string", "viscoelastic_synth",
     "config_c0", "config_c1", "config_c2", "config_c3", "config_small_qep",
     "config_small_delay",
@@ -136,6 +138,30 @@ def delay_diag(a: np.ndarray, b: np.ndarray) -> CoeffProblem:
         mats=[None, np.asarray(a, np.complex128), np.asarray(b, np.complex128)],
         fspecs=[("pow", -1.0, 1), ("pow", 1.0, 0), ("exp", 1.0, 0, -1.0)],
         name=f"delay_diag(n={n})")
+
+
+def sqrt_coupled(n: int, seed: int, derivatives: bool = True) -> CoeffProblem:
+    """T(z) = -z I + A0 + sqrt(z + 4) A1 (principal branch, cut on (-inf, -4]),
+    A0, A1 real N(0,1)/sqrt(n) drawn in that order: a coefficient form whose
+    third scalar function is outside the pow/exp/rat menu, given as Python
+    functions ("callable" specs; without derivatives when derivatives=False)."""
+    rng = np.random.default_rng(seed)
+    A0 = np.asfortranarray(rng.standard_normal((n, n)) / math.sqrt(n))
+    A1 = np.asfortranarray(rng.standard_normal((n, n)) / math.sqrt(n))
+
+    def f0(z):
+        return -z, (-np.ones_like(z) if derivatives else None)
+
+    def f1(z):
+        return np.ones_like(z), (np.zeros_like(z) if derivatives else None)
+
+    def f2(z):
+        r = np.sqrt(z + 4.0)
+        return r, (0.5 / r if derivatives else None)
+    return CoeffProblem(
+        n=n, kinds=["identity", "real", "real"], mats=[None, A0, A1],
+        fspecs=[("callable", f0), ("callable", f1), ("callable", f2)],
+        name=f"sqrt_coupled(n={n},seed={seed},derivatives={derivatives})")
 
 
 # ---------------------------------------------------------------- BEM family

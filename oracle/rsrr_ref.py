@@ -91,6 +91,12 @@ def eval_scalar(spec: tuple, z):
         dzp = p * z ** (p - 1) if p > 0 else np.zeros_like(z)
         df = c * e * (dzp + tau * z ** p)
         return f, df
+    if kind == "callable":
+        # a caller-supplied scalar function (any f_k of the coefficient form)
+        f, df = spec[1](z)
+        f = np.asarray(f, np.complex128)
+        df = np.full_like(f, np.nan) if df is None else np.asarray(df, np.complex128)
+        return f, df
     if kind == "rat":
         c, p, b = complex(spec[1]), int(spec[2]), complex(spec[3])
         f = c * z ** p / (z - b)
@@ -449,7 +455,8 @@ def solve_reduced(red: ReducedNEP, c: Contour, NS: int, K: int,
     n_gap, gmax = count_gap(sigma, tol_gap)
     m = numerical_rank(sigma, hankel_tol)
     lam, G, _ = extract_pairs(H, Hs, Hr, m, c)
-    return dict(lam=lam, G=G, n_wind=int(round(wind.real)), wind=wind,
+    n_wind = int(round(wind.real)) if np.isfinite(wind.real) else -1   # -1: no derivatives given
+    return dict(lam=lam, G=G, n_wind=n_wind, wind=wind,
                 n_gap=n_gap, gmax=gmax, m=m, hankel_sigma=sigma)
 
 

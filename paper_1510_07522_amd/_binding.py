@@ -63,12 +63,19 @@ SCHEME = {"sampling": 0, "moment": 1}
 MAT_KIND = {"identity": 0, "diag": 1, "real": 2, "dense": 3}
 FN_KIND = {"pow": 0, "exp": 1, "rat": 2}
 WARN_RANK_SATURATED, WARN_COUNT_MISMATCH, WARN_IR_FALLBACK = 1, 2, 4
+WARN_HANKEL_FULL, WARN_NO_WINDING = 8, 16
+ETIMEDOUT = -7
+
+# int (*rsrr_scalar_fn)(void* ctx, const rsrr_complex* z, size_t m, rsrr_complex* f, rsrr_complex* df)
+SCALAR_FN = C.CFUNCTYPE(C.c_int, C.c_void_p, C.POINTER(cplx), C.c_size_t, C.POINTER(cplx),
+                        C.POINTER(cplx))
 
 # Every symbol declared in include/rsrr.h, with its ctypes signature.
 _vp, _i, _d, _ll = C.c_void_p, C.c_int, C.c_double, C.c_longlong
 SIGNATURES = {
     "rsrr_default_params": (None, [C.POINTER(params_t)]),
     "rsrr_create": (_i, [C.POINTER(_vp), _i, _i, C.POINTER(_i), C.POINTER(_vp), C.POINTER(fn_t), _vp]),
+    "rsrr_create_fn": (_i, [C.POINTER(_vp), _i, _i, C.POINTER(_i), C.POINTER(_vp), _vp, _vp, _vp]),
     "rsrr_create_bem": (_i, [C.POINTER(_vp), _i, C.POINTER(_d), _d, _vp]),
     "rsrr_destroy": (None, [_vp]),
     "rsrr_sample": (_i, [_vp, C.POINTER(contour_t), C.POINTER(params_t), _vp, _i, _vp, _i,
@@ -82,7 +89,7 @@ SIGNATURES = {
     "rsrr_server_create": (_i, [C.POINTER(_vp), C.c_size_t, _i]),
     "rsrr_server_submit": (_i, [_vp, _vp, C.POINTER(contour_t), C.POINTER(params_t), _vp,
                                 C.POINTER(C.c_uint64)]),
-    "rsrr_server_wait": (_i, [_vp, C.c_uint64, C.POINTER(_vp), C.POINTER(_d)]),
+    "rsrr_server_wait": (_i, [_vp, C.c_uint64, _d, C.POINTER(_vp), C.POINTER(_d)]),
     "rsrr_server_pending": (_i, [_vp, C.POINTER(_i), C.POINTER(_i)]),
     "rsrr_server_destroy": (None, [_vp]),
     "rsrr_result_info": (_i, [_vp, C.POINTER(info_t)]),
@@ -94,6 +101,7 @@ SIGNATURES = {
                                 _ll, _i, _i, _vp]),
     "rsrr_gesv_batched": (_i, [_i, _i, _i, _vp, _i, _ll, _vp, _i, _ll, _i, _i, C.POINTER(_i), _vp]),
     "rsrr_timers_enable": (None, [_i]),
+    "rsrr_timers_only": (None, [C.c_char_p]),
     "rsrr_timers_reset": (None, []),
     "rsrr_timers_count": (_i, []),
     "rsrr_timers_get": (_i, [_i, C.c_char_p, _i, C.POINTER(_ll), C.POINTER(_d), C.POINTER(_d),
@@ -209,6 +217,33 @@ def _fn(spec) -> fn_t:
     return f
 
 
+def _scalar_callback(fns):
+    """rsrr_scalar_fn calling the Python functions fn_k(z) -> (f, f' or None)
+    for the m nodes the library passes; fills f[q*J + k] and df[q*J + k]."""
+    J = len(fns)
+
+    def cb(ctx, zp, m, fp, dfp):
+        try:
+            z = np.ctypeslib.as_array(C.cast(zp, C.POINTER(C.c_double)), shape=(m, 2))
+            z = z[:, 0] + 1j * z[:, 1]
+            f = np.ctypeslib.as_array(C.cast(fp, C.POINTER(C.c_double)), shape=(m, J, 2))
+            df = (np.ctypeslib.as_array(C.cast(dfp, C.POINTER(C.c_double)), shape=(m, J, 2))
+                  if dfp else None)
+            for k, fn in enumerate(fns):
+                v, dv = fn(z)
+                v = np.broadcast_to(np.asarray(v, np.complex128), (m,))
+                f[:, k, 0], f[:, k, 1] = v.real, v.imag
+                if df is not None:
+                    if dv is None:
+                        return 1                      # no derivatives: no winding count
+                    dv = np.broadcast_to(np.asarray(dv, np.complex128), (m,))
+                    df[:, k, 0], df[:, k, 1] = dv.real, dv.imag
+            return 0
+        except Exception:                             # reported as an error by the library
+            return -1
+    return SCALAR_FN(cb)
+
+
 # ------------------------------------------------------------------ problems
 class Problem:
     """A problem handle: coefficient form (nep_inputs.CoeffProblem) or BEM
@@ -241,8 +276,15 @@ class Problem:
                     arr = np.asfortranarray(A, dtype=np.complex128)
                 self._keep.append(arr)
                 ptrs[k] = arr.ctypes.data
-            fns = (fn_t * J)(*[_fn(s) for s in prob.fspecs])
-            check(lib.rsrr_create(C.byref(h), prob.n, J, kinds, ptrs, fns, stream_ptr()))
+            if any(sp[0] == "callable" for sp in prob.fspecs):
+                # every f_k comes from its Python function through the callback
+                assert all(sp[0] == "callable" for sp in prob.fspecs), "mix of callables and menu specs"
+                self._cb = _scalar_callback([sp[1] for sp in prob.fspecs])
+                check(lib.rsrr_create_fn(C.byref(h), prob.n, J, kinds, ptrs, C.cast(self._cb, C.c_void_p),
+                                         None, stream_ptr()))
+            else:
+                fns = (fn_t * J)(*[_fn(s) for s in prob.fspecs])
+                check(lib.rsrr_create(C.byref(h), prob.n, J, kinds, ptrs, fns, stream_ptr()))
             self._keep = []
             self.bem = False
         self.handle = h
@@ -337,12 +379,16 @@ class Server:
         self._req[t.value] = (prob.n, prm)
         return t.value
 
-    def wait(self, ticket: int):
-        """(result dict as Problem.solve returns it, latency in seconds)."""
-        n, prm = self._req.pop(ticket)
+    def wait(self, ticket: int, timeout_s: float = 0.0):
+        """(result dict as Problem.solve returns it, latency in seconds);
+        timeout_s > 0 bounds the wait (RsrrError with code ETIMEDOUT and the
+        server state in its message; the ticket stays valid)."""
+        n, prm = self._req[ticket]
         r = C.c_void_p()
         lat = C.c_double(0)
-        st = check(load().rsrr_server_wait(self.handle, C.c_uint64(ticket), C.byref(r), C.byref(lat)))
+        st = check(load().rsrr_server_wait(self.handle, C.c_uint64(ticket), float(timeout_s), C.byref(r),
+                                           C.byref(lat)))
+        del self._req[ticket]
         return _take_result(r, n, prm, st), lat.value
 
     def pending(self):
@@ -374,6 +420,11 @@ def orthonormalize(S, rows: int, cols: int, delta: float = 1e-14):
 
 def timers_enable(on: bool = True):
     load().rsrr_timers_enable(int(on))
+
+
+def timers_only(sym: str | None):
+    """Times only the launches of one kernel function (None: every class)."""
+    load().rsrr_timers_only(None if sym is None else sym.encode())
 
 
 def timers_reset():

@@ -62,6 +62,11 @@ int Arena::get(const char* name, size_t bytes, void** out) {
 }
 
 int Arena::aux_stream(hipStream_t* s, hipEvent_t* ev_main, hipEvent_t* ev_aux) {
+  if (no_aux) {
+    *s = nullptr;
+    *ev_main = *ev_aux = nullptr;
+    return ST_OK;
+  }
   if (!aux) {
     if (hipStreamCreateWithFlags(&aux, hipStreamNonBlocking) != hipSuccess) {
       aux = nullptr;
@@ -113,6 +118,24 @@ void eval_fn(const rsrr_fn& f, cd z, cd* val, cd* der) {
       *val = c * zp;
       if (der) *der = c * dzp;
   }
+}
+
+int eval_scalars(const rsrr_problem* p, const cd* z, size_t m, cd* f, cd* df) {
+  const int J = p->J;
+  if (!p->cb) {
+    for (size_t q = 0; q < m; ++q)
+      for (int k = 0; k < J; ++k) eval_fn(p->fns[k], z[q], f + q * J + k, df ? df + q * J + k : nullptr);
+    return ST_OK;
+  }
+  // std::complex<double> has the layout of rsrr_complex (two doubles)
+  static_assert(sizeof(cd) == sizeof(rsrr_complex), "complex layout");
+  int r = p->cb(p->cb_ctx, (const rsrr_complex*)z, m, (rsrr_complex*)f, (rsrr_complex*)df);
+  if (r == 1 && df) {
+    r = p->cb(p->cb_ctx, (const rsrr_complex*)z, m, (rsrr_complex*)f, nullptr);
+    if (r == 0) return 1;
+  }
+  if (r != 0) return set_error(ST_EINVAL, "scalar-function callback returned %d", r);
+  return ST_OK;
 }
 
 void gauss_legendre(int n, std::vector<double>* x, std::vector<double>* w) {
@@ -260,24 +283,23 @@ void rsrr_default_params(rsrr_params* p) {
   p->chunk_gib = 24.0;
 }
 
-int rsrr_create(rsrr_problem** out, int n, int J, const int* kinds, const void* const* A,
-                const rsrr_fn* f, void* stream) {
-  if (!out || !kinds || !f || !A) return set_error(ST_EINVAL, "rsrr_create: null argument");
+// Coefficient-form problem: validates and uploads the A_k and forms their
+// Gram matrix; the scalar functions are set by the caller.
+static int create_coeff(rsrr_problem** out, int n, int J, const int* kinds, const void* const* A,
+                        void* stream) {
+  if (!out || !kinds || !A) return set_error(ST_EINVAL, "rsrr_create: null argument");
   *out = nullptr;
   if (n < 1 || n > 8192) return set_error(ST_EINVAL, "rsrr_create: n=%d outside [1, 8192]", n);
   if (J < 1 || J > 16) return set_error(ST_EINVAL, "rsrr_create: J=%d outside [1, 16]", J);
   for (int k = 0; k < J; ++k) {
     if (kinds[k] < 0 || kinds[k] > 3) return set_error(ST_EINVAL, "rsrr_create: kind[%d]=%d", k, kinds[k]);
     if (kinds[k] != RSRR_MAT_IDENTITY && !A[k]) return set_error(ST_EINVAL, "rsrr_create: A[%d] is NULL", k);
-    if (f[k].kind < 0 || f[k].kind > 2 || f[k].p < 0)
-      return set_error(ST_EINVAL, "rsrr_create: bad scalar function %d", k);
   }
   rsrr_problem* p = new rsrr_problem();
   p->n = n;
   p->J = J;
   p->stream = (hipStream_t)stream;
   p->kinds.assign(kinds, kinds + J);
-  p->fns.assign(f, f + J);
   p->mats.assign(J, nullptr);
   const size_t nn = (size_t)n * n;
   for (int k = 0; k < J; ++k) {
@@ -307,8 +329,6 @@ int rsrr_create(rsrr_problem** out, int n, int J, const int* kinds, const void* 
       default: { const rsrr_complex* d = (const rsrr_complex*)A[k]; return cd(d[e].re, d[e].im); }
     }
   };
-  bool anydense = false;
-  for (int k = 0; k < J; ++k) anydense |= (kinds[k] >= RSRR_MAT_REAL);
   for (int k = 0; k < J; ++k)
     for (int l = 0; l < J; ++l) {
       cd s(0, 0);
@@ -324,8 +344,29 @@ int rsrr_create(rsrr_problem** out, int n, int J, const int* kinds, const void* 
       p->gram[2 * (k * J + l)] = s.real();
       p->gram[2 * (k * J + l) + 1] = s.imag();
     }
-  (void)anydense;
   *out = p;
+  return ST_OK;
+}
+
+int rsrr_create(rsrr_problem** out, int n, int J, const int* kinds, const void* const* A,
+                const rsrr_fn* f, void* stream) {
+  if (!out || !f) return set_error(ST_EINVAL, "rsrr_create: null argument");
+  *out = nullptr;
+  for (int k = 0; k < J && k < 16; ++k)
+    if (f[k].kind < 0 || f[k].kind > 2 || f[k].p < 0)
+      return set_error(ST_EINVAL, "rsrr_create: bad scalar function %d", k);
+  RSRR_TRY(create_coeff(out, n, J, kinds, A, stream));
+  (*out)->fns.assign(f, f + J);
+  return ST_OK;
+}
+
+int rsrr_create_fn(rsrr_problem** out, int n, int J, const int* kinds, const void* const* A,
+                   rsrr_scalar_fn f, void* f_ctx, void* stream) {
+  if (!out || !f) return set_error(ST_EINVAL, "rsrr_create_fn: null argument");
+  *out = nullptr;
+  RSRR_TRY(create_coeff(out, n, J, kinds, A, stream));
+  (*out)->cb = f;
+  (*out)->cb_ctx = f_ctx;
   return ST_OK;
 }
 

@@ -48,7 +48,7 @@ template <typename D, typename S> __host__ __device__ inline cplx<D> ccast(cplx<
 // ------------------------------------------------------------- status codes
 enum {
   ST_OK = 0, ST_EINVAL = -1, ST_ENOMEM = -2, ST_EHIP = -3, ST_ESINGULAR = -4,
-  ST_EBUSY = -5, ST_ENOTCONV = -6
+  ST_EBUSY = -5, ST_ENOTCONV = -6, ST_ETIMEDOUT = -7
 };
 
 // Records an error message in thread-local storage; returns code.

@@ -21,6 +21,9 @@ struct Arena {
   // the LU factorisations, created on first use
   hipStream_t aux = nullptr;
   hipEvent_t ev[2] = {nullptr, nullptr};
+  // no look-ahead stream: aux_stream() hands out none, and the LU
+  // factorisations run on the caller's stream alone
+  bool no_aux = false;
   int get(const char* name, size_t bytes, void** out);
   template <typename T> int get(const char* name, size_t count, T** out) {
     return get(name, count * sizeof(T), (void**)out);
@@ -41,7 +44,9 @@ struct rsrr_problem {
   bool bem = false;
   hipStream_t stream = nullptr;
   std::vector<int> kinds;
-  std::vector<rsrr_fn> fns;
+  std::vector<rsrr_fn> fns;           // menu entries (empty when cb is set)
+  rsrr_scalar_fn cb = nullptr;        // caller's scalar functions (rsrr_create_fn)
+  void* cb_ctx = nullptr;
   std::vector<void*> mats;            // device data per coefficient (nullptr for identity)
   std::vector<double> gram;           // J x J complex (re, im): gram[k,l] = sum conj(A_k) A_l
   double* xyz = nullptr;              // BEM points (device, n*3)
@@ -80,6 +85,10 @@ int solve_impl(rsrr_problem* p, const rsrr_contour* c, const rsrr_params* prm, c
 // Upper bound of the device workspace one solve of p with prm allocates.
 size_t solve_workspace_bound(const rsrr_problem* p, const rsrr_params* prm);
 int check_params(const rsrr_problem* p, const rsrr_contour* c, const rsrr_params* prm);
+// f_k(z_q) into f[q*J + k] for the m nodes z, and f_k'(z_q) into df when df is
+// not null: the problem's menu entries or the caller's callback.  Returns
+// ST_OK, 1 when the callback has no derivatives (f is then filled), or an error.
+int eval_scalars(const rsrr_problem* p, const cd* z, size_t m, cd* f, cd* df);
 // Gauss-Legendre nodes x (ascending) and weights w of the n-point rule on [-1, 1].
 void gauss_legendre(int n, std::vector<double>* x, std::vector<double>* w);
 // Per-side node counts of a rectangular contour for N nodes in total: the

@@ -18,14 +18,13 @@
 namespace rsrr {
 
 // Scalar coefficients f_k(z_j) for the given nodes (row j holds J values).
-static void node_coefs(const rsrr_problem* p, const std::vector<cd>& z, std::vector<c128>* f) {
-  f->resize(z.size() * p->J);
-  for (size_t j = 0; j < z.size(); ++j)
-    for (int k = 0; k < p->J; ++k) {
-      cd v;
-      eval_fn(p->fns[k], z[j], &v, nullptr);
-      (*f)[j * p->J + k] = mk<double>(v.real(), v.imag());
-    }
+static int node_coefs(const rsrr_problem* p, const std::vector<cd>& z, std::vector<c128>* f) {
+  std::vector<cd> v(z.size() * p->J);
+  const int st = eval_scalars(p, z.data(), z.size(), v.data(), nullptr);
+  if (st < 0) return st;
+  f->resize(v.size());
+  for (size_t e = 0; e < v.size(); ++e) (*f)[e] = mk<double>(v[e].real(), v[e].imag());
+  return ST_OK;
 }
 
 // ||T(z_j)||_F^2 for coefficient-form problems from the coefficient Gram.
@@ -171,7 +170,7 @@ int sample_impl(rsrr_problem* p, const rsrr_contour* c, const rsrr_params* prm, 
   contour_nodes(c, N, true, &z, nullptr);
   std::vector<c128> f, zc(N);
   for (int j = 0; j < N; ++j) zc[j] = mk<double>(z[j].real(), z[j].imag());
-  if (!p->bem) node_coefs(p, z, &f);
+  if (!p->bem) RSRR_TRY(node_coefs(p, z, &f));
 
   c128 *f_dev = nullptr, *z_dev = nullptr;
   int *ipiv = nullptr, *infod = nullptr;
@@ -340,7 +339,7 @@ int sample_impl(rsrr_problem* p, const rsrr_contour* c, const rsrr_params* prm, 
       std::vector<cd> zb(nbad);
       std::vector<c128> zbc(nbad), fb;
       for (int q = 0; q < nbad; ++q) { zb[q] = z[bad[q]]; zbc[q] = zc[bad[q]]; }
-      if (!p->bem) node_coefs(p, zb, &fb);
+      if (!p->bem) RSRR_TRY(node_coefs(p, zb, &fb));
       c128 *Tb = nullptr, *dinvb = nullptr, *Yb = nullptr, *fbd = nullptr, *zbd = nullptr;
       RSRR_TRY(p->ws.get<c128>("s_T128", (size_t)nbad * nn, &Tb));
       RSRR_TRY(p->ws.get<c128>("s_dinv128", LUWork<double>::dinv_elems(n, nb, nbad), &dinvb));

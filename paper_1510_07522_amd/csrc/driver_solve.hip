@@ -20,6 +20,7 @@
 #include <cstring>
 #include <numeric>
 
+#include "bounds.h"
 #include "driver.h"
 #include "eig.h"
 #include "reduced.h"
@@ -59,67 +60,36 @@ static void gaussian_probe(int n, int L, uint64_t seed, std::vector<c128>* U) {
   }
 }
 
-// g_k(z), g_k'(z) of the reduced problem: the f_k themselves, or the
-// Chebyshev polynomials tau_j((z - c)/a) for the BEM interpolant.
-static void reduced_scalars(const rsrr_problem* p, int J, double cx, double a, cd z,
-                            std::vector<cd>* g, std::vector<cd>* dg) {
-  g->assign(J, cd(0, 0));
-  dg->assign(J, cd(0, 0));
+// g_k(z_q), g_k'(z_q) of the reduced problem at m nodes (row q holds J values):
+// the f_k themselves, or the Chebyshev polynomials tau_j((z - c)/a) for the
+// BEM interpolant.  Returns 1 (g filled, dg zero) when the caller's scalar
+// functions come without derivatives.
+static int reduced_scalars(const rsrr_problem* p, int J, double cx, double a, const cd* z, size_t m,
+                           std::vector<cd>* g, std::vector<cd>* dg) {
+  g->assign(m * J, cd(0, 0));
+  dg->assign(m * J, cd(0, 0));
   if (!p->bem) {
-    for (int k = 0; k < J; ++k) eval_fn(p->fns[k], z, &(*g)[k], &(*dg)[k]);
-    return;
+    const int st = eval_scalars(p, z, m, g->data(), dg->data());
+    if (st == 1) dg->assign(m * J, cd(0, 0));
+    return st;
   }
-  const cd t = (z - cx) / a;
-  (*g)[0] = 1.0;
-  if (J > 1) { (*g)[1] = t; (*dg)[1] = 1.0; }
-  for (int j = 2; j < J; ++j) {
-    (*g)[j] = 2.0 * t * (*g)[j - 1] - (*g)[j - 2];
-    (*dg)[j] = 2.0 * (*g)[j - 1] + 2.0 * t * (*dg)[j - 1] - (*dg)[j - 2];
+  for (size_t q = 0; q < m; ++q) {
+    cd* gq = g->data() + q * J;
+    cd* dq = dg->data() + q * J;
+    const cd t = (z[q] - cx) / a;
+    gq[0] = 1.0;
+    if (J > 1) { gq[1] = t; dq[1] = 1.0; }
+    for (int j = 2; j < J; ++j) {
+      gq[j] = 2.0 * t * gq[j - 1] - gq[j - 2];
+      dq[j] = 2.0 * gq[j - 1] + 2.0 * t * dq[j - 1] - dq[j - 2];
+    }
+    for (int j = 0; j < J; ++j) dq[j] /= a;
   }
-  for (int j = 0; j < J; ++j) (*dg)[j] /= a;
-}
-
-// (number of batches, nodes per batch) for NS nodes of `per` bytes each in
-// chunk_gib GiB: the fewest batches that fit, with the nodes spread evenly.
-static std::pair<int, int> chunk_count(int NS, size_t per, double chunk_gib) {
-  const size_t cap = (size_t)(chunk_gib * 1073741824.0);
-  const int fit = (int)std::max<size_t>(1, std::min<size_t>(NS, cap / std::max<size_t>(per, 1)));
-  const int nb = (NS + fit - 1) / fit;
-  return {nb, (NS + nb - 1) / nb};
+  return ST_OK;
 }
 
 size_t solve_workspace_bound(const rsrr_problem* p, const rsrr_params* prm) {
-  const double z = 16.0;   // bytes of a complex128
-  const double cap = prm->chunk_gib * 1073741824.0;
-  const double n = p->n, N = prm->N, L = prm->L, NS = prm->NS, K = prm->K, nb = prm->nb;
-  const double NL = N * L;
-  const double cols = prm->scheme == RSRR_SCHEME_MOMENT ? (prm->Kp > 0 ? prm->Kp : prm->N) * L : NL;
-  const double kS = std::min(n, cols), kk = kS * kS, M = K * kS;   // m <= M
-  const double J = p->bem ? (prm->cheb_degree > 0 ? prm->cheb_degree : 40) + 1 : p->J;
-  // sampling: complex128 factors and diagonal-block inverses (the precision, or
-  // the fallback of every node), complex64 factors, solutions and residuals
-  double samp = N * n * n * z + 2 * N * n * nb * z + (J + 10) * n * NL * z;
-  if (prm->precision == RSRR_PREC_C64_IR) samp += N * n * n * 8 + 2 * N * n * nb * 8;
-  if (p->bem) samp += N * n * 8;
-  // basis: S_hat or M_hat, Q and the Gram matrices of the two levels
-  const double basis = (cols + kS) * n * z + 8 * cols * cols * z;
-  // projection (BEM: Chebyshev samples in chunks of at most 8 GB)
-  double proj = 2 * J * kk * z + n * kS * z;
-  if (p->bem) {   // Chebyshev samples T(x_k) and T(x_k) Q in chunks of at most 8 GB
-    const double chb = std::max(1.0, std::min(J, std::floor(cap / (n * n * z))));
-    proj += chb * (n * n + n * kS) * z + J * J * z + J * kk * z;
-  }
-  // moments: a chunk of T_S(zeta) and inverses sized to at most 8 GB
-  const double ch = chunk_count(prm->NS, (size_t)(kk * z * 2), prm->chunk_gib).second;
-  const double red = 2 * ch * kk * z + (2 * K + 1) * kk * z + 2 * ch * kS * nb * z + ch * (kS + 64) * z +
-                     ch * std::ceil(kS / nb) * kS * 4 +
-                     (double)moments_wind_parts((long)kk, (int)ch, (int)std::min(J, 4.0)) * z;
-  // Hankel matrices, SVD (basis, Jacobi copies), extraction, eigen-solve
-  const double hank = 18 * M * M * z + (kS + n) * M * z;
-  const double eig = 26 * M * M * z;
-  // residual filter
-  const double resid = (J + 4) * n * M * z;
-  return (size_t)(1.1 * (samp + basis + proj + red + hank + eig + resid)) + ((size_t)64 << 20);
+  return workspace_bound(p->n, p->J, p->bem, prm);
 }
 
 size_t Arena::bytes() const {
@@ -226,14 +196,18 @@ int solve_impl(rsrr_problem* p, const rsrr_contour* c, const rsrr_params* prm, c
   RSRR_TRY(ws.get<int>("rd_info", ch, &linfo));
   cd wind(0, 0);
   std::vector<cd> g, dg;
+  const int sst = reduced_scalars(p, J, cx, ax, zeta.data(), NS, &g, &dg);
+  if (sst < 0) return sst;
+  const bool have_wind = sst == ST_OK;
+  if (!have_wind) warn |= RSRR_WARN_NO_WINDING;
   std::vector<c128> hg((size_t)ch * J), hdg((size_t)ch * J), hcw((size_t)ch * 2 * K), hpart;
   for (int m0 = 0; m0 < NS; m0 += ch) {
     const int cnt = std::min(ch, NS - m0);
     for (int q = 0; q < cnt; ++q) {
-      reduced_scalars(p, J, cx, ax, zeta[m0 + q], &g, &dg);
       for (int k = 0; k < J; ++k) {
-        hg[(size_t)q * J + k] = mk<double>(g[k].real(), g[k].imag());
-        hdg[(size_t)q * J + k] = mk<double>(dg[k].real(), dg[k].imag());
+        const cd gv = g[(size_t)(m0 + q) * J + k], dv = dg[(size_t)(m0 + q) * J + k];
+        hg[(size_t)q * J + k] = mk<double>(gv.real(), gv.imag());
+        hdg[(size_t)q * J + k] = mk<double>(dv.real(), dv.imag());
       }
       const cd w = dzeta[m0 + q] / cd(0, 2.0 * M_PI);
       const cd sm = (zeta[m0 + q] - gamma) / rho;
@@ -293,9 +267,9 @@ int solve_impl(rsrr_problem* p, const rsrr_contour* c, const rsrr_params* prm, c
       wind += dzeta[m0 + q] / cd(0, 2.0 * M_PI) * tr;
     }
   }
-  info.wind_re = wind.real();
-  info.wind_im = wind.imag();
-  info.n_wind = (int)std::lround(wind.real());
+  info.wind_re = have_wind ? wind.real() : std::nan("");
+  info.wind_im = have_wind ? wind.imag() : std::nan("");
+  info.n_wind = have_wind ? (int)std::lround(wind.real()) : -1;
   vlog("moments NS=%d chunk=%d winding %.6f%+.2ei %.3fs", NS, ch, wind.real(), wind.imag(), now_s() - t0);
 
   // ---- Hankel matrices and the SVD of H
@@ -330,6 +304,9 @@ int solve_impl(rsrr_problem* p, const rsrr_contour* c, const rsrr_params* prm, c
   int m = 0;
   for (int j = 0; j < rH; ++j) if (sigma[j] > prm->hankel_tol * sigma[0]) ++m;
   info.m = m;
+  // every singular value retained: H may not have the rank Alg. 1 needs
+  // (K k_S at least the number of eigenvalues inside, eq. eq-ranks)
+  if (m == M) warn |= RSRR_WARN_HANKEL_FULL;
 
   // ---- A = V0^H H^< W0 S0^{-1}; eig; recovery
   c128 *W0s = nullptr, *T1 = nullptr, *Ar = nullptr, *Gp = nullptr, *T2 = nullptr, *Gv = nullptr, *Vv = nullptr;
@@ -419,12 +396,12 @@ int solve_impl(rsrr_problem* p, const rsrr_contour* c, const rsrr_params* prm, c
         P[k] = Pk;
       }
       std::vector<c128> hc((size_t)nin * p->J);
-      for (int q = 0; q < nin; ++q)
-        for (int k = 0; k < p->J; ++k) {
-          cd v;
-          eval_fn(p->fns[k], lam[inside[q]], &v, nullptr);
-          hc[(size_t)q * p->J + k] = mk<double>(v.real(), v.imag());
-        }
+      {
+        std::vector<cd> zl(nin), fv((size_t)nin * p->J);
+        for (int q = 0; q < nin; ++q) zl[q] = lam[inside[q]];
+        RSRR_TRY(eval_scalars(p, zl.data(), nin, fv.data(), nullptr));
+        for (size_t e = 0; e < fv.size(); ++e) hc[e] = mk<double>(fv[e].real(), fv[e].imag());
+      }
       RSRR_TRY(ws.get<c128>("fi_coef", hc.size(), &coef));
       RSRR_HIP(hipMemcpyAsync(coef, hc.data(), hc.size() * sizeof(c128), hipMemcpyHostToDevice, s));
       RSRR_TRY(combine_residual(zerov, n, P.data(), p->J, coef, n, 1, nin, Rr, n, s));
@@ -477,7 +454,7 @@ int solve_impl(rsrr_problem* p, const rsrr_contour* c, const rsrr_params* prm, c
   RSRR_HIP(hipStreamSynchronize(s));
   info.t_residual = now_s() - t0;
   info.ws_bytes = (double)ws.bytes();
-  if (ne != info.n_wind) warn |= RSRR_WARN_COUNT_MISMATCH;
+  if (have_wind && ne != info.n_wind) warn |= RSRR_WARN_COUNT_MISMATCH;
   return warn;
 }
 

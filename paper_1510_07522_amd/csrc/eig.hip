@@ -876,11 +876,27 @@ __global__ __launch_bounds__(256) void trevc_kernel(const c128* T, long ldt, int
   }
 }
 
-int tri_eigvecs(const c128* T, long ldt, int m, c128* X, long ldx, hipStream_t s) {
-  std::vector<c128> diag(m);
-  RSRR_HIP(hipMemcpy2DAsync(diag.data(), sizeof(c128), T, (ldt + 1) * sizeof(c128), sizeof(c128), m,
-                            hipMemcpyDeviceToHost, s));
+static __global__ __launch_bounds__(256) void diag_gather_kernel(const c128* A, long lda, int m, c128* d) {
+  const int j = blockIdx.x * 256 + threadIdx.x;
+  if (j < m) d[j] = A[j + (long)j * lda];
+}
+
+// Diagonal of A (device) to the host: gathered into tmp (m device elements)
+// by a kernel, then one contiguous copy.  (A strided 2-D copy of the diagonal
+// straight to pageable host memory returned zeros in runs under the kernel
+// profiler.)
+static int diag_to_host(const c128* A, long lda, int m, c128* tmp, std::vector<c128>* out, hipStream_t s) {
+  out->resize(m);
+  hipLaunchKernelGGL(diag_gather_kernel, dim3((unsigned)cdivl(m, 256)), dim3(256), 0, s, A, lda, m, tmp);
+  RSRR_LAUNCH_CHECK();
+  RSRR_HIP(hipMemcpyAsync(out->data(), tmp, (size_t)m * sizeof(c128), hipMemcpyDeviceToHost, s));
   RSRR_HIP(hipStreamSynchronize(s));
+  return ST_OK;
+}
+
+int tri_eigvecs(const c128* T, long ldt, int m, c128* X, long ldx, hipStream_t s) {
+  std::vector<c128> diag;
+  RSRR_TRY(diag_to_host(T, ldt, m, X, &diag, s));    // X is written by the kernel below
   double tnorm = 0;
   for (int j = 0; j < m; ++j) tnorm = std::max(tnorm, sqrt(abs2(diag[j])));
   const double small = std::max(tnorm, 1e-300) * 2.220446049250313e-16;
@@ -974,10 +990,8 @@ __global__ __launch_bounds__(256) void evec_correct_kernel(const c128* T, long l
 int tri_eigvecs_correct(const c128* T, long ldt, int m, const c128* P, long ldp, c128* X, long ldx,
                         c128* D, c128* mu, hipStream_t s) {
   if (m <= 0) return ST_OK;
-  std::vector<c128> diag(m);
-  RSRR_HIP(hipMemcpy2DAsync(diag.data(), sizeof(c128), T, (ldt + 1) * sizeof(c128), sizeof(c128), m,
-                            hipMemcpyDeviceToHost, s));
-  RSRR_HIP(hipStreamSynchronize(s));
+  std::vector<c128> diag;
+  RSRR_TRY(diag_to_host(T, ldt, m, mu, &diag, s));   // mu is written by the kernel below
   double tnorm = 0;
   for (int j = 0; j < m; ++j) tnorm = std::max(tnorm, sqrt(abs2(diag[j])));
   const double small = std::max(tnorm, 1e-300) * 2.220446049250313e-16;
@@ -1042,10 +1056,8 @@ int eig_general(c128* A, long lda, int m, std::vector<cd>* lam, c128* V, long ld
   RSRR_HIP(hipStreamSynchronize(s));
   if (st < 0) return set_error(ST_ENOTCONV, "Hessenberg QR did not converge (m=%d)", m);
   // ---- eigenvalues and eigenvectors
-  std::vector<c128> diag(m);
-  RSRR_HIP(hipMemcpy2DAsync(diag.data(), sizeof(c128), A, (lda + 1) * sizeof(c128), sizeof(c128), m,
-                            hipMemcpyDeviceToHost, s));
-  RSRR_HIP(hipStreamSynchronize(s));
+  std::vector<c128> diag;
+  RSRR_TRY(diag_to_host(A, lda, m, w, &diag, s));
   double tnorm = 0;
   for (int j = 0; j < m; ++j) tnorm = std::max(tnorm, sqrt(abs2(diag[j])));
   const double small = std::max(tnorm, 1e-300) * 2.220446049250313e-16;

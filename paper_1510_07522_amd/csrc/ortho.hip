@@ -1,15 +1,21 @@
 // Alg. 2, Step 3: an orthonormal basis of the sampling matrix S_hat keeping its
 // singular directions above delta * sigma_1.
 //
-// A Gram matrix squares singular values, so a single Gram pass resolves only
-// sigma_i / sigma_1 down to about sqrt(u) ~ 1e-8.  Two levels are used:
+// A Gram matrix squares singular values, so one Gram pass resolves sigma_i /
+// sigma_1 only down to its own rounding floor (about sqrt(rows u) sigma_1).
+// Up to three levels are used (the caller passes the number):
 //   level 1: G = S^H S, pivoted (rank-revealing) Cholesky G = P L L^H P^T
-//            stopped when the largest remaining pivot drops below tau1*sigma_1^2,
+//            stopped when the largest remaining pivot drops below
+//            1e-14 sigma_1^2 (singular-value ratio 1e-7, above the floor),
 //            S1 = S P(:, 1:k1) L11^{-H}, then one more Cholesky-QR pass
 //            (CholeskyQR2).
-//   level 2: R = (I - S1 S1^H)^2 S, the same on R^H R with the absolute stop
-//            (delta sigma_1)^2, orthogonalised against S1 and CholeskyQR2'd.
-// sigma_1^2 is the largest eigenvalue of G (power iteration).
+//   level l > 1: R = (I - Q Q^H)^2 S restricted to the columns the previous
+//            level left, the same on R^H R stopped at the larger of
+//            (delta sigma_1)^2 and its own floor, orthogonalised against the basis so far and
+//            CholeskyQR2'd; appended to the basis.
+// A level runs only while the basis is below min(rows, cols) and the previous
+// level stopped at its floor rather than at delta sigma_1.  sigma_1^2 is the
+// largest eigenvalue of G (power iteration).
 #include <algorithm>
 #include <cmath>
 

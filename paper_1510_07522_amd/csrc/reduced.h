@@ -1,5 +1,6 @@
 // Small kernels of the reduced problem and the final eigenpairs.
 #pragma once
+#include "bounds.h"
 #include "driver.h"
 
 namespace rsrr {
@@ -15,7 +16,6 @@ int dot_partials(const c128* X, const c128* Y, long len, int batch, int nchunk, 
 //   D[m J + k]  = sum_e X_m[e] BT[e + k kk]                                       (k < J)
 // Deterministic (fixed summation orders).  Dpart: moments_wind_parts(kk, cnt,
 // J) elements of work space.  Returns ST_EINVAL unless P <= 8 and J <= 4.
-long moments_wind_parts(long kk, int cnt, int J);
 int moments_wind(const c128* X, long kk, int cnt, const c128* cw, int P, const c128* BT, int J,
                  c128* A, bool accumulate, c128* Dpart, c128* D, hipStream_t s);
 int gather_scale_cols(const c128* in, long ldi, const int* perm, const double* scale, int rows,

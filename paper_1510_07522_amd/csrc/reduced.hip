@@ -177,7 +177,7 @@ __global__ __launch_bounds__(256) void sum_parts_kernel(const c128* Dpart, int n
   if (threadIdx.x == 0) D[o] = mk<double>(re_[0], im_[0]);
 }
 
-long moments_wind_parts(long kk, int cnt, int J) { return cdivl(kk, MWB) * (long)cnt * J; }
+static_assert(MWB == MOMENTS_BLOCK, "moments block of the workspace arithmetic");
 
 template <int P, int JJ>
 static int launch_mw(const c128* X, long kk, int cnt, const c128* cw, const c128* BT, c128* A, bool accumulate,

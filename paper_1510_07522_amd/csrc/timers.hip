@@ -14,6 +14,7 @@ struct Rec { hipEvent_t a, b; double flops, bytes; std::string sym; };
 struct Acc { long launches = 0; double ms = 0, flops = 0, bytes = 0; };
 std::mutex g_mu;
 bool g_on = false;
+std::string g_only;   // when set, only launches of this kernel function are timed
 std::map<std::string, std::vector<Rec>> g_pending;
 std::map<std::string, Acc> g_acc;
 std::vector<hipEvent_t> g_pool;
@@ -58,6 +59,7 @@ KernelTimer::KernelTimer(const char* n, hipStream_t st, double fl, double by, st
     : name(n), s(st), flops(fl), bytes(by), sym(std::move(symbol)) {
   if (!g_on) return;
   std::lock_guard<std::mutex> lk(g_mu);
+  if (!g_only.empty() && sym != g_only) return;
   a = take();
   if (a) (void)hipEventRecord(a, s);
 }
@@ -79,6 +81,11 @@ extern "C" {
 void rsrr_timers_enable(int on) {
   std::lock_guard<std::mutex> lk(g_mu);
   g_on = on != 0;
+}
+
+void rsrr_timers_only(const char* sym) {
+  std::lock_guard<std::mutex> lk(g_mu);
+  g_only = sym ? sym : "";
 }
 
 void rsrr_timers_reset(void) {

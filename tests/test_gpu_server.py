@@ -174,3 +174,24 @@ def test_server_uneven_qep_batch_matches_oracle(P):
         assert out["info"]["n_wind"] == ref["n_wind"]
         assert match_sets(out["lam"], ref["lam"]) <= 1e-9 * 14.0
         assert np.all(out["res"] <= 1e-10)
+
+
+def test_bounded_wait_times_out_then_returns_the_result(P):
+    # a wait shorter than the solve ends with RSRR_ETIMEDOUT and the slot /
+    # queue state; the ticket stays valid and a later wait returns the result
+    from paper_1510_07522_amd._binding import ETIMEDOUT
+    p, c, N, L, U = ni.config_small_delay(n=256, seed=29)
+    alone = solve_alone(P, p, c, dict(N=48, L=16, precision="c64_ir"), ni.probing_matrix(256, 16, seed=30))
+    h = P.Problem(p)
+    srv = P.Server(64 << 30, 2)
+    try:
+        t = srv.submit(h, ct(P, c), P.default_params(N=48, L=16, precision="c64_ir"),
+                       ni.probing_matrix(256, 16, seed=30))
+        with pytest.raises(P.RsrrError) as e:
+            srv.wait(t, timeout_s=1e-4)
+        assert e.value.code == ETIMEDOUT and "slot 0" in str(e.value)
+        out, lat = srv.wait(t, timeout_s=120.0)
+    finally:
+        srv.close()
+        h.close()
+    assert same_result(out, alone)

@@ -607,3 +607,53 @@ def test_bem_sphere_eigenvalues_approach_dirichlet_ball_eigenvalues():
     for d in (d0, d1, im0):
         ratios = np.array(d[1:]) / np.array(d[:-1])
         assert np.all((ratios > 0.4) & (ratios < 0.85)), (d, ratios)
+
+
+# ------------------------------------------- caller-supplied scalar functions
+def test_callable_spec_equals_menu_spec():
+    # the delay problem with its three scalar functions given as Python
+    # callables returns the same eigenvalues as with the menu specs
+    p = ni.delay_dense(24, seed=31)
+    calls = [("callable", lambda z: (-z, -np.ones_like(z))),
+             ("callable", lambda z: (np.ones_like(z), np.zeros_like(z))),
+             ("callable", lambda z: (np.exp(-z), -np.exp(-z)))]
+    q = ni.CoeffProblem(n=p.n, kinds=p.kinds, mats=p.mats, fspecs=calls)
+    c = ni.Contour(0.0, 1.5, 1.5)
+    U = ni.probing_matrix(24, 6, seed=32)
+    a = R.rsrr(p, c, 24, 6, U, NS=256)
+    b = R.rsrr(q, c, 24, 6, U, NS=256)
+    assert len(a["lam"]) == len(b["lam"]) > 0 and a["n_wind"] == b["n_wind"]
+    assert np.max(np.abs(a["lam"] - b["lam"])) < 1e-13
+
+
+def test_rsrr_sqrt_coefficient_matches_newton_on_determinant():
+    # T(z) = -zI + A0 + sqrt(z + 4) A1 (not in the pow/exp/rat menu): the
+    # eigenvalues inside |z| < 1.5 by Newton on det T from a grid of starts,
+    # and their count by the argument principle
+    p = ni.sqrt_coupled(5, seed=33)
+    c = ni.Contour(0.0, 1.5, 1.5)
+    U = ni.probing_matrix(5, 3, seed=34)
+    out = R.rsrr(p, c, 24, 3, U, NS=512, K=4)
+    roots = []
+    for x0 in np.linspace(-1.4, 1.4, 13):
+        for y0 in np.linspace(-1.4, 1.4, 13):
+            z = complex(x0, y0)
+            for _ in range(60):
+                T = R.T_matrix(p, z)
+                try:
+                    step = 1.0 / np.trace(np.linalg.solve(T, R.dT_matrix(p, z)))
+                except np.linalg.LinAlgError:
+                    break
+                z -= step
+                if abs(step) < 1e-15 * max(1.0, abs(z)):
+                    break
+            if abs(z) < 1.5 and abs(step) < 1e-12 and not any(abs(z - r) < 1e-8 for r in roots):
+                roots.append(z)
+    roots = np.array(roots)
+    assert len(roots) > 0 and contour_margin(c, roots) > 1e-3
+    assert len(out["lam"]) == len(roots) == round(argument_principle_count(p, c, 2000))
+    assert match_sets(out["lam"], roots) < 1e-11
+    # the same functions without derivatives: same eigenvalues, no winding count
+    q = ni.sqrt_coupled(5, seed=33, derivatives=False)
+    out2 = R.rsrr(q, c, 24, 3, U, NS=512, K=4)
+    assert out2["n_wind"] == -1 and match_sets(out2["lam"], roots) < 1e-11
