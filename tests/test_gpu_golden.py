@@ -1,0 +1,90 @@
+"""The benchmark workloads at their full sizes against the oracle's own
+results, written by tests/golden/make_oracle_golden.py (oracle only): the
+delay problem (n = 2048, N = 48, L = 48), the BEM sphere (n = 8192, N = 40,
+L = 64) and two instances of the batched QEPs (n = 723 and 1183, N = 64,
+L = 32), in complex128 and in complex64 with fp64 refinement.
+
+Compared: the returned count (eigenvalues strictly inside with residual
+<= 1e-10) exactly, the eigenvalue sets element by element after an optimal
+matching (|dl| <= 1e-9 max(|l|, rho), the reading of a relative error near
+zero), every returned residual, and the basis dimension k_S within 2 of the
+oracle's SVD rank."""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import nep_inputs as ni
+
+pytestmark = pytest.mark.gpu
+GOLD = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+
+@pytest.fixture(scope="module")
+def P():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a ROCm device"
+    import paper_1510_07522_amd as P
+    P.load()
+    return P
+
+
+def _workload(name):
+    if name == "c1":
+        return ni.config_c1()
+    if name == "c3":
+        return ni.config_c3()
+    if name.startswith("c2_"):
+        n = int(name[3:])
+        return [i for i in ni.config_c2() if i[0].n == n][0]
+    raise KeyError(name)
+
+
+def _golden(name):
+    g = json.load(open(os.path.join(GOLD, f"oracle_{name}.json")))
+    cand = np.array([complex(c[0], c[1]) for c in g["candidates"]])
+    res = np.array([c[2] for c in g["candidates"]])
+    return g, cand, res
+
+
+def _matched_relative_errors(a, b, rho):
+    """|a_i - b_j| / max(|b_j|, rho) over an optimal one-to-one matching."""
+    from scipy.optimize import linear_sum_assignment
+    if len(b) == 0:
+        return np.zeros(0)
+    cost = np.abs(a[:, None] - b[None, :])
+    r, c = linear_sum_assignment(cost)
+    return cost[r, c] / np.maximum(np.abs(b[c]), rho)
+
+
+def _check(P, name, precision):
+    g, cand, res = _golden(name)
+    p, c, N, L, U = _workload(name)
+    assert (p.n, N, L) == (g["n"], g["N"], g["L"])
+    h = P.Problem(p)
+    try:
+        out = h.solve(P.contour(c.center, c.a, c.b), P.default_params(N=N, L=L, precision=precision),
+                      P.to_device(U))
+    finally:
+        h.close()
+    info, lam = out["info"], out["lam"]
+    ref = cand[res <= g["tol_res"]]
+    rho = max(c.a, c.b)
+    print(f"{name} {precision}: k_S {info['k_S']} (oracle {g['k_S']}), m {info['m']} ({g['m']}), "
+          f"n_wind {info['n_wind']} ({g['n_wind']}), candidates {info['n_candidates']} ({g['n_candidates']}), "
+          f"count {info['n_eig']} ({g['count']})")
+    return g, info, lam, out["res"], ref, rho
+
+
+@pytest.mark.parametrize("precision", ["c128", "c64_ir"])
+@pytest.mark.parametrize("name", ["c2_723", "c1", "c3"])
+def test_full_size_matches_oracle(P, name, precision):
+    g, info, lam, res, ref, rho = _check(P, name, precision)
+    assert abs(info["k_S"] - g["k_S"]) <= 2
+    assert info["n_wind"] == g["n_wind"]
+    assert len(lam) == len(ref) == g["count"]
+    err = _matched_relative_errors(lam, ref, rho)
+    print("max relative |dl|", err.max() if len(err) else 0.0)
+    assert np.all(err <= 1e-9)
+    assert np.all(res <= 1e-10)
