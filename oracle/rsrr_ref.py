@@ -15,7 +15,8 @@ method for large-scale nonlinear eigenvalue problems", arXiv 1510.07522):
     Step 2  Y_i = T(z_i)^{-1} U                                     sample_resolvent
     Step 3  S_hat = [Y_0 ... Y_{N-1}] (eq. eq-hatS), truncated SVD  truncated_basis
     Step 4  T_S(z) = S^H T(z) S (eq. eq-Ts-NEP, eq-Zs-expr)         project_coefficients
-            (BEM: Chebyshev interpolation, eq. eq-Ts-coefs)         chebyshev_projection
+            (BEM: Chebyshev interpolation, eq. eq-Ts-coefs,         chebyshev_projection
+             or the interpolant on a circle, R14)                   circle_projection
             reduced NEP by Alg. 1                                   solve_reduced
     Step 5  v = S g                                                 rsrr
   Alg. 1 (modified block Sakurai-Sugiura)
@@ -51,6 +52,10 @@ design notes with its reason):
       nodes are always split that way.  Moments and the winding number use
       the quadrature weights dz/(2 pi i) and rho = max(a, b) as for the
       ellipse.
+  R14 matrices without a coefficient form (BEM) are interpolated in z
+      (Sec. 6.2): on the Chebyshev points of [center - a, center + a] when
+      the contour hugs that interval (b <= a/4), otherwise on d+1 equispaced
+      points of a circle around the contour, in the basis ((z-center)/R)^j.
   R13 the moment scheme (SSRR, Sec. 3.1-3.2) uses the shifted and scaled
       monomials s^alpha, s = (z - gamma)/rho, as the paper's own moment
       formula eq. eq-Ap-num does; over alpha < K' they span the same
@@ -348,6 +353,49 @@ def reduced_from_coefficients(prob: CoeffProblem, S: np.ndarray) -> ReducedNEP:
     return ReducedNEP(B, scal)
 
 
+def circle_projection(prob, S: np.ndarray, center: complex, R: float, d: int):
+    """P_hat_j, j = 0..d, of the interpolant T_S(z) ~ sum_j P_hat_j s^j,
+    s = (z - center)/R, through the d+1 equispaced points z_k = center +
+    R w^k, w = exp(2 pi i/(d+1)) (R14): P_hat_j = (1/(d+1)) sum_k w^(-jk)
+    S^H T(z_k) S, the discrete Fourier transform of the samples."""
+    nd = d + 1
+    SH = S.conj().T
+    zk = center + R * np.exp(2j * math.pi * np.arange(nd) / nd)
+    proj = [SH @ T_matrix(prob, z) @ S for z in zk]
+    P = []
+    for j in range(nd):
+        P.append(sum(np.exp(-2j * math.pi * j * k / nd) * proj[k] for k in range(nd)) / nd)
+    return P
+
+
+def reduced_from_circle(prob, S, center: complex, R: float, d: int) -> ReducedNEP:
+    P = circle_projection(prob, S, center, R, d)
+
+    def scal(z):
+        s = (z - center) / R
+        g = s ** np.arange(d + 1)
+        dg = np.zeros(d + 1, np.complex128)
+        dg[1:] = np.arange(1, d + 1) * s ** np.arange(d) / R
+        return g.astype(np.complex128), dg
+    return ReducedNEP(P, scal)
+
+
+def interpolation_kind(c: Contour, interp: str = "auto") -> str:
+    """R14: the Chebyshev interpolant on [center - a, center + a] (the paper's)
+    for contours that hug that interval (b <= a/4); otherwise the interpolant
+    through equispaced points of a circle around the contour (radius max(a, b)
+    for an ellipse, sqrt(a^2 + b^2) for a rectangle).  A Chebyshev series
+    evaluated a distance of order a off its interval multiplies the rounding
+    of its high coefficients by |tau_j| ~ (1 + sqrt 2)^j."""
+    if interp != "auto":
+        return interp
+    return "chebyshev" if c.b <= 0.25 * c.a else "circle"
+
+
+def circle_radius(c: Contour) -> float:
+    return math.hypot(c.a, c.b) if c.kind == "rect" else max(c.a, c.b)
+
+
 def reduced_from_chebyshev(prob, S, center: float, a: float, d: int) -> ReducedNEP:
     P = chebyshev_projection(prob, S, center, a, d)
 
@@ -463,7 +511,8 @@ def solve_reduced(red: ReducedNEP, c: Contour, NS: int, K: int,
 def rsrr(prob, c: Contour, N: int, L: int, U: np.ndarray, NS: int = 512,
          K: int = 2, delta: float = 1e-14, tol_gap: float = 1e3,
          tol_res: float = 1e-10, hankel_tol: float = 1e-13,
-         cheb_degree: int = 40, scheme: str = "sampling", Kp: int = 0) -> Dict:
+         cheb_degree: int = 40, scheme: str = "sampling", Kp: int = 0,
+         interp: str = "auto") -> Dict:
     """Alg. 2 end to end.  Returns eigenvalues strictly inside the contour with
     residual <= tol_res, sorted by (Re, Im), their eigenvectors and residuals,
     plus every intermediate the GPU path is compared against.  scheme
@@ -480,7 +529,10 @@ def rsrr(prob, c: Contour, N: int, L: int, U: np.ndarray, NS: int = 512,
         assert scheme == "sampling"
         S, sig_S, kS = truncated_basis(S_hat, delta)
     if isinstance(prob, BemProblem):
-        red = reduced_from_chebyshev(prob, S, float(np.real(c.center)), c.a, cheb_degree)
+        if interpolation_kind(c, interp) == "chebyshev":
+            red = reduced_from_chebyshev(prob, S, float(np.real(c.center)), c.a, cheb_degree)
+        else:
+            red = reduced_from_circle(prob, S, complex(c.center), circle_radius(c), cheb_degree)
     else:
         red = reduced_from_coefficients(prob, S)
     out = solve_reduced(red, c, NS, K, tol_gap, hankel_tol)

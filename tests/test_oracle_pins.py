@@ -657,3 +657,39 @@ def test_rsrr_sqrt_coefficient_matches_newton_on_determinant():
     q = ni.sqrt_coupled(5, seed=33, derivatives=False)
     out2 = R.rsrr(q, c, 24, 3, U, NS=512, K=4)
     assert out2["n_wind"] == -1 and match_sets(out2["lam"], roots) < 1e-11
+
+
+# ---------------------------- interpolation of T on a circle (reading R14)
+def test_circle_interpolant_reproduces_polynomials_exactly():
+    # a quadratic T(z) projected on a random orthonormal S: the degree-5
+    # interpolant through six points of a circle equals S^H T(z) S (to
+    # rounding inside and on the circle; outside, the rounding of the
+    # vanishing high coefficients grows like |s|^5)
+    p = ni.qep_dense(30, 50.0, seed=51)
+    rng = np.random.default_rng(52)
+    S, _ = np.linalg.qr(rng.standard_normal((30, 7)) + 1j * rng.standard_normal((30, 7)))
+    red = R.reduced_from_circle(p, S, 1.0 + 2.0j, 0.7, 5)
+    for z, tol in ((1.2 + 2.3j, 1e-13), (0.6 + 2.0j, 1e-13), (1.0 + 2.7j, 1e-13), (3.0 - 1.0j, 1e-10)):
+        exact = S.conj().T @ R.T_matrix(p, z) @ S
+        assert np.linalg.norm(red.T(z) - exact) <= tol * np.linalg.norm(exact), z
+        dexact = S.conj().T @ R.dT_matrix(p, z) @ S
+        assert np.linalg.norm(red.dT(z) - dexact) <= 10 * tol * np.linalg.norm(dexact), z
+
+
+def test_bem_circle_contour_counts_the_determinant_zeros():
+    # a circle around part of the real axis (not a thin ellipse): the
+    # interpolant on a circle finds the one eigenvalue the argument principle
+    # counts on the exact T; the Chebyshev series on [2.65, 3.85], evaluated up
+    # to 0.6 off the interval, amplifies its rounding and returns spurious
+    # zeros instead
+    p = ni.bem_sphere(512)
+    c = ni.Contour(3.25, 0.6, 0.6)
+    assert R.interpolation_kind(c) == "circle"
+    count = argument_principle_count(p, c, M=1500)
+    assert abs(count - 1.0) < 1e-2
+    U = ni.probing_matrix(512, 16, seed=9)
+    out = R.rsrr(p, c, 40, 16, U, NS=256, K=2, cheb_degree=40)
+    assert out["n_wind"] == 1 and len(out["lam"]) == 1
+    assert np.all(out["res"] <= 1e-10)
+    bad = R.rsrr(p, c, 40, 16, U, NS=256, K=2, cheb_degree=40, interp="chebyshev")
+    assert bad["n_wind"] > 100 and len(bad["lam"]) == 0
