@@ -117,6 +117,19 @@ typedef struct {
 
 enum { RSRR_PREC_C128 = 0, RSRR_PREC_C64_IR = 1 };
 
+/* How a matrix without a coefficient form (BEM) is interpolated in z for the
+ * reduced problem (Sec. 6.2): RSRR_INTERP_CHEB, the Chebyshev interpolant on
+ * [Re(center) - a, Re(center) + a] (eq. eq-T-interp, eq. eq-Ts-coefs), fit for
+ * contours that hug that interval; RSRR_INTERP_CIRCLE, the interpolant through
+ * d+1 equispaced points of the circle of radius R around the center (R =
+ * max(a, b) for an ellipse, sqrt(a^2 + b^2) for a rectangle), in the basis
+ * ((z - center)/R)^j, whose coefficients are the discrete Fourier transform
+ * of the samples; RSRR_INTERP_AUTO (default) takes the Chebyshev interpolant
+ * when b <= a/4 and the circle otherwise (a Chebyshev series evaluated at a
+ * distance of order a off its interval amplifies the rounding of its high
+ * coefficients like (1 + sqrt 2)^j). */
+enum { RSRR_INTERP_AUTO = 0, RSRR_INTERP_CHEB = 1, RSRR_INTERP_CIRCLE = 2 };
+
 /* How Alg. 2 Step 3 builds its subspace: from the sampling matrix S_hat
  * (eq. eq-hatS, the resolvent sampling scheme; default) or from the moment
  * matrix M_hat = S_hat D Z (eq. eq-hatMS, the moment scheme of SSRR,
@@ -137,13 +150,14 @@ typedef struct {
   int precision;      /* RSRR_PREC_C128 or RSRR_PREC_C64_IR (default) */
   int ir_max_iter;    /* refinement sweeps before the complex128 fallback, default 5 */
   double ir_tol;      /* refinement acceptance: normwise backward error, default 1e-14 */
-  int cheb_degree;    /* BEM only: Chebyshev degree d (eq. eq-T-interp), default 40 */
+  int cheb_degree;    /* BEM only: interpolation degree d (eq. eq-T-interp), default 40 */
   int nb;             /* LU panel width (1..64), default 64 */
   uint64_t seed;      /* seed of the probing matrix when U is not supplied */
   int scheme;         /* RSRR_SCHEME_SAMPLING (default) or RSRR_SCHEME_MOMENT */
   int Kp;             /* moment scheme: number of moments K' (0 = N, as in the paper's comparisons) */
   double chunk_gib;   /* device memory for one batch of T_S(zeta_m) and their inverses in the
                          reduced moments (and of BEM Chebyshev samples), GiB; default 24 */
+  int interp;         /* BEM only: RSRR_INTERP_*, default RSRR_INTERP_AUTO */
 } rsrr_params;
 
 /* Diagnostics of one solve. */
@@ -227,8 +241,9 @@ int rsrr_orthonormalize(int rows, int cols, const rsrr_complex* S, int lds, doub
 /* Alg. 2 Step 4, projection (eq. eq-Zs-expr): B_k = Q^H A_k Q for every
  * coefficient, written to B (device) as J blocks of k_S x k_S (leading dim
  * k_S, block stride k_S*k_S).  For a BEM problem the J = d+1 blocks are the
- * Chebyshev coefficients P_hat_j (eq. eq-Ts-coefs) on [Re(center) - a,
- * Re(center) + a] and *J_out = d+1.  Q: device, n x k_S, leading dim ldq. */
+ * coefficients P_hat_j of the interpolant prm->interp selects: Chebyshev on
+ * [Re(center) - a, Re(center) + a] (eq. eq-Ts-coefs) or the circle basis
+ * ((z - center)/R)^j; *J_out = d+1.  Q: device, n x k_S, leading dim ldq. */
 int rsrr_project(rsrr_problem* p, const rsrr_contour* c, const rsrr_params* prm,
                  const rsrr_complex* Q, int ldq, int k_S, rsrr_complex* B, int* J_out);
 

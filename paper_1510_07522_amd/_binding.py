@@ -43,7 +43,8 @@ class params_t(C.Structure):
                 ("delta", C.c_double), ("tol_gap", C.c_double), ("tol_res", C.c_double),
                 ("hankel_tol", C.c_double), ("precision", C.c_int), ("ir_max_iter", C.c_int),
                 ("ir_tol", C.c_double), ("cheb_degree", C.c_int), ("nb", C.c_int),
-                ("seed", C.c_uint64), ("scheme", C.c_int), ("Kp", C.c_int), ("chunk_gib", C.c_double)]
+                ("seed", C.c_uint64), ("scheme", C.c_int), ("Kp", C.c_int), ("chunk_gib", C.c_double),
+                ("interp", C.c_int)]
 
 
 class info_t(C.Structure):
@@ -60,6 +61,7 @@ class info_t(C.Structure):
 
 PREC_C128, PREC_C64_IR = 0, 1
 SCHEME = {"sampling": 0, "moment": 1}
+INTERP = {"auto": 0, "chebyshev": 1, "circle": 2}
 MAT_KIND = {"identity": 0, "diag": 1, "real": 2, "dense": 3}
 FN_KIND = {"pow": 0, "exp": 1, "rat": 2}
 WARN_RANK_SATURATED, WARN_COUNT_MISMATCH, WARN_IR_FALLBACK = 1, 2, 4
@@ -190,6 +192,8 @@ def default_params(**kw) -> params_t:
             v = {"c128": PREC_C128, "c64_ir": PREC_C64_IR}[v]
         if k == "scheme" and isinstance(v, str):
             v = SCHEME[v]
+        if k == "interp" and isinstance(v, str):
+            v = INTERP[v]
         setattr(p, k, v)
     return p
 

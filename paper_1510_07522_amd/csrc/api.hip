@@ -221,6 +221,13 @@ void contour_nodes(const rsrr_contour* c, int N, bool sampling, std::vector<cd>*
   }
 }
 
+bool bem_circle_interp(const rsrr_contour* c, const rsrr_params* prm, double* R) {
+  *R = c->kind == RSRR_CONTOUR_RECT ? std::hypot(c->a, c->b) : std::max(c->a, c->b);
+  if (prm->interp == RSRR_INTERP_CHEB) return false;
+  if (prm->interp == RSRR_INTERP_CIRCLE) return true;
+  return c->b > 0.25 * c->a;
+}
+
 bool contour_inside(const rsrr_contour* c, cd lam) {
   const double xr = (lam.real() - c->center.re) / c->a, xi = (lam.imag() - c->center.im) / c->b;
   if (c->kind == RSRR_CONTOUR_RECT) return fabs(xr) < 1.0 && fabs(xi) < 1.0;
@@ -250,6 +257,8 @@ int check_params(const rsrr_problem* p, const rsrr_contour* c, const rsrr_params
     return set_error(ST_EINVAL, "unknown scheme %d", prm->scheme);
   if (!(prm->chunk_gib >= 0.0625) || prm->chunk_gib > 256.0)
     return set_error(ST_EINVAL, "chunk_gib=%g outside [1/16, 256]", prm->chunk_gib);
+  if (prm->interp < RSRR_INTERP_AUTO || prm->interp > RSRR_INTERP_CIRCLE)
+    return set_error(ST_EINVAL, "unknown interpolation %d", prm->interp);
   if (prm->Kp < 0 || (long)prm->Kp * prm->L > (1L << 20))
     return set_error(ST_EINVAL, "Kp=%d outside [0, 2^20/L]", prm->Kp);
   return ST_OK;

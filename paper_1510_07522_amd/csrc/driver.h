@@ -99,6 +99,10 @@ bool rect_split(const rsrr_contour* c, int N, bool sampling, int* nh, int* nv);
 // sum_j dz[j] g(z[j]).  Sampling nodes when `sampling` (rectangles then use
 // the contour's own per-side counts), moment nodes otherwise.
 void contour_nodes(const rsrr_contour* c, int N, bool sampling, std::vector<cd>* z, std::vector<cd>* dz);
+// Interpolation of a BEM matrix for the reduced problem: true for the circle
+// basis ((z - center)/R)^j (radius in *R), false for the Chebyshev
+// interpolant on [Re(center) - a, Re(center) + a].
+bool bem_circle_interp(const rsrr_contour* c, const rsrr_params* prm, double* R);
 // lambda strictly inside the contour.
 bool contour_inside(const rsrr_contour* c, cd lam);
 double now_s();

@@ -1,8 +1,13 @@
 // Alg. 2, Step 4 (first half): the reduced coefficients.
 //   coefficient form (eq. eq-Zs-expr): B_k = Q^H A_k Q
-//   BEM (eq. eq-Ts-coefs): P_j = w_j sum_k cos(j theta_k) Q^H T(x_k) Q at the
-//   d+1 first-kind Chebyshev points x_k of [c - a, c + a], with w_0 = 1/(d+1)
-//   and w_j = 2/(d+1) (the standard interpolant).
+//   BEM, Chebyshev (eq. eq-Ts-coefs): P_j = w_j sum_k cos(j theta_k) Q^H T(x_k) Q
+//   at the d+1 first-kind Chebyshev points x_k of [c - a, c + a], with
+//   w_0 = 1/(d+1) and w_j = 2/(d+1) (the standard interpolant);
+//   BEM, circle: P_j = (1/(d+1)) sum_k w^(-jk) Q^H T(z_k) Q at the points
+//   z_k = c + R w^k, w = exp(2 pi i/(d+1)), for the basis ((z - c)/R)^j.
+// Either way the samples Q^H T(x_k) Q are formed first (T generated on the
+// fly, in batches that fit chunk_gib) and combined by one product with the
+// (d+1) x (d+1) weight matrix.
 #include <algorithm>
 #include <cmath>
 
@@ -52,15 +57,22 @@ int project_impl(rsrr_problem* p, const rsrr_contour* c, const rsrr_params* prm,
     RSRR_HIP(hipStreamSynchronize(s));
     return ST_OK;
   }
-  // ---- Chebyshev interpolation of the BEM matrix on [c - a, c + a]
+  // ---- interpolation of the BEM matrix: Chebyshev on [c - a, c + a] or a circle
   const int d = prm->cheb_degree > 0 ? prm->cheb_degree : 40;
   const int nd = d + 1;
   const double cx = c->center.re, a = c->a;
+  double Rc = 0;
+  const bool circle = bem_circle_interp(c, prm, &Rc);
   std::vector<double> theta(nd);
   std::vector<c128> xk(nd);
   for (int k = 0; k < nd; ++k) {
-    theta[k] = (k + 0.5) * M_PI / nd;
-    xk[k] = mk<double>(cx + a * cos(theta[k]), 0.0);
+    if (circle) {
+      theta[k] = 2.0 * M_PI * k / nd;
+      xk[k] = mk<double>(c->center.re + Rc * cos(theta[k]), c->center.im + Rc * sin(theta[k]));
+    } else {
+      theta[k] = (k + 0.5) * M_PI / nd;
+      xk[k] = mk<double>(cx + a * cos(theta[k]), 0.0);
+    }
   }
   const size_t per = (size_t)n * n * sizeof(c128);
   const int ch = (int)std::max<size_t>(1, std::min<size_t>(nd, (size_t)(prm->chunk_gib * 1073741824.0) / per));
@@ -79,11 +91,13 @@ int project_impl(rsrr_problem* p, const rsrr_contour* c, const rsrr_params* prm,
     RSRR_TRY(zgemm(OP_C, OP_N, kS, kS, n, one, Q, ldq, 0, W, n, (long)n * kS, zero, Mk + k0 * kk, kS,
                    kk, cnt, false, s));
   }
-  // P (kk x nd) = M (kk x nd) C,  C[k][j] = w_j cos(j theta_k)
+  // P (kk x nd) = M (kk x nd) C,  C[k][j] = w_j cos(j theta_k) (Chebyshev) or
+  // exp(-i j theta_k)/(d+1) (circle)
   std::vector<c128> Ch((size_t)nd * nd);
   for (int j = 0; j < nd; ++j)
     for (int k = 0; k < nd; ++k)
-      Ch[k + (size_t)j * nd] = mk<double>((j == 0 ? 1.0 : 2.0) / nd * cos(j * theta[k]), 0.0);
+      Ch[k + (size_t)j * nd] = circle ? mk<double>(cos(j * theta[k]) / nd, -sin(j * theta[k]) / nd)
+                                      : mk<double>((j == 0 ? 1.0 : 2.0) / nd * cos(j * theta[k]), 0.0);
   RSRR_HIP(hipMemcpyAsync(Cw, Ch.data(), Ch.size() * sizeof(c128), hipMemcpyHostToDevice, s));
   RSRR_TRY(zgemm(OP_N, OP_N, (int)kk, nd, nd, one, Mk, kk, 0, Cw, nd, 0, zero, B, kk, 0, 1, false, s));
   if (J_out) *J_out = nd;

@@ -61,11 +61,11 @@ static void gaussian_probe(int n, int L, uint64_t seed, std::vector<c128>* U) {
 }
 
 // g_k(z_q), g_k'(z_q) of the reduced problem at m nodes (row q holds J values):
-// the f_k themselves, or the Chebyshev polynomials tau_j((z - c)/a) for the
-// BEM interpolant.  Returns 1 (g filled, dg zero) when the caller's scalar
-// functions come without derivatives.
-static int reduced_scalars(const rsrr_problem* p, int J, double cx, double a, const cd* z, size_t m,
-                           std::vector<cd>* g, std::vector<cd>* dg) {
+// the f_k themselves, or for the BEM interpolant the Chebyshev polynomials
+// tau_j((z - c)/a) or the powers ((z - c)/R)^j.  Returns 1 (g filled, dg
+// zero) when the caller's scalar functions come without derivatives.
+static int reduced_scalars(const rsrr_problem* p, int J, const rsrr_contour* c, const rsrr_params* prm,
+                           const cd* z, size_t m, std::vector<cd>* g, std::vector<cd>* dg) {
   g->assign(m * J, cd(0, 0));
   dg->assign(m * J, cd(0, 0));
   if (!p->bem) {
@@ -73,6 +73,22 @@ static int reduced_scalars(const rsrr_problem* p, int J, double cx, double a, co
     if (st == 1) dg->assign(m * J, cd(0, 0));
     return st;
   }
+  double Rc = 0;
+  if (bem_circle_interp(c, prm, &Rc)) {
+    const cd ctr(c->center.re, c->center.im);
+    for (size_t q = 0; q < m; ++q) {
+      cd* gq = g->data() + q * J;
+      cd* dq = dg->data() + q * J;
+      const cd sq = (z[q] - ctr) / Rc;
+      gq[0] = 1.0;
+      for (int j = 1; j < J; ++j) {
+        gq[j] = gq[j - 1] * sq;
+        dq[j] = (double)j * gq[j - 1] / Rc;
+      }
+    }
+    return ST_OK;
+  }
+  const double cx = c->center.re, a = c->a;
   for (size_t q = 0; q < m; ++q) {
     cd* gq = g->data() + q * J;
     cd* dq = dg->data() + q * J;
@@ -168,7 +184,6 @@ int solve_impl(rsrr_problem* p, const rsrr_contour* c, const rsrr_params* prm, c
   t0 = now_s();
   std::vector<cd> zeta, dzeta;
   contour_nodes(c, NS, false, &zeta, &dzeta);
-  const double cx = c->center.re, ax = c->a;
   const size_t per = (size_t)kk * sizeof(c128) * 2;
   // nodes per batch: as many as the chunk memory holds, balanced over the batches
   const int ch = chunk_count(NS, per, prm->chunk_gib).second;
@@ -196,7 +211,7 @@ int solve_impl(rsrr_problem* p, const rsrr_contour* c, const rsrr_params* prm, c
   RSRR_TRY(ws.get<int>("rd_info", ch, &linfo));
   cd wind(0, 0);
   std::vector<cd> g, dg;
-  const int sst = reduced_scalars(p, J, cx, ax, zeta.data(), NS, &g, &dg);
+  const int sst = reduced_scalars(p, J, c, prm, zeta.data(), NS, &g, &dg);
   if (sst < 0) return sst;
   const bool have_wind = sst == ST_OK;
   if (!have_wind) warn |= RSRR_WARN_NO_WINDING;

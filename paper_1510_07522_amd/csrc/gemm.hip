@@ -14,7 +14,9 @@
 // through LDS 16 at a time with one register-prefetched tile in flight.  The
 // LDS tiles are stored [k][m ^ (k & 15)]: a store with k running across lanes
 // (column-major B, or A^T / A^H) then hits 16 different banks instead of one,
-// and the MFMA operand reads stay conflict-free.
+// and the MFMA operand reads stay conflict-free.  The epilogue stages the
+// products through the same LDS bytes so that C is read and written one
+// contiguous column per wave instruction.
 #include "common.h"
 #include "kernels.h"
 #include "timers.h"
@@ -47,10 +49,17 @@ __global__ __launch_bounds__(sizeof(R) == 8 ? 512 : 256) void gemm_kernel(GemmBa
   constexpr int NT = gemm_threads<R>();
   constexpr int WJ = NT == 512 ? 1 : 2;          // 16-column blocks per wave
   constexpr int LP = BM * BK / NT;               // tile elements per thread and operand
-  __shared__ R As_re[BK][BM + PAD];
-  __shared__ R As_im[AREAL ? 1 : BK][BM + PAD];
-  __shared__ R Bs_re[BK][BN + PAD];
-  __shared__ R Bs_im[BK][BN + PAD];
+  // operand tiles during the K loop; the epilogue reuses the same bytes to
+  // stage half of the C tile (32 columns x 64 rows of complex values)
+  constexpr int OPND = (3 * BK + (AREAL ? 1 : BK)) * (BM + PAD) * (int)sizeof(R);
+  constexpr int SLD = BM + 1;                    // staged column stride (odd: fewer bank conflicts)
+  constexpr int STAGE = (BN / 2) * SLD * 2 * (int)sizeof(R);
+  __shared__ __align__(16) unsigned char smem[OPND > STAGE ? OPND : STAGE];
+  typedef R Tile[BM + PAD];
+  Tile* As_re = (Tile*)smem;
+  Tile* Bs_re = As_re + BK;
+  Tile* Bs_im = Bs_re + BK;
+  Tile* As_im = Bs_im + BK;
 
   const int bz = blockIdx.z;
   if (g.active && !g.active[bz]) return;
@@ -176,30 +185,56 @@ __global__ __launch_bounds__(sizeof(R) == 8 ? 512 : 256) void gemm_kernel(GemmBa
   // epilogue.  Accumulator lane layout (column lane%16 of each 16x16 block):
   //   f32 16x16x4: element r holds row 4*(lane/16) + r
   //   f64 16x16x4: element r holds row lane/16 + 4*r
+  // The combined complex products go through LDS, half a tile (32 columns) at
+  // a time, so that the read-modify-write of C runs one column of 64 rows per
+  // wave instruction (contiguous) instead of 16 columns by 4 rows.
   const bool beta0 = (g.beta.re == R(0) && g.beta.im == R(0));
+  R* st_re = (R*)smem;                       // [32 columns][SLD] real parts
+  R* st_im = st_re + (BN / 2) * SLD;         // imaginary parts
 #pragma unroll
-  for (int i = 0; i < 2; ++i)
+  for (int h = 0; h < 2; ++h) {
+    // waves whose columns lie in this half write their values
+    const int wcol0 = wn * 16 * WJ;          // first column of this wave in the tile
+    if (wcol0 / (BN / 2) == h) {
 #pragma unroll
-    for (int j = 0; j < WJ; ++j) {
-      int col = n0 + wn * 16 * WJ + j * 16 + (lane & 15);
-      if (col >= N) continue;
+      for (int i = 0; i < 2; ++i)
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int rr = (sizeof(R) == 8) ? (lane >> 4) + 4 * r : 4 * (lane >> 4) + r;
-        int row = m0 + wm * 32 + i * 16 + rr;
-        if (row >= M) continue;
+        for (int j = 0; j < WJ; ++j) {
+          const int cl = wcol0 - h * (BN / 2) + j * 16 + (lane & 15);
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const int rr = (sizeof(R) == 8) ? (lane >> 4) + 4 * r : 4 * (lane >> 4) + r;
+            const int rl = wm * 32 + i * 16 + rr;
+            R vr, vi;
+            if (AREAL) { vr = acc0[i][j][r]; vi = acc1[i][j][r]; }
+            else if (G3M) {
+              vr = acc0[i][j][r] - acc1[i][j][r];
+              vi = acc2[i][j][r] - acc0[i][j][r] - acc1[i][j][r];
+            } else { vr = acc0[i][j][r]; vi = acc1[i][j][r]; }
+            st_re[cl * SLD + rl] = vr;
+            st_im[cl * SLD + rl] = vi;
+          }
+        }
+    }
+    __syncthreads();
+    // one column of 64 rows per wave instruction
+#pragma unroll
+    for (int e = 0; e < (BN / 2) * BM / NT; ++e) {
+      const int q = e * NT + tid;
+      const int cl = q / BM, rl = q % BM;
+      const int row = m0 + rl, col = n0 + h * (BN / 2) + cl;
+      if (row < M && col < N) {
         cplx<R> v;
-        if (AREAL) { v.re = acc0[i][j][r]; v.im = acc1[i][j][r]; }
-        else if (G3M) {
-          v.re = acc0[i][j][r] - acc1[i][j][r];
-          v.im = acc2[i][j][r] - acc0[i][j][r] - acc1[i][j][r];
-        } else { v.re = acc0[i][j][r]; v.im = acc1[i][j][r]; }
+        v.re = st_re[cl * SLD + rl];
+        v.im = st_im[cl * SLD + rl];
         cplx<R> out = g.alpha * v;
-        long idx = (long)row + (long)col * g.ldc;
+        const long idx = (long)row + (long)col * g.ldc;
         if (!beta0) out = out + g.beta * Cp[idx];
         Cp[idx] = out;
       }
     }
+    __syncthreads();
+  }
 }
 
 template <typename R, int OPA, int OPB, bool AREAL, bool G3M>
