@@ -341,6 +341,22 @@ int rsrr_cgemm_batched(int opA, int opB, int M, int N, int K, rsrr_complex alpha
 int rsrr_gesv_batched(int precision, int n, int nrhs, void* A, int lda, long long sA, void* B,
                       int ldb, long long sB, int batch, int nb, int* info_host, void* stream);
 
+/* rsrr_gesv_batched for callers that cannot allocate device memory (code
+ * under stream capture, tight serving loops, hosts that forbid allocation
+ * calls): the same factorisation and solve kernels, with the pivots, the
+ * diagonal-block inverses and the per-matrix status in a fixed 64 MiB device
+ * array of the library (one per GPU, held until the process ends) instead of
+ * allocations: the call makes no device allocation (no hipMalloc, hipFree or
+ * allocating library call).  Work space needed:
+ * batch * (n * 4 + panels * 2 * nb^2 * element bytes) plus alignment, with
+ * panels = ceil(n / nb) and 16 (complex128) or 8 (complex64) bytes per
+ * element; a call that needs more than 64 MiB fails with RSRR_EINVAL and
+ * touches nothing.  All calls on one GPU share the array: calls that overlap
+ * in time on one GPU (other threads or streams) race and must be serialised
+ * by the caller.  Arguments, results and errors as rsrr_gesv_batched. */
+int rsrr_gesv_batched_noalloc(int precision, int n, int nrhs, void* A, int lda, long long sA, void* B,
+                              int ldb, long long sB, int batch, int nb, int* info_host, void* stream);
+
 /* ------------------------------------------------------------------------
  * Kernel timers: when enabled, the main kernel classes (LU panel, LU trailing
  * update, solves, Gram/Cholesky, Jacobi rounds, QR sweeps, ...) are bracketed

@@ -102,6 +102,7 @@ SIGNATURES = {
     "rsrr_cgemm_batched": (_i, [_i, _i, _i, _i, _i, cplx, _vp, _i, _ll, _vp, _i, _ll, cplx, _vp, _i,
                                 _ll, _i, _i, _vp]),
     "rsrr_gesv_batched": (_i, [_i, _i, _i, _vp, _i, _ll, _vp, _i, _ll, _i, _i, C.POINTER(_i), _vp]),
+    "rsrr_gesv_batched_noalloc": (_i, [_i, _i, _i, _vp, _i, _ll, _vp, _i, _ll, _i, _i, C.POINTER(_i), _vp]),
     "rsrr_timers_enable": (None, [_i]),
     "rsrr_timers_only": (None, [C.c_char_p]),
     "rsrr_timers_reset": (None, []),
@@ -470,11 +471,13 @@ def gemm(opA: str, opB: str, A, B, Cm, M: int, N: int, K: int, alpha=1.0, beta=0
                                         int(gauss3m), stream_ptr()))
 
 
-def gesv(A, B, n: int, nrhs: int, batch: int, nb: int = 64):
-    """Batched LU solve in place (A: batch x n x n, B: batch x n x nrhs, column-major)."""
+def gesv(A, B, n: int, nrhs: int, batch: int, nb: int = 64, noalloc: bool = False):
+    """Batched LU solve in place (A: batch x n x n, B: batch x n x nrhs,
+    column-major); noalloc uses the entry point whose work space is the
+    library's fixed device array."""
     torch = _torch()
     prec = PREC_C128 if A.dtype == torch.complex128 else PREC_C64_IR
     info = (C.c_int * batch)()
-    st = load().rsrr_gesv_batched(prec, n, nrhs, _ptr(A), n, n * n, _ptr(B), n, n * nrhs, batch,
-                                  nb, info, stream_ptr())
+    f = load().rsrr_gesv_batched_noalloc if noalloc else load().rsrr_gesv_batched
+    st = f(prec, n, nrhs, _ptr(A), n, n * n, _ptr(B), n, n * nrhs, batch, nb, info, stream_ptr())
     return st, list(info)
