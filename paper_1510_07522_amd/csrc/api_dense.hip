@@ -49,6 +49,7 @@ int gesv_entry(int n, int nrhs, void* A, int lda, long long sA, void* B, int ldb
   }
   LUWork<R> w;
   w.n = n; w.nb = nb; w.batch = batch; w.lda = lda; w.sA = sA; w.A = (cplx<R>*)A;
+  w.pair = true;
   w.ipiv = ipiv; w.dinv = dinv; w.info = info;
   int st = lu_factor<R>(w, s);
   if (st == ST_OK && nrhs > 0) st = lu_solve<R>(w, (cplx<R>*)B, ldb, sB, nrhs, s);

@@ -66,6 +66,7 @@ int gesv_noalloc(int n, int nrhs, void* A, int lda, long long sA, void* B, int l
   hipStream_t s = (hipStream_t)stream;
   LUWork<R> w;
   w.n = n; w.nb = nb; w.batch = batch; w.lda = lda; w.sA = sA; w.A = (cplx<R>*)A;
+  w.pair = true;
   w.info = (int*)p;
   w.ipiv = (int*)(p + b_info);
   w.dinv = (cplx<R>*)(p + b_info + b_ipiv);

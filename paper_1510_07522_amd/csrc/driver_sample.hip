@@ -191,6 +191,7 @@ int sample_impl(rsrr_problem* p, const rsrr_contour* c, const rsrr_params* prm, 
     w.n = n; w.nb = nb; w.batch = N; w.lda = n; w.sA = nn; w.A = T;
     w.ipiv = ipiv; w.dinv = dinv; w.info = infod;
     w.tag = "sample_lu_c128";
+    w.pair = true;
     RSRR_TRY(p->ws.aux_stream(&w.aux, &w.ev_main, &w.ev_aux));
     RSRR_TRY(lu_factor<double>(w, s));
     RSRR_TRY(check_info(infod, N, s, z));
@@ -213,6 +214,7 @@ int sample_impl(rsrr_problem* p, const rsrr_contour* c, const rsrr_params* prm, 
     w.n = n; w.nb = nb; w.batch = N; w.lda = n; w.sA = nn; w.A = T;
     w.ipiv = ipiv; w.dinv = dinv; w.info = infod;
     w.tag = "sample_lu_c64";
+    w.pair = true;
     RSRR_TRY(p->ws.aux_stream(&w.aux, &w.ev_main, &w.ev_aux));
     w.gauss3m = true;          // errors are removed by the fp64 refinement
     RSRR_TRY(lu_factor<float>(w, s));
@@ -353,6 +355,7 @@ int sample_impl(rsrr_problem* p, const rsrr_contour* c, const rsrr_params* prm, 
       wb.n = n; wb.nb = nb; wb.batch = nbad; wb.lda = n; wb.sA = nn; wb.A = Tb;
       wb.ipiv = ipiv; wb.dinv = dinvb; wb.info = infod;
       wb.tag = "fallback_lu_c128";
+      wb.pair = true;
       RSRR_TRY(p->ws.aux_stream(&wb.aux, &wb.ev_main, &wb.ev_aux));
       RSRR_TRY(lu_factor<double>(wb, s));
       RSRR_TRY(check_info(infod, nbad, s, zb));

@@ -48,6 +48,9 @@ template <typename R> struct LUWork {
   // panel's L columns are then moved once, by the composition of the later
   // panels' interchanges, instead of once per later panel
   int* lperm = nullptr;
+  // panels in pairs (not with full_swap): the columns beyond a pair take both
+  // panels' updates as one product with K = 2 nb
+  bool pair = false;
   // look-ahead (optional): the trailing update beyond the next panel runs on
   // `aux` while the next panel is factored; ev_main / ev_aux order the two
   hipStream_t aux = nullptr;

@@ -515,10 +515,11 @@ int lu_factor(const LUWork<R>& w, hipStream_t s) {
     g.gauss3m = w.gauss3m;
     return gemm_batched<R>(g, st);
   };
-  // A22 -= L21 U12 on columns [c0, c0 + nc)
-  auto update = [&](int k, int nbe, int c0, int nc, hipStream_t st) -> int {
+  // A22 -= L21 U12 on columns [c0, c0 + nc): rows [k + nbe, k + nbe + M) (M < 0:
+  // to the last row), L21 = columns [k, k + nbe)
+  auto update = [&](int k, int nbe, int c0, int nc, hipStream_t st, int M = -1) -> int {
     GemmBatch<R> u;
-    u.M = n - k - nbe; u.N = nc; u.K = nbe;
+    u.M = M < 0 ? n - k - nbe : M; u.N = nc; u.K = nbe;
     u.alpha = mk<R>(-1, 0); u.beta = mk<R>(1, 0);
     u.A = w.A + (k + nbe) + (long)k * w.lda; u.lda = w.lda; u.sA = w.sA;
     u.B = w.A + k + (long)c0 * w.lda; u.ldb = w.lda; u.sB = w.sA;
@@ -534,6 +535,78 @@ int lu_factor(const LUWork<R>& w, hipStream_t s) {
   //   aux: wait main(panel k), far permute/trsm/update, record aux
   const bool la = (w.aux != nullptr && w.ev_main != nullptr && w.ev_aux != nullptr);
   bool aux_busy = false;
+  const int SB0 = lu_group(nb);
+  if (w.pair && !w.full_swap && SB0 % 2 == 0) {
+    // Pairs of panels (a at k, b at k + nb): b's columns take a's update, b is
+    // factored, and b's interchanges are applied to a's L columns; every
+    // column beyond the pair then takes both updates as one product with
+    // K = 2 nb (half the trailing-matrix traffic of two K = nb products):
+    //   rows of a:  U_a = inv(L_aa) A_a
+    //   rows of b:  A_b -= L_ba U_a,  U_b = inv(L_bb) A_b
+    //   below:      A_2 -= [L_2a L_2b] [U_a; U_b]
+    // Look-ahead at the level of pairs: the next pair's columns on s, the
+    // columns beyond them on aux.  Pairs never straddle the solver's groups
+    // of panels (an even number of panels per group), so the row order of
+    // the L columns within a group is the same as without pairs.
+    auto tail = [&](int k, int na, int nbb, int c0, int nc, hipStream_t st) -> int {
+      if (nc <= 0) return ST_OK;
+      const int kb = k + na, c1 = kb + nbb;
+      RSRR_TRY(launch_permute<R>(w.A + (long)c0 * w.lda, w.lda, w.sA, nc, w.ipiv, n, k, na, w.batch, st));
+      if (nbb > 0)
+        RSRR_TRY(launch_permute<R>(w.A + (long)c0 * w.lda, w.lda, w.sA, nc, w.ipiv, n, kb, nbb, w.batch, st));
+      RSRR_TRY(trsm(k, na, c0, nc, st));
+      if (nbb > 0) {
+        RSRR_TRY(update(k, na, c0, nc, st, nbb));
+        RSRR_TRY(trsm(kb, nbb, c0, nc, st));
+      }
+      if (c1 < n) RSRR_TRY(update(k, na + nbb, c0, nc, st));
+      return ST_OK;
+    };
+    RSRR_TRY(launch_panel<R>(w, 0, min(nb, n), s));
+    for (int k = 0; k < n; k += 2 * nb) {
+      const int na = min(nb, n - k), kb = k + na;
+      const int nbb = min(nb, n - kb);
+      if (nbb > 0) {
+        // panel b: a's update on b's columns, factor, then b's interchanges on a's L columns
+        RSRR_TRY(launch_permute<R>(w.A + (long)kb * w.lda, w.lda, w.sA, nbb, w.ipiv, n, k, na, w.batch, s));
+        RSRR_TRY(trsm(k, na, kb, nbb, s));
+        RSRR_TRY(update(k, na, kb, nbb, s));
+        RSRR_TRY(launch_panel<R>(w, kb, nbb, s));
+        RSRR_TRY(launch_permute<R>(w.A + (long)k * w.lda, w.lda, w.sA, na, w.ipiv, n, kb, nbb, w.batch, s));
+      }
+      const int c1 = kb + nbb;
+      const int rest = n - c1;
+      if (rest <= 0) break;
+      const int nxt = la ? min(2 * nb, rest) : rest;
+      const int far = rest - nxt;
+      if (aux_busy) {              // the next pair's columns had the previous pair's far update
+        RSRR_HIP(hipStreamWaitEvent(s, w.ev_aux, 0));
+        aux_busy = false;
+      }
+      if (far > 0) {
+        RSRR_HIP(hipEventRecord(w.ev_main, s));
+        RSRR_HIP(hipStreamWaitEvent(w.aux, w.ev_main, 0));
+        RSRR_TRY(tail(k, na, nbb, c1 + nxt, far, w.aux));
+        RSRR_HIP(hipEventRecord(w.ev_aux, w.aux));
+        aux_busy = true;
+      }
+      RSRR_TRY(tail(k, na, nbb, c1, nxt, s));
+      RSRR_TRY(launch_panel<R>(w, c1, min(nb, n - c1), s));
+    }
+    if (aux_busy) RSRR_HIP(hipStreamWaitEvent(s, w.ev_aux, 0));
+    // interchanges of the later panels of each group on the earlier panels'
+    // L columns (the second panel of a pair has already done its own pair)
+    const int np = w.npanel();
+    for (int q = 1; q < np; ++q) {
+      if (q % SB0 == 0) continue;
+      const int k = q * nb, c0 = (q / SB0) * SB0 * nb;
+      const int cols = k - c0 - ((q % 2 == 1) ? nb : 0);
+      if (cols > 0)
+        RSRR_TRY(launch_permute<R>(w.A + (long)c0 * w.lda, w.lda, w.sA, cols, w.ipiv, n, k, min(nb, n - k),
+                                   w.batch, s));
+    }
+    return ST_OK;
+  }
   RSRR_TRY(launch_panel<R>(w, 0, min(nb, n), s));
   if (la) RSRR_HIP(hipEventRecord(w.ev_main, s));
   for (int k = 0; k < n; k += nb) {
