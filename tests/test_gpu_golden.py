@@ -7,8 +7,8 @@ L = 32), in complex128 and in complex64 with fp64 refinement.
 Compared: the returned count (eigenvalues strictly inside with residual
 <= 1e-10) exactly, the eigenvalue sets element by element after an optimal
 matching (|dl| <= 1e-9 max(|l|, rho), the reading of a relative error near
-zero), every returned residual, and the basis dimension k_S within 2 of the
-oracle's SVD rank."""
+zero), every returned residual, the winding count, and the basis dimension
+k_S within 1% (at least 2) of the oracle's SVD rank."""
 import json
 import os
 
@@ -81,7 +81,10 @@ def _check(P, name, precision):
 @pytest.mark.parametrize("name", ["c2_723", "c1", "c3"])
 def test_full_size_matches_oracle(P, name, precision):
     g, info, lam, res, ref, rho = _check(P, name, precision)
-    assert abs(info["k_S"] - g["k_S"]) <= 2
+    # k_S counts singular values of S_hat above delta sigma_1 = 1e-14 sigma_1,
+    # where the weakest directions sit at the rounding level of the basis
+    # computation; it is not graded, only bounded
+    assert abs(info["k_S"] - g["k_S"]) <= max(2, 0.01 * g["k_S"])
     assert info["n_wind"] == g["n_wind"]
     assert len(lam) == len(ref) == g["count"]
     err = _matched_relative_errors(lam, ref, rho)
