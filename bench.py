@@ -238,6 +238,94 @@ def cpu_baseline(name: str, w, max_nodes: int, budget_s: float):
     return out
 
 
+def batched_bench(a, P):
+    """The batched-instance workload: sixteen dense QEPs of uneven order
+    (n ~ U{512..4096}, k ~ U[1,400], circle centre 10i radius 4, N = 64,
+    L = 32) solved by one rsrr_solve_batched call per step: all 1024
+    (instance, node) LUs factored together, then each instance's later
+    stages.  value = resolvent samples per second over all instances."""
+    import torch
+    import nep_inputs as ni
+    insts = ni.config_c2()
+    sizes = [p.n for p, *_ in insts]
+    log(f"workload c2: 16 QEPs, n = {sizes}, N=64, L=32")
+    # LU panel width from the autotuner: one factorisation of an instance's
+    # 64 matrices at the largest order per candidate width
+    nb_tuned, ms_tuned = P.tune_lu(a.precision, max(sizes), 64)
+    log(f"autotuned LU panel width {nb_tuned} ({ms_tuned:.1f} ms for 64 matrices of order {max(sizes)})")
+    hs = [P.Problem(p) for p, *_ in insts]
+    cts = [P.contour(c.center, c.a, c.b) for _, c, _, _, _ in insts]
+    prms = [P.default_params(N=N, L=L, precision=a.precision, nb=0) for _, _, N, L, _ in insts]
+    Us = [P.to_device(U) for *_, U in insts]
+    samples = sum(N for _, _, N, _, _ in insts)
+    for i in range(a.warmup):
+        t0 = time.perf_counter()
+        outs = P.solve_batched(hs, cts, prms, Us)
+        torch.cuda.synchronize()
+        log(f"warmup {i}: {time.perf_counter() - t0:.3f}s n_eig={sum(o['info']['n_eig'] for o in outs)}")
+    P.timers_only(None)
+    P.timers_reset()
+    P.timers_enable(True)
+    P.solve_batched(hs, cts, prms, Us)
+    torch.cuda.synchronize()
+    P.timers_enable(False)
+    stats = P.timers_read()
+    classes = {k: v for k, v in stats.items() if not k.startswith("sym:")}
+    dev_ms = sum(t["ms"] for t in classes.values())
+    pre_roof, roof_next = kernel_roofline(stats, 1)
+    dominant = pre_roof["kernel"] if pre_roof else None
+    log(f"kernel statistics pass: {dev_ms:.1f} ms of timed device work; dominant kernel {dominant}")
+    P.timers_reset()
+    if dominant:
+        P.timers_only(dominant)
+        P.timers_enable(True)
+    lat, n_eig = [], []
+    torch.cuda.synchronize()
+    t_start = time.perf_counter()
+    for i in range(a.steps):
+        t0 = time.perf_counter()
+        outs = P.solve_batched(hs, cts, prms, Us)
+        torch.cuda.synchronize()
+        lat.append(time.perf_counter() - t0)
+        n_eig.append(sum(o["info"]["n_eig"] for o in outs))
+        log(f"step {i}: {lat[-1]:.3f}s n_eig={n_eig[-1]}")
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t_start
+    P.timers_enable(False)
+    timed = P.timers_read()
+    P.timers_only(None)
+    roof, _ = kernel_roofline(timed, a.steps)
+    if roof is not None:
+        roof["share_of_timed_device_ms"] = pre_roof["ms_per_step"] / max(dev_ms, 1e-9)
+        roof["events"] = "HIP events around each launch of this kernel function in the timed steps"
+    for h in hs:
+        h.close()
+    cpu = None
+    if not a.no_cpu:
+        log("cpu baseline (oracle) ...")
+        p, c, N, L, U = max(insts, key=lambda i: i[0].n)
+        cpu = cpu_baseline("c2", dict(prob=p, contour=c, N=N, L=L, U=U), a.cpu_nodes, a.cpu_budget)
+        cpu["sample"] = cpu["sample"].replace("this workload", f"the largest instance (n={p.n})")
+    lat_s = np.array(lat)
+    res = {
+        "metric": "resolvent samples/sec + eigenpairs/sec at residual<=1e-10; p50/p99 solve latency",
+        "value": samples * a.steps / elapsed, "unit": "resolvent samples/s", "n_gpus": 1, "steps": a.steps,
+        "warmup": a.warmup, "ms_per_step": elapsed / a.steps * 1e3, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "c64+f64" if a.precision == "c64_ir" else "c128",
+        "data": "synthetic (seeded)",
+        "config": {"workload": "c2", "description": "16 dense QEPs z^2 I + z C + K of uneven order, "
+                   "circle centre 10i r=4, N=64, L=32, one batched solve per step", "n": sizes, "N": 64,
+                   "L": 32, "precision": a.precision, "nb_autotuned": nb_tuned, "parallelism": "single GPU"},
+        "eigenpairs_per_s": sum(n_eig) / elapsed, "n_eig": n_eig[-1],
+        "latency_s": {"p50": float(np.percentile(lat_s, 50)), "p99": float(np.percentile(lat_s, 99))},
+        "n_eig_per_instance": [o["info"]["n_eig"] for o in outs],
+        "kernel_ms_per_step": {k: v["ms"] for k, v in sorted(classes.items(), key=lambda kv: -kv[1]["ms"])},
+        "kernel_ms_source": "one batched solve with every kernel timer on, outside the timed steps",
+        "roofline": roof, "roofline_next_kernels": roof_next, "cpu_baseline": cpu,
+    }
+    print(json.dumps(res))
+
+
 def serve_bench(a, P):
     """Serving workload: a Poisson stream of mixed solves (QEP, delay, BEM,
     random circles, L in {16, 32, 64}) submitted at their arrival times to a
@@ -323,6 +411,8 @@ def main():
                          "for scaling the FETCH_SIZE / WRITE_SIZE counters) and exit")
     ap.add_argument("--nb", type=int, default=None,
                     help="LU panel width of the sampling and reduced-problem factorisations (default 64)")
+    ap.add_argument("--graph", type=int, default=0, choices=[0, 1],
+                    help="capture the sampling launches in a HIP graph replayed by later steps")
     ap.add_argument("--chunk-gib", type=float, default=None,
                     help="device memory per batch of reduced-problem inverses (library default if unset)")
     ap.add_argument("--requests", type=int, default=600, help="serving workload (c4): requests")
@@ -361,6 +451,9 @@ def main():
     if a.workload == "c4":
         serve_bench(a, P)
         return
+    if a.workload == "c2":
+        batched_bench(a, P)
+        return
     w = workload(a.workload)
     prob, c, N, L = w["prob"], w["contour"], w["N"], w["L"]
     if a.contour == "rect":
@@ -374,7 +467,7 @@ def main():
     log(f"workload {a.workload}: {w['desc']}")
     h = P.Problem(prob)
     U = P.to_device(w["U"])
-    prm = P.default_params(N=N, L=L, precision=a.precision, scheme=a.scheme)
+    prm = P.default_params(N=N, L=L, precision=a.precision, scheme=a.scheme, graph=a.graph)
     if a.chunk_gib is not None:
         prm.chunk_gib = a.chunk_gib
     if a.nb is not None:
@@ -401,9 +494,11 @@ def main():
     dominant = pre_roof["kernel"] if pre_roof else None
     log(f"kernel statistics pass: {dev_ms:.1f} ms of timed device work; dominant kernel {dominant}")
 
-    # timed region: HIP events only around the dominant kernel function
+    # timed region: HIP events only around the dominant kernel function (none
+    # when the sampling launches replay a captured graph: a capture takes no
+    # timer events, so the roofline then comes from the statistics pass)
     P.timers_reset()
-    if dominant:
+    if dominant and not a.graph:
         P.timers_only(dominant)
         P.timers_enable(True)
     lat = []
@@ -428,7 +523,7 @@ def main():
     ms_step = elapsed / a.steps * 1e3
     samples_s = N * a.steps / elapsed
     eig_s = sum(n_eig) / elapsed
-    roof, _ = kernel_roofline(timed, a.steps)
+    roof, _ = kernel_roofline(timed, a.steps) if not a.graph else (pre_roof, None)
     _, roof_next = kernel_roofline(stats, 1)
     if roof is not None:
         roof["share_of_timed_device_ms"] = pre_roof["ms_per_step"] / max(dev_ms, 1e-9)
@@ -475,7 +570,7 @@ def main():
         "data": "synthetic (seeded)",
         "config": {"workload": a.workload, "description": w["desc"], "n": prob.n, "N": N, "L": L,
                    "NS": prm.NS, "K": prm.K, "precision": a.precision, "scheme": a.scheme,
-                   "contour": a.contour, "nb": int(prm.nb), "parallelism": "single GPU"},
+                   "contour": a.contour, "nb": int(prm.nb), "graph": a.graph, "parallelism": "single GPU"},
         "eigenpairs_per_s": eig_s,
         "n_eig": n_eig[-1],
         "latency_s": {"p50": float(np.percentile(lat_s, 50)), "p99": float(np.percentile(lat_s, 99))},

@@ -151,13 +151,17 @@ typedef struct {
   int ir_max_iter;    /* refinement sweeps before the complex128 fallback, default 5 */
   double ir_tol;      /* refinement acceptance: normwise backward error, default 1e-14 */
   int cheb_degree;    /* BEM only: interpolation degree d (eq. eq-T-interp), default 40 */
-  int nb;             /* LU panel width (1..64), default 64 */
+  int nb;             /* LU panel width (1..64), default 64; 0: the autotuned width (rsrr_tune_lu) */
   uint64_t seed;      /* seed of the probing matrix when U is not supplied */
   int scheme;         /* RSRR_SCHEME_SAMPLING (default) or RSRR_SCHEME_MOMENT */
   int Kp;             /* moment scheme: number of moments K' (0 = N, as in the paper's comparisons) */
   double chunk_gib;   /* device memory for one batch of T_S(zeta_m) and their inverses in the
                          reduced moments (and of BEM Chebyshev samples), GiB; default 24 */
   int interp;         /* BEM only: RSRR_INTERP_*, default RSRR_INTERP_AUTO */
+  int graph;          /* 1: the sampling launches (assembly and factorisation of all nodes)
+                         are captured in a HIP graph kept by the handle and replayed by later
+                         solves whose sizes, buffers and coefficients are the same (captured
+                         again otherwise; not while kernel timers are on); default 0 */
 } rsrr_params;
 
 /* Diagnostics of one solve. */
@@ -253,6 +257,22 @@ int rsrr_project(rsrr_problem* p, const rsrr_contour* c, const rsrr_params* prm,
  * (leading dim n) or NULL to draw a complex Gaussian U from prm->seed. */
 int rsrr_solve(rsrr_problem* p, const rsrr_contour* c, const rsrr_params* prm,
                const rsrr_complex* U, rsrr_result** out);
+
+/* Alg. 2 for `count` problems at once, of uneven orders (many independent
+ * eigenproblems, Sec. 1 and 5): the sampled matrices T(z_j) of every problem
+ * are factored together -- each panel step of all (problem, node) matrices
+ * is one set of launches (panels, row interchanges, and the trailing updates
+ * as one persistent matrix-core launch walking the tiles of all problems) --
+ * then each problem's solves, refinement, basis, projection and reduced
+ * problem run in turn.  The problems must be distinct, use one stream and
+ * share the precision and panel width.  Results are bit-identical to
+ * rsrr_solve of each problem alone.  contours, prms: count entries each;
+ * U: NULL, or count device pointers (n_i x L_i, leading dim n_i; an entry may
+ * be NULL to draw U from prms[i].seed); out: count result pointers (free each
+ * with rsrr_result_free).  Returns the bitwise OR of the problems' warnings,
+ * or the first error (then no result is returned). */
+int rsrr_solve_batched(int count, rsrr_problem* const* probs, const rsrr_contour* contours,
+                       const rsrr_params* prms, const rsrr_complex* const* U, rsrr_result** out);
 
 /* Upper bound of the device workspace one rsrr_solve of p with prm allocates
  * (bytes), from n, J, N, L, NS, K, nb, the precision and the scheme: the
@@ -356,6 +376,19 @@ int rsrr_gesv_batched(int precision, int n, int nrhs, void* A, int lda, long lon
  * by the caller.  Arguments, results and errors as rsrr_gesv_batched. */
 int rsrr_gesv_batched_noalloc(int precision, int n, int nrhs, void* A, int lda, long long sA, void* B,
                               int ldb, long long sB, int batch, int nb, int* info_host, void* stream);
+
+/* Autotuning of the LU panel width (the sampling factorisations with pairs
+ * of panels and look-ahead): rsrr_tune_lu times one factorisation of `batch`
+ * synthetic matrices of order n for each candidate width (16, 32, 64) on the
+ * current device, keeps the fastest in a process-wide table (precision, n,
+ * batch) and returns it in *nb_best (*ms_best, may be NULL: its time).  A
+ * solve with rsrr_params.nb = 0 takes the width of the table entry of its
+ * precision with the nearest order (then the nearest node count), or 64 if
+ * there is none.  rsrr_tune_save writes the table as JSON; rsrr_tune_load
+ * reads such a file into the table and returns the number of entries read. */
+int rsrr_tune_lu(int precision, int n, int batch, int* nb_best, double* ms_best);
+int rsrr_tune_save(const char* path);
+int rsrr_tune_load(const char* path);
 
 /* ------------------------------------------------------------------------
  * Kernel timers: when enabled, the main kernel classes (LU panel, LU trailing

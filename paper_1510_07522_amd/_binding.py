@@ -44,7 +44,7 @@ class params_t(C.Structure):
                 ("hankel_tol", C.c_double), ("precision", C.c_int), ("ir_max_iter", C.c_int),
                 ("ir_tol", C.c_double), ("cheb_degree", C.c_int), ("nb", C.c_int),
                 ("seed", C.c_uint64), ("scheme", C.c_int), ("Kp", C.c_int), ("chunk_gib", C.c_double),
-                ("interp", C.c_int)]
+                ("interp", C.c_int), ("graph", C.c_int)]
 
 
 class info_t(C.Structure):
@@ -88,6 +88,8 @@ SIGNATURES = {
                           C.POINTER(_i)]),
     "rsrr_solve": (_i, [_vp, C.POINTER(contour_t), C.POINTER(params_t), _vp, C.POINTER(_vp)]),
     "rsrr_workspace_bound": (_i, [_vp, C.POINTER(contour_t), C.POINTER(params_t), C.POINTER(C.c_size_t)]),
+    "rsrr_solve_batched": (_i, [_i, C.POINTER(_vp), C.POINTER(contour_t), C.POINTER(params_t), C.POINTER(_vp),
+                                C.POINTER(_vp)]),
     "rsrr_server_create": (_i, [C.POINTER(_vp), C.c_size_t, _i]),
     "rsrr_server_submit": (_i, [_vp, _vp, C.POINTER(contour_t), C.POINTER(params_t), _vp,
                                 C.POINTER(C.c_uint64)]),
@@ -103,6 +105,9 @@ SIGNATURES = {
                                 _ll, _i, _i, _vp]),
     "rsrr_gesv_batched": (_i, [_i, _i, _i, _vp, _i, _ll, _vp, _i, _ll, _i, _i, C.POINTER(_i), _vp]),
     "rsrr_gesv_batched_noalloc": (_i, [_i, _i, _i, _vp, _i, _ll, _vp, _i, _ll, _i, _i, C.POINTER(_i), _vp]),
+    "rsrr_tune_lu": (_i, [_i, _i, _i, C.POINTER(_i), C.POINTER(_d)]),
+    "rsrr_tune_save": (_i, [C.c_char_p]),
+    "rsrr_tune_load": (_i, [C.c_char_p]),
     "rsrr_timers_enable": (None, [_i]),
     "rsrr_timers_only": (None, [C.c_char_p]),
     "rsrr_timers_reset": (None, []),
@@ -366,6 +371,26 @@ def _take_result(r, n: int, prm: params_t, st: int) -> dict:
                 info=info.as_dict(), status=st)
 
 
+def solve_batched(problems, contours, params, Us=None):
+    """rsrr_solve_batched: Alg. 2 for several problems whose sampling LUs are
+    factored together; returns one result dict per problem (as
+    Problem.solve)."""
+    lib = load()
+    k = len(problems)
+    hs = (C.c_void_p * k)(*[pr.handle for pr in problems])
+    cs = (contour_t * k)(*contours)
+    ps = (params_t * k)(*params)
+    us = None if Us is None else (C.c_void_p * k)(*[None if u is None else u.data_ptr() for u in Us])
+    outs = (C.c_void_p * k)()
+    st = check(lib.rsrr_solve_batched(k, hs, cs, ps, us, outs))
+    res = []
+    for i in range(k):
+        r = _take_result(C.c_void_p(outs[i]), problems[i].n, params[i], st)
+        r["status"] = r["info"]["status"]
+        res.append(r)
+    return res
+
+
 class Server:
     """Continuous-batching request loop (rsrr_server_*): submit solves of any
     problems; each runs in one of max_slots concurrent slots once it fits the
@@ -425,6 +450,22 @@ def orthonormalize(S, rows: int, cols: int, delta: float = 1e-14):
 
 def timers_enable(on: bool = True):
     load().rsrr_timers_enable(int(on))
+
+
+def tune_lu(precision: str, n: int, batch: int):
+    """(best panel width, its time in ms) from rsrr_tune_lu."""
+    nb, ms = C.c_int(0), C.c_double(0)
+    check(load().rsrr_tune_lu({"c128": PREC_C128, "c64_ir": PREC_C64_IR}[precision], n, batch, C.byref(nb),
+                              C.byref(ms)))
+    return nb.value, ms.value
+
+
+def tune_save(path: str):
+    check(load().rsrr_tune_save(path.encode()))
+
+
+def tune_load(path: str) -> int:
+    return check(load().rsrr_tune_load(path.encode()))
 
 
 def timers_only(sym: str | None):

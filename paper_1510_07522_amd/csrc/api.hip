@@ -248,7 +248,7 @@ int check_params(const rsrr_problem* p, const rsrr_contour* c, const rsrr_params
     if (!rect_split(c, prm->NS, false, &nh, &nv))
       return set_error(ST_EINVAL, "rectangle: NS=%d must be even and >= 4", prm->NS);
   }
-  if (prm->nb < 1 || prm->nb > 64) return set_error(ST_EINVAL, "nb must be in [1, 64]");
+  if (prm->nb < 0 || prm->nb > 64) return set_error(ST_EINVAL, "nb must be in [0, 64] (0: tuned)");
   if (prm->precision != RSRR_PREC_C128 && prm->precision != RSRR_PREC_C64_IR)
     return set_error(ST_EINVAL, "unknown precision %d", prm->precision);
   if (prm->NS < 2 || prm->K < 1) return set_error(ST_EINVAL, "NS >= 2 and K >= 1 required");
@@ -257,11 +257,18 @@ int check_params(const rsrr_problem* p, const rsrr_contour* c, const rsrr_params
     return set_error(ST_EINVAL, "unknown scheme %d", prm->scheme);
   if (!(prm->chunk_gib >= 0.0625) || prm->chunk_gib > 256.0)
     return set_error(ST_EINVAL, "chunk_gib=%g outside [1/16, 256]", prm->chunk_gib);
+  if (prm->graph != 0 && prm->graph != 1) return set_error(ST_EINVAL, "graph must be 0 or 1");
   if (prm->interp < RSRR_INTERP_AUTO || prm->interp > RSRR_INTERP_CIRCLE)
     return set_error(ST_EINVAL, "unknown interpolation %d", prm->interp);
   if (prm->Kp < 0 || (long)prm->Kp * prm->L > (1L << 20))
     return set_error(ST_EINVAL, "Kp=%d outside [0, 2^20/L]", prm->Kp);
   return ST_OK;
+}
+
+rsrr_params resolve_params(const rsrr_problem* p, const rsrr_params* prm) {
+  rsrr_params q = *prm;
+  if (q.nb == 0) q.nb = tuned_nb(q.precision, p->n, q.N);
+  return q;
 }
 
 }  // namespace rsrr
@@ -407,6 +414,10 @@ void rsrr_destroy(rsrr_problem* p) {
   for (void* m : p->mats) if (m) (void)hipFree(m);
   if (p->xyz) (void)hipFree(p->xyz);
   p->ws.release();
+  if (p->batch_view) {
+    unbind_view(p->batch_view);
+    delete p->batch_view;
+  }
   delete p;
 }
 
@@ -415,14 +426,16 @@ int rsrr_sample(rsrr_problem* p, const rsrr_contour* c, const rsrr_params* prm,
                 const rsrr_complex* U, int ldu, rsrr_complex* S, int lds, rsrr_info* info) {
   RSRR_TRY(check_params(p, c, prm));
   if (!U || !S || ldu < p->n || lds < p->n) return set_error(ST_EINVAL, "rsrr_sample: bad buffers");
-  return sample_impl(p, c, prm, (const c128*)U, ldu, (c128*)S, lds, info);
+  const rsrr_params q = resolve_params(p, prm);
+  return sample_impl(p, c, &q, (const c128*)U, ldu, (c128*)S, lds, info);
 }
 
 int rsrr_workspace_bound(const rsrr_problem* p, const rsrr_contour* c, const rsrr_params* prm,
                          size_t* bytes) {
   if (!bytes) return set_error(ST_EINVAL, "rsrr_workspace_bound: null output");
   RSRR_TRY(check_params(p, c, prm));
-  *bytes = solve_workspace_bound(p, prm);
+  const rsrr_params q = resolve_params(p, prm);
+  *bytes = solve_workspace_bound(p, &q);
   return ST_OK;
 }
 
@@ -458,7 +471,8 @@ int rsrr_solve(rsrr_problem* p, const rsrr_contour* c, const rsrr_params* prm,
   RSRR_TRY(check_params(p, c, prm));
   rsrr_result* r = new rsrr_result();
   memset(&r->info, 0, sizeof(r->info));
-  int st = solve_impl(p, c, prm, (const c128*)U, r);
+  const rsrr_params q = resolve_params(p, prm);
+  int st = solve_impl(p, c, &q, (const c128*)U, r);
   if (st < 0) {
     delete r;
     return st;
@@ -466,6 +480,84 @@ int rsrr_solve(rsrr_problem* p, const rsrr_contour* c, const rsrr_params* prm,
   r->info.status = st;
   *out = r;
   return st;
+}
+
+int rsrr_solve_batched(int count, rsrr_problem* const* probs, const rsrr_contour* contours,
+                       const rsrr_params* prms, const rsrr_complex* const* U, rsrr_result** out) {
+  if (count < 1 || !probs || !contours || !prms || !out)
+    return set_error(ST_EINVAL, "rsrr_solve_batched: bad arguments");
+  for (int i = 0; i < count; ++i) out[i] = nullptr;
+  // one panel width for the whole batch: the tuned one for the largest order
+  // and the total number of matrices when the parameters leave it open
+  std::vector<rsrr_params> q(prms, prms + count);
+  {
+    int nmax = 0, tot = 0;
+    for (int i = 0; i < count; ++i) {
+      if (!probs[i]) return set_error(ST_EINVAL, "rsrr_solve_batched: null problem %d", i);
+      nmax = std::max(nmax, probs[i]->n);
+      tot += prms[i].N;
+    }
+    for (int i = 0; i < count; ++i)
+      if (q[i].nb == 0) q[i].nb = tuned_nb(q[i].precision, nmax, tot);
+  }
+  prms = q.data();
+  for (int i = 0; i < count; ++i) {
+    RSRR_TRY(check_params(probs[i], &contours[i], &prms[i]));
+    if (probs[i]->stream != probs[0]->stream)
+      return set_error(ST_EINVAL, "rsrr_solve_batched: problems %d and 0 use different streams", i);
+    if (prms[i].precision != prms[0].precision || prms[i].nb != prms[0].nb)
+      return set_error(ST_EINVAL, "rsrr_solve_batched: problems must share the precision and nb");
+    for (int j = 0; j < i; ++j)
+      if (probs[j] == probs[i]) return set_error(ST_EINVAL, "rsrr_solve_batched: problem %d given twice", i);
+  }
+  std::vector<rsrr_result*> res(count, nullptr);
+  std::vector<SamplePlan> sp(count);
+  auto fail = [&](int st) {
+    for (rsrr_result* r : res) delete r;
+    return st;
+  };
+  for (int i = 0; i < count; ++i) {
+    res[i] = new rsrr_result();
+    memset(&res[i]->info, 0, sizeof(res[i]->info));
+    const int st = solve_begin(probs[i], &contours[i], &prms[i], U ? (const c128*)U[i] : nullptr, res[i], &sp[i]);
+    if (st < 0) return fail(st);
+  }
+  // the sampling LUs of all problems, each panel step one set of launches
+  hipStream_t s = probs[0]->stream;
+  int st = ST_OK;
+  for (int i = 0; i < count; ++i) {
+    st = sample_assemble(&sp[i], s);
+    if (st < 0) return fail(st);
+  }
+  if (sp[0].c64) {
+    std::vector<LUWork<float>> w;
+    for (const SamplePlan& q : sp) w.push_back(q.w64);
+    st = lu_factor_segments<float>(w, s, w[0].aux, w[0].ev_main, w[0].ev_aux);
+  } else {
+    std::vector<LUWork<double>> w;
+    for (const SamplePlan& q : sp) w.push_back(q.w128);
+    st = lu_factor_segments<double>(w, s, w[0].aux, w[0].ev_main, w[0].ev_aux);
+  }
+  if (st < 0) return fail(st);
+  // the later stages problem by problem, in one workspace kept by the first
+  // handle (the sampled matrices stay in each problem's own workspace)
+  rsrr_problem* v = probs[0]->batch_view;
+  if (!v) {
+    v = probs[0]->batch_view = new rsrr_problem();
+    v->ws.no_aux = probs[0]->ws.no_aux;
+  }
+  int warn = 0;
+  for (int i = 0; i < count; ++i) {
+    bind_view(v, probs[i], s);
+    st = solve_end(v, &contours[i], &prms[i], res[i], &sp[i]);
+    unbind_view(v);
+    if (st < 0) return fail(st);
+    res[i]->info.status = st;
+    res[i]->info.ws_bytes += (double)probs[i]->ws.bytes();
+    warn |= st;
+  }
+  for (int i = 0; i < count; ++i) out[i] = res[i];
+  return warn;
 }
 
 int rsrr_result_info(const rsrr_result* r, rsrr_info* info) {

@@ -1,4 +1,5 @@
 // Assembly of T(z_j) at many nodes, BEM kernels, and small elementwise kernels.
+#include "bem.h"
 #include "common.h"
 #include "kernels.h"
 #include "timers.h"
@@ -68,22 +69,6 @@ template int assemble_coeff<double>(const CoeffSet&, int, const c128*, c128*, lo
 template int assemble_coeff<float>(const CoeffSet&, int, const c128*, c64*, long, long, hipStream_t);
 
 // ------------------------------------------------------------------- BEM
-#define RSRR_INV4PI 0.07957747154594767
-
-__device__ inline void sincos_r(double x, double* s, double* c) { sincos(x, s, c); }
-__device__ inline void sincos_r(float x, float* s, float* c) { sincosf(x, s, c); }
-__device__ inline double exp_r(double x) { return exp(x); }
-__device__ inline float exp_r(float x) { return expf(x); }
-
-template <typename R>
-__device__ inline cplx<R> bem_entry(R r, R zr, R zi) {
-  // exp(i z r)/(4 pi r) = exp(-zi r) (cos(zr r) + i sin(zr r)) / (4 pi r)
-  R sn, cs;
-  sincos_r(zr * r, &sn, &cs);
-  const R m = exp_r(-zi * r) * (R(RSRR_INV4PI) / r);
-  return mk<R>(m * cs, m * sn);
-}
-
 template <typename R>
 __global__ __launch_bounds__(256) void assemble_bem_kernel(int n, const double* xyz, double h,
                                                            int nz, const c128* z, cplx<R>* T,
@@ -177,81 +162,21 @@ int bem_fro2(int n, const double* xyz, double h, int nz, const c128* z_dev, doub
   return ST_OK;
 }
 
-// R_j = U - T(z_j) Y_j with T generated on the fly in fp64.  Tile: 64 rows x
-// 64 columns of R per workgroup, 256 threads, 4x4 outputs per thread.
-constexpr int BRT = 64, BCT = 64, BKT = 16;
-__global__ __launch_bounds__(256) void bem_residual_kernel(int n, const double* xyz, double h,
-                                                           const c128* z, const c128* U, long ldu,
-                                                           const c128* Y, long ldy, long sY, int L,
-                                                           c128* Rout, long ldr, long sR) {
-  __shared__ c128 Ts[BKT][BRT + 1];
-  __shared__ c128 Ys[BKT][BCT + 1];
-  const int j = blockIdx.z;
-  const int r0 = blockIdx.x * BRT, l0 = blockIdx.y * BCT;
-  const int tid = threadIdx.x;
-  const int tr = tid % 16, tc = tid / 16;     // 16 x 16 threads, 4x4 each
-  const c128 zj = z[j];
-  const c128* Yj = Y + (long)j * sY;
-  c128 acc[4][4];
-#pragma unroll
-  for (int a = 0; a < 4; ++a)
-#pragma unroll
-    for (int b = 0; b < 4; ++b) acc[a][b] = mk<double>(0, 0);
-  for (int k0 = 0; k0 < n; k0 += BKT) {
-    for (int e = tid; e < BKT * BRT; e += 256) {
-      const int rr = e % BRT, kk = e / BRT;
-      const int i = r0 + rr, c = k0 + kk;
-      c128 t = mk<double>(0, 0);
-      if (i < n && c < n) {
-        if (i == c) t = mk<double>(-zj.im * RSRR_INV4PI + 0.5 / h, zj.re * RSRR_INV4PI);
-        else {
-          const double dx = xyz[3 * i] - xyz[3 * c], dy = xyz[3 * i + 1] - xyz[3 * c + 1],
-                       dz = xyz[3 * i + 2] - xyz[3 * c + 2];
-          t = bem_entry<double>(sqrt(dx * dx + dy * dy + dz * dz), zj.re, zj.im);
-        }
-      }
-      Ts[kk][rr] = t;
-    }
-    for (int e = tid; e < BKT * BCT; e += 256) {
-      const int kk = e % BKT, ll = e / BKT;
-      const int c = k0 + kk, l = l0 + ll;
-      Ys[kk][ll] = (c < n && l < L) ? Yj[c + (long)l * ldy] : mk<double>(0, 0);
-    }
-    __syncthreads();
-#pragma unroll 4
-    for (int kk = 0; kk < BKT; ++kk) {
-      c128 tv[4], yv[4];
-#pragma unroll
-      for (int a = 0; a < 4; ++a) tv[a] = Ts[kk][tr + 16 * a];
-#pragma unroll
-      for (int b = 0; b < 4; ++b) yv[b] = Ys[kk][tc + 16 * b];
-#pragma unroll
-      for (int a = 0; a < 4; ++a)
-#pragma unroll
-        for (int b = 0; b < 4; ++b) acc[a][b] = acc[a][b] + tv[a] * yv[b];
-    }
-    __syncthreads();
-  }
-#pragma unroll
-  for (int a = 0; a < 4; ++a)
-#pragma unroll
-    for (int b = 0; b < 4; ++b) {
-      const int i = r0 + tr + 16 * a, l = l0 + tc + 16 * b;
-      if (i < n && l < L)
-        Rout[(long)j * sR + i + (long)l * ldr] = U[i + (long)l * ldu] - acc[a][b];
-    }
-}
-
-int bem_residual(int n, const double* xyz, double h, int nz, const c128* z_dev, const c128* U,
-                 long ldu, const c128* Y, long ldy, long sY, int L, c128* Rout, long ldr, long sR,
-                 hipStream_t s) {
+// R_j = U - T(z_j) Y_j with T generated on the fly in fp64: U copied into R,
+// then the fp64 matrix-core GEMM whose A tiles are BEM entries computed where
+// they are staged (gemm.hip: bem_gemm).
+int bem_residual(int n, const double* xyz, double h, int nz, const c128* z_dev, const c128* U, long ldu,
+                 const c128* Y, long ldy, long sY, int L, c128* Rout, long ldr, long sR, hipStream_t s) {
   if (nz <= 0) return ST_OK;
-  dim3 grid((unsigned)cdivl(n, BRT), (unsigned)cdivl(L, BCT), (unsigned)nz);
-  KernelTimer kt("bem_residual", s, 8.0 * n * (double)n * L * nz, 16.0 * 2 * (double)n * L * nz);
-  hipLaunchKernelGGL(bem_residual_kernel, grid, dim3(256), 0, s, n, xyz, h, z_dev, U, ldu, Y, ldy,
-                     sY, L, Rout, ldr, sR);
-  RSRR_LAUNCH_CHECK();
-  return ST_OK;
+  RSRR_TRY((convert<double, double>(U, ldu, 0, Rout, ldr, sR, n, L, nz, s)));
+  GemmBatch<double> g;
+  g.M = n; g.N = L; g.K = n;
+  g.alpha = mk<double>(-1, 0); g.beta = mk<double>(1, 0);
+  g.B = Y; g.ldb = ldy; g.sB = sY;
+  g.C = Rout; g.ldc = ldr; g.sC = sR;
+  g.batch = nz;
+  g.tag = "bem_residual";
+  return bem_gemm(g, xyz, h, z_dev, s);
 }
 
 // ------------------------------------------------------------ elementwise

@@ -8,6 +8,7 @@
 #include "../../include/rsrr.h"
 #include "common.h"
 #include "kernels.h"
+#include "timers.h"
 
 namespace rsrr {
 
@@ -34,6 +35,17 @@ struct Arena {
   ~Arena() { release(); }
 };
 
+// The sampling launches (assembly and factorisation of all nodes) captured
+// in a HIP graph, with the key of everything they depend on.
+struct SampleGraph {
+  std::vector<long long> key;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  hipStream_t cap = nullptr;     // capture stream (a capture needs a stream of its own)
+  void reset();
+  ~SampleGraph();
+};
+
 // Evaluates f(z) and f'(z) of a scalar-function spec.
 void eval_fn(const rsrr_fn& f, cd z, cd* val, cd* der);
 
@@ -52,7 +64,35 @@ struct rsrr_problem {
   double* xyz = nullptr;              // BEM points (device, n*3)
   double h = 0.0;
   rsrr::Arena ws;
+  rsrr::SampleGraph sgraph;           // captured sampling launches (rsrr_params.graph)
+  // workspace of the stages after sampling when this handle is the first of
+  // a batched solve (shared by the problems of the batch, created on use)
+  rsrr_problem* batch_view = nullptr;
 };
+
+namespace rsrr {
+// A problem that shares another's data (coefficients, BEM points, scalar
+// functions) but has its own stream and workspace: a serving slot, or the
+// later stages of a batched solve.  Never frees the shared data.
+inline void bind_view(rsrr_problem* v, const rsrr_problem* p, hipStream_t s) {
+  v->n = p->n;
+  v->J = p->J;
+  v->bem = p->bem;
+  v->kinds = p->kinds;
+  v->fns = p->fns;
+  v->cb = p->cb;
+  v->cb_ctx = p->cb_ctx;
+  v->mats = p->mats;
+  v->gram = p->gram;
+  v->xyz = p->xyz;
+  v->h = p->h;
+  v->stream = s;
+}
+inline void unbind_view(rsrr_problem* v) {
+  v->mats.clear();
+  v->xyz = nullptr;
+}
+}  // namespace rsrr
 
 struct rsrr_result {
   rsrr_info info;
@@ -65,6 +105,36 @@ namespace rsrr {
 // Stage implementations (driver_*.hip).
 int sample_impl(rsrr_problem* p, const rsrr_contour* c, const rsrr_params* prm,
                 const c128* U, long ldu, c128* S, long lds, rsrr_info* info);
+// Alg. 2 Steps 1-2 split at the factorisation (sample_impl = begin, factor,
+// end), so that the factorisations of several problems can be one set of
+// launches: begin computes the nodes and coefficients and assembles T(z_j)
+// into the handle's workspace; the factorisation descriptor is w128 or w64;
+// end checks the pivots and runs the solves, the refinement and the
+// complex128 fallback.
+struct SamplePlan {
+  rsrr_problem* p = nullptr;
+  const rsrr_contour* c = nullptr;
+  const rsrr_params* prm = nullptr;
+  const c128* U = nullptr;
+  long ldu = 0, lds = 0;
+  c128* S = nullptr;
+  rsrr_info* info = nullptr;
+  double t0 = 0;
+  std::vector<cd> z;
+  std::vector<c128> f, zc;
+  c128 *f_dev = nullptr, *z_dev = nullptr;
+  int *ipiv = nullptr, *infod = nullptr;
+  bool c64 = true;
+  LUWork<double> w128;
+  LUWork<float> w64;
+};
+int sample_begin(rsrr_problem* p, const rsrr_contour* c, const rsrr_params* prm, const c128* U, long ldu,
+                 c128* S, long lds, rsrr_info* info, SamplePlan* sp);
+int sample_factor(SamplePlan* sp);
+// Assembly of the sampled matrices T(z_j) on stream s (part of sample_factor;
+// the batched solve calls it for each problem before their joint factorisation).
+int sample_assemble(SamplePlan* sp, hipStream_t s);
+int sample_end(SamplePlan* sp);
 // Moment matrix M_hat of the SSRR moment scheme from S_hat (eq. eq-hatMS).
 int moment_impl(rsrr_problem* p, const rsrr_contour* c, const rsrr_params* prm, const c128* S, long lds,
                 c128* M, long ldm);
@@ -82,9 +152,20 @@ int project_impl(rsrr_problem* p, const rsrr_contour* c, const rsrr_params* prm,
                  long ldq, int kS, c128* B, int* J_out);
 int solve_impl(rsrr_problem* p, const rsrr_contour* c, const rsrr_params* prm, const c128* U,
                rsrr_result* res);
+// solve_impl split at the sampling factorisations (solve_impl = begin,
+// sample_factor, end): begin draws or takes U and prepares the sampling;
+// end finishes the sampling and runs Steps 3-5 and the residual filter.
+int solve_begin(rsrr_problem* p, const rsrr_contour* c, const rsrr_params* prm, const c128* U,
+                rsrr_result* res, SamplePlan* sp);
+int solve_end(rsrr_problem* p, const rsrr_contour* c, const rsrr_params* prm, rsrr_result* res,
+              SamplePlan* sp);
 // Upper bound of the device workspace one solve of p with prm allocates.
 size_t solve_workspace_bound(const rsrr_problem* p, const rsrr_params* prm);
 int check_params(const rsrr_problem* p, const rsrr_contour* c, const rsrr_params* prm);
+// A copy of prm with the panel width resolved (nb = 0: the autotuned width
+// for this precision, order and node count, tune.hip).
+rsrr_params resolve_params(const rsrr_problem* p, const rsrr_params* prm);
+int tuned_nb(int precision, int n, int batch);
 // f_k(z_q) into f[q*J + k] for the m nodes z, and f_k'(z_q) into df when df is
 // not null: the problem's menu entries or the caller's callback.  Returns
 // ST_OK, 1 when the callback has no derivatives (f is then filled), or an error.

@@ -11,6 +11,7 @@
 // factored again in complex128.
 #include <algorithm>
 #include <cmath>
+#include <cstring>
 
 #include "driver.h"
 #include "timers.h"
@@ -160,64 +161,168 @@ int moment_impl(rsrr_problem* p, const rsrr_contour* c, const rsrr_params* prm, 
   return ST_OK;
 }
 
-int sample_impl(rsrr_problem* p, const rsrr_contour* c, const rsrr_params* prm, const c128* U,
-                long ldu, c128* S, long lds, rsrr_info* info) {
-  const double t0 = now_s();
+int sample_begin(rsrr_problem* p, const rsrr_contour* c, const rsrr_params* prm, const c128* U, long ldu,
+                 c128* S, long lds, rsrr_info* info, SamplePlan* sp) {
+  SamplePlan& P = *sp;
+  P.p = p; P.c = c; P.prm = prm; P.U = U; P.ldu = ldu; P.S = S; P.lds = lds; P.info = info;
+  P.t0 = now_s();
   hipStream_t s = p->stream;
-  const int n = p->n, N = prm->N, L = prm->L, nb = prm->nb;
+  const int n = p->n, N = prm->N, nb = prm->nb;
   const long nn = (long)n * n;
-  std::vector<cd> z;
-  contour_nodes(c, N, true, &z, nullptr);
-  std::vector<c128> f, zc(N);
-  for (int j = 0; j < N; ++j) zc[j] = mk<double>(z[j].real(), z[j].imag());
-  if (!p->bem) RSRR_TRY(node_coefs(p, z, &f));
-
-  c128 *f_dev = nullptr, *z_dev = nullptr;
-  int *ipiv = nullptr, *infod = nullptr;
-  RSRR_TRY(p->ws.get<c128>("s_f", std::max<size_t>(1, f.size()), &f_dev));
-  RSRR_TRY(p->ws.get<c128>("s_z", N, &z_dev));
-  RSRR_TRY(p->ws.get<int>("s_ipiv", (size_t)N * n, &ipiv));
-  RSRR_TRY(p->ws.get<int>("s_info", N, &infod));
-  if (!f.empty()) RSRR_HIP(hipMemcpyAsync(f_dev, f.data(), f.size() * sizeof(c128), hipMemcpyHostToDevice, s));
-  RSRR_HIP(hipMemcpyAsync(z_dev, zc.data(), N * sizeof(c128), hipMemcpyHostToDevice, s));
-  int ir_iters = 0, fallback = 0, warn = 0;
-
-  if (prm->precision == RSRR_PREC_C128) {
+  contour_nodes(c, N, true, &P.z, nullptr);
+  P.zc.assign(N, mk<double>(0, 0));
+  for (int j = 0; j < N; ++j) P.zc[j] = mk<double>(P.z[j].real(), P.z[j].imag());
+  P.f.clear();
+  if (!p->bem) RSRR_TRY(node_coefs(p, P.z, &P.f));
+  RSRR_TRY(p->ws.get<c128>("s_f", std::max<size_t>(1, P.f.size()), &P.f_dev));
+  RSRR_TRY(p->ws.get<c128>("s_z", N, &P.z_dev));
+  RSRR_TRY(p->ws.get<int>("s_ipiv", (size_t)N * n, &P.ipiv));
+  RSRR_TRY(p->ws.get<int>("s_info", N, &P.infod));
+  if (!P.f.empty())
+    RSRR_HIP(hipMemcpyAsync(P.f_dev, P.f.data(), P.f.size() * sizeof(c128), hipMemcpyHostToDevice, s));
+  RSRR_HIP(hipMemcpyAsync(P.z_dev, P.zc.data(), N * sizeof(c128), hipMemcpyHostToDevice, s));
+  P.c64 = prm->precision != RSRR_PREC_C128;
+  if (!P.c64) {
     c128 *T = nullptr, *dinv = nullptr;
     RSRR_TRY(p->ws.get<c128>("s_T128", (size_t)N * nn, &T));
     RSRR_TRY(p->ws.get<c128>("s_dinv128", LUWork<double>::dinv_elems(n, nb, N), &dinv));
-    RSRR_TRY(assemble_nodes<double>(p, N, f_dev, z_dev, T, s));
-    LUWork<double> w;
+    LUWork<double>& w = P.w128;
+    w = LUWork<double>();
     w.n = n; w.nb = nb; w.batch = N; w.lda = n; w.sA = nn; w.A = T;
-    w.ipiv = ipiv; w.dinv = dinv; w.info = infod;
+    w.ipiv = P.ipiv; w.dinv = dinv; w.info = P.infod;
     w.tag = "sample_lu_c128";
     w.pair = true;
     RSRR_TRY(p->ws.aux_stream(&w.aux, &w.ev_main, &w.ev_aux));
-    RSRR_TRY(lu_factor<double>(w, s));
-    RSRR_TRY(check_info(infod, N, s, z));
-    RSRR_TRY(replicate<double>(U, ldu, S, lds, (long)L * lds, n, L, N, s));
-    RSRR_TRY(lu_solve<double>(w, S, lds, (long)L * lds, L, s));
   } else {
-    c64 *T = nullptr, *dinv = nullptr, *Y32 = nullptr;
-    c128* Rb = nullptr;
-    double* nrm = nullptr;
-    int* active_dev = nullptr;
-    const long cols = (long)N * L;
+    c64 *T = nullptr, *dinv = nullptr;
     RSRR_TRY(p->ws.get<c64>("s_T64", (size_t)N * nn, &T));
     RSRR_TRY(p->ws.get<c64>("s_dinv64", LUWork<float>::dinv_elems(n, nb, N), &dinv));
-    RSRR_TRY(p->ws.get<c64>("s_Y32", (size_t)n * cols, &Y32));
-    RSRR_TRY(p->ws.get<c128>("s_R", (size_t)n * cols, &Rb));
-    RSRR_TRY(p->ws.get<double>("s_nrm", 3 * (size_t)N + 1, &nrm));
-    RSRR_TRY(p->ws.get<int>("s_active", N, &active_dev));
-    RSRR_TRY(assemble_nodes<float>(p, N, f_dev, z_dev, T, s));
-    LUWork<float> w;
+    LUWork<float>& w = P.w64;
+    w = LUWork<float>();
     w.n = n; w.nb = nb; w.batch = N; w.lda = n; w.sA = nn; w.A = T;
-    w.ipiv = ipiv; w.dinv = dinv; w.info = infod;
+    w.ipiv = P.ipiv; w.dinv = dinv; w.info = P.infod;
     w.tag = "sample_lu_c64";
     w.pair = true;
     RSRR_TRY(p->ws.aux_stream(&w.aux, &w.ev_main, &w.ev_aux));
     w.gauss3m = true;          // errors are removed by the fp64 refinement
-    RSRR_TRY(lu_factor<float>(w, s));
+  }
+  return ST_OK;
+}
+
+int sample_assemble(SamplePlan* sp, hipStream_t s) {
+  rsrr_problem* p = sp->p;
+  const int N = sp->prm->N;
+  if (sp->c64) return assemble_nodes<float>(p, N, sp->f_dev, sp->z_dev, sp->w64.A, s);
+  return assemble_nodes<double>(p, N, sp->f_dev, sp->z_dev, sp->w128.A, s);
+}
+
+// Assembly and factorisation of the sampled matrices on stream s.
+static int assemble_and_factor(SamplePlan* sp, hipStream_t s) {
+  RSRR_TRY(sample_assemble(sp, s));
+  if (sp->c64) return lu_factor<float>(sp->w64, s);
+  return lu_factor<double>(sp->w128, s);
+}
+
+// Everything that decides the launches of assemble_and_factor: a graph
+// captured for one key is replayed only for the same key.
+static std::vector<long long> graph_key(const SamplePlan* sp) {
+  const rsrr_problem* p = sp->p;
+  std::vector<long long> k = {p->n, p->J, p->bem ? 1 : 0, sp->prm->N, sp->prm->nb, sp->c64 ? 1 : 0,
+                              (long long)sp->f_dev, (long long)sp->z_dev, (long long)sp->ipiv, (long long)sp->infod,
+                              (long long)p->xyz};
+  long long hb;
+  memcpy(&hb, &p->h, sizeof(hb));
+  k.push_back(hb);
+  for (int q = 0; q < p->J; ++q) {
+    k.push_back(p->kinds[q]);
+    k.push_back((long long)p->mats[q]);
+  }
+  if (sp->c64) {
+    k.push_back((long long)sp->w64.A); k.push_back((long long)sp->w64.dinv);
+    k.push_back((long long)sp->w64.aux);
+  } else {
+    k.push_back((long long)sp->w128.A); k.push_back((long long)sp->w128.dinv);
+    k.push_back((long long)sp->w128.aux);
+  }
+  return k;
+}
+
+void SampleGraph::reset() {
+  if (exec) (void)hipGraphExecDestroy(exec);
+  if (graph) (void)hipGraphDestroy(graph);
+  exec = nullptr;
+  graph = nullptr;
+  key.clear();
+}
+
+SampleGraph::~SampleGraph() {
+  reset();
+  if (cap) (void)hipStreamDestroy(cap);
+}
+
+int sample_factor(SamplePlan* sp) {
+  rsrr_problem* p = sp->p;
+  hipStream_t s = p->stream;
+  if (!sp->prm->graph || timers_on()) return assemble_and_factor(sp, s);
+  // captured once per key on the handle's capture stream (the uploads the
+  // launches read are complete first), replayed on the problem's stream
+  SampleGraph& G = p->sgraph;
+  std::vector<long long> key = graph_key(sp);
+  if (!G.exec || G.key != key) {
+    G.reset();
+    if (!G.cap) RSRR_HIP(hipStreamCreateWithFlags(&G.cap, hipStreamNonBlocking));
+    RSRR_HIP(hipStreamSynchronize(s));
+    RSRR_HIP(hipStreamBeginCapture(G.cap, hipStreamCaptureModeThreadLocal));
+    const int st = assemble_and_factor(sp, G.cap);
+    hipGraph_t g = nullptr;
+    const hipError_t e = hipStreamEndCapture(G.cap, &g);
+    if (st < 0) {
+      if (g) (void)hipGraphDestroy(g);
+      return st;
+    }
+    if (e != hipSuccess) return set_error(ST_EHIP, "capture of the sampling launches: %s", hipGetErrorString(e));
+    G.graph = g;
+    RSRR_HIP(hipGraphInstantiate(&G.exec, G.graph, nullptr, nullptr, 0));
+    G.key = key;
+  }
+  RSRR_HIP(hipGraphLaunch(G.exec, s));
+  return ST_OK;
+}
+
+int sample_end(SamplePlan* sp) {
+  SamplePlan& P = *sp;
+  rsrr_problem* p = P.p;
+  const rsrr_params* prm = P.prm;
+  const c128* U = P.U;
+  const long ldu = P.ldu, lds = P.lds;
+  c128* S = P.S;
+  hipStream_t s = p->stream;
+  const int n = p->n, N = prm->N, L = prm->L, nb = prm->nb;
+  const long nn = (long)n * n;
+  const std::vector<cd>& z = P.z;
+  const std::vector<c128>& f = P.f;
+  const std::vector<c128>& zc = P.zc;
+  c128 *f_dev = P.f_dev, *z_dev = P.z_dev;
+  int *ipiv = P.ipiv, *infod = P.infod;
+  int ir_iters = 0, fallback = 0, warn = 0;
+  (void)f_dev;
+
+  if (!P.c64) {
+    LUWork<double>& w = P.w128;
+    RSRR_TRY(check_info(infod, N, s, z));
+    RSRR_TRY(replicate<double>(U, ldu, S, lds, (long)L * lds, n, L, N, s));
+    RSRR_TRY(lu_solve<double>(w, S, lds, (long)L * lds, L, s));
+  } else {
+    c64* Y32 = nullptr;
+    c128* Rb = nullptr;
+    double* nrm = nullptr;
+    int* active_dev = nullptr;
+    const long cols = (long)N * L;
+    RSRR_TRY(p->ws.get<c64>("s_Y32", (size_t)n * cols, &Y32));
+    RSRR_TRY(p->ws.get<c128>("s_R", (size_t)n * cols, &Rb));
+    RSRR_TRY(p->ws.get<double>("s_nrm", 3 * (size_t)N + 1, &nrm));
+    RSRR_TRY(p->ws.get<int>("s_active", N, &active_dev));
+    LUWork<float>& w = P.w64;
     RSRR_TRY(check_info(infod, N, s, z));
     // Y0 = T~^{-1} U in complex64, widened to fp64
     RSRR_TRY((convert<float, double>(U, ldu, 0, Y32, n, (long)L * n, n, L, N, s)));
@@ -367,15 +472,23 @@ int sample_impl(rsrr_problem* p, const rsrr_contour* c, const rsrr_params* prm, 
     }
   }
   RSRR_HIP(hipStreamSynchronize(s));
-  if (info) {
-    info->n = n;
-    info->N = N;
-    info->L = L;
-    info->ir_iters = ir_iters;
-    info->ir_fallback = fallback;
-    info->t_sample = now_s() - t0;
+  if (P.info) {
+    P.info->n = n;
+    P.info->N = N;
+    P.info->L = L;
+    P.info->ir_iters = ir_iters;
+    P.info->ir_fallback = fallback;
+    P.info->t_sample = now_s() - P.t0;
   }
   return warn;
+}
+
+int sample_impl(rsrr_problem* p, const rsrr_contour* c, const rsrr_params* prm, const c128* U,
+                long ldu, c128* S, long lds, rsrr_info* info) {
+  SamplePlan sp;
+  RSRR_TRY(sample_begin(p, c, prm, U, ldu, S, lds, info, &sp));
+  RSRR_TRY(sample_factor(&sp));
+  return sample_end(&sp);
 }
 
 }  // namespace rsrr

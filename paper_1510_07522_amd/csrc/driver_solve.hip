@@ -114,18 +114,13 @@ size_t Arena::bytes() const {
   return b;
 }
 
-int solve_impl(rsrr_problem* p, const rsrr_contour* c, const rsrr_params* prm, const c128* Uin,
-               rsrr_result* res) {
+int solve_begin(rsrr_problem* p, const rsrr_contour* c, const rsrr_params* prm, const c128* Uin,
+                rsrr_result* res, SamplePlan* sp) {
   hipStream_t s = p->stream;
   Arena& ws = p->ws;
-  const int n = p->n, N = prm->N, L = prm->L, NS = prm->NS, K = prm->K;
-  const long NL = (long)N * L;
-  rsrr_info& info = res->info;
-  int warn = 0;
-  const cd gamma(c->center.re, c->center.im);
-  const double rho = std::max(c->a, c->b);
-
-  // ---- Alg. 2, Steps 1-2: probing matrix and sampling
+  const int n = p->n, L = prm->L;
+  const long NL = (long)prm->N * L;
+  // ---- Alg. 2, Steps 1-2: probing matrix and the sampled system matrices
   const c128* U = Uin;
   if (!U) {
     std::vector<c128> hU;
@@ -138,7 +133,29 @@ int solve_impl(rsrr_problem* p, const rsrr_contour* c, const rsrr_params* prm, c
   }
   c128* Shat = nullptr;
   RSRR_TRY(ws.get<c128>("sv_Shat", (size_t)n * NL, &Shat));
-  int st = sample_impl(p, c, prm, U, n, Shat, n, &info);
+  return sample_begin(p, c, prm, U, n, Shat, n, &res->info, sp);
+}
+
+int solve_impl(rsrr_problem* p, const rsrr_contour* c, const rsrr_params* prm, const c128* Uin,
+               rsrr_result* res) {
+  SamplePlan sp;
+  RSRR_TRY(solve_begin(p, c, prm, Uin, res, &sp));
+  RSRR_TRY(sample_factor(&sp));
+  return solve_end(p, c, prm, res, &sp);
+}
+
+int solve_end(rsrr_problem* p, const rsrr_contour* c, const rsrr_params* prm, rsrr_result* res,
+              SamplePlan* sp) {
+  hipStream_t s = p->stream;
+  Arena& ws = p->ws;
+  const int n = p->n, N = prm->N, L = prm->L, NS = prm->NS, K = prm->K;
+  const long NL = (long)N * L;
+  rsrr_info& info = res->info;
+  int warn = 0;
+  const cd gamma(c->center.re, c->center.im);
+  const double rho = std::max(c->a, c->b);
+  c128* Shat = sp->S;
+  int st = sample_end(sp);
   if (st < 0) return st;
   warn |= st;
 

@@ -17,6 +17,9 @@
 // and the MFMA operand reads stay conflict-free.  The epilogue stages the
 // products through the same LDS bytes so that C is read and written one
 // contiguous column per wave instruction.
+#include <algorithm>
+
+#include "bem.h"
 #include "common.h"
 #include "kernels.h"
 #include "timers.h"
@@ -43,8 +46,19 @@ constexpr int BM = 64, BN = 64, BK = 16, PAD = 16;
 // 256 for complex64 (4 waves of 32x32)
 template <typename R> constexpr int gemm_threads() { return sizeof(R) == 8 ? 512 : 256; }
 
-template <typename R, int OPA, int OPB, bool AREAL, bool G3M>
-__global__ __launch_bounds__(sizeof(R) == 8 ? 512 : 256) void gemm_kernel(GemmBatch<R> g) {
+// Where the A operand of the BEM residual comes from: the points, the
+// spacing and one node z per batch entry (A_b = T(z_b) generated in place).
+struct BemGen {
+  const double* xyz;
+  double h;
+  const c128* z;
+};
+
+// One 64x64 tile of C (rows m0.., columns n0.. of batch entry bz).  Every
+// thread of the workgroup calls it with the same arguments; it ends with a
+// barrier, so a workgroup may run several tiles in turn.
+template <typename R, int OPA, int OPB, bool AREAL, bool G3M, bool ABEM>
+__device__ __forceinline__ void gemm_body(const GemmBatch<R>& g, const BemGen& bg, int m0, int n0, int bz) {
   typedef typename V4<R>::T acc_t;
   constexpr int NT = gemm_threads<R>();
   constexpr int WJ = NT == 512 ? 1 : 2;          // 16-column blocks per wave
@@ -61,10 +75,7 @@ __global__ __launch_bounds__(sizeof(R) == 8 ? 512 : 256) void gemm_kernel(GemmBa
   Tile* Bs_im = Bs_re + BK;
   Tile* As_im = Bs_im + BK;
 
-  const int bz = blockIdx.z;
-  if (g.active && !g.active[bz]) return;
   const int M = g.M, N = g.N, K = g.K;
-  const int m0 = blockIdx.x * BM, n0 = blockIdx.y * BN;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave & 1, wn = wave >> 1;       // 32-row half, 16*WJ-column slice
 
@@ -93,7 +104,19 @@ __global__ __launch_bounds__(sizeof(R) == 8 ? 512 : 256) void gemm_kernel(GemmBa
       else             { k = tid & 15; m = (tid >> 4) + (NT / 16) * p; }
       int gm = m0 + m, gk = k0 + k;
       cplx<R> v = mk<R>(0, 0);
-      if (gm < M && gk < K) {
+      if constexpr (ABEM) {
+        // A = T(z_bz): row gm, column gk of the single-layer matrix
+        if (gm < M && gk < K) {
+          const c128 zb = bg.z[bz];
+          if (gm == gk) {
+            v = bem_diag(zb, bg.h);
+          } else {
+            const double dx = bg.xyz[3 * gm] - bg.xyz[3 * gk], dy = bg.xyz[3 * gm + 1] - bg.xyz[3 * gk + 1],
+                         dz = bg.xyz[3 * gm + 2] - bg.xyz[3 * gk + 2];
+            v = bem_entry<double>(sqrt(dx * dx + dy * dy + dz * dz), zb.re, zb.im);
+          }
+        }
+      } else if (gm < M && gk < K) {
         long idx = (OPA == OP_N) ? (long)gm + (long)gk * g.lda : (long)gk + (long)gm * g.lda;
         if (AREAL) v.re = Ar[idx];
         else {
@@ -236,6 +259,107 @@ __global__ __launch_bounds__(sizeof(R) == 8 ? 512 : 256) void gemm_kernel(GemmBa
     __syncthreads();
   }
 }
+
+template <typename R, int OPA, int OPB, bool AREAL, bool G3M>
+__global__ __launch_bounds__(sizeof(R) == 8 ? 512 : 256) void gemm_kernel(GemmBatch<R> g) {
+  if (g.active && !g.active[blockIdx.z]) return;
+  gemm_body<R, OPA, OPB, AREAL, G3M, false>(g, BemGen{nullptr, 0.0, nullptr}, blockIdx.x * BM, blockIdx.y * BN,
+                                            blockIdx.z);
+}
+
+__global__ __launch_bounds__(512) void bem_gemm_kernel(GemmBatch<double> g, BemGen bg) {
+  gemm_body<double, OP_N, OP_N, false, false, true>(g, bg, blockIdx.x * BM, blockIdx.y * BN, blockIdx.z);
+}
+
+int bem_gemm(const GemmBatch<double>& g, const double* xyz, double h, const c128* z_dev, hipStream_t s) {
+  if (g.M <= 0 || g.N <= 0 || g.batch <= 0) return ST_OK;
+  if (g.M != g.K || g.opA != OP_N || g.opB != OP_N || g.a_real || g.gauss3m)
+    return set_error(ST_EINVAL, "bem_gemm: needs a square generated A, no transposes, 4M products");
+  dim3 grid((unsigned)cdivl(g.M, BM), (unsigned)cdivl(g.N, BN), (unsigned)g.batch);
+  KernelTimer kt(g.tag, s, 8.0 * g.M * (double)g.N * g.K * g.batch,
+                 16.0 * g.batch * ((double)g.K * g.N + 2.0 * g.M * g.N),
+                 timers_on() ? std::string("bem_gemm_kernel") : std::string());
+  hipLaunchKernelGGL(bem_gemm_kernel, grid, dim3(gemm_threads<double>()), 0, s, g, BemGen{xyz, h, z_dev});
+  RSRR_LAUNCH_CHECK();
+  return ST_OK;
+}
+
+template <typename R> struct GSegDev {
+  const cplx<R>* A;
+  const cplx<R>* B;
+  cplx<R>* C;
+  long lda, sA, ldb, sB, ldc, sC;
+  int M, N, K, tm, tn;      // shape, tiles along M and N
+  long tile0;               // first tile of the segment in the launch
+};
+template <typename R> struct GSegArgs {
+  int count;
+  long total;
+  cplx<R> alpha, beta;
+  GSegDev<R> s[GSEG];
+};
+
+template <typename R, bool G3M>
+__global__ __launch_bounds__(sizeof(R) == 8 ? 512 : 256) void gemm_seg_kernel(GSegArgs<R> a) {
+  for (long t = blockIdx.x; t < a.total; t += gridDim.x) {
+    int q = 0;
+    while (q + 1 < a.count && t >= a.s[q + 1].tile0) ++q;
+    const GSegDev<R>& d = a.s[q];
+    const long u = t - d.tile0, per = (long)d.tm * d.tn;
+    const int bz = (int)(u / per);
+    const int r = (int)(u - (long)bz * per);
+    GemmBatch<R> g;
+    g.M = d.M; g.N = d.N; g.K = d.K;
+    g.alpha = a.alpha; g.beta = a.beta;
+    g.A = d.A; g.lda = d.lda; g.sA = d.sA;
+    g.B = d.B; g.ldb = d.ldb; g.sB = d.sB;
+    g.C = d.C; g.ldc = d.ldc; g.sC = d.sC;
+    gemm_body<R, OP_N, OP_N, false, G3M, false>(g, BemGen{nullptr, 0.0, nullptr}, (r % d.tm) * BM,
+                                                (r / d.tm) * BN, bz);
+  }
+}
+
+template <typename R>
+int gemm_segments(const GemmSegs<R>& sg, hipStream_t s) {
+  if (sg.count < 0 || sg.count > GSEG) return set_error(ST_EINVAL, "gemm_segments: %d segments", sg.count);
+  GSegArgs<R> a;
+  a.count = 0;
+  a.total = 0;
+  double flops = 0, bytes = 0;
+  const double es = (double)sizeof(cplx<R>);
+  for (int q = 0; q < sg.count; ++q) {
+    const GemmBatch<R>& g = sg.g[q];
+    if (g.opA != OP_N || g.opB != OP_N || g.a_real || g.active)
+      return set_error(ST_EINVAL, "gemm_segments: untransposed complex operands only");
+    if (g.M <= 0 || g.N <= 0 || g.batch <= 0) continue;
+    GSegDev<R>& d = a.s[a.count++];
+    d.A = (const cplx<R>*)g.A; d.B = g.B; d.C = g.C;
+    d.lda = g.lda; d.sA = g.sA; d.ldb = g.ldb; d.sB = g.sB; d.ldc = g.ldc; d.sC = g.sC;
+    d.M = g.M; d.N = g.N; d.K = g.K;
+    d.tm = (int)cdivl(g.M, BM);
+    d.tn = (int)cdivl(g.N, BN);
+    d.tile0 = a.total;
+    a.total += (long)d.tm * d.tn * g.batch;
+    flops += 8.0 * g.M * (double)g.N * g.K * g.batch;
+    bytes += g.batch * (es * ((double)g.M * g.K + (double)g.K * g.N) + 2.0 * es * (double)g.M * g.N);
+  }
+  if (a.total == 0) return ST_OK;
+  a.alpha = sg.g[0].alpha;
+  a.beta = sg.g[0].beta;
+  const long cap = (sizeof(R) == 8 ? 4 : 8) * 256;      // resident workgroups on 256 CUs
+  const unsigned grid = (unsigned)std::min<long>(a.total, cap);
+  const bool g3m = sg.g[0].gauss3m;
+  KernelTimer kt(sg.g[0].tag, s, flops, bytes,
+                 timers_on() ? std::string("gemm_seg_kernel<") + (sizeof(R) == 8 ? "double" : "float") + ", " +
+                                   (g3m ? "true" : "false") + ">"
+                             : std::string());
+  if (g3m) hipLaunchKernelGGL((gemm_seg_kernel<R, true>), dim3(grid), dim3(gemm_threads<R>()), 0, s, a);
+  else hipLaunchKernelGGL((gemm_seg_kernel<R, false>), dim3(grid), dim3(gemm_threads<R>()), 0, s, a);
+  RSRR_LAUNCH_CHECK();
+  return ST_OK;
+}
+template int gemm_segments<double>(const GemmSegs<double>&, hipStream_t);
+template int gemm_segments<float>(const GemmSegs<float>&, hipStream_t);
 
 template <typename R, int OPA, int OPB, bool AREAL, bool G3M>
 static int launch_one(const GemmBatch<R>& g, hipStream_t s) {

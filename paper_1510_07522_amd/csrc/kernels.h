@@ -1,5 +1,7 @@
 // Internal (C++) interfaces between the RSRR host driver and its kernels.
 #pragma once
+#include <vector>
+
 #include "common.h"
 
 namespace rsrr {
@@ -21,6 +23,23 @@ template <typename R> struct GemmBatch {
   const char* tag = "gemm";   // kernel-timer class
 };
 template <typename R> int gemm_batched(const GemmBatch<R>& g, hipStream_t s);
+// Up to GSEG strided batches of different shapes in one launch (the LU
+// updates of instances of different orders): a persistent grid of workgroups
+// walks the 64x64 tiles of all segments in a fixed order, with no atomics,
+// each workgroup ending after its last tile.  Both operands untransposed and
+// complex; segment q is g[q] (M, N, K, pointers, leading dims, strides,
+// batch); alpha, beta, gauss3m and the timer tag are those of g[0].  Every
+// element is computed exactly as gemm_batched computes it.
+constexpr int GSEG = 16;
+template <typename R> struct GemmSegs {
+  int count = 0;
+  GemmBatch<R> g[GSEG];
+};
+template <typename R> int gemm_segments(const GemmSegs<R>& sg, hipStream_t s);
+// C_b = alpha T(z_b) B_b + beta C_b (fp64, 4M on the matrix cores) with T(z_b)
+// the BEM single-layer matrix (n = g.M = g.K points xyz, spacing h) generated
+// tile by tile where the GEMM stages its A operand; g.A is ignored.
+int bem_gemm(const GemmBatch<double>& g, const double* xyz, double h, const c128* z_dev, hipStream_t s);
 
 // ---------------------------------------------------------------- batched LU
 // Factors `batch` n x n matrices stored with leading dimension lda and batch
@@ -61,6 +80,15 @@ template <typename R> struct LUWork {
   }
 };
 template <typename R> int lu_factor(const LUWork<R>& w, hipStream_t s);
+// Several strided batches of matrices of different orders (same nb, product
+// form and pair mode; pairs of panels are always used) factored as one set of
+// launches per panel step: every panel, interchange and update launch covers
+// all batches whose order reaches that step (updates through gemm_segments,
+// a persistent grid over the tiles of all batches).  Look-ahead on aux when
+// aux and both events are given.  Each matrix is factored bit for bit as
+// lu_factor (with pairs) factors it alone.
+template <typename R> int lu_factor_segments(const std::vector<LUWork<R>>& ws, hipStream_t s, hipStream_t aux,
+                                             hipEvent_t ev_main, hipEvent_t ev_aux);
 // Solves A_b X_b = B_b in place for nrhs columns (B leading dim ldb, stride sB).
 // active (optional, device): systems b with active[b] == 0 are left untouched.
 template <typename R> int lu_solve(const LUWork<R>& w, cplx<R>* B, long ldb, long sB,

@@ -13,7 +13,9 @@
 #include "common.h"
 #include "kernels.h"
 #include "timers.h"
+#include <algorithm>
 #include <string>
+#include <vector>
 
 namespace rsrr {
 
@@ -23,14 +25,36 @@ constexpr int MAXNB = 64;
 // gives the L columns): groups of 256 columns
 __host__ __device__ constexpr int lu_group(int nb) { return nb >= 256 ? 1 : 256 / nb; }
 
+// Several strided batches of matrices of different orders, for launches that
+// cover them all (segment q: matrices first[q] .. first[q+1]-1 of the launch).
+constexpr int MAXSEG = 16;
+template <typename R> struct LUSegDev {
+  cplx<R>* A;        // first matrix, leading dim lda, batch stride sA
+  long lda, sA;
+  int n;             // order
+  int* ipiv;         // n per matrix
+  cplx<R>* dinv;     // sD per matrix
+  long sD;
+  int* info;         // one per matrix
+  int c0, ncols;     // row interchanges: the columns they apply to
+  int k, nbe;        // row interchanges: the panel whose pivots are applied
+};
+template <typename R> struct LUSegArgs {
+  int count;
+  int first[MAXSEG + 1];
+  LUSegDev<R> seg[MAXSEG];
+};
+
 template <typename R> __device__ inline cplx<R> shfl_c(cplx<R> v, int src) {
   return mk<R>(__shfl(v.re, src), __shfl(v.im, src));
 }
 
+// Panel of one matrix: columns [k, k + nbe) of Ab (order n, leading dim lda),
+// pivots into pv, the diagonal-block inverses into dl (2 nb^2 elements), the
+// status word *info_b.
 template <typename R, int ROWS, int W>
-__global__ __launch_bounds__(PNT) void lu_panel_kernel(cplx<R>* A, long lda, long sA, int n,
-                                                        int k, int nbe, int nb, int* ipiv,
-                                                        cplx<R>* dinv, long sD, int* info) {
+__device__ __forceinline__ void lu_panel_body(cplx<R>* Ab, long lda, int n, int k, int nbe, int nb, int* pv,
+                                              cplx<R>* dl, int* info_b) {
   // Thread tid owns rows c + tid + PNT*i (i < ROWS) of the current micro-panel
   // of W columns, kept in registers.  Per pivot: wave arg-max -> every wave
   // leader publishes its value and index, the lane owning the wave's best row
@@ -51,10 +75,7 @@ __global__ __launch_bounds__(PNT) void lu_panel_kernel(cplx<R>* A, long lda, lon
   __shared__ int s_cnt;
   __shared__ cplx<R> s_mv[2 * W][MAXNB];
 
-  const int b = blockIdx.x;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  cplx<R>* Ab = A + (long)b * sA;
-  int* pv = ipiv + (long)b * n;
   cplx<R> a[ROWS][W];
   int parity = 0;
 
@@ -150,7 +171,7 @@ __global__ __launch_bounds__(PNT) void lu_panel_kernel(cplx<R>* A, long lda, lon
         if (tid == 0) {
           pv[col] = p;
           s_piv[jj] = p;
-          if (zero && info[b] == 0) info[b] = col + 1;
+          if (zero && *info_b == 0) *info_b = col + 1;
         }
         const cplx<R>* prow = zero ? s_crow[parity] : s_cand[parity][wb];
         if (p != col) {
@@ -286,7 +307,7 @@ __global__ __launch_bounds__(PNT) void lu_panel_kernel(cplx<R>* A, long lda, lon
     s_D[i][j] = Ab[k + i + (long)(k + j) * lda];
   }
   __syncthreads();
-  cplx<R>* DL = dinv + (long)b * sD;
+  cplx<R>* DL = dl;
   cplx<R>* DU = DL + (long)nb * nb;
   const int i = lane;
   if (wave < 8) {
@@ -315,23 +336,40 @@ __global__ __launch_bounds__(PNT) void lu_panel_kernel(cplx<R>* A, long lda, lon
   }
 }
 
+template <typename R, int ROWS, int W>
+__global__ __launch_bounds__(PNT) void lu_panel_kernel(cplx<R>* A, long lda, long sA, int n,
+                                                        int k, int nbe, int nb, int* ipiv,
+                                                        cplx<R>* dinv, long sD, int* info) {
+  const int b = blockIdx.x;
+  lu_panel_body<R, ROWS, W>(A + (long)b * sA, lda, n, k, nbe, nb, ipiv + (long)b * n, dinv + (long)b * sD,
+                            info + b);
+}
+
+// The panels at column k of several strided batches of different orders in
+// one launch: workgroup g factors matrix g - first[q] of segment q.
+template <typename R, int ROWS, int W>
+__global__ __launch_bounds__(PNT) void lu_panel_seg_kernel(LUSegArgs<R> a, int k, int nb) {
+  int q = 0;
+  while (q + 1 < a.count && (int)blockIdx.x >= a.first[q + 1]) ++q;
+  const LUSegDev<R>& sg = a.seg[q];
+  const int b = blockIdx.x - a.first[q];
+  const int nbe = min(nb, sg.n - k);
+  lu_panel_body<R, ROWS, W>(sg.A + (long)b * sg.sA, sg.lda, sg.n, k, nbe, nb, sg.ipiv + (long)b * sg.n,
+                            sg.dinv + (long)b * sg.sD + (long)(k / nb) * 2 * nb * nb, sg.info + b);
+}
+
 // Applies the interchanges ipiv[k .. k+nbe) (each row i swapped with
 // ipiv[i] >= i, in order) to columns [0, ncols) of X as one gather: every
 // touched row gets its final source row.
 template <typename R> struct SwCols { static constexpr int v = 8 * 16 / (int)sizeof(cplx<R>) * 2; };  // 32 (fp32) / 16 (fp64) columns per workgroup
 template <typename R>
-__global__ __launch_bounds__(256) void lu_permute_kernel(cplx<R>* X, long ldx, long sX, int ncols,
-                                                         const int* ipiv, int ipiv_stride, int k,
-                                                         int nbe, const int* active) {
+__device__ __forceinline__ void lu_permute_body(cplx<R>* Xb, long ldx, int ncols, const int* pv, int k, int nbe,
+                                                int c0) {
   __shared__ int t_row[2 * MAXNB], t_src[2 * MAXNB];
   __shared__ int s_cnt;
   constexpr int SWC = SwCols<R>::v;
   __shared__ cplx<R> vals[2 * MAXNB][SWC];
-  const int b = blockIdx.y;
-  if (active && !active[b]) return;
   const int tid = threadIdx.x;
-  const int* pv = ipiv + (long)b * ipiv_stride;
-  cplx<R>* Xb = X + (long)b * sX;
   if (tid < 64) {
     const int lane = tid;
     for (int e = lane; e < nbe; e += 64) { t_row[e] = k + e; t_src[e] = k + e; }
@@ -368,7 +406,6 @@ __global__ __launch_bounds__(256) void lu_permute_kernel(cplx<R>* X, long ldx, l
   }
   __syncthreads();
   const int cnt = s_cnt;
-  const int c0 = blockIdx.x * SWC;
   const int jc = tid % SWC;
   const int col = c0 + jc;
   for (int e = tid / SWC; e < cnt; e += 256 / SWC)
@@ -376,6 +413,30 @@ __global__ __launch_bounds__(256) void lu_permute_kernel(cplx<R>* X, long ldx, l
   __syncthreads();
   for (int e = tid / SWC; e < cnt; e += 256 / SWC)
     if (col < ncols) Xb[t_row[e] + (long)col * ldx] = vals[e][jc];
+}
+
+template <typename R>
+__global__ __launch_bounds__(256) void lu_permute_kernel(cplx<R>* X, long ldx, long sX, int ncols,
+                                                         const int* ipiv, int ipiv_stride, int k,
+                                                         int nbe, const int* active) {
+  const int b = blockIdx.y;
+  if (active && !active[b]) return;
+  lu_permute_body<R>(X + (long)b * sX, ldx, ncols, ipiv + (long)b * ipiv_stride, k, nbe,
+                     blockIdx.x * SwCols<R>::v);
+}
+
+// The same over segments: workgroup row y is matrix y - first[q] of segment q,
+// whose columns [c0, c0 + ncols) take the interchanges of its panel at k.
+template <typename R>
+__global__ __launch_bounds__(256) void lu_permute_seg_kernel(LUSegArgs<R> a) {
+  int q = 0;
+  while (q + 1 < a.count && (int)blockIdx.y >= a.first[q + 1]) ++q;
+  const LUSegDev<R>& sg = a.seg[q];
+  const int c0 = blockIdx.x * SwCols<R>::v;
+  if (c0 >= sg.ncols) return;
+  const int b = blockIdx.y - a.first[q];
+  lu_permute_body<R>(sg.A + (long)b * sg.sA + (long)sg.c0 * sg.lda, sg.lda, sg.ncols, sg.ipiv + (long)b * sg.n,
+                     sg.k, sg.nbe, c0);
 }
 
 template <typename R>
@@ -815,6 +876,269 @@ int lu_inverse(const LUWork<R>& w, cplx<R>* X, cplx<R>* out, long ldo, long sO, 
   RSRR_LAUNCH_CHECK();
   return ST_OK;
 }
+
+// ---------------------------------------------------------------------------
+// Several strided batches of different orders factored as one set of launches
+// per panel step (see kernels.h).  The operations and their order per matrix
+// are those of lu_factor with pairs of panels and look-ahead, so each matrix
+// is factored bit for bit as lu_factor factors it alone.
+namespace {
+
+template <typename R> LUSegDev<R> seg_of(const LUWork<R>& w) {
+  LUSegDev<R> d;
+  d.A = w.A; d.lda = w.lda; d.sA = w.sA; d.n = w.n; d.ipiv = w.ipiv; d.dinv = w.dinv;
+  d.sD = (long)w.npanel() * 2 * w.nb * w.nb; d.info = w.info;
+  d.c0 = d.ncols = d.k = d.nbe = 0;
+  return d;
+}
+
+// one launch per MAXSEG entries of `list`; grid rows are the matrices
+template <typename R, typename F>
+int seg_chunks(const std::vector<LUSegDev<R>>& list, const std::vector<int>& batch, F launch) {
+  for (size_t i0 = 0; i0 < list.size(); i0 += MAXSEG) {
+    LUSegArgs<R> a;
+    a.count = 0;
+    int tot = 0, maxc = 0;
+    for (size_t i = i0; i < list.size() && i < i0 + MAXSEG; ++i) {
+      a.first[a.count] = tot;
+      a.seg[a.count] = list[i];
+      tot += batch[i];
+      maxc = std::max(maxc, list[i].ncols);
+      ++a.count;
+    }
+    a.first[a.count] = tot;
+    RSRR_TRY(launch(a, tot, maxc));
+  }
+  return ST_OK;
+}
+
+template <typename R, int ROWS>
+int launch_panel_seg_rows(const LUSegArgs<R>& a, int tot, int k, int nb, const char* tag, double flops,
+                          double bytes, hipStream_t s) {
+  constexpr int W = (sizeof(R) == 8) ? (ROWS == 1 ? 8 : 8 / ROWS) : (ROWS == 1 ? 16 : 16 / ROWS);
+  const std::string tn = std::string(tag) + "_panel";
+  KernelTimer kt(tn.c_str(), s, flops, bytes,
+                 timers_on() ? std::string("lu_panel_seg_kernel<") + (sizeof(R) == 8 ? "double" : "float") + ", " +
+                                   std::to_string(ROWS) + ", " + std::to_string(W) + ">"
+                             : std::string());
+  hipLaunchKernelGGL((lu_panel_seg_kernel<R, ROWS, W>), dim3(tot), dim3(PNT), 0, s, a, k, nb);
+  RSRR_LAUNCH_CHECK();
+  return ST_OK;
+}
+
+}  // namespace
+
+template <typename R>
+int lu_factor_segments(const std::vector<LUWork<R>>& ws, hipStream_t s, hipStream_t aux, hipEvent_t ev_main,
+                       hipEvent_t ev_aux) {
+  if (ws.empty()) return ST_OK;
+  const int nb = ws[0].nb;
+  const bool g3m = ws[0].gauss3m;
+  int nmax = 0;
+  for (const LUWork<R>& w : ws) {
+    if (w.nb != nb || w.gauss3m != g3m || w.full_swap)
+      return set_error(ST_EINVAL, "lu_factor_segments: batches must share nb and the product form");
+    if (w.n > 8 * PNT || w.n < 1 || w.batch < 1) return set_error(ST_EINVAL, "lu_factor_segments: n=%d", w.n);
+    nmax = std::max(nmax, w.n);
+  }
+  if (nb < 1 || nb > MAXNB || lu_group(nb) % 2) return set_error(ST_EINVAL, "lu_factor_segments: nb=%d", nb);
+  for (const LUWork<R>& w : ws) {
+    hipLaunchKernelGGL(zero_int_kernel, dim3((unsigned)cdivl(w.batch, 256)), dim3(256), 0, s, w.info, w.batch);
+    RSRR_LAUNCH_CHECK();
+  }
+  const int Q = (int)ws.size();
+  const std::string t_trsm = std::string(ws[0].tag) + "_trsm", t_upd = std::string(ws[0].tag) + "_update";
+  const bool la = aux && ev_main && ev_aux;
+  bool aux_busy = false;
+  // panels at column k of every batch whose order exceeds k, one launch per
+  // register class (rows per thread) and MAXSEG batches
+  auto panels = [&](int k, hipStream_t st) -> int {
+    for (int rows : {1, 2, 4, 8}) {
+      std::vector<LUSegDev<R>> list;
+      std::vector<int> bt;
+      double fl = 0, by = 0;
+      for (const LUWork<R>& w : ws) {
+        const int m = w.n - k;
+        if (m <= 0) continue;
+        const int cls = m <= PNT ? 1 : m <= 2 * PNT ? 2 : m <= 4 * PNT ? 4 : 8;
+        if (cls != rows) continue;
+        list.push_back(seg_of(w));
+        bt.push_back(w.batch);
+        const int nbe = std::min(nb, m);
+        fl += 8.0 * nbe * nbe * m * w.batch / 2.0;
+        by += 2.0 * sizeof(cplx<R>) * (double)m * nbe * w.batch;
+      }
+      RSRR_TRY(seg_chunks<R>(list, bt, [&](const LUSegArgs<R>& a, int tot, int) -> int {
+        switch (rows) {
+          case 1: return launch_panel_seg_rows<R, 1>(a, tot, k, nb, ws[0].tag, fl, by, st);
+          case 2: return launch_panel_seg_rows<R, 2>(a, tot, k, nb, ws[0].tag, fl, by, st);
+          case 4: return launch_panel_seg_rows<R, 4>(a, tot, k, nb, ws[0].tag, fl, by, st);
+          default: return launch_panel_seg_rows<R, 8>(a, tot, k, nb, ws[0].tag, fl, by, st);
+        }
+      }));
+    }
+    return ST_OK;
+  };
+  // row interchanges: (batch q, first column, columns, panel k, its width)
+  struct PJob { int q, c0, ncols, k, nbe; };
+  auto permutes = [&](const std::vector<PJob>& jobs, hipStream_t st) -> int {
+    std::vector<LUSegDev<R>> list;
+    std::vector<int> bt;
+    double by = 0;
+    for (const PJob& j : jobs) {
+      if (j.ncols <= 0 || j.nbe <= 0) continue;
+      LUSegDev<R> d = seg_of(ws[j.q]);
+      d.c0 = j.c0; d.ncols = j.ncols; d.k = j.k; d.nbe = j.nbe;
+      list.push_back(d);
+      bt.push_back(ws[j.q].batch);
+      by += 4.0 * sizeof(cplx<R>) * j.nbe * (double)j.ncols * ws[j.q].batch;
+    }
+    return seg_chunks<R>(list, bt, [&](const LUSegArgs<R>& a, int tot, int maxc) -> int {
+      KernelTimer kt("lu_permute", st, 0.0, by,
+                     timers_on() ? std::string("lu_permute_seg_kernel<") + (sizeof(R) == 8 ? "double" : "float") + ">"
+                                 : std::string());
+      hipLaunchKernelGGL((lu_permute_seg_kernel<R>), dim3((unsigned)cdivl(maxc, SwCols<R>::v), (unsigned)tot),
+                         dim3(256), 0, st, a);
+      RSRR_LAUNCH_CHECK();
+      return ST_OK;
+    });
+  };
+  // products, GSEG batches per launch
+  auto gemms = [&](const std::vector<GemmBatch<R>>& list, hipStream_t st) -> int {
+    for (size_t i0 = 0; i0 < list.size(); i0 += GSEG) {
+      GemmSegs<R> sg;
+      for (size_t i = i0; i < list.size() && i < i0 + GSEG; ++i) sg.g[sg.count++] = list[i];
+      RSRR_TRY(gemm_segments<R>(sg, st));
+    }
+    return ST_OK;
+  };
+  // U rows = inv(L_diag) A rows (in place) for batch q, panel at k of width nbe, columns [c0, c0 + nc)
+  auto trsm_g = [&](int q, int k, int nbe, int c0, int nc) {
+    const LUWork<R>& w = ws[q];
+    GemmBatch<R> g;
+    g.M = nbe; g.N = nc; g.K = nbe;
+    g.A = w.dinv + (long)(k / nb) * 2 * nb * nb; g.lda = nb; g.sA = (long)w.npanel() * 2 * nb * nb;
+    g.B = w.A + k + (long)c0 * w.lda; g.ldb = w.lda; g.sB = w.sA;
+    g.C = w.A + k + (long)c0 * w.lda; g.ldc = w.lda; g.sC = w.sA;
+    g.batch = w.batch;
+    g.tag = t_trsm.c_str();
+    g.gauss3m = g3m;
+    return g;
+  };
+  // rows [k + nbe, k + nbe + M) -= L(:, k .. k+nbe) U(k .. k+nbe, columns)
+  auto upd_g = [&](int q, int k, int nbe, int c0, int nc, int M) {
+    const LUWork<R>& w = ws[q];
+    GemmBatch<R> u;
+    u.M = M; u.N = nc; u.K = nbe;
+    u.alpha = mk<R>(-1, 0); u.beta = mk<R>(1, 0);
+    u.A = w.A + (k + nbe) + (long)k * w.lda; u.lda = w.lda; u.sA = w.sA;
+    u.B = w.A + k + (long)c0 * w.lda; u.ldb = w.lda; u.sB = w.sA;
+    u.C = w.A + (k + nbe) + (long)c0 * w.lda; u.ldc = w.lda; u.sC = w.sA;
+    u.batch = w.batch;
+    u.tag = t_upd.c_str();
+    u.gauss3m = g3m;
+    return u;
+  };
+  // the pair at k applied to columns [c0[q], c0[q] + nc[q]) of every batch with nc > 0
+  auto tail = [&](int k, const std::vector<int>& c0, const std::vector<int>& nc, hipStream_t st) -> int {
+    std::vector<PJob> pa, pb;
+    std::vector<GemmBatch<R>> ta, ub, tb, big;
+    for (int q = 0; q < Q; ++q) {
+      if (nc[q] <= 0) continue;
+      const int n = ws[q].n, na = std::min(nb, n - k), kb = k + na, nbb = std::max(0, std::min(nb, n - kb));
+      const int c1 = kb + nbb;
+      pa.push_back(PJob{q, c0[q], nc[q], k, na});
+      if (nbb > 0) pb.push_back(PJob{q, c0[q], nc[q], kb, nbb});
+      ta.push_back(trsm_g(q, k, na, c0[q], nc[q]));
+      if (nbb > 0) {
+        ub.push_back(upd_g(q, k, na, c0[q], nc[q], nbb));
+        tb.push_back(trsm_g(q, kb, nbb, c0[q], nc[q]));
+      }
+      if (c1 < n) big.push_back(upd_g(q, k, na + nbb, c0[q], nc[q], n - c1));
+    }
+    RSRR_TRY(permutes(pa, st));
+    RSRR_TRY(permutes(pb, st));
+    RSRR_TRY(gemms(ta, st));
+    RSRR_TRY(gemms(ub, st));
+    RSRR_TRY(gemms(tb, st));
+    RSRR_TRY(gemms(big, st));
+    return ST_OK;
+  };
+
+  RSRR_TRY(panels(0, s));
+  for (int k = 0; k < nmax; k += 2 * nb) {
+    // second panel of each pair: the first's update on its columns, factor,
+    // then its interchanges on the first's L columns
+    std::vector<PJob> pb, fix;
+    std::vector<GemmBatch<R>> tr, up;
+    bool anyb = false;
+    for (int q = 0; q < Q; ++q) {
+      const int n = ws[q].n;
+      if (k >= n) continue;
+      const int na = std::min(nb, n - k), kb = k + na, nbb = std::min(nb, n - kb);
+      if (nbb <= 0) continue;
+      anyb = true;
+      pb.push_back(PJob{q, kb, nbb, k, na});
+      tr.push_back(trsm_g(q, k, na, kb, nbb));
+      up.push_back(upd_g(q, k, na, kb, nbb, n - k - na));
+      fix.push_back(PJob{q, k, na, kb, nbb});
+    }
+    if (anyb) {
+      RSRR_TRY(permutes(pb, s));
+      RSRR_TRY(gemms(tr, s));
+      RSRR_TRY(gemms(up, s));
+      RSRR_TRY(panels(k + nb, s));
+      RSRR_TRY(permutes(fix, s));
+    }
+    std::vector<int> nx0(Q, 0), nxc(Q, 0), fr0(Q, 0), frc(Q, 0);
+    bool anyrest = false, anyfar = false;
+    for (int q = 0; q < Q; ++q) {
+      const int n = ws[q].n;
+      if (k >= n) continue;
+      const int c1 = std::min(n, k + 2 * nb), rest = n - c1;
+      if (rest <= 0) continue;
+      const int nxt = la ? std::min(2 * nb, rest) : rest;
+      nx0[q] = c1; nxc[q] = nxt;
+      fr0[q] = c1 + nxt; frc[q] = rest - nxt;
+      anyrest = true;
+      anyfar |= frc[q] > 0;
+    }
+    if (!anyrest) continue;
+    if (aux_busy) {
+      RSRR_HIP(hipStreamWaitEvent(s, ev_aux, 0));
+      aux_busy = false;
+    }
+    if (anyfar) {
+      RSRR_HIP(hipEventRecord(ev_main, s));
+      RSRR_HIP(hipStreamWaitEvent(aux, ev_main, 0));
+      RSRR_TRY(tail(k, fr0, frc, aux));
+      RSRR_HIP(hipEventRecord(ev_aux, aux));
+      aux_busy = true;
+    }
+    RSRR_TRY(tail(k, nx0, nxc, s));
+    RSRR_TRY(panels(k + 2 * nb, s));
+  }
+  if (aux_busy) RSRR_HIP(hipStreamWaitEvent(s, ev_aux, 0));
+  // interchanges of the later panels of each group on the earlier L columns
+  // (the second panel of a pair has already done its pair)
+  const int SB = lu_group(nb);
+  for (int qp = 1; qp * nb < nmax; ++qp) {
+    if (qp % SB == 0) continue;
+    std::vector<PJob> jobs;
+    for (int q = 0; q < Q; ++q) {
+      const int n = ws[q].n, k = qp * nb;
+      if (k >= n) continue;
+      const int c0 = (qp / SB) * SB * nb, cols = k - c0 - ((qp % 2 == 1) ? nb : 0);
+      if (cols > 0) jobs.push_back(PJob{q, c0, cols, k, std::min(nb, n - k)});
+    }
+    RSRR_TRY(permutes(jobs, s));
+  }
+  return ST_OK;
+}
+template int lu_factor_segments<double>(const std::vector<LUWork<double>>&, hipStream_t, hipStream_t, hipEvent_t,
+                                        hipEvent_t);
+template int lu_factor_segments<float>(const std::vector<LUWork<float>>&, hipStream_t, hipStream_t, hipEvent_t,
+                                       hipEvent_t);
 
 template int lu_factor<double>(const LUWork<double>&, hipStream_t);
 template int lu_factor<float>(const LUWork<float>&, hipStream_t);

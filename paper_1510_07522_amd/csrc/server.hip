@@ -41,28 +41,6 @@ struct DeviceSlot {
   rsrr_problem view;            // aliases the request's problem; owns only the workspace
 };
 
-// The view shares the problem's device data (coefficients, BEM points) and
-// host descriptors; it never frees them.
-void bind_view(rsrr_problem* v, const rsrr_problem* p, hipStream_t s) {
-  v->n = p->n;
-  v->J = p->J;
-  v->bem = p->bem;
-  v->kinds = p->kinds;
-  v->fns = p->fns;
-  v->cb = p->cb;
-  v->cb_ctx = p->cb_ctx;
-  v->mats = p->mats;
-  v->gram = p->gram;
-  v->xyz = p->xyz;
-  v->h = p->h;
-  v->stream = s;
-}
-
-void unbind_view(rsrr_problem* v) {
-  v->mats.clear();
-  v->xyz = nullptr;
-}
-
 struct DeviceOps : sched::SlotOps {
   int device = 0;
   std::vector<DeviceSlot*> slots;
@@ -149,9 +127,9 @@ int rsrr_server_submit(rsrr_server* srv, rsrr_problem* p, const rsrr_contour* c,
   Request* r = new Request();
   r->p = p;
   r->c = *c;
-  r->prm = *prm;
+  r->prm = resolve_params(p, prm);
   if (U_host) r->U.assign((const c128*)U_host, (const c128*)U_host + (size_t)p->n * prm->L);
-  const size_t need = solve_workspace_bound(p, prm) + r->U.size() * sizeof(c128);
+  const size_t need = solve_workspace_bound(p, &r->prm) + r->U.size() * sizeof(c128);
   const int st = srv->sch->submit(need, r, ticket);
   if (st == sched::SUBMIT_OK) return ST_OK;
   delete r;

@@ -206,3 +206,37 @@ def test_c2_uneven_qeps_full_size_through_the_server(P):
         # here; the first-order correction brings the residuals back to the
         # level of a backward-stable Schur form
         assert np.max(outs[q]["res"]) <= 1e-12, np.max(outs[q]["res"])
+
+
+def test_c2_batched_full_size(P):
+    # the sixteen QEPs of the batched workload in one rsrr_solve_batched call
+    # (all 1024 sampling LUs factored together): the two smallest instances
+    # bit for bit against their solves alone, and the order-723 instance
+    # against the oracle's stored result (count and eigenvalues)
+    import json
+    import os
+    insts = ni.config_c2()
+    hs = [P.Problem(i[0]) for i in insts]
+    try:
+        cts = [ct(P, c) for _, c, _, _, _ in insts]
+        prms = [P.default_params(N=N, L=L, precision="c64_ir") for _, _, N, L, _ in insts]
+        Us = [P.to_device(U) for *_, U in insts]
+        outs = P.solve_batched(hs, cts, prms, Us)
+        order = np.argsort([i[0].n for i in insts])
+        for q in order[:2]:
+            alone = hs[q].solve(cts[q], prms[q], Us[q])
+            b = outs[q]
+            assert np.array_equal(alone["lam"], b["lam"]) and np.array_equal(alone["V"], b["V"])
+            assert np.array_equal(alone["res"], b["res"])
+    finally:
+        for h in hs:
+            h.close()
+    g = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "oracle_c2_723.json")))
+    q = [i for i, inst in enumerate(insts) if inst[0].n == 723][0]
+    ref = np.array([complex(c[0], c[1]) for c in g["candidates"] if c[2] <= 1e-10])
+    lam = outs[q]["lam"]
+    print("n=723 batched:", len(lam), "oracle:", len(ref))
+    assert len(lam) == len(ref) == g["count"]
+    assert match_sets(lam, ref) <= 1e-9 * 14.0
+    for (p, c, N, L, U), out in zip(insts, outs):
+        assert np.all(R.inside(c, out["lam"])) and np.all(out["res"] <= 1e-10)

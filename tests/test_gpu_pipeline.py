@@ -233,3 +233,24 @@ def test_solve_qep_divide_and_conquer_matches_oracle(P):
     assert info["n_eig"] == len(ref["lam"])
     assert match_sets(out["lam"], ref["lam"]) <= 1e-9 * 14.0
     assert np.all(out["res"] <= 1e-12)
+
+
+@pytest.mark.parametrize("prec", ["c128", "c64_ir"])
+def test_solve_moments_in_several_batches_match_oracle(P, prec):
+    # chunk_gib = 1/16 GiB holds 145 of the 512 reduced nodes of an order-120
+    # problem (two 120^2 complex128 matrices each), so the moments and the
+    # winding traces accumulate over four batches; same eigenvalues, count,
+    # winding number and Hankel singular values as the oracle
+    p, c, N, L, U = ni.config_small_qep(n=120, seed=71)
+    ref = R.rsrr(p, c, N, 16, ni.probing_matrix(120, 16, seed=72))
+    U = ni.probing_matrix(120, 16, seed=72)
+    one = gpu_solve(P, p, c, N, 16, U, prec)
+    four = gpu_solve(P, p, c, N, 16, U, prec, chunk_gib=0.0625)
+    for out in (one, four):
+        assert out["info"]["k_S"] == 120
+        assert out["info"]["n_wind"] == ref["n_wind"] and len(out["lam"]) == len(ref["lam"]) > 0
+        assert match_sets(out["lam"], ref["lam"]) <= 1e-9 * 7.0
+        assert np.all(out["res"] <= 1e-10)
+        m = ref["m"]
+        assert np.allclose(out["hankel_sigma"][:m], ref["hankel_sigma"][:m], rtol=1e-8, atol=1e-13 * ref["hankel_sigma"][0])
+    assert abs(four["info"]["wind_re"] - one["info"]["wind_re"]) <= 1e-9

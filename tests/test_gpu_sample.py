@@ -34,13 +34,19 @@ def oracle_S(prob, c, N, U):
     return R.sample_resolvent(prob, z, U)
 
 
+def column_errors(S, ref):
+    """Relative forward error of every column of S against the oracle's."""
+    return np.linalg.norm(S - ref, axis=0) / np.linalg.norm(ref, axis=0)
+
+
 def check_against_oracle(prob, c, N, L, U, S, prec, ir_tol=1e-14):
-    """complex128: forward error <= 1e-12.  complex64 + refinement: every block
-    has normwise backward error <= ir_tol (recomputed here in fp64) and a
-    forward error within cond(T(z_j)) * 4 ir_tol of the oracle's solve."""
+    """complex128: forward error of every column <= 1e-12.  complex64 +
+    refinement: every block has normwise backward error <= ir_tol (recomputed
+    here in fp64) and every column a forward error within cond(T(z_j)) * 4
+    ir_tol of the oracle's solve."""
     ref = oracle_S(prob, c, N, U)
     if prec == "c128":
-        assert np.linalg.norm(S - ref) / np.linalg.norm(ref) <= 1e-12
+        assert np.max(column_errors(S, ref)) <= 1e-12
         return
     _, z, _ = R.contour_nodes(c, N)
     for j, zj in enumerate(z):
@@ -49,7 +55,7 @@ def check_against_oracle(prob, c, N, L, U, S, prec, ir_tol=1e-14):
         eta = np.linalg.norm(U - T @ Y) / (np.linalg.norm(T) * np.linalg.norm(Y) + np.linalg.norm(U))
         assert eta <= 2 * ir_tol, (j, eta)
         Yr = ref[:, j * L:(j + 1) * L]
-        assert np.linalg.norm(Y - Yr) / np.linalg.norm(Yr) <= np.linalg.cond(T) * 4 * ir_tol + 1e-13
+        assert np.max(column_errors(Y, Yr)) <= np.linalg.cond(T) * 4 * ir_tol + 1e-13, j
 
 
 @pytest.mark.parametrize("prec", ["c128", "c64_ir"])
