@@ -75,12 +75,22 @@ def traffic_record(sym: str):
 
 
 def _pmc_rows(folder: str):
+    """Per-dispatch counter values of one rocprofv3 --pmc output folder, as
+    {"Kernel_Name", "Counter_Value"} rows: from its counter_collection.csv
+    (--output-format csv) or from its results database (the default format)."""
     import csv
     import glob
     files = glob.glob(os.path.join(folder, "**", "*counter_collection.csv"), recursive=True)
-    if len(files) != 1:
-        raise SystemExit(f"{folder}: expected one counter_collection.csv, found {len(files)}")
-    return list(csv.DictReader(open(files[0])))
+    if len(files) == 1:
+        return list(csv.DictReader(open(files[0])))
+    dbs = glob.glob(os.path.join(folder, "**", "*results.db"), recursive=True)
+    if len(files) == 0 and len(dbs) == 1:
+        import sqlite3
+        con = sqlite3.connect(dbs[0])
+        rows = con.execute("select name, counter_value from pmc_events").fetchall()
+        con.close()
+        return [{"Kernel_Name": n, "Counter_Value": v} for n, v in rows]
+    raise SystemExit(f"{folder}: expected one counter_collection.csv or one results database")
 
 
 def _kernel_sym(name: str) -> str:
