@@ -50,8 +50,11 @@ inline size_t workspace_bound(int n_, int J_, bool bem, const rsrr_params* prm) 
   // projection (BEM: Chebyshev samples T(x_k) and T(x_k) Q in chunks)
   double proj = 2 * J * kk * z + n * kS * z;
   if (bem) {
-    const double chb = std::max(1.0, std::min(J, std::floor(cap / (n * n * z))));
-    proj += chb * (n * n + n * kS) * z + J * J * z + J * kk * z;
+    // the buffer of the interpolation samples also holds the fp64 T(z_j) of
+    // the refinement residual (a batch of nodes within chunk_gib)
+    const double fit = std::max(1.0, std::floor(cap / (n * n * z)));
+    const double chb = std::min(J, fit), chr = std::min(N, fit);
+    proj += std::max(chb, chr) * n * n * z + chb * n * kS * z + J * J * z + J * kk * z;
   }
   // moments: a batch of T_S(zeta) and inverses within chunk_gib
   const double ch = chunk_count(prm->NS, (size_t)(kk * z * 2), prm->chunk_gib).second;

@@ -13,6 +13,7 @@
 #include <cmath>
 #include <cstring>
 
+#include "bounds.h"
 #include "driver.h"
 #include "timers.h"
 
@@ -90,12 +91,35 @@ __global__ __launch_bounds__(256) void scatter_node_cols_c64_kernel(const c128* 
 }
 
 static int residual_fp64(rsrr_problem* p, int N, int L, const c128* f_dev, const c128* z_dev,
-                         const c128* U, long ldu, const c128* Y, long ldy, c128* Rb, hipStream_t s) {
+                         const c128* U, long ldu, const c128* Y, long ldy, c128* Rb, double chunk_gib,
+                         hipStream_t s) {
   const int n = p->n;
   const long cols = (long)N * L;
-  if (p->bem)
-    return bem_residual(n, p->xyz, p->h, N, z_dev, U, ldu, Y, ldy, (long)L * ldy, L, Rb, n,
-                        (long)L * n, s);
+  if (p->bem) {
+    // T(z_j) assembled in fp64 for a balanced batch of nodes that fits
+    // chunk_gib (in the buffer the interpolation samples of the projection
+    // use later), then R_j = U - T(z_j) Y_j on the matrix cores: the entries
+    // are computed once per sweep by a kernel that does nothing else, instead
+    // of inside the GEMM's operand staging where their latency is not hidden
+    const std::pair<int, int> bc = chunk_count(N, (size_t)n * n * sizeof(c128), chunk_gib);
+    c128* T = nullptr;
+    RSRR_TRY(p->ws.get<c128>("pj_T", (size_t)bc.second * n * n, &T));
+    RSRR_TRY((convert<double, double>(U, ldu, 0, Rb, n, (long)L * n, n, L, N, s)));
+    for (int j0 = 0; j0 < N; j0 += bc.second) {
+      const int cnt = std::min(bc.second, N - j0);
+      RSRR_TRY(assemble_bem<double>(n, p->xyz, p->h, cnt, z_dev + j0, T, n, (long)n * n, s));
+      GemmBatch<double> g;
+      g.M = n; g.N = L; g.K = n;
+      g.alpha = mk<double>(-1, 0); g.beta = mk<double>(1, 0);
+      g.A = T; g.lda = n; g.sA = (long)n * n;
+      g.B = Y + (long)j0 * L * ldy; g.ldb = ldy; g.sB = (long)L * ldy;
+      g.C = Rb + (long)j0 * L * n; g.ldc = n; g.sC = (long)L * n;
+      g.batch = cnt;
+      g.tag = "ir_residual_gemm";
+      RSRR_TRY(gemm_batched<double>(g, s));
+    }
+    return ST_OK;
+  }
   std::vector<const c128*> P(p->J);
   for (int k = 0; k < p->J; ++k) {
     c128* Pk = nullptr;
@@ -355,7 +379,7 @@ int sample_end(SamplePlan* sp) {
       // residuals of the nodes corrected in the last sweep (all in the first)
       const bool res_full = (nact == N);
       if (res_full) {
-        RSRR_TRY(residual_fp64(p, N, L, f_dev, z_dev, U, ldu, S, lds, Rb, s));
+        RSRR_TRY(residual_fp64(p, N, L, f_dev, z_dev, U, ldu, S, lds, Rb, prm->chunk_gib, s));
         RSRR_TRY(block_fro2(Rb, n, (long)L * n, n, L, N, nrm, s));
         RSRR_TRY(block_fro2(S, lds, (long)L * lds, n, L, N, nrm + N, s));
         RSRR_HIP(hipMemcpyAsync(r2.data(), nrm, N * sizeof(double), hipMemcpyDeviceToHost, s));
@@ -381,7 +405,7 @@ int sample_end(SamplePlan* sp) {
         hipLaunchKernelGGL(gather_node_cols_kernel, dim3((unsigned)cdivl((long)n * ca, 256)), dim3(256), 0, s, S,
                            lds, n, L, idx_dev, na, Sa, (long)n);
         RSRR_LAUNCH_CHECK();
-        RSRR_TRY(residual_fp64(p, na, L, fa_dev, za_dev, U, ldu, Sa, n, Ra, s));
+        RSRR_TRY(residual_fp64(p, na, L, fa_dev, za_dev, U, ldu, Sa, n, Ra, prm->chunk_gib, s));
         RSRR_TRY(block_fro2(Ra, n, (long)L * n, n, L, na, nrm, s));
         RSRR_TRY(block_fro2(Sa, n, (long)L * n, n, L, na, nrm + N, s));
         std::vector<double> ra(na), ya(na);
