@@ -373,7 +373,11 @@ int rsrr_gesv_batched(int precision, int n, int nrhs, void* A, int lda, long lon
  * element; a call that needs more than 64 MiB fails with RSRR_EINVAL and
  * touches nothing.  All calls on one GPU share the array: calls that overlap
  * in time on one GPU (other threads or streams) race and must be serialised
- * by the caller.  Arguments, results and errors as rsrr_gesv_batched. */
+ * by the caller.  Arguments, results and errors as rsrr_gesv_batched, except
+ * that with info_host NULL the call only enqueues its kernels on `stream`
+ * and returns without copying or waiting (so it can be recorded under stream
+ * capture): zero pivots are then not reported, and the results are complete
+ * when the stream reaches that point. */
 int rsrr_gesv_batched_noalloc(int precision, int n, int nrhs, void* A, int lda, long long sA, void* B,
                               int ldb, long long sB, int batch, int nb, int* info_host, void* stream);
 

@@ -512,13 +512,15 @@ def gemm(opA: str, opB: str, A, B, Cm, M: int, N: int, K: int, alpha=1.0, beta=0
                                         int(gauss3m), stream_ptr()))
 
 
-def gesv(A, B, n: int, nrhs: int, batch: int, nb: int = 64, noalloc: bool = False):
+def gesv(A, B, n: int, nrhs: int, batch: int, nb: int = 64, noalloc: bool = False, status: bool = True):
     """Batched LU solve in place (A: batch x n x n, B: batch x n x nrhs,
     column-major); noalloc uses the entry point whose work space is the
-    library's fixed device array."""
+    library's fixed device array.  status=False passes no status buffer (the
+    allocation-free call then only enqueues its kernels); the returned list is
+    then empty."""
     torch = _torch()
     prec = PREC_C128 if A.dtype == torch.complex128 else PREC_C64_IR
-    info = (C.c_int * batch)()
+    info = (C.c_int * batch)() if status else None
     f = load().rsrr_gesv_batched_noalloc if noalloc else load().rsrr_gesv_batched
     st = f(prec, n, nrhs, _ptr(A), n, n * n, _ptr(B), n, n * nrhs, batch, nb, info, stream_ptr())
-    return st, list(info)
+    return st, list(info) if status else []

@@ -72,6 +72,9 @@ int gesv_noalloc(int n, int nrhs, void* A, int lda, long long sA, void* B, int l
   w.dinv = (cplx<R>*)(p + b_info + b_ipiv);
   RSRR_TRY(lu_factor<R>(w, s));      // clears the status words first
   if (nrhs > 0) RSRR_TRY(lu_solve<R>(w, (cplx<R>*)B, ldb, sB, nrhs, s));
+  // without a status buffer the call only enqueues kernels (no copy, no wait:
+  // it can be recorded under stream capture); zero pivots are then not reported
+  if (!info_host) return ST_OK;
   // per-matrix status through a fixed host buffer
   int first_bad = -1, bad_at = 0;
   int h[256];
@@ -80,7 +83,7 @@ int gesv_noalloc(int n, int nrhs, void* A, int lda, long long sA, void* B, int l
     RSRR_HIP(hipMemcpyAsync(h, w.info + b0, cnt * sizeof(int), hipMemcpyDeviceToHost, s));
     RSRR_HIP(hipStreamSynchronize(s));
     for (int q = 0; q < cnt; ++q) {
-      if (info_host) info_host[b0 + q] = h[q];
+      info_host[b0 + q] = h[q];
       if (h[q] && first_bad < 0) { first_bad = b0 + q; bad_at = h[q]; }
     }
   }

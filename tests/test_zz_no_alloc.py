@@ -73,3 +73,42 @@ def test_noalloc_reports_exact_singularity(P):
     dB = torch.ones(2 * n, dtype=torch.complex128, device="cuda")
     st, info = P.gesv(dA, dB, n, 1, 2, 16, noalloc=True)
     assert st == -4 and info[0] == 8 and info[1] == 0
+
+
+@pytest.mark.parametrize("prec", ["c128", "c64"])
+def test_noalloc_without_status_enqueues_only_and_replays_in_a_graph(P, prec):
+    """With no status buffer the allocation-free call only enqueues kernels: it
+    gives the same bits as with one, and it can be captured in a HIP graph
+    (the inputs restored by a copy inside the graph); every replay, with
+    eager work and synchronisations between replays, equals the eager call."""
+    import torch
+    dt = np.complex128 if prec == "c128" else np.complex64
+    n, nrhs, batch, nb = 300, 4, 3, 32
+    rng = np.random.default_rng(21)
+    A, B, dA0, dB0 = _batch(rng, n, nrhs, batch, dt)
+    ref_A, ref_B = dA0.clone(), dB0.clone()
+    st, info = P.gesv(ref_A, ref_B, n, nrhs, batch, nb, noalloc=True)
+    assert st == 0 and info == [0] * batch
+    dA, dB = dA0.clone(), dB0.clone()
+    st, info = P.gesv(dA, dB, n, nrhs, batch, nb, noalloc=True, status=False)
+    torch.cuda.synchronize()
+    assert st == 0 and info == []
+    assert torch.equal(dA, ref_A) and torch.equal(dB, ref_B)
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.stream(side):
+        with torch.cuda.graph(g, stream=side):
+            dA.copy_(dA0)
+            dB.copy_(dB0)
+            st = P.gesv(dA, dB, n, nrhs, batch, nb, noalloc=True, status=False)[0]
+    assert st == 0
+    for rep in range(3):
+        dA.fill_(0)
+        dB.fill_(0)
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        print(f"{prec} replay {rep}", flush=True)
+        assert torch.equal(dA, ref_A), f"replay {rep}: factors differ"
+        assert torch.equal(dB, ref_B), f"replay {rep}: solutions differ"
