@@ -151,7 +151,8 @@ typedef struct {
   int ir_max_iter;    /* refinement sweeps before the complex128 fallback, default 5 */
   double ir_tol;      /* refinement acceptance: normwise backward error, default 1e-14 */
   int cheb_degree;    /* BEM only: interpolation degree d (eq. eq-T-interp), default 40 */
-  int nb;             /* LU panel width (1..64), default 64; 0: the autotuned width (rsrr_tune_lu) */
+  int nb;             /* LU panel width of the sampling factorisations (1..64), default 64;
+                         0: the autotuned width (rsrr_tune_lu) */
   uint64_t seed;      /* seed of the probing matrix when U is not supplied */
   int scheme;         /* RSRR_SCHEME_SAMPLING (default) or RSRR_SCHEME_MOMENT */
   int Kp;             /* moment scheme: number of moments K' (0 = N, as in the paper's comparisons) */
@@ -162,6 +163,8 @@ typedef struct {
                          are captured in a HIP graph kept by the handle and replayed by later
                          solves whose sizes, buffers and coefficients are the same (captured
                          again otherwise; not while kernel timers are on); default 0 */
+  int nb_reduced;     /* LU panel width of the reduced-problem factorisations (1..64);
+                         0 (default): 64 */
 } rsrr_params;
 
 /* Diagnostics of one solve. */
@@ -381,7 +384,7 @@ int rsrr_gesv_batched(int precision, int n, int nrhs, void* A, int lda, long lon
 int rsrr_gesv_batched_noalloc(int precision, int n, int nrhs, void* A, int lda, long long sA, void* B,
                               int ldb, long long sB, int batch, int nb, int* info_host, void* stream);
 
-/* Autotuning of the LU panel width (the sampling factorisations with pairs
+/* Autotuning of the LU panel width (the sampling factorisations with blocks
  * of panels and look-ahead): rsrr_tune_lu times one factorisation of `batch`
  * synthetic matrices of order n for each candidate width (16, 32, 64) on the
  * current device, keeps the fastest in a process-wide table (precision, n,

@@ -44,7 +44,7 @@ class params_t(C.Structure):
                 ("hankel_tol", C.c_double), ("precision", C.c_int), ("ir_max_iter", C.c_int),
                 ("ir_tol", C.c_double), ("cheb_degree", C.c_int), ("nb", C.c_int),
                 ("seed", C.c_uint64), ("scheme", C.c_int), ("Kp", C.c_int), ("chunk_gib", C.c_double),
-                ("interp", C.c_int), ("graph", C.c_int)]
+                ("interp", C.c_int), ("graph", C.c_int), ("nb_reduced", C.c_int)]
 
 
 class info_t(C.Structure):

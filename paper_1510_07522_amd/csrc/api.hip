@@ -249,6 +249,8 @@ int check_params(const rsrr_problem* p, const rsrr_contour* c, const rsrr_params
       return set_error(ST_EINVAL, "rectangle: NS=%d must be even and >= 4", prm->NS);
   }
   if (prm->nb < 0 || prm->nb > 64) return set_error(ST_EINVAL, "nb must be in [0, 64] (0: tuned)");
+  if (prm->nb_reduced < 0 || prm->nb_reduced > 64)
+    return set_error(ST_EINVAL, "nb_reduced must be in [0, 64] (0: 64)");
   if (prm->precision != RSRR_PREC_C128 && prm->precision != RSRR_PREC_C64_IR)
     return set_error(ST_EINVAL, "unknown precision %d", prm->precision);
   if (prm->NS < 2 || prm->K < 1) return set_error(ST_EINVAL, "NS >= 2 and K >= 1 required");

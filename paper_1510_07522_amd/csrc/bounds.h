@@ -30,12 +30,15 @@ inline std::pair<int, int> chunk_count(int NS, size_t per, double chunk_gib) {
   return {nb, (NS + nb - 1) / nb};
 }
 
+// Panel width of the reduced-problem LUs.
+inline int reduced_nb(const rsrr_params* prm) { return prm->nb_reduced > 0 ? prm->nb_reduced : 64; }
+
 // Upper bound of the device workspace of one solve of an order-n problem with
 // J coefficients (BEM: the Chebyshev degree decides J) and parameters prm.
 inline size_t workspace_bound(int n_, int J_, bool bem, const rsrr_params* prm) {
   const double z = 16.0;   // bytes of a complex128
   const double cap = prm->chunk_gib * 1073741824.0;
-  const double n = n_, N = prm->N, L = prm->L, K = prm->K, nb = prm->nb;
+  const double n = n_, N = prm->N, L = prm->L, K = prm->K, nb = prm->nb, nbr = reduced_nb(prm);
   const double NL = N * L;
   const double cols = prm->scheme == RSRR_SCHEME_MOMENT ? (double)(prm->Kp > 0 ? prm->Kp : prm->N) * L : NL;
   const double kS = std::min(n, cols), kk = kS * kS, M = K * kS;   // m <= M
@@ -58,8 +61,8 @@ inline size_t workspace_bound(int n_, int J_, bool bem, const rsrr_params* prm) 
   }
   // moments: a batch of T_S(zeta) and inverses within chunk_gib
   const double ch = chunk_count(prm->NS, (size_t)(kk * z * 2), prm->chunk_gib).second;
-  const double red = 2 * ch * kk * z + (2 * K + 1) * kk * z + 2 * ch * kS * nb * z + ch * (kS + 64) * z +
-                     ch * std::ceil(kS / nb) * kS * 4 +
+  const double red = 2 * ch * kk * z + (2 * K + 1) * kk * z + 2 * ch * kS * nbr * z + ch * (kS + 64) * z +
+                     ch * std::ceil(kS / nbr) * kS * 4 +
                      (double)moments_wind_parts((long)kk, (int)ch, (int)std::min(J, 4.0)) * z;
   // Hankel matrices, SVD (basis, Jacobi copies), extraction, eigen-solve
   const double hank = 18 * M * M * z + (kS + n) * M * z;

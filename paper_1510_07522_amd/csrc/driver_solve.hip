@@ -213,7 +213,9 @@ int solve_end(rsrr_problem* p, const rsrr_contour* c, const rsrr_params* prm, rs
   RSRR_TRY(ws.get<c128>("rd_A", (size_t)2 * K * kk, &Amom));
   RSRR_TRY(ws.get<c128>("rd_g", (size_t)2 * ch * J, &gdev));
   RSRR_TRY(ws.get<c128>("rd_cw", (size_t)ch * 2 * K, &cw));
-  RSRR_TRY(ws.get<c128>("rd_dinv", LUWork<double>::dinv_elems(kS, prm->nb, ch), &dinv));
+  // panel width of the reduced LUs (their own: the tuned width is the sampling's)
+  const int nbr = reduced_nb(prm);
+  RSRR_TRY(ws.get<c128>("rd_dinv", LUWork<double>::dinv_elems(kS, nbr, ch), &dinv));
   RSRR_TRY(ws.get<c128>("rd_part", (size_t)ch * nchunk, &part));
   // moments and winding traces in one pass over the inverses when the sizes
   // allow it (2K <= 8, J <= 4, the batch's wave sums in LDS)
@@ -224,7 +226,7 @@ int solve_end(rsrr_problem* p, const rsrr_contour* c, const rsrr_params* prm, rs
   int* iperm = nullptr;
   RSRR_TRY(ws.get<int>("rd_perm", (size_t)ch * kS, &iperm));
   int* lperm = nullptr;
-  RSRR_TRY(ws.get<int>("rd_lperm", (size_t)ch * ((kS + prm->nb - 1) / prm->nb) * kS, &lperm));
+  RSRR_TRY(ws.get<int>("rd_lperm", (size_t)ch * ((kS + nbr - 1) / nbr) * kS, &lperm));
   RSRR_TRY(ws.get<int>("rd_info", ch, &linfo));
   cd wind(0, 0);
   std::vector<cd> g, dg;
@@ -257,7 +259,7 @@ int solve_end(rsrr_problem* p, const rsrr_contour* c, const rsrr_params* prm, rs
     // T_S(zeta_q) = sum_k g_k(zeta_q) B_k for the chunk: (kk x J) (J x cnt)
     RSRR_TRY(zgemm(OP_N, OP_N, (int)kk, cnt, J, ONE, B, kk, gdev, J, ZERO, TS, kk, s));
     LUWork<double> w;
-    w.n = kS; w.nb = prm->nb; w.batch = cnt; w.lda = kS; w.sA = kk; w.A = TS;
+    w.n = kS; w.nb = nbr; w.batch = cnt; w.lda = kS; w.sA = kk; w.A = TS;
     w.ipiv = ipiv; w.dinv = dinv; w.info = linfo;
     w.tag = "reduced_lu_c128";
     RSRR_TRY(ws.aux_stream(&w.aux, &w.ev_main, &w.ev_aux));

@@ -67,8 +67,9 @@ template <typename R> struct LUWork {
   // panel's L columns are then moved once, by the composition of the later
   // panels' interchanges, instead of once per later panel
   int* lperm = nullptr;
-  // panels in pairs (not with full_swap): the columns beyond a pair take both
-  // panels' updates as one product with K = 2 nb
+  // panels in blocks of lu_group(nb) (not with full_swap): inside a block
+  // each panel updates the block's later columns; the columns beyond a block
+  // take all its panels' updates as one product with K = 256 (nb <= 128)
   bool pair = false;
   // look-ahead (optional): the trailing update beyond the next panel runs on
   // `aux` while the next panel is factored; ev_main / ev_aux order the two
@@ -80,8 +81,8 @@ template <typename R> struct LUWork {
   }
 };
 template <typename R> int lu_factor(const LUWork<R>& w, hipStream_t s);
-// Several strided batches of matrices of different orders (same nb, product
-// form and pair mode; pairs of panels are always used) factored as one set of
+// Several strided batches of matrices of different orders (same nb and product
+// form; blocks of panels as lu_factor's pair mode are always used) factored as one set of
 // launches per panel step: every panel, interchange and update launch covers
 // all batches whose order reaches that step (updates through gemm_segments,
 // a persistent grid over the tiles of all batches).  Look-ahead on aux when

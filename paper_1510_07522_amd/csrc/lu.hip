@@ -597,75 +597,67 @@ int lu_factor(const LUWork<R>& w, hipStream_t s) {
   const bool la = (w.aux != nullptr && w.ev_main != nullptr && w.ev_aux != nullptr);
   bool aux_busy = false;
   const int SB0 = lu_group(nb);
-  if (w.pair && !w.full_swap && SB0 % 2 == 0) {
-    // Pairs of panels (a at k, b at k + nb): b's columns take a's update, b is
-    // factored, and b's interchanges are applied to a's L columns; every
-    // column beyond the pair then takes both updates as one product with
-    // K = 2 nb (half the trailing-matrix traffic of two K = nb products):
-    //   rows of a:  U_a = inv(L_aa) A_a
-    //   rows of b:  A_b -= L_ba U_a,  U_b = inv(L_bb) A_b
-    //   below:      A_2 -= [L_2a L_2b] [U_a; U_b]
-    // Look-ahead at the level of pairs: the next pair's columns on s, the
-    // columns beyond them on aux.  Pairs never straddle the solver's groups
-    // of panels (an even number of panels per group), so the row order of
-    // the L columns within a group is the same as without pairs.
-    auto tail = [&](int k, int na, int nbb, int c0, int nc, hipStream_t st) -> int {
+  if (w.pair && !w.full_swap && SB0 >= 2) {
+    // Blocks of P = SB0 panels (the solver's groups of 256 columns).  Inside
+    // a block, each panel once factored updates the block's later columns
+    // (right-looking: interchanges, U rows, the rows below), and its
+    // interchanges are applied to the block's earlier L columns, so that all
+    // L columns of the block share one row order.  Every column beyond the
+    // block then takes the block's interchanges, its U rows (panel by panel:
+    // U_q = inv(L_qq) A_q, then the rows of the later panels of the block
+    // take panel q's update) and one product with K = P nb for all rows
+    // below the block: the trailing matrix is read and written once per 256
+    // columns, by products four times as deep as single panels (for
+    // nb = 64).  Look-ahead at the level of blocks: the next block's columns
+    // on s, the columns beyond them on aux.
+    const int P = SB0, BW = P * nb;
+    auto tail = [&](int k, int c0, int nc, hipStream_t st) -> int {
       if (nc <= 0) return ST_OK;
-      const int kb = k + na, c1 = kb + nbb;
-      RSRR_TRY(launch_permute<R>(w.A + (long)c0 * w.lda, w.lda, w.sA, nc, w.ipiv, n, k, na, w.batch, st));
-      if (nbb > 0)
-        RSRR_TRY(launch_permute<R>(w.A + (long)c0 * w.lda, w.lda, w.sA, nc, w.ipiv, n, kb, nbb, w.batch, st));
-      RSRR_TRY(trsm(k, na, c0, nc, st));
-      if (nbb > 0) {
-        RSRR_TRY(update(k, na, c0, nc, st, nbb));
-        RSRR_TRY(trsm(kb, nbb, c0, nc, st));
+      const int kend = min(n, k + BW);
+      for (int kq = k; kq < kend; kq += nb)
+        RSRR_TRY(launch_permute<R>(w.A + (long)c0 * w.lda, w.lda, w.sA, nc, w.ipiv, n, kq, min(nb, n - kq),
+                                   w.batch, st));
+      for (int kq = k; kq < kend; kq += nb) {
+        const int nq = min(nb, n - kq);
+        RSRR_TRY(trsm(kq, nq, c0, nc, st));
+        if (kq + nq < kend) RSRR_TRY(update(kq, nq, c0, nc, st, kend - kq - nq));
       }
-      if (c1 < n) RSRR_TRY(update(k, na + nbb, c0, nc, st));
+      if (kend < n) RSRR_TRY(update(k, kend - k, c0, nc, st));
       return ST_OK;
     };
     RSRR_TRY(launch_panel<R>(w, 0, min(nb, n), s));
-    for (int k = 0; k < n; k += 2 * nb) {
-      const int na = min(nb, n - k), kb = k + na;
-      const int nbb = min(nb, n - kb);
-      if (nbb > 0) {
-        // panel b: a's update on b's columns, factor, then b's interchanges on a's L columns
-        RSRR_TRY(launch_permute<R>(w.A + (long)kb * w.lda, w.lda, w.sA, nbb, w.ipiv, n, k, na, w.batch, s));
-        RSRR_TRY(trsm(k, na, kb, nbb, s));
-        RSRR_TRY(update(k, na, kb, nbb, s));
-        RSRR_TRY(launch_panel<R>(w, kb, nbb, s));
-        RSRR_TRY(launch_permute<R>(w.A + (long)k * w.lda, w.lda, w.sA, na, w.ipiv, n, kb, nbb, w.batch, s));
+    for (int k = 0; k < n; k += BW) {
+      const int kend = min(n, k + BW);
+      for (int kq = k + nb; kq < kend; kq += nb) {
+        // the previous panel's update on the block's remaining columns,
+        // then this panel, then its interchanges on the block's earlier L columns
+        const int kp = kq - nb, rem = kend - kq;
+        RSRR_TRY(launch_permute<R>(w.A + (long)kq * w.lda, w.lda, w.sA, rem, w.ipiv, n, kp, nb, w.batch, s));
+        RSRR_TRY(trsm(kp, nb, kq, rem, s));
+        RSRR_TRY(update(kp, nb, kq, rem, s));
+        RSRR_TRY(launch_panel<R>(w, kq, min(nb, n - kq), s));
+        RSRR_TRY(launch_permute<R>(w.A + (long)k * w.lda, w.lda, w.sA, kq - k, w.ipiv, n, kq, min(nb, n - kq),
+                                   w.batch, s));
       }
-      const int c1 = kb + nbb;
-      const int rest = n - c1;
+      const int rest = n - kend;
       if (rest <= 0) break;
-      const int nxt = la ? min(2 * nb, rest) : rest;
+      const int nxt = la ? min(BW, rest) : rest;
       const int far = rest - nxt;
-      if (aux_busy) {              // the next pair's columns had the previous pair's far update
+      if (aux_busy) {              // the next block's columns had the previous block's far update
         RSRR_HIP(hipStreamWaitEvent(s, w.ev_aux, 0));
         aux_busy = false;
       }
       if (far > 0) {
         RSRR_HIP(hipEventRecord(w.ev_main, s));
         RSRR_HIP(hipStreamWaitEvent(w.aux, w.ev_main, 0));
-        RSRR_TRY(tail(k, na, nbb, c1 + nxt, far, w.aux));
+        RSRR_TRY(tail(k, kend + nxt, far, w.aux));
         RSRR_HIP(hipEventRecord(w.ev_aux, w.aux));
         aux_busy = true;
       }
-      RSRR_TRY(tail(k, na, nbb, c1, nxt, s));
-      RSRR_TRY(launch_panel<R>(w, c1, min(nb, n - c1), s));
+      RSRR_TRY(tail(k, kend, nxt, s));
+      RSRR_TRY(launch_panel<R>(w, kend, min(nb, n - kend), s));
     }
     if (aux_busy) RSRR_HIP(hipStreamWaitEvent(s, w.ev_aux, 0));
-    // interchanges of the later panels of each group on the earlier panels'
-    // L columns (the second panel of a pair has already done its own pair)
-    const int np = w.npanel();
-    for (int q = 1; q < np; ++q) {
-      if (q % SB0 == 0) continue;
-      const int k = q * nb, c0 = (q / SB0) * SB0 * nb;
-      const int cols = k - c0 - ((q % 2 == 1) ? nb : 0);
-      if (cols > 0)
-        RSRR_TRY(launch_permute<R>(w.A + (long)c0 * w.lda, w.lda, w.sA, cols, w.ipiv, n, k, min(nb, n - k),
-                                   w.batch, s));
-    }
     return ST_OK;
   }
   RSRR_TRY(launch_panel<R>(w, 0, min(nb, n), s));
@@ -880,7 +872,7 @@ int lu_inverse(const LUWork<R>& w, cplx<R>* X, cplx<R>* out, long ldo, long sO, 
 // ---------------------------------------------------------------------------
 // Several strided batches of different orders factored as one set of launches
 // per panel step (see kernels.h).  The operations and their order per matrix
-// are those of lu_factor with pairs of panels and look-ahead, so each matrix
+// are those of lu_factor with blocks of panels and look-ahead, so each matrix
 // is factored bit for bit as lu_factor factors it alone.
 namespace {
 
@@ -941,7 +933,8 @@ int lu_factor_segments(const std::vector<LUWork<R>>& ws, hipStream_t s, hipStrea
     if (w.n > 8 * PNT || w.n < 1 || w.batch < 1) return set_error(ST_EINVAL, "lu_factor_segments: n=%d", w.n);
     nmax = std::max(nmax, w.n);
   }
-  if (nb < 1 || nb > MAXNB || lu_group(nb) % 2) return set_error(ST_EINVAL, "lu_factor_segments: nb=%d", nb);
+  if (nb < 1 || nb > MAXNB || lu_group(nb) < 2) return set_error(ST_EINVAL, "lu_factor_segments: nb=%d", nb);
+  const int P = lu_group(nb), BW = P * nb;      // blocks of panels, as lu_factor
   for (const LUWork<R>& w : ws) {
     hipLaunchKernelGGL(zero_int_kernel, dim3((unsigned)cdivl(w.batch, 256)), dim3(256), 0, s, w.info, w.batch);
     RSRR_LAUNCH_CHECK();
@@ -1039,55 +1032,58 @@ int lu_factor_segments(const std::vector<LUWork<R>>& ws, hipStream_t s, hipStrea
     u.gauss3m = g3m;
     return u;
   };
-  // the pair at k applied to columns [c0[q], c0[q] + nc[q]) of every batch with nc > 0
+  // the block at k applied to columns [c0[q], c0[q] + nc[q]) of every batch
+  // with nc > 0: its interchanges panel by panel, the U rows of its panels
+  // (each followed by its update of the later panels' rows), one product below
   auto tail = [&](int k, const std::vector<int>& c0, const std::vector<int>& nc, hipStream_t st) -> int {
-    std::vector<PJob> pa, pb;
-    std::vector<GemmBatch<R>> ta, ub, tb, big;
-    for (int q = 0; q < Q; ++q) {
-      if (nc[q] <= 0) continue;
-      const int n = ws[q].n, na = std::min(nb, n - k), kb = k + na, nbb = std::max(0, std::min(nb, n - kb));
-      const int c1 = kb + nbb;
-      pa.push_back(PJob{q, c0[q], nc[q], k, na});
-      if (nbb > 0) pb.push_back(PJob{q, c0[q], nc[q], kb, nbb});
-      ta.push_back(trsm_g(q, k, na, c0[q], nc[q]));
-      if (nbb > 0) {
-        ub.push_back(upd_g(q, k, na, c0[q], nc[q], nbb));
-        tb.push_back(trsm_g(q, kb, nbb, c0[q], nc[q]));
-      }
-      if (c1 < n) big.push_back(upd_g(q, k, na + nbb, c0[q], nc[q], n - c1));
+    for (int kq = k; kq < k + BW; kq += nb) {
+      std::vector<PJob> pj;
+      for (int q = 0; q < Q; ++q)
+        if (nc[q] > 0 && kq < ws[q].n) pj.push_back(PJob{q, c0[q], nc[q], kq, std::min(nb, ws[q].n - kq)});
+      RSRR_TRY(permutes(pj, st));
     }
-    RSRR_TRY(permutes(pa, st));
-    RSRR_TRY(permutes(pb, st));
-    RSRR_TRY(gemms(ta, st));
-    RSRR_TRY(gemms(ub, st));
-    RSRR_TRY(gemms(tb, st));
+    for (int kq = k; kq < k + BW; kq += nb) {
+      std::vector<GemmBatch<R>> tq, uq;
+      for (int q = 0; q < Q; ++q) {
+        const int n = ws[q].n;
+        if (nc[q] <= 0 || kq >= n) continue;
+        const int nq = std::min(nb, n - kq), kend = std::min(n, k + BW);
+        tq.push_back(trsm_g(q, kq, nq, c0[q], nc[q]));
+        if (kq + nq < kend) uq.push_back(upd_g(q, kq, nq, c0[q], nc[q], kend - kq - nq));
+      }
+      RSRR_TRY(gemms(tq, st));
+      RSRR_TRY(gemms(uq, st));
+    }
+    std::vector<GemmBatch<R>> big;
+    for (int q = 0; q < Q; ++q) {
+      const int n = ws[q].n, kend = std::min(n, k + BW);
+      if (nc[q] > 0 && kend < n) big.push_back(upd_g(q, k, kend - k, c0[q], nc[q], n - kend));
+    }
     RSRR_TRY(gemms(big, st));
     return ST_OK;
   };
 
   RSRR_TRY(panels(0, s));
-  for (int k = 0; k < nmax; k += 2 * nb) {
-    // second panel of each pair: the first's update on its columns, factor,
-    // then its interchanges on the first's L columns
-    std::vector<PJob> pb, fix;
-    std::vector<GemmBatch<R>> tr, up;
-    bool anyb = false;
-    for (int q = 0; q < Q; ++q) {
-      const int n = ws[q].n;
-      if (k >= n) continue;
-      const int na = std::min(nb, n - k), kb = k + na, nbb = std::min(nb, n - kb);
-      if (nbb <= 0) continue;
-      anyb = true;
-      pb.push_back(PJob{q, kb, nbb, k, na});
-      tr.push_back(trsm_g(q, k, na, kb, nbb));
-      up.push_back(upd_g(q, k, na, kb, nbb, n - k - na));
-      fix.push_back(PJob{q, k, na, kb, nbb});
-    }
-    if (anyb) {
+  for (int k = 0; k < nmax; k += BW) {
+    // the block's later panels: the previous panel's update on the block's
+    // remaining columns, the panel, its interchanges on the block's earlier L columns
+    for (int kq = k + nb; kq < k + BW && kq < nmax; kq += nb) {
+      std::vector<PJob> pb, fix;
+      std::vector<GemmBatch<R>> tr, up;
+      for (int q = 0; q < Q; ++q) {
+        const int n = ws[q].n;
+        if (kq >= n) continue;
+        const int kp = kq - nb, rem = std::min(n, k + BW) - kq;
+        pb.push_back(PJob{q, kq, rem, kp, nb});
+        tr.push_back(trsm_g(q, kp, nb, kq, rem));
+        up.push_back(upd_g(q, kp, nb, kq, rem, n - kp - nb));
+        fix.push_back(PJob{q, k, kq - k, kq, std::min(nb, n - kq)});
+      }
+      if (pb.empty()) continue;
       RSRR_TRY(permutes(pb, s));
       RSRR_TRY(gemms(tr, s));
       RSRR_TRY(gemms(up, s));
-      RSRR_TRY(panels(k + nb, s));
+      RSRR_TRY(panels(kq, s));
       RSRR_TRY(permutes(fix, s));
     }
     std::vector<int> nx0(Q, 0), nxc(Q, 0), fr0(Q, 0), frc(Q, 0);
@@ -1095,11 +1091,11 @@ int lu_factor_segments(const std::vector<LUWork<R>>& ws, hipStream_t s, hipStrea
     for (int q = 0; q < Q; ++q) {
       const int n = ws[q].n;
       if (k >= n) continue;
-      const int c1 = std::min(n, k + 2 * nb), rest = n - c1;
+      const int kend = std::min(n, k + BW), rest = n - kend;
       if (rest <= 0) continue;
-      const int nxt = la ? std::min(2 * nb, rest) : rest;
-      nx0[q] = c1; nxc[q] = nxt;
-      fr0[q] = c1 + nxt; frc[q] = rest - nxt;
+      const int nxt = la ? std::min(BW, rest) : rest;
+      nx0[q] = kend; nxc[q] = nxt;
+      fr0[q] = kend + nxt; frc[q] = rest - nxt;
       anyrest = true;
       anyfar |= frc[q] > 0;
     }
@@ -1116,23 +1112,9 @@ int lu_factor_segments(const std::vector<LUWork<R>>& ws, hipStream_t s, hipStrea
       aux_busy = true;
     }
     RSRR_TRY(tail(k, nx0, nxc, s));
-    RSRR_TRY(panels(k + 2 * nb, s));
+    RSRR_TRY(panels(k + BW, s));
   }
   if (aux_busy) RSRR_HIP(hipStreamWaitEvent(s, ev_aux, 0));
-  // interchanges of the later panels of each group on the earlier L columns
-  // (the second panel of a pair has already done its pair)
-  const int SB = lu_group(nb);
-  for (int qp = 1; qp * nb < nmax; ++qp) {
-    if (qp % SB == 0) continue;
-    std::vector<PJob> jobs;
-    for (int q = 0; q < Q; ++q) {
-      const int n = ws[q].n, k = qp * nb;
-      if (k >= n) continue;
-      const int c0 = (qp / SB) * SB * nb, cols = k - c0 - ((qp % 2 == 1) ? nb : 0);
-      if (cols > 0) jobs.push_back(PJob{q, c0, cols, k, std::min(nb, n - k)});
-    }
-    RSRR_TRY(permutes(jobs, s));
-  }
   return ST_OK;
 }
 template int lu_factor_segments<double>(const std::vector<LUWork<double>>&, hipStream_t, hipStream_t, hipEvent_t,

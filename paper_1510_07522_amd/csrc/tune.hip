@@ -1,6 +1,6 @@
 // Autotuning of the LU panel width nb for the sampling factorisations.
 //
-// rsrr_tune_lu times the batched factorisation (pairs of panels, look-ahead
+// rsrr_tune_lu times the batched factorisation (blocks of panels, look-ahead
 // stream) of `batch` synthetic matrices of order n for every candidate panel
 // width and keeps the fastest in a process-wide table keyed by precision,
 // order and batch size; rsrr_tune_save / rsrr_tune_load persist the table as
