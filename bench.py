@@ -428,7 +428,7 @@ def main():
     ap.add_argument("--requests", type=int, default=600, help="serving workload (c4): requests")
     ap.add_argument("--wait-timeout", type=float, default=600.0,
                     help="serving workload (c4): bound of each wait for a result, seconds")
-    ap.add_argument("--slots", type=int, default=4, help="serving workload (c4): concurrent slots")
+    ap.add_argument("--slots", type=int, default=2, help="serving workload (c4): concurrent slots")
     ap.add_argument("--budget-gib", type=float, default=200.0, help="serving workload (c4): HBM budget")
     ap.add_argument("--traffic-from", nargs=4, default=None,
                     metavar=("FETCH_DIR", "WRITE_DIR", "COPY_FETCH_DIR", "COPY_WRITE_DIR"),
