@@ -75,14 +75,20 @@ class Scheduler {
   // the job is forgotten and its payload, status and latency are returned.
   int wait(uint64_t ticket, double timeout_s, void** payload, int* status, double* latency) {
     std::unique_lock<std::mutex> lk(mu_);
-    auto it = jobs_.find(ticket);
-    if (it == jobs_.end()) return WAIT_UNKNOWN;
-    auto done = [&] { return it->second.done; };
+    if (jobs_.find(ticket) == jobs_.end()) return WAIT_UNKNOWN;
+    // the job is looked up again at every wake-up: another waiter of the same
+    // ticket, or stop(), may have removed it meanwhile
+    auto done = [&] {
+      auto f = jobs_.find(ticket);
+      return f == jobs_.end() || f->second.done;
+    };
     if (timeout_s > 0) {
       if (!cv_.wait_until(lk, deadline(timeout_s), done)) return WAIT_TIMEOUT;
     } else {
       cv_.wait(lk, done);
     }
+    auto it = jobs_.find(ticket);
+    if (it == jobs_.end()) return WAIT_UNKNOWN;
     *payload = it->second.payload;
     *status = it->second.status;
     *latency = it->second.latency;

@@ -59,9 +59,16 @@ int tune_one(int n, int batch, int* nb_best, double* ms_best, double* ms_all) {
   RSRR_TRY(ws.get<int>("t_ipiv", (size_t)batch * n, &ipiv));
   RSRR_TRY(ws.get<int>("t_info", batch, &info));
   RSRR_TRY(ws.get<cplx<R>>("t_dinv", LUWork<R>::dinv_elems(n, 64, batch), &dinv));
-  hipEvent_t e0 = nullptr, e1 = nullptr;
-  RSRR_HIP(hipEventCreate(&e0));
-  RSRR_HIP(hipEventCreate(&e1));
+  struct Events {               // destroyed on every return path
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    ~Events() {
+      if (e0) (void)hipEventDestroy(e0);
+      if (e1) (void)hipEventDestroy(e1);
+    }
+  } ev;
+  RSRR_HIP(hipEventCreate(&ev.e0));
+  RSRR_HIP(hipEventCreate(&ev.e1));
+  hipEvent_t e0 = ev.e0, e1 = ev.e1;
   int best = 64;
   double tbest = INFINITY;
   int ci = 0;
@@ -90,8 +97,6 @@ int tune_one(int n, int batch, int* nb_best, double* ms_best, double* ms_all) {
     ++ci;
     if (t < tbest) { tbest = t; best = nb; }
   }
-  (void)hipEventDestroy(e0);
-  (void)hipEventDestroy(e1);
   *nb_best = best;
   *ms_best = tbest;
   return ST_OK;

@@ -145,11 +145,38 @@ int main() {
     printf("request %zu: family %d n %d L %d need %.1f GiB latency %.3f (modelled s)\n", i + 1,
            reqs[i].family, reqs[i].n, reqs[i].L, reqs[i].need / 1073741824.0, lat / scale);
   }
+  // two waiters of one ticket: one receives the result, the other learns
+  // that the ticket is gone (no access to a removed job)
+  Req extra;
+  extra.need = 1;
+  extra.latency = 0.05;
+  uint64_t tk = 0;
+  bool dbl_ok = sch.submit(extra.need, &extra, &tk) == rsrr::sched::SUBMIT_OK;
+  int wa = -1, wb = -1;
+  if (dbl_ok) {
+    std::thread ta([&] {
+      void* p = nullptr;
+      int st = 0;
+      double l = 0;
+      wa = sch.wait(tk, 30.0, &p, &st, &l);
+    });
+    std::thread tb([&] {
+      void* p = nullptr;
+      int st = 0;
+      double l = 0;
+      wb = sch.wait(tk, 30.0, &p, &st, &l);
+    });
+    ta.join();
+    tb.join();
+    dbl_ok = (wa == rsrr::sched::WAIT_DONE) != (wb == rsrr::sched::WAIT_DONE) &&
+             (wa == rsrr::sched::WAIT_UNKNOWN || wb == rsrr::sched::WAIT_UNKNOWN);
+  }
+  printf("double wait: %s (%d, %d)\n", dbl_ok ? "ok" : "FAILED", wa, wb);
   sch.stop();
   int nref = 0;
   for (int v : refused) nref += v;
   printf("summary: %d done, %d refused, %d timeouts, peak held %.1f of %.1f GiB, max concurrent %d, "
          "max latency %.2f, over budget %d\n", done, nref, timeouts, ops.peak / 1073741824.0, budget_gib,
          ops.max_running.load(), lat_max, ops.over ? 1 : 0);
-  return (timeouts == 0 && done + nref == (int)reqs.size() && !ops.over) ? 0 : 1;
+  return (timeouts == 0 && done + nref == (int)reqs.size() && !ops.over && dbl_ok) ? 0 : 1;
 }
