@@ -269,7 +269,9 @@ int rsrr_solve(rsrr_problem* p, const rsrr_contour* c, const rsrr_params* prm,
  * then each problem's solves, refinement, basis, projection and reduced
  * problem run in turn.  The problems must be distinct, use one stream and
  * share the precision and panel width.  Results are bit-identical to
- * rsrr_solve of each problem alone.  contours, prms: count entries each;
+ * rsrr_solve of each problem alone with the same panel width (nb = 0 takes
+ * the width tuned for the batch's largest order and total node count, which
+ * a solve alone may not).  contours, prms: count entries each;
  * U: NULL, or count device pointers (n_i x L_i, leading dim n_i; an entry may
  * be NULL to draw U from prms[i].seed); out: count result pointers (free each
  * with rsrr_result_free).  Returns the bitwise OR of the problems' warnings,
