@@ -20,6 +20,8 @@
 namespace rsrr {
 
 constexpr int PNT = 1024;           // panel workgroup size (16 waves)
+// flops per launch of the look-ahead stream's trailing-update pieces
+constexpr double WINDOW_FLOP = 1.6e11;
 constexpr int MAXNB = 64;
 // panels per group of the triangular solves (and of the row order lu_factor
 // gives the L columns): groups of 256 columns
@@ -622,7 +624,20 @@ int lu_factor(const LUWork<R>& w, hipStream_t s) {
         RSRR_TRY(trsm(kq, nq, c0, nc, st));
         if (kq + nq < kend) RSRR_TRY(update(kq, nq, c0, nc, st, kend - kq - nq));
       }
-      if (kend < n) RSRR_TRY(update(k, kend - k, c0, nc, st));
+      if (kend < n) {
+        // On the look-ahead stream the product goes in column pieces of
+        // about WINDOW_FLOP each: a panel queued on the other stream needs a
+        // whole CU, which it finds only where one launch has drained and the
+        // next has not begun.
+        int pw = nc;
+        if (la && st == w.aux) {
+          const double fl = 8.0 * (double)(n - kend) * nc * (kend - k) * w.batch;
+          const int np = (int)std::max(1.0, std::min(64.0, std::floor(fl / WINDOW_FLOP)));
+          pw = std::max(256, (nc + np - 1) / np + 63) / 64 * 64;
+        }
+        for (int off = 0; off < nc; off += pw)
+          RSRR_TRY(update(k, kend - k, c0 + off, std::min(pw, nc - off), st));
+      }
       return ST_OK;
     };
     RSRR_TRY(launch_panel<R>(w, 0, min(nb, n), s));
@@ -1054,12 +1069,25 @@ int lu_factor_segments(const std::vector<LUWork<R>>& ws, hipStream_t s, hipStrea
       RSRR_TRY(gemms(tq, st));
       RSRR_TRY(gemms(uq, st));
     }
-    std::vector<GemmBatch<R>> big;
+    // the product below the block; on the look-ahead stream in column
+    // pieces of about WINDOW_FLOP together, as lu_factor does
+    double fl = 0;
     for (int q = 0; q < Q; ++q) {
       const int n = ws[q].n, kend = std::min(n, k + BW);
-      if (nc[q] > 0 && kend < n) big.push_back(upd_g(q, k, kend - k, c0[q], nc[q], n - kend));
+      if (nc[q] > 0 && kend < n) fl += 8.0 * (double)(n - kend) * nc[q] * (kend - k) * ws[q].batch;
     }
-    RSRR_TRY(gemms(big, st));
+    const int np = (la && st == aux) ? (int)std::max(1.0, std::min(64.0, std::floor(fl / WINDOW_FLOP))) : 1;
+    for (int p = 0; p < np; ++p) {
+      std::vector<GemmBatch<R>> big;
+      for (int q = 0; q < Q; ++q) {
+        const int n = ws[q].n, kend = std::min(n, k + BW);
+        if (nc[q] <= 0 || kend >= n) continue;
+        const int pw = std::max(256, (nc[q] + np - 1) / np + 63) / 64 * 64;
+        const int off = p * pw;
+        if (off < nc[q]) big.push_back(upd_g(q, k, kend - k, c0[q] + off, std::min(pw, nc[q] - off), n - kend));
+      }
+      RSRR_TRY(gemms(big, st));
+    }
     return ST_OK;
   };
 

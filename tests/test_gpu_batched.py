@@ -63,6 +63,26 @@ def test_batched_equals_alone_and_oracle(P, precision):
     assert np.all(got["res"] <= 1e-10)
 
 
+@pytest.mark.parametrize("precision", ["c64_ir", "c128"])
+def test_batched_equals_alone_with_tall_panels(P, precision):
+    # orders above 1024 (several blocks of four panels with look-ahead): the
+    # segmented launches factor every matrix as it is factored alone
+    insts = _instances([1100, 1300, 700])
+    hs = [P.Problem(i[0]) for i in insts]
+    try:
+        cts = [P.contour(c.center, c.a, c.b) for _, c, _, _, _ in insts]
+        prms = [P.default_params(N=N, L=L, precision=precision) for _, _, N, L, _ in insts]
+        Us = [P.to_device(U) for *_, U in insts]
+        batched = P.solve_batched(hs, cts, prms, Us)
+        alone = [h.solve(ct, prm, U) for h, ct, prm, U in zip(hs, cts, prms, Us)]
+    finally:
+        for h in hs:
+            h.close()
+    for (p, c, N, L, U), b, a in zip(insts, batched, alone):
+        print(p.n, "batched", b["info"]["n_eig"], "alone", a["info"]["n_eig"])
+        assert _same(a, b), p.n
+
+
 def test_batched_rejects_mixed_precision(P):
     insts = _instances([40, 50])
     hs = [P.Problem(i[0]) for i in insts]

@@ -64,7 +64,7 @@ def test_gemm_matches_numpy(P, opA, opB, prec):
 @pytest.mark.parametrize("n,nrhs,batch,nb", [(1, 3, 2, 64), (37, 5, 3, 16), (200, 20, 4, 64),
                                              (333, 7, 2, 64), (1100, 9, 2, 64), (2100, 4, 1, 64),
                                              (300, 6, 5, 32), (777, 3, 3, 24), (2600, 5, 2, 32),
-                                             (600, 3, 50, 32)])
+                                             (600, 3, 50, 32), (1500, 6, 3, 16)])
 @pytest.mark.parametrize("prec", ["c128", "c64"])
 def test_batched_lu_solve(P, n, nrhs, batch, nb, prec):
     import torch
@@ -100,3 +100,20 @@ def test_batched_lu_reports_exact_singularity(P):
     st, info = P.gesv(dA, dB, n, 1, 2, 16)
     assert st == -4
     assert info[0] == 8 and info[1] == 0
+
+
+def test_batched_lu_reports_zero_pivot_in_later_blocks(P):
+    # an exactly zero column gives the status of its own step, in the first
+    # panel and in the panel at column 1024, after four blocks of panels
+    n = 2100
+    rng = np.random.default_rng(2)
+    A0 = rnd(rng, n, n)
+    A0[:, 7] = 0.0
+    A1 = rnd(rng, n, n)
+    A1[:, 1030] = 0.0
+    A2 = rnd(rng, n, n) + 2 * np.sqrt(n) * np.eye(n)
+    dA = batch_to_dev(P, [A0, A1, A2])
+    dB = batch_to_dev(P, [np.ones((n, 1), complex)] * 3)
+    st, info = P.gesv(dA, dB, n, 1, 3, 64)
+    assert st == -4
+    assert info == [8, 1031, 0]
