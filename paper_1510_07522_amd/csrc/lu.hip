@@ -592,6 +592,20 @@ int lu_factor(const LUWork<R>& w, hipStream_t s) {
     u.gauss3m = w.gauss3m;
     return gemm_batched<R>(u, st);
   };
+  // The trailing update on the look-ahead stream goes in column pieces of
+  // about WINDOW_FLOP each: a panel queued on the other stream needs a whole
+  // CU, which it finds only where one launch has drained and the next has
+  // not begun.
+  auto far_update = [&](int k, int K, int c0, int nc, hipStream_t st) -> int {
+    int pw = nc;
+    if (w.aux && st == w.aux) {
+      const double fl = 8.0 * (double)(n - k - K) * nc * K * w.batch;
+      const int np = (int)std::max(1.0, std::min(64.0, std::floor(fl / WINDOW_FLOP)));
+      pw = std::max(256, (nc + np - 1) / np + 63) / 64 * 64;
+    }
+    for (int off = 0; off < nc; off += pw) RSRR_TRY(update(k, K, c0 + off, std::min(pw, nc - off), st));
+    return ST_OK;
+  };
   // With look-ahead, step k updates the next panel's columns on s and starts
   // the next panel at once, while the columns beyond it are updated on aux:
   //   s:   [wait aux(k-1)] next-panel permute/trsm/update, panel k+1, record main
@@ -624,20 +638,7 @@ int lu_factor(const LUWork<R>& w, hipStream_t s) {
         RSRR_TRY(trsm(kq, nq, c0, nc, st));
         if (kq + nq < kend) RSRR_TRY(update(kq, nq, c0, nc, st, kend - kq - nq));
       }
-      if (kend < n) {
-        // On the look-ahead stream the product goes in column pieces of
-        // about WINDOW_FLOP each: a panel queued on the other stream needs a
-        // whole CU, which it finds only where one launch has drained and the
-        // next has not begun.
-        int pw = nc;
-        if (la && st == w.aux) {
-          const double fl = 8.0 * (double)(n - kend) * nc * (kend - k) * w.batch;
-          const int np = (int)std::max(1.0, std::min(64.0, std::floor(fl / WINDOW_FLOP)));
-          pw = std::max(256, (nc + np - 1) / np + 63) / 64 * 64;
-        }
-        for (int off = 0; off < nc; off += pw)
-          RSRR_TRY(update(k, kend - k, c0 + off, std::min(pw, nc - off), st));
-      }
+      if (kend < n) RSRR_TRY(far_update(k, kend - k, c0, nc, st));
       return ST_OK;
     };
     RSRR_TRY(launch_panel<R>(w, 0, min(nb, n), s));
@@ -693,7 +694,7 @@ int lu_factor(const LUWork<R>& w, hipStream_t s) {
       RSRR_TRY(launch_permute<R>(w.A + (long)(c1 + nxt) * w.lda, w.lda, w.sA, far, w.ipiv, n, k, nbe,
                                  w.batch, w.aux));
       RSRR_TRY(trsm(k, nbe, c1 + nxt, far, w.aux));
-      RSRR_TRY(update(k, nbe, c1 + nxt, far, w.aux));
+      RSRR_TRY(far_update(k, nbe, c1 + nxt, far, w.aux));
       RSRR_HIP(hipEventRecord(w.ev_aux, w.aux));
       aux_busy = true;
     }
