@@ -90,11 +90,31 @@ __global__ __launch_bounds__(256) void scatter_node_cols_c64_kernel(const c128* 
   dst[r + ((long)idx[q] * L + c) * ldd] = mk<float>((float)v.re, (float)v.im);
 }
 
+// R_j = U - T(z_j) Y_j in fp64 for the N nodes whose solutions are the
+// column blocks of Y.  BEM with Tres: the fp64 matrices of all sampling nodes
+// are resident (node j at Tres + j n^2), and nodes[q] (host; none: q) names
+// the node of block q.
 static int residual_fp64(rsrr_problem* p, int N, int L, const c128* f_dev, const c128* z_dev,
                          const c128* U, long ldu, const c128* Y, long ldy, c128* Rb, double chunk_gib,
-                         hipStream_t s) {
+                         hipStream_t s, const c128* Tres = nullptr, const int* nodes = nullptr) {
   const int n = p->n;
   const long cols = (long)N * L;
+  if (p->bem && Tres) {
+    const long nn = (long)n * n;
+    RSRR_TRY((convert<double, double>(U, ldu, 0, Rb, n, (long)L * n, n, L, N, s)));
+    for (int q = 0; q < N; q += nodes ? 1 : N) {
+      GemmBatch<double> g;
+      g.M = n; g.N = L; g.K = n;
+      g.alpha = mk<double>(-1, 0); g.beta = mk<double>(1, 0);
+      g.A = Tres + (nodes ? nodes[q] : 0) * nn; g.lda = n; g.sA = nn;
+      g.B = Y + (long)q * L * ldy; g.ldb = ldy; g.sB = (long)L * ldy;
+      g.C = Rb + (long)q * L * n; g.ldc = n; g.sC = (long)L * n;
+      g.batch = nodes ? 1 : N;
+      g.tag = "ir_residual_gemm";
+      RSRR_TRY(gemm_batched<double>(g, s));
+    }
+    return ST_OK;
+  }
   if (p->bem) {
     // T(z_j) assembled in fp64 for a balanced batch of nodes that fits
     // chunk_gib (in the buffer the interpolation samples of the projection
@@ -364,6 +384,13 @@ int sample_end(SamplePlan* sp) {
     }
     RSRR_TRY(block_fro2(U, ldu, 0, n, L, 1, nrm + 3 * N, s));
     RSRR_HIP(hipMemcpyAsync(u2.data(), nrm + 3 * N, sizeof(double), hipMemcpyDeviceToHost, s));
+    // BEM: the fp64 T(z_j) of every node assembled once for all refinement
+    // sweeps, in the buffer a complex128 fallback factors them in
+    c128* Tres = nullptr;
+    if (p->bem) {
+      RSRR_TRY(p->ws.get<c128>("s_T128", (size_t)N * nn, &Tres));
+      RSRR_TRY(assemble_bem<double>(n, p->xyz, p->h, N, z_dev, Tres, n, nn, s));
+    }
     std::vector<int> active(N, 1);
     std::vector<double> r2(N), y2(N), eta_v(N, INFINITY);
     const double eta_floor = 4 * 1.1102230246251565e-16;
@@ -379,7 +406,7 @@ int sample_end(SamplePlan* sp) {
       // residuals of the nodes corrected in the last sweep (all in the first)
       const bool res_full = (nact == N);
       if (res_full) {
-        RSRR_TRY(residual_fp64(p, N, L, f_dev, z_dev, U, ldu, S, lds, Rb, prm->chunk_gib, s));
+        RSRR_TRY(residual_fp64(p, N, L, f_dev, z_dev, U, ldu, S, lds, Rb, prm->chunk_gib, s, Tres));
         RSRR_TRY(block_fro2(Rb, n, (long)L * n, n, L, N, nrm, s));
         RSRR_TRY(block_fro2(S, lds, (long)L * lds, n, L, N, nrm + N, s));
         RSRR_HIP(hipMemcpyAsync(r2.data(), nrm, N * sizeof(double), hipMemcpyDeviceToHost, s));
@@ -405,7 +432,8 @@ int sample_end(SamplePlan* sp) {
         hipLaunchKernelGGL(gather_node_cols_kernel, dim3((unsigned)cdivl((long)n * ca, 256)), dim3(256), 0, s, S,
                            lds, n, L, idx_dev, na, Sa, (long)n);
         RSRR_LAUNCH_CHECK();
-        RSRR_TRY(residual_fp64(p, na, L, fa_dev, za_dev, U, ldu, Sa, n, Ra, prm->chunk_gib, s));
+        RSRR_TRY(residual_fp64(p, na, L, fa_dev, za_dev, U, ldu, Sa, n, Ra, prm->chunk_gib, s, Tres,
+                               idx.data()));
         RSRR_TRY(block_fro2(Ra, n, (long)L * n, n, L, na, nrm, s));
         RSRR_TRY(block_fro2(Sa, n, (long)L * n, n, L, na, nrm + N, s));
         std::vector<double> ra(na), ya(na);
