@@ -256,6 +256,21 @@ __device__ __forceinline__ void gemm_body(const GemmBatch<R>& g, const BemGen& b
         Cp[idx] = out;
       }
     }
+    if (g.herm && m0 > n0) {
+      // the conjugate transpose of this tile below the diagonal, above it:
+      // consecutive threads take consecutive columns of the staged half,
+      // which are consecutive rows of the mirrored tile
+#pragma unroll
+      for (int e = 0; e < (BN / 2) * BM / NT; ++e) {
+        const int q = e * NT + tid;
+        const int cl = q % (BN / 2), rl = q / (BN / 2);
+        const int row = m0 + rl, col = n0 + h * (BN / 2) + cl;
+        if (row < M && col < N) {
+          const cplx<R> v = mk<R>(st_re[cl * SLD + rl], -st_im[cl * SLD + rl]);
+          Cp[(long)col + (long)row * g.ldc] = g.alpha.re * v;
+        }
+      }
+    }
     __syncthreads();
   }
 }
@@ -263,6 +278,7 @@ __device__ __forceinline__ void gemm_body(const GemmBatch<R>& g, const BemGen& b
 template <typename R, int OPA, int OPB, bool AREAL, bool G3M>
 __global__ __launch_bounds__(sizeof(R) == 8 ? 512 : 256) void gemm_kernel(GemmBatch<R> g) {
   if (g.active && !g.active[blockIdx.z]) return;
+  if (g.herm && blockIdx.x < blockIdx.y) return;   // above the diagonal: written by its mirror
   gemm_body<R, OPA, OPB, AREAL, G3M, false>(g, BemGen{nullptr, 0.0, nullptr}, blockIdx.x * BM, blockIdx.y * BN,
                                             blockIdx.z);
 }
@@ -365,7 +381,9 @@ template <typename R, int OPA, int OPB, bool AREAL, bool G3M>
 static int launch_one(const GemmBatch<R>& g, hipStream_t s) {
   dim3 grid((unsigned)cdivl(g.M, BM), (unsigned)cdivl(g.N, BN), (unsigned)g.batch);
   const double es = (double)sizeof(cplx<R>);
-  const double flops = (AREAL ? 4.0 : 8.0) * g.M * (double)g.N * g.K * g.batch;
+  const double tiles = (double)cdivl(g.M, BM);
+  const double flops = (AREAL ? 4.0 : 8.0) * g.M * (double)g.N * g.K * g.batch *
+                       (g.herm ? (tiles + 1) / (2 * tiles) : 1.0);
   const double bytes = g.batch * ((AREAL ? es / 2 : es) * (double)g.M * g.K + es * (double)g.K * g.N +
                                   es * (double)g.M * g.N *
                                       ((g.beta.re != R(0) || g.beta.im != R(0)) ? 2.0 : 1.0));
@@ -395,6 +413,9 @@ int gemm_batched(const GemmBatch<R>& g, hipStream_t s) {
     return set_error(ST_EINVAL, "gemm: negative size");
   if (g.M == 0 || g.N == 0 || g.batch == 0) return ST_OK;
   if (g.a_real && g.opA == OP_C) return set_error(ST_EINVAL, "gemm: real A with conj op");
+  if (g.herm && (g.opA != OP_C || g.opB != OP_N || (const void*)g.B != g.A || g.M != g.N || g.a_real ||
+                 g.alpha.im != R(0) || g.beta.re != R(0) || g.beta.im != R(0) || g.active))
+    return set_error(ST_EINVAL, "gemm: the Gram form needs C = alpha A^H A with real alpha and beta 0");
   if (g.a_real) return launch_ops<R, true, false>(g, s);
   if (g.gauss3m) return launch_ops<R, false, true>(g, s);
   return launch_ops<R, false, false>(g, s);

@@ -20,6 +20,10 @@ template <typename R> struct GemmBatch {
   bool a_real = false;
   bool gauss3m = false;   // 3-multiplication complex product (normwise stable)
   const int* active = nullptr;   // optional: batch entries with active[b] == 0 are skipped
+  // Gram matrix C = alpha A^H A (opA OP_C, opB OP_N, B == A, M == N, real
+  // alpha, beta 0): only the tiles on and below the diagonal are formed; each
+  // one below it also stores its conjugate transpose above
+  bool herm = false;
   const char* tag = "gemm";   // kernel-timer class
 };
 template <typename R> int gemm_batched(const GemmBatch<R>& g, hipStream_t s);

@@ -281,6 +281,18 @@ static int gemm_z(int opA, int opB, int M, int N, int K, c128 alpha, const c128*
   return gemm_batched<double>(g, s);
 }
 
+// G = X^H X (cols x cols, leading dim ldg): the tiles on and below the
+// diagonal, mirrored above it
+static int gram_z(int cols, int rows, const c128* X, long ldx, c128* G, long ldg, hipStream_t s) {
+  GemmBatch<double> g;
+  g.opA = OP_C; g.opB = OP_N; g.M = cols; g.N = cols; g.K = rows;
+  g.alpha = mk<double>(1, 0); g.beta = mk<double>(0, 0);
+  g.A = X; g.lda = ldx; g.B = X; g.ldb = ldx; g.C = G; g.ldc = ldg;
+  g.herm = true;
+  g.tag = "ortho_gemm";
+  return gemm_batched<double>(g, s);
+}
+
 static const c128 ONE = {1, 0}, ZERO = {0, 0}, MONE = {-1, 0};
 
 // Largest eigenvalue of the Hermitian PSD m x m matrix G (power iteration).
@@ -430,7 +442,7 @@ static int cholqr_pass(c128* X, long ldx, int rows, int k, Arena& ws, hipStream_
   RSRR_TRY(ws.get<c128>("cq_G", (size_t)k * k, &G));
   RSRR_TRY(ws.get<int>("cq_perm", k, &perm));
   (void)perm;
-  RSRR_TRY(gemm_z(OP_C, OP_N, k, k, rows, ONE, X, ldx, X, ldx, ZERO, G, k, s));
+  RSRR_TRY(gram_z(k, rows, X, ldx, G, k, s));
   RSRR_TRY(chol_blocked(G, k, k, ws, s, ok));
   if (!*ok) return ST_OK;
   return trsm_right_lh(G, k, k, X, ldx, rows, ws, s);
@@ -450,7 +462,7 @@ int basis_of_columns(const c128* X, long ldx, int rows, int cols, int rank, c128
   int* perm = nullptr;
   RSRR_TRY(ws.get<c128>("bc_G", (size_t)cols * cols, &G));
   RSRR_TRY(ws.get<int>("bc_perm", cols, &perm));
-  RSRR_TRY(gemm_z(OP_C, OP_N, cols, cols, rows, ONE, X, ldx, X, ldx, ZERO, G, cols, s));
+  RSRR_TRY(gram_z(cols, rows, X, ldx, G, cols, s));
   int r = 0;
   RSRR_TRY(pchol(G, cols, cols, rank, 0.0, true, perm, ws, s, &r));
   if (r < rank) return set_error(ST_ENOTCONV, "basis_of_columns: rank %d < %d", r, rank);
@@ -472,7 +484,7 @@ int ortho_impl(int rows, int cols, const c128* S, long lds, double delta, c128* 
   RSRR_TRY(ws.get<c128>("or_G", (size_t)m * m, &G));
   RSRR_TRY(ws.get<int>("or_perm", m, &perm));
   // ---- level 1
-  RSRR_TRY(gemm_z(OP_C, OP_N, m, m, rows, ONE, S, lds, S, lds, ZERO, G, m, s));
+  RSRR_TRY(gram_z(m, rows, S, lds, G, m, s));
   double lam1 = 0;
   RSRR_TRY(power_lambda(G, m, m, ws, s, &lam1));
   if (!(lam1 > 0)) { *k_S = 0; return ST_OK; }
@@ -507,7 +519,7 @@ int ortho_impl(int rows, int cols, const c128* S, long lds, double delta, c128* 
         RSRR_TRY(gemm_z(OP_C, OP_N, kn, m, rows, ONE, Q + (long)k0 * ldq, ldq, Rm, rows, ZERO, Cc, kn, s));
         RSRR_TRY(gemm_z(OP_N, OP_N, rows, m, kn, MONE, Q + (long)k0 * ldq, ldq, Cc, kn, ONE, Rm, rows, s));
       }
-      RSRR_TRY(gemm_z(OP_C, OP_N, m, m, rows, ONE, Rm, rows, Rm, rows, ZERO, G, m, s));
+      RSRR_TRY(gram_z(m, rows, Rm, rows, G, m, s));
       // stop at (delta sigma_1)^2, but not below the rounding floor of the Gram
       // matrix of R: pivots under rows * u * max_i ||R_i||^2 are noise
       double dmax = 0;
