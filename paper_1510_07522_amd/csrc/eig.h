@@ -35,10 +35,11 @@ int set_identity(c128* X, long ldx, int m, hipStream_t s);
 constexpr int DC_LEAF = 128;
 int eig_dc(c128* A, long lda, int m, std::vector<cd>* lam, c128* V, long ldv, Arena& ws,
            hipStream_t s, double refine_above = 0.0);
-// Schur forms of `count` independent small matrices (len <= 512), in place, with
-// their unitary factors Z_b (status_b = QR iterations, or -1 on failure).
+// Schur forms of `count` independent small matrices (len <= DC_LEAF, the
+// largest max_len), in place, with their unitary factors Z_b (status_b = QR
+// iterations, or -1 on failure).  One workgroup each, in LDS when it fits.
 int leaf_schur_batched(c128* const* H_dev, c128* const* Z_dev, const int* len_dev, int count,
-                       int* status_dev, hipStream_t s);
+                       int* status_dev, hipStream_t s, int max_len);
 // Eigenvectors X (columns) of the m x m upper-triangular T.
 int tri_eigvecs(const c128* T, long ldt, int m, c128* X, long ldx, hipStream_t s);
 // First-order correction of the eigenvectors X of T (from tri_eigvecs) for

@@ -528,119 +528,11 @@ int hankel_svd(const c128* H, int M, double basis_tol, double trunc, c128* Vh, l
   return ST_OK;
 }
 
-// ------------------------------------------------------------ Hessenberg
-// Householder vector of x = A[k+1:m, k]: v (unit, stored in Vh[:, k]),
-// A[k+1][k] = alpha, A[k+2:m][k] = 0.  Reflector P = I - 2 v v^H.
-__global__ __launch_bounds__(256) void house_kernel(c128* A, long lda, int m, int k, c128* Vh,
-                                                    long ldv, int* skip) {
-  __shared__ double red[256];
-  const int n1 = m - k - 1;
-  double acc = 0;
-  for (int r = threadIdx.x; r < n1; r += 256) acc += abs2(A[k + 1 + r + (long)k * lda]);
-  red[threadIdx.x] = acc;
-  __syncthreads();
-  for (int o = 128; o > 0; o >>= 1) {
-    if (threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
-    __syncthreads();
-  }
-  const double nx = sqrt(red[0]);
-  const c128 x0 = A[k + 1 + (long)k * lda];
-  const double ax0 = sqrt(abs2(x0));
-  // tail norm (entries below the first)
-  const double tail2 = red[0] - abs2(x0);
-  c128* v = Vh + (long)k * ldv;
-  if (!(tail2 > 0.0) || nx == 0.0) {        // already reduced
-    for (int r = threadIdx.x; r < m; r += 256) v[r] = mk<double>(0, 0);
-    if (threadIdx.x == 0) *skip = 1;
-    return;
-  }
-  const c128 ph = ax0 > 0 ? mk<double>(x0.re / ax0, x0.im / ax0) : mk<double>(1, 0);
-  const c128 alpha = mk<double>(-ph.re * nx, -ph.im * nx);
-  // v = x - alpha e1, ||v||^2 = ||x||^2 - 2 Re(conj(alpha) x0) + |alpha|^2 = 2 nx (nx + ax0)
-  const double vn = sqrt(2.0 * nx * (nx + ax0));
-  for (int r = threadIdx.x; r < m; r += 256) {
-    c128 val = mk<double>(0, 0);
-    if (r > k) {
-      val = A[r + (long)k * lda];
-      if (r == k + 1) val = val - alpha;
-      val = (1.0 / vn) * val;
-    }
-    v[r] = val;
-  }
-  __syncthreads();
-  for (int r = threadIdx.x; r < n1; r += 256)
-    A[k + 1 + r + (long)k * lda] = (r == 0) ? alpha : mk<double>(0, 0);
-  if (threadIdx.x == 0) *skip = 0;
-}
-
-// w[c] = sum_r conj(v[r]) X[r][c] over rows r in [r0, m), columns c in [c0, c1)
-__global__ __launch_bounds__(256) void vhx_kernel(const c128* v, const c128* X, long ldx, int r0,
-                                                  int m, int c0, int c1, c128* w, const int* skip) {
-  if (*skip) return;
-  __shared__ double re_[256], im_[256];
-  const int c = c0 + blockIdx.x;
-  if (c >= c1) return;
-  double ar = 0, ai = 0;
-  for (int r = r0 + threadIdx.x; r < m; r += 256) {
-    const c128 t = cmul(v[r], X[r + (long)c * ldx]);
-    ar += t.re;
-    ai += t.im;
-  }
-  re_[threadIdx.x] = ar;
-  im_[threadIdx.x] = ai;
-  __syncthreads();
-  for (int o = 128; o > 0; o >>= 1) {
-    if (threadIdx.x < o) { re_[threadIdx.x] += re_[threadIdx.x + o]; im_[threadIdx.x] += im_[threadIdx.x + o]; }
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) w[c] = mk<double>(re_[0], im_[0]);
-}
-
-// X[r][c] -= 2 v[r] w[c]  for r in [r0, m), c in [c0, c1)
-__global__ __launch_bounds__(256) void left_update_kernel(const c128* v, c128* X, long ldx, int r0,
-                                                          int m, int c0, int c1, const c128* w,
-                                                          const int* skip) {
-  if (*skip) return;
-  const long nr = m - r0, cnt = nr * (long)(c1 - c0);
-  const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= cnt) return;
-  const int r = r0 + (int)(e % nr), c = c0 + (int)(e / nr);
-  const c128 t = v[r] * w[c];
-  c128& x = X[r + (long)c * ldx];
-  x = mk<double>(x.re - 2.0 * t.re, x.im - 2.0 * t.im);
-}
-
-// u[r] = sum_c X[r][c] v[c] over c in [c0, m), rows r in [0, nrow)
-__global__ __launch_bounds__(256) void xv_kernel(const c128* X, long ldx, const c128* v, int c0, int m,
-                                                 int nrow, c128* u, const int* skip) {
-  if (*skip) return;
-  const int r = blockIdx.x * blockDim.x + threadIdx.x;
-  if (r >= nrow) return;
-  c128 acc = mk<double>(0, 0);
-  for (int c = c0; c < m; ++c) acc = acc + X[r + (long)c * ldx] * v[c];
-  u[r] = acc;
-}
-
-// X[r][c] -= 2 u[r] conj(v[c])  for r in [0, nrow), c in [c0, m)
-__global__ __launch_bounds__(256) void right_update_kernel(c128* X, long ldx, const c128* u,
-                                                           const c128* v, int c0, int m, int nrow,
-                                                           const int* skip) {
-  if (*skip) return;
-  const long cnt = (long)nrow * (m - c0);
-  const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= cnt) return;
-  const int r = (int)(e % nrow), c = c0 + (int)(e / nrow);
-  const c128 t = mulc(u[r], v[c]);
-  c128& x = X[r + (long)c * ldx];
-  x = mk<double>(x.re - 2.0 * t.re, x.im - 2.0 * t.im);
-}
-
 // ------------------------------------------------------------- Schur QR
 // Single-shift complex QR on the Hessenberg matrix (one workgroup), with the
 // full Schur form (rotations applied to all columns right / rows above) and
 // the accumulated unitary Z.
 constexpr int QT = 1024;
-constexpr int LEAF_MAX = 512;
 __device__ inline c128 csqrt_d(c128 z) {
   const double r = sqrt(sqrt(abs2(z)));
   const double th = 0.5 * atan2(z.im, z.re);
@@ -759,11 +651,6 @@ __device__ __forceinline__ void hqr_body(c128* H, long ldh, c128* Z, long ldz, i
   if (tid == 0) *status = s_total;
 }
 
-__global__ __launch_bounds__(QT) void hqr_kernel(c128* H, long ldh, c128* Z, long ldz, int m,
-                                                 int maxit, int* status) {
-  hqr_body(H, ldh, Z, ldz, m, maxit, status);
-}
-
 // Schur form of many small independent matrices, one workgroup each:
 // Householder reduction to Hessenberg form (accumulated into Z = I ...), then
 // the single-shift QR of hqr_body.  H_b and Z_b are len_b x len_b, ld len_b.
@@ -772,17 +659,32 @@ struct LeafArgs {
   c128* const* Z;
   const int* len;
   int* status;
+  int lds_len;      // matrices up to this order are worked on in LDS
 };
+// dynamic LDS for H (m x m complex128) beside the kernel's static arrays
+constexpr int LEAF_LDS_BYTES = 144 * 1024;
+inline int leaf_lds_len() {
+  int m = 0;
+  while ((long)(m + 1) * (m + 1) * (long)sizeof(c128) <= LEAF_LDS_BYTES) ++m;
+  return m;
+}
 
 __global__ __launch_bounds__(QT) void leaf_schur_kernel(LeafArgs a) {
-  __shared__ c128 s_v[LEAF_MAX];
+  __shared__ c128 s_v[DC_LEAF];
   __shared__ double s_red[QT / 64];
+  extern __shared__ c128 s_H[];
   const int b = blockIdx.x;
-  c128* H = a.H[b];
+  c128* const Hg = a.H[b];
   c128* Z = a.Z[b];
   const int m = a.len[b];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  // small enough: the reduction and the QR iteration run on a copy in LDS,
+  // where every step's reads and writes take a fraction of a global round trip
+  const bool lds = m <= a.lds_len;
+  c128* H = lds ? s_H : Hg;
   for (int e = tid; e < m * m; e += QT) Z[e] = mk<double>((e % m) == (e / m) ? 1.0 : 0.0, 0);
+  if (lds)
+    for (int e = tid; e < m * m; e += QT) s_H[e] = Hg[e];
   __syncthreads();
   for (int k = 0; k + 2 < m; ++k) {
     double acc = 0;
@@ -836,15 +738,22 @@ __global__ __launch_bounds__(QT) void leaf_schur_kernel(LeafArgs a) {
     __syncthreads();
   }
   hqr_body(H, m, Z, m, m, 60 * m + 100, a.status + b);
+  if (lds) {
+    __syncthreads();
+    for (int e = tid; e < m * m; e += QT) Hg[e] = s_H[e];
+  }
 }
 
 int leaf_schur_batched(c128* const* H_dev, c128* const* Z_dev, const int* len_dev, int count,
-                       int* status_dev, hipStream_t s) {
+                       int* status_dev, hipStream_t s, int max_len) {
   if (count <= 0) return ST_OK;
+  if (max_len > DC_LEAF) return set_error(ST_EINVAL, "leaf_schur: order %d above %d", max_len, DC_LEAF);
   LeafArgs a;
   a.H = H_dev; a.Z = Z_dev; a.len = len_dev; a.status = status_dev;
+  a.lds_len = leaf_lds_len();
+  const size_t shm = (size_t)std::min(max_len, a.lds_len) * std::min(max_len, a.lds_len) * sizeof(c128);
   KernelTimer kt("leaf_schur", s, 0.0, 0.0);
-  hipLaunchKernelGGL(leaf_schur_kernel, dim3(count), dim3(QT), 0, s, a);
+  hipLaunchKernelGGL(leaf_schur_kernel, dim3(count), dim3(QT), shm, s, a);
   RSRR_LAUNCH_CHECK();
   return ST_OK;
 }
@@ -1011,60 +920,40 @@ int eig_general(c128* A, long lda, int m, std::vector<cd>* lam, c128* V, long ld
   lam->clear();
   if (m <= 0) return ST_OK;
   if (m > DC_LEAF) return eig_dc(A, lda, m, lam, V, ldv, ws, s, refine_above);
-  c128 *Vh = nullptr, *Z = nullptr, *w = nullptr, *X = nullptr;
-  int* skip = nullptr;
-  RSRR_TRY(ws.get<c128>("eg_Vh", (size_t)m * m, &Vh));
+  // ---- Schur form A = Z T Z^H: Householder reduction to Hessenberg form and
+  // the QR iteration in one workgroup (in LDS when the matrix fits), on a
+  // contiguous copy H of A
+  c128 *H = nullptr, *Z = nullptr, *w = nullptr, *X = nullptr;
+  c128** pdev = nullptr;
+  int* idev = nullptr;
+  RSRR_TRY(ws.get<c128>("eg_H", (size_t)m * m, &H));
   RSRR_TRY(ws.get<c128>("eg_Z", (size_t)m * m, &Z));
   RSRR_TRY(ws.get<c128>("eg_w", m, &w));
   RSRR_TRY(ws.get<c128>("eg_X", (size_t)m * m, &X));
-  RSRR_TRY(ws.get<int>("eg_skip", 2, &skip));
-  RSRR_TRY(set_identity(Z, m, m, s));
-  // ---- Hessenberg reduction A = Q Hs Q^H; Z accumulates Q
-  for (int k = 0; k + 2 < m; ++k) {
-    KernelTimer kt("hessenberg", s, 8.0 * 4.0 * (double)m * (m - k), 16.0 * 6 * (double)m * (m - k));
-    hipLaunchKernelGGL(house_kernel, dim3(1), dim3(256), 0, s, A, lda, m, k, Vh, m, skip);
-    RSRR_LAUNCH_CHECK();
-    const c128* v = Vh + (long)k * m;
-    // left: A[k+1:, k+1:] -= 2 v (v^H A[k+1:, k+1:])
-    hipLaunchKernelGGL(vhx_kernel, dim3(m - k - 1), dim3(256), 0, s, v, A, lda, k + 1, m, k + 1, m, w, skip);
-    RSRR_LAUNCH_CHECK();
-    long cnt = (long)(m - k - 1) * (m - k - 1);
-    hipLaunchKernelGGL(left_update_kernel, dim3((unsigned)cdivl(cnt, 256)), dim3(256), 0, s, v, A, lda,
-                       k + 1, m, k + 1, m, w, skip);
-    RSRR_LAUNCH_CHECK();
-    // right: A[:, k+1:] -= 2 (A[:, k+1:] v) v^H ; same for Z
-    hipLaunchKernelGGL(xv_kernel, dim3((unsigned)cdivl(m, 256)), dim3(256), 0, s, A, lda, v, k + 1, m, m, w, skip);
-    RSRR_LAUNCH_CHECK();
-    cnt = (long)m * (m - k - 1);
-    hipLaunchKernelGGL(right_update_kernel, dim3((unsigned)cdivl(cnt, 256)), dim3(256), 0, s, A, lda, w, v,
-                       k + 1, m, m, skip);
-    RSRR_LAUNCH_CHECK();
-    hipLaunchKernelGGL(xv_kernel, dim3((unsigned)cdivl(m, 256)), dim3(256), 0, s, Z, m, v, k + 1, m, m, w, skip);
-    RSRR_LAUNCH_CHECK();
-    hipLaunchKernelGGL(right_update_kernel, dim3((unsigned)cdivl(cnt, 256)), dim3(256), 0, s, Z, m, w, v,
-                       k + 1, m, m, skip);
-    RSRR_LAUNCH_CHECK();
-  }
-  // ---- Schur form
+  RSRR_TRY(ws.get<c128*>("eg_P", 2, &pdev));
+  RSRR_TRY(ws.get<int>("eg_I", 2, &idev));
+  RSRR_TRY((convert<double, double>(A, lda, 0, H, m, 0, m, m, 1, s)));
+  c128* hp[2] = {H, Z};
+  RSRR_HIP(hipMemcpyAsync(pdev, hp, sizeof(hp), hipMemcpyHostToDevice, s));
+  RSRR_HIP(hipMemcpyAsync(idev, &m, sizeof(int), hipMemcpyHostToDevice, s));
   {
   KernelTimer kt("hqr", s, 0.0, 0.0);
-  hipLaunchKernelGGL(hqr_kernel, dim3(1), dim3(QT), 0, s, A, lda, Z, m, m, 60 * m + 100, skip + 1);
-  RSRR_LAUNCH_CHECK();
+  RSRR_TRY(leaf_schur_batched(pdev, pdev + 1, idev, 1, idev + 1, s, m));
   }
   int st = 0;
-  RSRR_HIP(hipMemcpyAsync(&st, skip + 1, sizeof(int), hipMemcpyDeviceToHost, s));
+  RSRR_HIP(hipMemcpyAsync(&st, idev + 1, sizeof(int), hipMemcpyDeviceToHost, s));
   RSRR_HIP(hipStreamSynchronize(s));
   if (st < 0) return set_error(ST_ENOTCONV, "Hessenberg QR did not converge (m=%d)", m);
   // ---- eigenvalues and eigenvectors
   std::vector<c128> diag;
-  RSRR_TRY(diag_to_host(A, lda, m, w, &diag, s));
+  RSRR_TRY(diag_to_host(H, m, m, w, &diag, s));
   double tnorm = 0;
   for (int j = 0; j < m; ++j) tnorm = std::max(tnorm, sqrt(abs2(diag[j])));
   const double small = std::max(tnorm, 1e-300) * 2.220446049250313e-16;
   const size_t shm = (size_t)m * sizeof(c128);
   if (shm > 150 * 1024) return set_error(ST_EINVAL, "eigenvectors: m=%d too large", m);
   KernelTimer kt("trevc", s, 8.0 * (double)m * m * m / 6, 16.0 * (double)m * m * m / 2);
-  hipLaunchKernelGGL(trevc_kernel, dim3(m), dim3(256), shm, s, A, lda, m, small, X, m);
+  hipLaunchKernelGGL(trevc_kernel, dim3(m), dim3(256), shm, s, H, (long)m, m, small, X, m);
   RSRR_LAUNCH_CHECK();
   GemmBatch<double> g;                    // V = Z X
   g.M = m; g.N = m; g.K = m;

@@ -836,7 +836,9 @@ int eig_dc(c128* A, long lda, int m, std::vector<cd>* lam, c128* V, long ldv, Ar
   RSRR_HIP(hipMemcpyAsync(pdev, hH.data(), nl * sizeof(c128*), hipMemcpyHostToDevice, s));
   RSRR_HIP(hipMemcpyAsync(pdev + nl, hZ.data(), nl * sizeof(c128*), hipMemcpyHostToDevice, s));
   RSRR_HIP(hipMemcpyAsync(idev, hlen.data(), nl * sizeof(int), hipMemcpyHostToDevice, s));
-  RSRR_TRY(leaf_schur_batched(pdev, pdev + nl, idev, nl, idev + nl, s));
+  int maxlen = 0;
+  for (int i = 0; i < nl; ++i) maxlen = std::max(maxlen, hlen[i]);
+  RSRR_TRY(leaf_schur_batched(pdev, pdev + nl, idev, nl, idev + nl, s, maxlen));
   std::vector<int> st(nl);
   RSRR_HIP(hipMemcpyAsync(st.data(), idev + nl, nl * sizeof(int), hipMemcpyDeviceToHost, s));
   RSRR_HIP(hipStreamSynchronize(s));
