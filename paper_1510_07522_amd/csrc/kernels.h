@@ -76,7 +76,8 @@ template <typename R> struct LUWork {
   // take all its panels' updates as one product with K = 256 (nb <= 128)
   bool pair = false;
   // look-ahead (optional): the trailing update beyond the next panel runs on
-  // `aux` while the next panel is factored; ev_main / ev_aux order the two
+  // `aux`, in column pieces, while the next panel is factored; ev_main /
+  // ev_aux order the two
   hipStream_t aux = nullptr;
   hipEvent_t ev_main = nullptr, ev_aux = nullptr;
   int npanel() const { return (n + nb - 1) / nb; }

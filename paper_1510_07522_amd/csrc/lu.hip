@@ -10,6 +10,9 @@
 //   2. lu_permute_kernel: the panel's interchanges, applied as one gather to
 //      the columns right of the panel.
 //   3. U12 = inv(L11) A12 and A22 -= L21 U12 as matrix-core GEMMs.
+// Panels come in blocks of lu_group(nb) (K = 256 products for the columns
+// beyond a block); with look-ahead, the far columns' product runs on a second
+// stream in column pieces while the next panels are factored.
 #include "common.h"
 #include "kernels.h"
 #include "timers.h"

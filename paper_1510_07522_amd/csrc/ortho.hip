@@ -281,16 +281,65 @@ static int gemm_z(int opA, int opB, int M, int N, int K, c128 alpha, const c128*
   return gemm_batched<double>(g, s);
 }
 
+__global__ __launch_bounds__(256) void sum_slices_kernel(const c128* W, int S, int M, int N, c128 alpha,
+                                                          c128* C, long ldc) {
+  const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= (long)M * N) return;
+  c128 acc = W[e];
+  for (int q = 1; q < S; ++q) acc = acc + W[(long)q * M * N + e];
+  C[e % M + (e / M) * ldc] = alpha * acc;
+}
+
+// C = alpha A^H B (beta 0, one product) with K = the rows of the sample
+// matrix.  With few 64x64 output tiles each workgroup would walk the whole K
+// while most CUs idle, so the K range is cut into S slices that run as one
+// batched product into work space, summed afterwards in slice order.
+static int gemm_hk(GemmBatch<double> g, Arena& ws, hipStream_t s) {
+  const long tiles = cdivl(g.M, 64) * cdivl(g.N, 64);
+  const int S = (int)std::min<long>(256 / std::max<long>(1, tiles), g.K / 1024);
+  if (S < 2) return gemm_batched<double>(g, s);
+  c128* W = nullptr;
+  RSRR_TRY(ws.get<c128>("or_kslices", (size_t)S * g.M * g.N, &W));
+  const int K = g.K, Ks = K / S;
+  const c128 alpha = g.alpha;
+  c128* const C = g.C;
+  const long ldc = g.ldc, mn = (long)g.M * g.N;
+  const c128* A = (const c128*)g.A;
+  const c128* B = g.B;
+  g.alpha = mk<double>(1, 0);
+  g.C = W; g.ldc = g.M; g.sC = mn;
+  g.K = Ks; g.sA = Ks; g.sB = Ks; g.batch = S - 1;     // rows [q Ks, (q+1) Ks) of A and B
+  RSRR_TRY(gemm_batched<double>(g, s));
+  g.A = A + (long)(S - 1) * Ks; g.B = B + (long)(S - 1) * Ks; g.C = W + (S - 1) * mn;
+  g.K = K - (S - 1) * Ks; g.batch = 1;
+  RSRR_TRY(gemm_batched<double>(g, s));
+  hipLaunchKernelGGL(sum_slices_kernel, dim3((unsigned)cdivl(mn, 256)), dim3(256), 0, s, W, S, g.M, g.N, alpha, C,
+                     ldc);
+  RSRR_LAUNCH_CHECK();
+  return ST_OK;
+}
+
+// C = A^H B (M x N, K = rows)
+static int gemm_ct(int M, int N, int rows, const c128* A, long lda, const c128* B, long ldb, c128* C, long ldc,
+                   Arena& ws, hipStream_t s) {
+  GemmBatch<double> g;
+  g.opA = OP_C; g.opB = OP_N; g.M = M; g.N = N; g.K = rows;
+  g.alpha = mk<double>(1, 0); g.beta = mk<double>(0, 0);
+  g.A = A; g.lda = lda; g.B = B; g.ldb = ldb; g.C = C; g.ldc = ldc;
+  g.tag = "ortho_gemm";
+  return gemm_hk(g, ws, s);
+}
+
 // G = X^H X (cols x cols, leading dim ldg): the tiles on and below the
 // diagonal, mirrored above it
-static int gram_z(int cols, int rows, const c128* X, long ldx, c128* G, long ldg, hipStream_t s) {
+static int gram_z(int cols, int rows, const c128* X, long ldx, c128* G, long ldg, Arena& ws, hipStream_t s) {
   GemmBatch<double> g;
   g.opA = OP_C; g.opB = OP_N; g.M = cols; g.N = cols; g.K = rows;
   g.alpha = mk<double>(1, 0); g.beta = mk<double>(0, 0);
   g.A = X; g.lda = ldx; g.B = X; g.ldb = ldx; g.C = G; g.ldc = ldg;
   g.herm = true;
   g.tag = "ortho_gemm";
-  return gemm_batched<double>(g, s);
+  return gemm_hk(g, ws, s);
 }
 
 static const c128 ONE = {1, 0}, ZERO = {0, 0}, MONE = {-1, 0};
@@ -442,7 +491,7 @@ static int cholqr_pass(c128* X, long ldx, int rows, int k, Arena& ws, hipStream_
   RSRR_TRY(ws.get<c128>("cq_G", (size_t)k * k, &G));
   RSRR_TRY(ws.get<int>("cq_perm", k, &perm));
   (void)perm;
-  RSRR_TRY(gram_z(k, rows, X, ldx, G, k, s));
+  RSRR_TRY(gram_z(k, rows, X, ldx, G, k, ws, s));
   RSRR_TRY(chol_blocked(G, k, k, ws, s, ok));
   if (!*ok) return ST_OK;
   return trsm_right_lh(G, k, k, X, ldx, rows, ws, s);
@@ -462,7 +511,7 @@ int basis_of_columns(const c128* X, long ldx, int rows, int cols, int rank, c128
   int* perm = nullptr;
   RSRR_TRY(ws.get<c128>("bc_G", (size_t)cols * cols, &G));
   RSRR_TRY(ws.get<int>("bc_perm", cols, &perm));
-  RSRR_TRY(gram_z(cols, rows, X, ldx, G, cols, s));
+  RSRR_TRY(gram_z(cols, rows, X, ldx, G, cols, ws, s));
   int r = 0;
   RSRR_TRY(pchol(G, cols, cols, rank, 0.0, true, perm, ws, s, &r));
   if (r < rank) return set_error(ST_ENOTCONV, "basis_of_columns: rank %d < %d", r, rank);
@@ -484,7 +533,7 @@ int ortho_impl(int rows, int cols, const c128* S, long lds, double delta, c128* 
   RSRR_TRY(ws.get<c128>("or_G", (size_t)m * m, &G));
   RSRR_TRY(ws.get<int>("or_perm", m, &perm));
   // ---- level 1
-  RSRR_TRY(gram_z(m, rows, S, lds, G, m, s));
+  RSRR_TRY(gram_z(m, rows, S, lds, G, m, ws, s));
   double lam1 = 0;
   RSRR_TRY(power_lambda(G, m, m, ws, s, &lam1));
   if (!(lam1 > 0)) { *k_S = 0; return ST_OK; }
@@ -516,10 +565,10 @@ int ortho_impl(int rows, int cols, const c128* S, long lds, double delta, c128* 
     int k0 = 0, kn = kS;
     for (int level = 2; level <= levels && kS < kmax; ++level) {
       for (int pass = 0; pass < 2; ++pass) {
-        RSRR_TRY(gemm_z(OP_C, OP_N, kn, m, rows, ONE, Q + (long)k0 * ldq, ldq, Rm, rows, ZERO, Cc, kn, s));
+        RSRR_TRY(gemm_ct(kn, m, rows, Q + (long)k0 * ldq, ldq, Rm, rows, Cc, kn, ws, s));
         RSRR_TRY(gemm_z(OP_N, OP_N, rows, m, kn, MONE, Q + (long)k0 * ldq, ldq, Cc, kn, ONE, Rm, rows, s));
       }
-      RSRR_TRY(gram_z(m, rows, Rm, rows, G, m, s));
+      RSRR_TRY(gram_z(m, rows, Rm, rows, G, m, ws, s));
       // stop at (delta sigma_1)^2, but not below the rounding floor of the Gram
       // matrix of R: pivots under rows * u * max_i ||R_i||^2 are noise
       double dmax = 0;
@@ -535,7 +584,7 @@ int ortho_impl(int rows, int cols, const c128* S, long lds, double delta, c128* 
       RSRR_LAUNCH_CHECK();
       RSRR_TRY(trsm_right_lh(G, m, k2, Q2, ldq, rows, ws, s));
       for (int pass = 0; pass < 2; ++pass) {
-        RSRR_TRY(gemm_z(OP_C, OP_N, kS, k2, rows, ONE, Q, ldq, Q2, ldq, ZERO, Cc, kS, s));
+        RSRR_TRY(gemm_ct(kS, k2, rows, Q, ldq, Q2, ldq, Cc, kS, ws, s));
         RSRR_TRY(gemm_z(OP_N, OP_N, rows, k2, kS, MONE, Q, ldq, Cc, kS, ONE, Q2, ldq, s));
         bool ok2 = true;
         RSRR_TRY(cholqr_pass(Q2, ldq, rows, k2, ws, s, &ok2));
