@@ -266,6 +266,7 @@ int solve_end(rsrr_problem* p, const rsrr_contour* c, const rsrr_params* prm, rs
     w.gauss3m = true;
     w.full_swap = true;
     w.lperm = lperm;
+    w.pair = true;
     RSRR_TRY(lu_factor<double>(w, s));
     // the inverses replace the factors in TS once the solves are done; X is
     // the work space of the solves

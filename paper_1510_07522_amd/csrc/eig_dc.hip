@@ -151,6 +151,7 @@ static int newton_sign(int len, DcWork& w, Arena& ws, hipStream_t s, int* iters)
   lw.ipiv = w.ipiv; lw.dinv = w.dinv; lw.info = w.info;
   lw.tag = "dc_lu";
   lw.gauss3m = true;
+  lw.pair = true;
   RSRR_TRY(ws.aux_stream(&lw.aux, &lw.ev_main, &lw.ev_aux));
   bool scaling = true, schulz = false;
   double prev_r = 1e300;
@@ -365,6 +366,7 @@ static int newton_sign_batched(DcBatch& bt, Arena& ws, hipStream_t s, std::vecto
   lw.ipiv = bt.ipiv; lw.dinv = bt.dinv; lw.info = bt.info;
   lw.tag = "dc_lu";
   lw.gauss3m = true;
+  lw.pair = true;
   RSRR_TRY(ws.aux_stream(&lw.aux, &lw.ev_main, &lw.ev_aux));
   GemmBatch<double> g;
   g.tag = "dc_gemm";

@@ -71,9 +71,10 @@ template <typename R> struct LUWork {
   // panel's L columns are then moved once, by the composition of the later
   // panels' interchanges, instead of once per later panel
   int* lperm = nullptr;
-  // panels in blocks of lu_group(nb) (not with full_swap): inside a block
-  // each panel updates the block's later columns; the columns beyond a block
-  // take all its panels' updates as one product with K = 256 (nb <= 128)
+  // panels in blocks of lu_group(nb): inside a block each panel updates the
+  // block's later columns; the columns beyond a block take all its panels'
+  // updates as one product with K = 256 (nb <= 128).  With full_swap the
+  // later blocks' interchanges reach a block's L columns at the end.
   bool pair = false;
   // look-ahead (optional): the trailing update beyond the next panel runs on
   // `aux`, in column pieces, while the next panel is factored; ev_main /

@@ -496,14 +496,18 @@ __global__ __launch_bounds__(256) void lu_left_perm_kernel(const int* ipiv, int 
 
 // Applies G to the L columns: column c of panel p = c / nb < np - 1, rows
 // [k_{p+1}, n), gathered through registers (every read before any write);
-// rows that keep their place are not touched.
+// rows that keep their place are not touched.  With blocks of grp panels, p
+// is the last panel of c's block.
 constexpr int LGT = 1024;               // threads per column
 constexpr int LGR = 4;                  // rows per thread: n - nb <= LGT * LGR
 template <typename R>
 __global__ __launch_bounds__(LGT) void lu_left_gather_kernel(cplx<R>* A, long lda, long sA, int n, int nb,
-                                                             const int* G) {
+                                                             const int* G, int grp) {
   const int c = blockIdx.x, b = blockIdx.y, tid = threadIdx.x, np = (n + nb - 1) / nb;
-  const int p = c / nb;
+  // factored in blocks of grp panels, a panel's L columns already carry the
+  // interchanges of its block's later panels: they take those of the panels
+  // after the block, the composition stored for the block's last panel
+  const int p = min(np - 1, (c / nb / grp + 1) * grp - 1);
   if (p >= np - 1) return;
   const int k1 = (p + 1) * nb;
   cplx<R>* col = A + (long)b * sA + (long)c * lda;
@@ -616,7 +620,37 @@ int lu_factor(const LUWork<R>& w, hipStream_t s) {
   const bool la = (w.aux != nullptr && w.ev_main != nullptr && w.ev_aux != nullptr);
   bool aux_busy = false;
   const int SB0 = lu_group(nb);
-  if (w.pair && !w.full_swap && SB0 >= 2) {
+  // full_swap: every panel's interchanges on all earlier L columns, after the
+  // factorisation, as one gather per L column (lperm) or one permute per panel;
+  // grp = panels per block, whose interchanges the L columns of a block
+  // already took inside the block
+  auto left_swaps = [&](int grp) -> int {
+    const int np = w.npanel();
+    if (w.lperm && np > 1 && n - nb <= LGT * LGR && 2 * (size_t)n * sizeof(int) <= 64 * 1024) {
+      {
+        KernelTimer kt("lu_permute", s, 0.0, 4.0 * (double)np * n * w.batch, "lu_left_perm_kernel");
+        hipLaunchKernelGGL(lu_left_perm_kernel, dim3(w.batch), dim3(256), 2 * (size_t)n * sizeof(int), s, w.ipiv,
+                           n, nb, w.lperm);
+        RSRR_LAUNCH_CHECK();
+      }
+      const int lcols = (np - 1) * nb;
+      KernelTimer kt("lu_permute", s, 0.0, 2.0 * sizeof(cplx<R>) * 0.5 * (double)n * lcols * w.batch,
+                     timers_on() ? std::string("lu_left_gather_kernel<") + (sizeof(R) == 8 ? "double" : "float") +
+                                       ">"
+                                 : std::string());
+      hipLaunchKernelGGL((lu_left_gather_kernel<R>), dim3(lcols, w.batch), dim3(LGT), 0, s, w.A, w.lda, w.sA, n,
+                         nb, w.lperm, grp);
+      RSRR_LAUNCH_CHECK();
+      return ST_OK;
+    }
+    for (int q = 1; q < np; ++q) {
+      const int cols = (q / grp) * grp * nb;      // the L columns of the earlier blocks
+      if (cols > 0)
+        RSRR_TRY(launch_permute<R>(w.A, w.lda, w.sA, cols, w.ipiv, n, q * nb, min(nb, n - q * nb), w.batch, s));
+    }
+    return ST_OK;
+  };
+  if (w.pair && SB0 >= 2) {
     // Blocks of P = SB0 panels (the solver's groups of 256 columns).  Inside
     // a block, each panel once factored updates the block's later columns
     // (right-looking: interchanges, U rows, the rows below), and its
@@ -677,7 +711,7 @@ int lu_factor(const LUWork<R>& w, hipStream_t s) {
       RSRR_TRY(launch_panel<R>(w, kend, min(nb, n - kend), s));
     }
     if (aux_busy) RSRR_HIP(hipStreamWaitEvent(s, w.ev_aux, 0));
-    return ST_OK;
+    return w.full_swap ? left_swaps(P) : ST_OK;
   }
   RSRR_TRY(launch_panel<R>(w, 0, min(nb, n), s));
   if (la) RSRR_HIP(hipEventRecord(w.ev_main, s));
@@ -716,26 +750,11 @@ int lu_factor(const LUWork<R>& w, hipStream_t s) {
   // the solver can update the rows below a group with one product.  Rows of a
   // panel's own diagonal block are never touched, so L stays unit lower
   // triangular and dinv is unchanged.
+  if (w.full_swap) return left_swaps(1);
   const int np = w.npanel(), SB = lu_group(nb);
-  if (w.full_swap && w.lperm && np > 1 && n - nb <= LGT * LGR && 2 * (size_t)n * sizeof(int) <= 64 * 1024) {
-    {
-      KernelTimer kt("lu_permute", s, 0.0, 4.0 * (double)np * n * w.batch, "lu_left_perm_kernel");
-      hipLaunchKernelGGL(lu_left_perm_kernel, dim3(w.batch), dim3(256), 2 * (size_t)n * sizeof(int), s, w.ipiv,
-                         n, nb, w.lperm);
-      RSRR_LAUNCH_CHECK();
-    }
-    const int lcols = (np - 1) * nb;
-    KernelTimer kt("lu_permute", s, 0.0, 2.0 * sizeof(cplx<R>) * 0.5 * (double)n * lcols * w.batch,
-                   timers_on() ? std::string("lu_left_gather_kernel<") + (sizeof(R) == 8 ? "double" : "float") + ">"
-                               : std::string());
-    hipLaunchKernelGGL((lu_left_gather_kernel<R>), dim3(lcols, w.batch), dim3(LGT), 0, s, w.A, w.lda, w.sA, n,
-                       nb, w.lperm);
-    RSRR_LAUNCH_CHECK();
-    return ST_OK;
-  }
   for (int q = 1; q < np; ++q) {
-    if (!w.full_swap && q % SB == 0) continue;
-    const int k = q * nb, c0 = w.full_swap ? 0 : (q / SB) * SB * nb;
+    if (q % SB == 0) continue;
+    const int k = q * nb, c0 = (q / SB) * SB * nb;
     RSRR_TRY(launch_permute<R>(w.A + (long)c0 * w.lda, w.lda, w.sA, k - c0, w.ipiv, n, k, min(nb, n - k),
                                w.batch, s));
   }
