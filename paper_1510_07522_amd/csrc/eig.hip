@@ -936,10 +936,7 @@ int eig_general(c128* A, long lda, int m, std::vector<cd>* lam, c128* V, long ld
   c128* hp[2] = {H, Z};
   RSRR_HIP(hipMemcpyAsync(pdev, hp, sizeof(hp), hipMemcpyHostToDevice, s));
   RSRR_HIP(hipMemcpyAsync(idev, &m, sizeof(int), hipMemcpyHostToDevice, s));
-  {
-  KernelTimer kt("hqr", s, 0.0, 0.0);
   RSRR_TRY(leaf_schur_batched(pdev, pdev + 1, idev, 1, idev + 1, s, m));
-  }
   int st = 0;
   RSRR_HIP(hipMemcpyAsync(&st, idev + 1, sizeof(int), hipMemcpyDeviceToHost, s));
   RSRR_HIP(hipStreamSynchronize(s));
