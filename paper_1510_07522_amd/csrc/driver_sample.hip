@@ -110,6 +110,7 @@ static int residual_fp64(rsrr_problem* p, int N, int L, const c128* f_dev, const
       g.B = Y + (long)q * L * ldy; g.ldb = ldy; g.sB = (long)L * ldy;
       g.C = Rb + (long)q * L * n; g.ldc = n; g.sC = (long)L * n;
       g.batch = nodes ? 1 : N;
+      g.gauss3m = true;        // normwise stable, which is what the backward error needs
       g.tag = "ir_residual_gemm";
       RSRR_TRY(gemm_batched<double>(g, s));
     }
