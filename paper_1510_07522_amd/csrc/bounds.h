@@ -43,8 +43,9 @@ inline size_t workspace_bound(int n_, int J_, bool bem, const rsrr_params* prm) 
   const double cols = prm->scheme == RSRR_SCHEME_MOMENT ? (double)(prm->Kp > 0 ? prm->Kp : prm->N) * L : NL;
   const double kS = std::min(n, cols), kk = kS * kS, M = K * kS;   // m <= M
   const double J = bem ? (prm->cheb_degree > 0 ? prm->cheb_degree : 40) + 1 : J_;
-  // sampling: complex128 factors and diagonal-block inverses (the precision, or
-  // the fallback of every node), complex64 factors, solutions and residuals
+  // sampling: complex128 factors and diagonal-block inverses (the precision,
+  // the fallback of every node, or the fp64 BEM matrices of the refinement),
+  // complex64 factors, solutions and residuals
   double samp = N * n * n * z + 2 * N * n * nb * z + (J + 10) * n * NL * z;
   if (prm->precision == RSRR_PREC_C64_IR) samp += N * n * n * 8 + 2 * N * n * nb * 8;
   if (bem) samp += N * n * 8;
@@ -53,11 +54,11 @@ inline size_t workspace_bound(int n_, int J_, bool bem, const rsrr_params* prm) 
   // projection (BEM: Chebyshev samples T(x_k) and T(x_k) Q in chunks)
   double proj = 2 * J * kk * z + n * kS * z;
   if (bem) {
-    // the buffer of the interpolation samples also holds the fp64 T(z_j) of
-    // the refinement residual (a batch of nodes within chunk_gib)
+    // the interpolation samples T(x_k) in batches within chunk_gib (the fp64
+    // T(z_j) of the refinement use the complex128 factor buffer above)
     const double fit = std::max(1.0, std::floor(cap / (n * n * z)));
-    const double chb = std::min(J, fit), chr = std::min(N, fit);
-    proj += std::max(chb, chr) * n * n * z + chb * n * kS * z + J * J * z + J * kk * z;
+    const double chb = std::min(J, fit);
+    proj += chb * n * n * z + chb * n * kS * z + J * J * z + J * kk * z;
   }
   // moments: a batch of T_S(zeta) and inverses within chunk_gib
   const double ch = chunk_count(prm->NS, (size_t)(kk * z * 2), prm->chunk_gib).second;

@@ -91,12 +91,13 @@ __global__ __launch_bounds__(256) void scatter_node_cols_c64_kernel(const c128* 
 }
 
 // R_j = U - T(z_j) Y_j in fp64 for the N nodes whose solutions are the
-// column blocks of Y.  BEM with Tres: the fp64 matrices of all sampling nodes
-// are resident (node j at Tres + j n^2), and nodes[q] (host; none: q) names
-// the node of block q.
-static int residual_fp64(rsrr_problem* p, int N, int L, const c128* f_dev, const c128* z_dev,
-                         const c128* U, long ldu, const c128* Y, long ldy, c128* Rb, double chunk_gib,
-                         hipStream_t s, const c128* Tres = nullptr, const int* nodes = nullptr) {
+// column blocks of Y.  BEM: the fp64 matrices of all sampling nodes are
+// resident in Tres (node j at Tres + j n^2), and nodes[q] (host; none: q)
+// names the node of block q.  Coefficient form: f_dev holds the N nodes'
+// coefficients.
+static int residual_fp64(rsrr_problem* p, int N, int L, const c128* f_dev, const c128* U, long ldu,
+                         const c128* Y, long ldy, c128* Rb, hipStream_t s, const c128* Tres = nullptr,
+                         const int* nodes = nullptr) {
   const int n = p->n;
   const long cols = (long)N * L;
   if (p->bem && Tres) {
@@ -116,31 +117,7 @@ static int residual_fp64(rsrr_problem* p, int N, int L, const c128* f_dev, const
     }
     return ST_OK;
   }
-  if (p->bem) {
-    // T(z_j) assembled in fp64 for a balanced batch of nodes that fits
-    // chunk_gib (in the buffer the interpolation samples of the projection
-    // use later), then R_j = U - T(z_j) Y_j on the matrix cores: the entries
-    // are computed once per sweep by a kernel that does nothing else, instead
-    // of inside the GEMM's operand staging where their latency is not hidden
-    const std::pair<int, int> bc = chunk_count(N, (size_t)n * n * sizeof(c128), chunk_gib);
-    c128* T = nullptr;
-    RSRR_TRY(p->ws.get<c128>("pj_T", (size_t)bc.second * n * n, &T));
-    RSRR_TRY((convert<double, double>(U, ldu, 0, Rb, n, (long)L * n, n, L, N, s)));
-    for (int j0 = 0; j0 < N; j0 += bc.second) {
-      const int cnt = std::min(bc.second, N - j0);
-      RSRR_TRY(assemble_bem<double>(n, p->xyz, p->h, cnt, z_dev + j0, T, n, (long)n * n, s));
-      GemmBatch<double> g;
-      g.M = n; g.N = L; g.K = n;
-      g.alpha = mk<double>(-1, 0); g.beta = mk<double>(1, 0);
-      g.A = T; g.lda = n; g.sA = (long)n * n;
-      g.B = Y + (long)j0 * L * ldy; g.ldb = ldy; g.sB = (long)L * ldy;
-      g.C = Rb + (long)j0 * L * n; g.ldc = n; g.sC = (long)L * n;
-      g.batch = cnt;
-      g.tag = "ir_residual_gemm";
-      RSRR_TRY(gemm_batched<double>(g, s));
-    }
-    return ST_OK;
-  }
+  if (p->bem) return set_error(ST_EINVAL, "residual: the BEM matrices are not resident");
   std::vector<const c128*> P(p->J);
   for (int k = 0; k < p->J; ++k) {
     c128* Pk = nullptr;
@@ -399,7 +376,7 @@ int sample_end(SamplePlan* sp) {
     // their columns are gathered for the fp64 residual, and the solves skip
     // the others
     int *idx_dev = nullptr;
-    c128 *Sa = nullptr, *Ra = nullptr, *fa_dev = nullptr, *za_dev = nullptr;
+    c128 *Sa = nullptr, *Ra = nullptr, *fa_dev = nullptr;
     RSRR_TRY(p->ws.get<int>("s_idx", N, &idx_dev));
     std::vector<int> idx;
     int nact = N;
@@ -407,7 +384,7 @@ int sample_end(SamplePlan* sp) {
       // residuals of the nodes corrected in the last sweep (all in the first)
       const bool res_full = (nact == N);
       if (res_full) {
-        RSRR_TRY(residual_fp64(p, N, L, f_dev, z_dev, U, ldu, S, lds, Rb, prm->chunk_gib, s, Tres));
+        RSRR_TRY(residual_fp64(p, N, L, f_dev, U, ldu, S, lds, Rb, s, Tres));
         RSRR_TRY(block_fro2(Rb, n, (long)L * n, n, L, N, nrm, s));
         RSRR_TRY(block_fro2(S, lds, (long)L * lds, n, L, N, nrm + N, s));
         RSRR_HIP(hipMemcpyAsync(r2.data(), nrm, N * sizeof(double), hipMemcpyDeviceToHost, s));
@@ -418,23 +395,18 @@ int sample_end(SamplePlan* sp) {
         const long ca = (long)na * L;
         RSRR_TRY(p->ws.get<c128>("s_Sa", (size_t)n * ca, &Sa));
         RSRR_TRY(p->ws.get<c128>("s_Ra", (size_t)n * ca, &Ra));
-        std::vector<c128> fa(p->bem ? 0 : (size_t)na * p->J), za(na);
-        for (int q = 0; q < na; ++q) {
-          za[q] = zc[idx[q]];
-          if (!p->bem)
+        std::vector<c128> fa(p->bem ? 0 : (size_t)na * p->J);
+        if (!p->bem)
+          for (int q = 0; q < na; ++q)
             for (int k = 0; k < p->J; ++k) fa[(size_t)q * p->J + k] = f[(size_t)idx[q] * p->J + k];
-        }
         RSRR_TRY(p->ws.get<c128>("s_fa", std::max<size_t>(1, fa.size()), &fa_dev));
-        RSRR_TRY(p->ws.get<c128>("s_za", na, &za_dev));
         if (!fa.empty())
           RSRR_HIP(hipMemcpyAsync(fa_dev, fa.data(), fa.size() * sizeof(c128), hipMemcpyHostToDevice, s));
-        RSRR_HIP(hipMemcpyAsync(za_dev, za.data(), na * sizeof(c128), hipMemcpyHostToDevice, s));
         RSRR_HIP(hipMemcpyAsync(idx_dev, idx.data(), na * sizeof(int), hipMemcpyHostToDevice, s));
         hipLaunchKernelGGL(gather_node_cols_kernel, dim3((unsigned)cdivl((long)n * ca, 256)), dim3(256), 0, s, S,
                            lds, n, L, idx_dev, na, Sa, (long)n);
         RSRR_LAUNCH_CHECK();
-        RSRR_TRY(residual_fp64(p, na, L, fa_dev, za_dev, U, ldu, Sa, n, Ra, prm->chunk_gib, s, Tres,
-                               idx.data()));
+        RSRR_TRY(residual_fp64(p, na, L, fa_dev, U, ldu, Sa, n, Ra, s, Tres, idx.data()));
         RSRR_TRY(block_fro2(Ra, n, (long)L * n, n, L, na, nrm, s));
         RSRR_TRY(block_fro2(Sa, n, (long)L * n, n, L, na, nrm + N, s));
         std::vector<double> ra(na), ya(na);
