@@ -373,51 +373,78 @@ __device__ __forceinline__ void lu_permute_body(cplx<R>* Xb, long ldx, int ncols
   __shared__ int t_row[2 * MAXNB], t_src[2 * MAXNB];
   __shared__ int s_cnt;
   constexpr int SWC = SwCols<R>::v;
-  __shared__ cplx<R> vals[2 * MAXNB][SWC];
+  __shared__ cplx<R> vals[SWC][2 * MAXNB];
   const int tid = threadIdx.x;
   if (tid < 64) {
     const int lane = tid;
     for (int e = lane; e < nbe; e += 64) { t_row[e] = k + e; t_src[e] = k + e; }
     int cnt = nbe;
     wave_sync();
-    for (int i = 0; i < nbe; ++i) {
-      const int p = pv[k + i];
-      if (p == k + i) continue;
-      // locate p among the touched rows (rows k..k+nbe-1 sit at index row-k)
-      int pos = -1;
-      if (p < k + nbe) pos = p - k;
-      else {
-        for (int base = nbe; base < cnt; base += 64) {
-          const int e = base + lane;
-          const bool hit = (e < cnt) && (t_row[e] == p);
-          const unsigned long long m = __ballot(hit);
-          if (m) { pos = base + __ffsll((long long)m) - 1; break; }
+    for (int c = 0; c < nbe; c += 64) {
+      // the chunk's pivots in one load; only the rows that move are visited
+      const int mp = c + lane < nbe ? pv[k + c + lane] : k + c + lane;
+      unsigned long long moved = __ballot(mp != k + c + lane);
+      while (moved) {
+        const int j = __ffsll((long long)moved) - 1;
+        moved &= moved - 1;
+        const int i = c + j;
+        const int p = __shfl(mp, j);
+        // locate p among the touched rows (rows k..k+nbe-1 sit at index row-k)
+        int pos = -1;
+        if (p < k + nbe) pos = p - k;
+        else {
+          for (int base = nbe; base < cnt; base += 64) {
+            const int e = base + lane;
+            const bool hit = (e < cnt) && (t_row[e] == p);
+            const unsigned long long m = __ballot(hit);
+            if (m) { pos = base + __ffsll((long long)m) - 1; break; }
+          }
+          if (pos < 0) {
+            pos = cnt;
+            if (lane == 0) { t_row[cnt] = p; t_src[cnt] = p; }
+            cnt += 1;
+            wave_sync();
+          }
         }
-        if (pos < 0) {
-          pos = cnt;
-          if (lane == 0) { t_row[cnt] = p; t_src[cnt] = p; }
-          cnt += 1;
-          wave_sync();
+        if (lane == 0) {
+          const int s = t_src[i];
+          t_src[i] = t_src[pos];
+          t_src[pos] = s;
         }
+        wave_sync();
       }
-      if (lane == 0) {
-        const int s = t_src[i];
-        t_src[i] = t_src[pos];
-        t_src[pos] = s;
-      }
+    }
+    // keep only the rows whose source differs (a panel that pivots on its
+    // diagonal moves nothing); a chunk's entries are read before any is
+    // written, and land at or below their own index
+    int kept = 0;
+    for (int base = 0; base < cnt; base += 64) {
+      const int e = base + lane;
+      const int r = e < cnt ? t_row[e] : 0, sr = e < cnt ? t_src[e] : 0;
+      const bool keep = e < cnt && sr != r;
+      const unsigned long long m = __ballot(keep);
+      const int at = kept + __popcll(m & ((1ull << lane) - 1ull));
+      wave_sync();
+      if (keep) { t_row[at] = r; t_src[at] = sr; }
+      kept += __popcll(m);
       wave_sync();
     }
-    if (lane == 0) s_cnt = cnt;
+    if (lane == 0) s_cnt = kept;
   }
   __syncthreads();
   const int cnt = s_cnt;
-  const int jc = tid % SWC;
-  const int col = c0 + jc;
-  for (int e = tid / SWC; e < cnt; e += 256 / SWC)
-    if (col < ncols) vals[e][jc] = Xb[t_src[e] + (long)col * ldx];
+  // a wave moves whole columns, its lanes along the touched rows (the panel's
+  // rows are contiguous in a column, so those accesses coalesce)
+  const int lane = tid & 63, wv = tid >> 6;
+  for (int jc = wv; jc < SWC && c0 + jc < ncols; jc += 4) {
+    const cplx<R>* xc = Xb + (long)(c0 + jc) * ldx;
+    for (int e = lane; e < cnt; e += 64) vals[jc][e] = xc[t_src[e]];
+  }
   __syncthreads();
-  for (int e = tid / SWC; e < cnt; e += 256 / SWC)
-    if (col < ncols) Xb[t_row[e] + (long)col * ldx] = vals[e][jc];
+  for (int jc = wv; jc < SWC && c0 + jc < ncols; jc += 4) {
+    cplx<R>* xc = Xb + (long)(c0 + jc) * ldx;
+    for (int e = lane; e < cnt; e += 64) xc[t_row[e]] = vals[jc][e];
+  }
 }
 
 template <typename R>
