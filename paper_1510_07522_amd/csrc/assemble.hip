@@ -1,4 +1,6 @@
 // Assembly of T(z_j) at many nodes, BEM kernels, and small elementwise kernels.
+#include <algorithm>
+
 #include "bem.h"
 #include "common.h"
 #include "kernels.h"
@@ -107,34 +109,37 @@ int assemble_bem(int n, const double* xyz, double h, int nz, const c128* z_dev, 
 template int assemble_bem<double>(int, const double*, double, int, const c128*, c128*, long, long, hipStream_t);
 template int assemble_bem<float>(int, const double*, double, int, const c128*, c64*, long, long, hipStream_t);
 
-// ||T(z_j)||_F^2 of the BEM matrix: per row-block partial sums, then a fixed-order
-// final sum per node (no float atomics: results are bit-reproducible).
+// ||T(z_j)||_F^2 of the BEM matrix.  |T_ic| depends on the distance of points i
+// and c alone, so each workgroup sums the entries right of the diagonal in rows
+// x and n-1-x (n-1 entries together), doubled, plus their diagonal entries
+// (the same value in every row); the pairs' partial sums are then added in a
+// fixed order per node (no float atomics: results are bit-reproducible).
 __global__ __launch_bounds__(256) void bem_fro2_partial(int n, const double* xyz, double h, int nz,
                                                         const c128* z, double* partial) {
-  __shared__ double red[256];
-  const int i = blockIdx.x;       // one row per block
-  const int j = blockIdx.y;       // node
+  __shared__ double red[4];
+  const int x = blockIdx.x, j = blockIdx.y, tid = threadIdx.x;
+  const int np = (n + 1) / 2, i1 = x, i2 = n - 1 - x;
+  const int len1 = n - 1 - i1, len = i2 != i1 ? len1 + (n - 1 - i2) : len1;
   const c128 zj = z[j];
   double acc = 0.0;
-  for (int c = threadIdx.x; c < n; c += 256) {
-    if (c == i) {
-      const double re = -zj.im * RSRR_INV4PI + 0.5 / h, im = zj.re * RSRR_INV4PI;
-      acc += re * re + im * im;
-    } else {
-      const double dx = xyz[3 * i] - xyz[3 * c], dy = xyz[3 * i + 1] - xyz[3 * c + 1],
-                   dz = xyz[3 * i + 2] - xyz[3 * c + 2];
-      const double r = sqrt(dx * dx + dy * dy + dz * dz);
-      const double m = exp(-zj.im * r) * (RSRR_INV4PI / r);
-      acc += m * m;
-    }
+  for (int t = tid; t < len; t += 256) {
+    const int i = t < len1 ? i1 : i2;
+    const int c = t < len1 ? i1 + 1 + t : i2 + 1 + (t - len1);
+    const double dx = xyz[3 * i] - xyz[3 * c], dy = xyz[3 * i + 1] - xyz[3 * c + 1],
+                 dz = xyz[3 * i + 2] - xyz[3 * c + 2];
+    const double r = sqrt(dx * dx + dy * dy + dz * dz);
+    const double m = exp(-zj.im * r) * (RSRR_INV4PI / r);
+    acc += m * m;
   }
-  red[threadIdx.x] = acc;
+  acc *= 2.0;
+  if (tid == 0) {
+    const double re = -zj.im * RSRR_INV4PI + 0.5 / h, im = zj.re * RSRR_INV4PI;
+    acc += (i2 != i1 ? 2.0 : 1.0) * (re * re + im * im);
+  }
+  for (int o = 32; o > 0; o >>= 1) acc += __shfl_down(acc, o);
+  if ((tid & 63) == 0) red[tid >> 6] = acc;
   __syncthreads();
-  for (int o = 128; o > 0; o >>= 1) {
-    if (threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) partial[(long)j * n + i] = red[0];
+  if (tid == 0) partial[(long)j * np + x] = (red[0] + red[1]) + (red[2] + red[3]);
 }
 
 __global__ __launch_bounds__(256) void sum_rows_kernel(const double* partial, int len, int count,
@@ -155,9 +160,10 @@ __global__ __launch_bounds__(256) void sum_rows_kernel(const double* partial, in
 int bem_fro2(int n, const double* xyz, double h, int nz, const c128* z_dev, double* partial,
              double* fro2, hipStream_t s) {
   if (nz <= 0) return ST_OK;
-  hipLaunchKernelGGL(bem_fro2_partial, dim3(n, nz), dim3(256), 0, s, n, xyz, h, nz, z_dev, partial);
+  const int np = (n + 1) / 2;
+  hipLaunchKernelGGL(bem_fro2_partial, dim3(np, nz), dim3(256), 0, s, n, xyz, h, nz, z_dev, partial);
   RSRR_LAUNCH_CHECK();
-  hipLaunchKernelGGL(sum_rows_kernel, dim3(nz), dim3(256), 0, s, partial, n, nz, fro2);
+  hipLaunchKernelGGL(sum_rows_kernel, dim3(nz), dim3(256), 0, s, partial, np, nz, fro2);
   RSRR_LAUNCH_CHECK();
   return ST_OK;
 }
@@ -266,30 +272,35 @@ int combine_residual(const c128* U, long ldu, const c128* const* P_host, int J, 
   return ST_OK;
 }
 
+// Column slices of each batch entry, one workgroup each (lanes along the rows,
+// so a wave reads a contiguous piece of a column); the slices' sums are added
+// in a fixed order afterwards.
 __global__ __launch_bounds__(256) void block_fro2_kernel(const c128* X, long ldx, long sX, int rows,
-                                                         int cols, double* out) {
-  __shared__ double red[256];
-  const int b = blockIdx.x;
+                                                         int cols, int P, double* part) {
+  __shared__ double red[4];
+  const int x = blockIdx.x, b = blockIdx.y, tid = threadIdx.x;
+  const c128* Xb = X + (long)b * sX;
   double acc = 0.0;
-  const long cnt = (long)rows * cols;
-  for (long e = threadIdx.x; e < cnt; e += 256) {
-    const int i = (int)(e % rows), c = (int)(e / rows);
-    acc += abs2(X[(long)b * sX + i + (long)c * ldx]);
-  }
-  red[threadIdx.x] = acc;
+  for (int c = x; c < cols; c += P)
+    for (int i = tid; i < rows; i += 256) acc += abs2(Xb[i + (long)c * ldx]);
+  for (int o = 32; o > 0; o >>= 1) acc += __shfl_down(acc, o);
+  if ((tid & 63) == 0) red[tid >> 6] = acc;
   __syncthreads();
-  for (int o = 128; o > 0; o >>= 1) {
-    if (threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) out[b] = red[0];
+  if (tid == 0) part[(long)b * P + x] = (red[0] + red[1]) + (red[2] + red[3]);
 }
 
 int block_fro2(const c128* X, long ldx, long sX, int rows, int cols, int batch, double* out,
-               hipStream_t s) {
+               double* part, hipStream_t s) {
   if (batch <= 0) return ST_OK;
-  hipLaunchKernelGGL(block_fro2_kernel, dim3(batch), dim3(256), 0, s, X, ldx, sX, rows, cols, out);
+  const int P = std::max(1, std::min(cols, BLOCK_FRO2_PARTS));
+  if (P > 1 && !part) return set_error(ST_EINVAL, "block_fro2: no buffer for the partial sums");
+  hipLaunchKernelGGL(block_fro2_kernel, dim3(P, batch), dim3(256), 0, s, X, ldx, sX, rows, cols, P,
+                     P > 1 ? part : out);
   RSRR_LAUNCH_CHECK();
+  if (P > 1) {
+    hipLaunchKernelGGL(sum_rows_kernel, dim3(batch), dim3(256), 0, s, part, P, batch, out);
+    RSRR_LAUNCH_CHECK();
+  }
   return ST_OK;
 }
 

@@ -344,6 +344,8 @@ int sample_end(SamplePlan* sp) {
     RSRR_TRY(p->ws.get<c128>("s_R", (size_t)n * cols, &Rb));
     RSRR_TRY(p->ws.get<double>("s_nrm", 3 * (size_t)N + 1, &nrm));
     RSRR_TRY(p->ws.get<int>("s_active", N, &active_dev));
+    double* fpart = nullptr;
+    RSRR_TRY(p->ws.get<double>("s_fpart", (size_t)N * BLOCK_FRO2_PARTS, &fpart));
     LUWork<float>& w = P.w64;
     RSRR_TRY(check_info(infod, N, s, z));
     // Y0 = T~^{-1} U in complex64, widened to fp64
@@ -360,7 +362,7 @@ int sample_end(SamplePlan* sp) {
     } else {
       for (int j = 0; j < N; ++j) fro2[j] = fro2_coeff(p, &f[(size_t)j * p->J]);
     }
-    RSRR_TRY(block_fro2(U, ldu, 0, n, L, 1, nrm + 3 * N, s));
+    RSRR_TRY(block_fro2(U, ldu, 0, n, L, 1, nrm + 3 * N, fpart, s));
     RSRR_HIP(hipMemcpyAsync(u2.data(), nrm + 3 * N, sizeof(double), hipMemcpyDeviceToHost, s));
     // BEM: the fp64 T(z_j) of every node assembled once for all refinement
     // sweeps, in the buffer a complex128 fallback factors them in
@@ -385,8 +387,8 @@ int sample_end(SamplePlan* sp) {
       const bool res_full = (nact == N);
       if (res_full) {
         RSRR_TRY(residual_fp64(p, N, L, f_dev, U, ldu, S, lds, Rb, s, Tres));
-        RSRR_TRY(block_fro2(Rb, n, (long)L * n, n, L, N, nrm, s));
-        RSRR_TRY(block_fro2(S, lds, (long)L * lds, n, L, N, nrm + N, s));
+        RSRR_TRY(block_fro2(Rb, n, (long)L * n, n, L, N, nrm, fpart, s));
+        RSRR_TRY(block_fro2(S, lds, (long)L * lds, n, L, N, nrm + N, fpart, s));
         RSRR_HIP(hipMemcpyAsync(r2.data(), nrm, N * sizeof(double), hipMemcpyDeviceToHost, s));
         RSRR_HIP(hipMemcpyAsync(y2.data(), nrm + N, N * sizeof(double), hipMemcpyDeviceToHost, s));
         RSRR_HIP(hipStreamSynchronize(s));
@@ -407,8 +409,8 @@ int sample_end(SamplePlan* sp) {
                            lds, n, L, idx_dev, na, Sa, (long)n);
         RSRR_LAUNCH_CHECK();
         RSRR_TRY(residual_fp64(p, na, L, fa_dev, U, ldu, Sa, n, Ra, s, Tres, idx.data()));
-        RSRR_TRY(block_fro2(Ra, n, (long)L * n, n, L, na, nrm, s));
-        RSRR_TRY(block_fro2(Sa, n, (long)L * n, n, L, na, nrm + N, s));
+        RSRR_TRY(block_fro2(Ra, n, (long)L * n, n, L, na, nrm, fpart, s));
+        RSRR_TRY(block_fro2(Sa, n, (long)L * n, n, L, na, nrm + N, fpart, s));
         std::vector<double> ra(na), ya(na);
         RSRR_HIP(hipMemcpyAsync(ra.data(), nrm, na * sizeof(double), hipMemcpyDeviceToHost, s));
         RSRR_HIP(hipMemcpyAsync(ya.data(), nrm + N, na * sizeof(double), hipMemcpyDeviceToHost, s));

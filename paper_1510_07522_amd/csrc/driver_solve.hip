@@ -452,7 +452,7 @@ int solve_end(rsrr_problem* p, const rsrr_contour* c, const rsrr_params* prm, rs
         fro2[q] = std::max(0.0, ss.real());
       }
     }
-    RSRR_TRY(block_fro2(Rr, n, n, n, 1, nin, nrm, s));
+    RSRR_TRY(block_fro2(Rr, n, n, n, 1, nin, nrm, nullptr, s));
     std::vector<double> r2(nin);
     RSRR_HIP(hipMemcpyAsync(r2.data(), nrm, nin * sizeof(double), hipMemcpyDeviceToHost, s));
     RSRR_HIP(hipStreamSynchronize(s));

@@ -125,7 +125,8 @@ template <typename R> int assemble_coeff(const CoeffSet& cs, int nz, const c128*
 template <typename R> int assemble_bem(int n, const double* xyz, double h, int nz,
                                        const c128* z_dev, cplx<R>* T, long ldt, long sT,
                                        hipStream_t s);
-// Frobenius norms of the BEM matrices at nz nodes (fp64), fro2[j] = ||T(z_j)||_F^2.
+// Frobenius norms of the BEM matrices at nz nodes (fp64), fro2[j] = ||T(z_j)||_F^2;
+// partial holds nz * ceil(n / 2) doubles.
 int bem_fro2(int n, const double* xyz, double h, int nz, const c128* z_dev,
              double* partial, double* fro2, hipStream_t s);
 // R_j = U - T(z_j) Y_j for the BEM matrix, assembled on the fly in fp64.
@@ -149,8 +150,11 @@ int combine_residual(const c128* U, long ldu, const c128* const* P_dev, int J,
                      const c128* coef, int n, int L, int batch, c128* R, long ldr,
                      hipStream_t s);
 // Per-batch Frobenius norm squared of an n x cols block: out[b] (deterministic).
+// part holds batch * min(cols, 32) partial sums (unused, and may be null, when
+// cols == 1).
+constexpr int BLOCK_FRO2_PARTS = 32;
 int block_fro2(const c128* X, long ldx, long sX, int rows, int cols, int batch,
-               double* out, hipStream_t s);
+               double* out, double* part, hipStream_t s);
 
 // Y = diag(d) X  (n x cols)
 int diag_scale(const c128* d, const c128* X, long ldx, c128* Y, long ldy, int n, int cols,
