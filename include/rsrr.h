@@ -40,7 +40,8 @@ enum {
   RSRR_EHIP = -3,        /* a HIP runtime call or kernel launch failed */
   RSRR_ESINGULAR = -4,   /* T(z_j) exactly singular at a sampling node */
   RSRR_EBUSY = -5,       /* request does not fit the memory budget */
-  RSRR_ENOTCONV = -6,    /* an inner iteration (eigen / SVD) did not converge */
+  RSRR_ENOTCONV = -6,    /* an inner iteration (eigen / SVD, or the sampling's refinement
+                            above order 8192) did not converge */
   RSRR_ETIMEDOUT = -7,   /* a bounded wait ended before the request finished */
   RSRR_WARN_RANK_SATURATED = 1,  /* k_S == N*L < n: the sample space may be too small (eq. eq-rank-nc) */
   RSRR_WARN_COUNT_MISMATCH = 2,  /* final count differs from the winding count (eq. eq-ncs) */
@@ -194,7 +195,11 @@ void rsrr_default_params(rsrr_params* p);
 /* Coefficient-form problem T(z) = sum_{k<J} f_k(z) A_k (eq. eq-Z-expr).
  * kinds[k] is RSRR_MAT_*, A[k] a host pointer to its data (copied to the
  * device; the caller may free it on return), f[k] its scalar function.
- * 1 <= n <= 8192, 1 <= J <= 16.  stream: hipStream_t or NULL. */
+ * 1 <= n <= 16384, 1 <= J <= 16.  stream: hipStream_t or NULL.  Orders above
+ * 8192 need precision RSRR_PREC_C64_IR (complex128 factorisations, those of the
+ * precision RSRR_PREC_C128 and of the refinement's fallback, go up to 8192):
+ * rsrr_solve then fails with RSRR_EINVAL for RSRR_PREC_C128, and with
+ * RSRR_ENOTCONV when the refinement leaves a node above ir_tol. */
 int rsrr_create(rsrr_problem** out, int n, int J, const int* kinds,
                 const void* const* A, const rsrr_fn* f, void* stream);
 
@@ -208,7 +213,8 @@ int rsrr_create_fn(rsrr_problem** out, int n, int J, const int* kinds, const voi
  * T_ij(z) = exp(i z r_ij)/(4 pi r_ij) for i != j, T_ii(z) = i z/(4 pi) + 1/(2h).
  * xyz: host, n*3 doubles (x, y, z per point).  Entries are generated on the fly
  * at every node; the reduced problem uses the Chebyshev interpolation of
- * eq. eq-Ts-coefs on [Re(center) - a, Re(center) + a]. */
+ * eq. eq-Ts-coefs on [Re(center) - a, Re(center) + a].  2 <= n <= 16384, with the
+ * limits of rsrr_create above order 8192. */
 int rsrr_create_bem(rsrr_problem** out, int n, const double* xyz, double h, void* stream);
 
 void rsrr_destroy(rsrr_problem* p);
@@ -362,7 +368,8 @@ int rsrr_cgemm_batched(int opA, int opB, int M, int N, int K, rsrr_complex alpha
  * the L columns of earlier ones), B by the solution.  complex128 when
  * precision = RSRR_PREC_C128, complex64 (interleaved floats) when
  * RSRR_PREC_C64_IR.  info_host (may be NULL): batch ints, 0 or the 1-based
- * index of the first exactly-zero pivot.  Returns RSRR_ESINGULAR if any. */
+ * index of the first exactly-zero pivot.  Returns RSRR_ESINGULAR if any.
+ * Orders: n <= 8192 (complex128), n <= 16384 (complex64). */
 int rsrr_gesv_batched(int precision, int n, int nrhs, void* A, int lda, long long sA, void* B,
                       int ldb, long long sB, int batch, int nb, int* info_host, void* stream);
 
@@ -394,7 +401,8 @@ int rsrr_gesv_batched_noalloc(int precision, int n, int nrhs, void* A, int lda, 
  * solve with rsrr_params.nb = 0 takes the width of the table entry of its
  * precision with the nearest order (then the nearest node count), or 64 if
  * there is none.  rsrr_tune_save writes the table as JSON; rsrr_tune_load
- * reads such a file into the table and returns the number of entries read. */
+ * reads such a file into the table and returns the number of entries read.
+ * Orders as rsrr_gesv_batched. */
 int rsrr_tune_lu(int precision, int n, int batch, int* nb_best, double* ms_best);
 int rsrr_tune_save(const char* path);
 int rsrr_tune_load(const char* path);

@@ -253,6 +253,9 @@ int check_params(const rsrr_problem* p, const rsrr_contour* c, const rsrr_params
     return set_error(ST_EINVAL, "nb_reduced must be in [0, 64] (0: 64)");
   if (prm->precision != RSRR_PREC_C128 && prm->precision != RSRR_PREC_C64_IR)
     return set_error(ST_EINVAL, "unknown precision %d", prm->precision);
+  if (prm->precision == RSRR_PREC_C128 && p->n > LU_MAX_N_C128)
+    return set_error(ST_EINVAL, "n=%d: complex128 factorisations go up to order %d (use c64_ir)", p->n,
+                     LU_MAX_N_C128);
   if (prm->NS < 2 || prm->K < 1) return set_error(ST_EINVAL, "NS >= 2 and K >= 1 required");
   if ((long)prm->N * prm->L > (1L << 20)) return set_error(ST_EINVAL, "N*L too large");
   if (prm->scheme != RSRR_SCHEME_SAMPLING && prm->scheme != RSRR_SCHEME_MOMENT)
@@ -307,7 +310,8 @@ static int create_coeff(rsrr_problem** out, int n, int J, const int* kinds, cons
                         void* stream) {
   if (!out || !kinds || !A) return set_error(ST_EINVAL, "rsrr_create: null argument");
   *out = nullptr;
-  if (n < 1 || n > 8192) return set_error(ST_EINVAL, "rsrr_create: n=%d outside [1, 8192]", n);
+  if (n < 1 || n > LU_MAX_N_C64)
+    return set_error(ST_EINVAL, "rsrr_create: n=%d outside [1, %d]", n, LU_MAX_N_C64);
   if (J < 1 || J > 16) return set_error(ST_EINVAL, "rsrr_create: J=%d outside [1, 16]", J);
   for (int k = 0; k < J; ++k) {
     if (kinds[k] < 0 || kinds[k] > 3) return set_error(ST_EINVAL, "rsrr_create: kind[%d]=%d", k, kinds[k]);
@@ -391,7 +395,8 @@ int rsrr_create_fn(rsrr_problem** out, int n, int J, const int* kinds, const voi
 int rsrr_create_bem(rsrr_problem** out, int n, const double* xyz, double h, void* stream) {
   if (!out || !xyz) return set_error(ST_EINVAL, "rsrr_create_bem: null argument");
   *out = nullptr;
-  if (n < 2 || n > 8192) return set_error(ST_EINVAL, "rsrr_create_bem: n=%d outside [2, 8192]", n);
+  if (n < 2 || n > LU_MAX_N_C64)
+    return set_error(ST_EINVAL, "rsrr_create_bem: n=%d outside [2, %d]", n, LU_MAX_N_C64);
   if (!(h > 0)) return set_error(ST_EINVAL, "rsrr_create_bem: h must be positive");
   rsrr_problem* p = new rsrr_problem();
   p->n = n;

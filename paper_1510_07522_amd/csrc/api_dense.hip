@@ -32,7 +32,7 @@ int gemm_entry(int opA, int opB, int M, int N, int K, rsrr_complex alpha, const 
 template <typename R>
 int gesv_entry(int n, int nrhs, void* A, int lda, long long sA, void* B, int ldb, long long sB,
                int batch, int nb, int* info_host, void* stream) {
-  if (n < 1 || n > 8192 || nrhs < 0 || batch < 1 || lda < n || ldb < n || nb < 1 || nb > 64)
+  if (n < 1 || n > lu_max_order<R>() || nrhs < 0 || batch < 1 || lda < n || ldb < n || nb < 1 || nb > 64)
     return set_error(ST_EINVAL, "gesv: bad arguments");
   if (!A || (nrhs > 0 && !B)) return set_error(ST_EINVAL, "gesv: null pointer");
   hipStream_t s = (hipStream_t)stream;

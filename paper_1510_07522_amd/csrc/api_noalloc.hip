@@ -50,7 +50,7 @@ size_t round256(size_t b) { return (b + 255) & ~(size_t)255; }
 template <typename R>
 int gesv_noalloc(int n, int nrhs, void* A, int lda, long long sA, void* B, int ldb, long long sB, int batch,
                  int nb, int* info_host, void* stream) {
-  if (n < 1 || n > 8192 || nrhs < 0 || batch < 1 || lda < n || ldb < n || nb < 1 || nb > 64)
+  if (n < 1 || n > lu_max_order<R>() || nrhs < 0 || batch < 1 || lda < n || ldb < n || nb < 1 || nb > 64)
     return set_error(ST_EINVAL, "gesv_noalloc: bad arguments");
   if (!A || (nrhs > 0 && !B)) return set_error(ST_EINVAL, "gesv_noalloc: null pointer");
   const size_t b_info = round256((size_t)batch * sizeof(int));

@@ -466,6 +466,9 @@ int sample_end(SamplePlan* sp) {
     // complex128 fallback for the nodes left above ir_tol
     std::vector<int> bad;
     for (int j = 0; j < N; ++j) if (!(eta_v[j] <= prm->ir_tol)) bad.push_back(j);
+    if (!bad.empty() && n > LU_MAX_N_C128)
+      return set_error(ST_ENOTCONV, "refinement left %d node(s) above ir_tol=%g and the complex128 fallback "
+                       "goes up to order %d (n=%d)", (int)bad.size(), prm->ir_tol, LU_MAX_N_C128, n);
     if (!bad.empty()) {
       fallback = (int)bad.size();
       warn |= RSRR_WARN_IR_FALLBACK;

@@ -54,6 +54,10 @@ int bem_gemm(const GemmBatch<double>& g, const double* xyz, double h, const c128
 // interchanges panel by panel.  The inverses of the unit-lower and upper
 // diagonal blocks of every panel are kept in dinv (batch x npanel x 2 x nb x nb).
 // info[b] = 0 or the 1-based index of the first exactly-zero pivot.
+// Orders up to lu_max_order<R>(): a panel's rows live in the registers of one
+// 1024-thread workgroup, 16 complex64 or 8 complex128 values per thread.
+constexpr int LU_MAX_N_C64 = 16384, LU_MAX_N_C128 = 8192;
+template <typename R> constexpr int lu_max_order() { return sizeof(R) == 4 ? LU_MAX_N_C64 : LU_MAX_N_C128; }
 template <typename R> struct LUWork {
   int n = 0, nb = 64, batch = 0;
   long lda = 0, sA = 0;

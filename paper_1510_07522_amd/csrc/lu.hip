@@ -586,13 +586,16 @@ static int launch_panel(const LUWork<R>& w, int k, int nbe, hipStream_t s) {
   if (m <= PNT) return launch_panel_rows<R, 1>(w, k, nbe, s);
   if (m <= 2 * PNT) return launch_panel_rows<R, 2>(w, k, nbe, s);
   if (m <= 4 * PNT) return launch_panel_rows<R, 4>(w, k, nbe, s);
+  if constexpr (sizeof(R) == 4) {
+    if (m > 8 * PNT) return launch_panel_rows<R, 16>(w, k, nbe, s);
+  }
   return launch_panel_rows<R, 8>(w, k, nbe, s);
 }
 
 template <typename R>
 int lu_factor(const LUWork<R>& w, hipStream_t s) {
   if (w.n <= 0 || w.batch <= 0) return ST_OK;
-  if (w.n > 8 * PNT) return set_error(ST_EINVAL, "lu_factor: n=%d exceeds 8192", w.n);
+  if (w.n > lu_max_order<R>()) return set_error(ST_EINVAL, "lu_factor: n=%d exceeds %d", w.n, lu_max_order<R>());
   if (w.nb < 1 || w.nb > MAXNB) return set_error(ST_EINVAL, "lu_factor: nb=%d", w.nb);
   hipLaunchKernelGGL(zero_int_kernel, dim3((unsigned)cdivl(w.batch, 256)), dim3(256), 0, s,
                      w.info, w.batch);
@@ -995,7 +998,7 @@ int lu_factor_segments(const std::vector<LUWork<R>>& ws, hipStream_t s, hipStrea
   for (const LUWork<R>& w : ws) {
     if (w.nb != nb || w.gauss3m != g3m || w.full_swap)
       return set_error(ST_EINVAL, "lu_factor_segments: batches must share nb and the product form");
-    if (w.n > 8 * PNT || w.n < 1 || w.batch < 1) return set_error(ST_EINVAL, "lu_factor_segments: n=%d", w.n);
+    if (w.n > lu_max_order<R>() || w.n < 1 || w.batch < 1) return set_error(ST_EINVAL, "lu_factor_segments: n=%d", w.n);
     nmax = std::max(nmax, w.n);
   }
   if (nb < 1 || nb > MAXNB || lu_group(nb) < 2) return set_error(ST_EINVAL, "lu_factor_segments: nb=%d", nb);
@@ -1011,14 +1014,14 @@ int lu_factor_segments(const std::vector<LUWork<R>>& ws, hipStream_t s, hipStrea
   // panels at column k of every batch whose order exceeds k, one launch per
   // register class (rows per thread) and MAXSEG batches
   auto panels = [&](int k, hipStream_t st) -> int {
-    for (int rows : {1, 2, 4, 8}) {
+    for (int rows : {1, 2, 4, 8, 16}) {
       std::vector<LUSegDev<R>> list;
       std::vector<int> bt;
       double fl = 0, by = 0;
       for (const LUWork<R>& w : ws) {
         const int m = w.n - k;
         if (m <= 0) continue;
-        const int cls = m <= PNT ? 1 : m <= 2 * PNT ? 2 : m <= 4 * PNT ? 4 : 8;
+        const int cls = m <= PNT ? 1 : m <= 2 * PNT ? 2 : m <= 4 * PNT ? 4 : m <= 8 * PNT ? 8 : 16;
         if (cls != rows) continue;
         list.push_back(seg_of(w));
         bt.push_back(w.batch);
@@ -1031,7 +1034,10 @@ int lu_factor_segments(const std::vector<LUWork<R>>& ws, hipStream_t s, hipStrea
           case 1: return launch_panel_seg_rows<R, 1>(a, tot, k, nb, ws[0].tag, fl, by, st);
           case 2: return launch_panel_seg_rows<R, 2>(a, tot, k, nb, ws[0].tag, fl, by, st);
           case 4: return launch_panel_seg_rows<R, 4>(a, tot, k, nb, ws[0].tag, fl, by, st);
-          default: return launch_panel_seg_rows<R, 8>(a, tot, k, nb, ws[0].tag, fl, by, st);
+          case 8: return launch_panel_seg_rows<R, 8>(a, tot, k, nb, ws[0].tag, fl, by, st);
+          default:
+            if constexpr (sizeof(R) == 4) return launch_panel_seg_rows<R, 16>(a, tot, k, nb, ws[0].tag, fl, by, st);
+            return set_error(ST_EINVAL, "lu_factor_segments: order above %d", lu_max_order<R>());
         }
       }));
     }

@@ -124,9 +124,10 @@ using namespace rsrr;
 extern "C" {
 
 int rsrr_tune_lu(int precision, int n, int batch, int* nb_best, double* ms_best) {
-  if (n < 1 || n > 8192 || batch < 1 || !nb_best) return set_error(ST_EINVAL, "rsrr_tune_lu: bad arguments");
   if (precision != RSRR_PREC_C128 && precision != RSRR_PREC_C64_IR)
     return set_error(ST_EINVAL, "rsrr_tune_lu: unknown precision %d", precision);
+  const int nmax = precision == RSRR_PREC_C128 ? LU_MAX_N_C128 : LU_MAX_N_C64;
+  if (n < 1 || n > nmax || batch < 1 || !nb_best) return set_error(ST_EINVAL, "rsrr_tune_lu: bad arguments");
   double ms = 0, all[3] = {0, 0, 0};
   int nb = 64;
   const int st = precision == RSRR_PREC_C128 ? tune_one<double>(n, batch, &nb, &ms, all)

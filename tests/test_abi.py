@@ -58,6 +58,29 @@ def test_default_params_and_error_paths_without_gpu():
 
 
 @pytest.mark.skipif(not os.path.exists(LIB), reason="librsrr.so not built")
+def test_order_limits_are_checked_before_any_device_call():
+    # complex64 factorisations go up to order 16384, complex128 ones to 8192
+    import paper_1510_07522_amd as P
+    from paper_1510_07522_amd import _binding
+    lib = P.load()
+    h = ctypes.c_void_p()
+    kinds = (ctypes.c_int * 1)(0)
+    ptrs = (ctypes.c_void_p * 1)(ctypes.c_void_p(1))
+    fns = (_binding.fn_t * 1)()
+    st = lib.rsrr_create(ctypes.byref(h), 16385, 1, kinds, ptrs, fns, None)
+    assert st == -1 and b"16384" in lib.rsrr_last_error()
+    xyz = (ctypes.c_double * 3)()
+    st = lib.rsrr_create_bem(ctypes.byref(h), 16385, xyz, ctypes.c_double(0.1), None)
+    assert st == -1 and b"16384" in lib.rsrr_last_error()
+    one = ctypes.c_void_p(1)
+    # precision 0 = complex128: 8193 is refused, before any allocation
+    st = lib.rsrr_gesv_batched(0, 8193, 1, one, 8193, 0, one, 8193, 0, 1, 64, None, None)
+    assert st == -1 and b"gesv" in lib.rsrr_last_error()
+    st = lib.rsrr_gesv_batched(1, 16385, 1, one, 16385, 0, one, 16385, 0, 1, 64, None, None)
+    assert st == -1 and b"gesv" in lib.rsrr_last_error()
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="librsrr.so not built")
 def test_load_shares_torchs_hip_runtime():
     # loading the library before torch is imported must not leave a second HIP
     # runtime in the process (torch's memory and streams would be foreign to it)
