@@ -283,6 +283,65 @@ __global__ __launch_bounds__(sizeof(R) == 8 ? 512 : 256) void gemm_kernel(GemmBa
                                             blockIdx.z);
 }
 
+// Workgroup (x, b) takes columns 64x .. 64x+63 of B_b through the group's
+// panels in order, one 64x64 tile product at a time: the columns are
+// independent, so no other workgroup reads or writes them, and the barrier
+// that ends each product makes its stores visible to the next one.  The
+// diagonal block's product is in place: its single row tile reads all of B_k
+// before writing it.
+template <typename R, bool G3M>
+__global__ __launch_bounds__(sizeof(R) == 8 ? 512 : 256) void lu_group_solve_kernel(LUGroupSolve<R> q) {
+  const int b = blockIdx.y, n0 = blockIdx.x * BN;
+  if (q.active && !q.active[b]) return;
+  const BemGen none{nullptr, 0.0, nullptr};
+  GemmBatch<R> g;
+  g.N = q.nrhs;
+  g.ldb = q.ldb; g.sB = q.sB;
+  g.ldc = q.ldb; g.sC = q.sB;
+  for (int t = 0; t < q.p1 - q.p0; ++t) {
+    const int p = q.lower ? q.p0 + t : q.p1 - 1 - t;
+    const int k = p * q.nb, nbe = min(q.nb, q.n - k);
+    g.M = nbe; g.K = nbe;
+    g.alpha = mk<R>(1, 0); g.beta = mk<R>(0, 0);
+    g.A = q.dinv + (long)p * 2 * q.nb * q.nb + (q.lower ? 0 : (long)q.nb * q.nb);
+    g.lda = q.nb; g.sA = q.sD;
+    g.B = q.B + k; g.C = q.B + k;
+    gemm_body<R, OP_N, OP_N, false, G3M, false>(g, none, 0, n0, b);
+    const int k0 = q.p0 * q.nb, k1 = min(q.n, q.p1 * q.nb);
+    const int r0 = q.lower ? k + nbe : k0, rows = q.lower ? k1 - k - nbe : k - k0;
+    if (rows <= 0) continue;
+    g.M = rows; g.K = nbe;
+    g.alpha = mk<R>(-1, 0); g.beta = mk<R>(1, 0);
+    g.A = q.A + r0 + (long)k * q.lda; g.lda = q.lda; g.sA = q.sA;
+    g.B = q.B + k; g.C = q.B + r0;
+    for (int m0 = 0; m0 < rows; m0 += BM) gemm_body<R, OP_N, OP_N, false, G3M, false>(g, none, m0, n0, b);
+  }
+}
+
+template <typename R>
+int lu_group_solve(const LUGroupSolve<R>& q, hipStream_t s) {
+  if (q.nrhs <= 0 || q.batch <= 0 || q.p1 <= q.p0) return ST_OK;
+  if (q.nb < 1 || q.nb > BM || q.p0 < 0 || (long)q.p1 * q.nb > (long)q.n + q.nb - 1)
+    return set_error(ST_EINVAL, "lu_group_solve: bad group %d..%d (nb %d, n %d)", q.p0, q.p1, q.nb, q.n);
+  const dim3 grid((unsigned)cdivl(q.nrhs, BN), (unsigned)q.batch);
+  const int k0 = q.p0 * q.nb, k1 = std::min(q.n, q.p1 * q.nb), w = k1 - k0;
+  // the group's triangle (w^2 / 2 entries) applied to nrhs columns
+  const double fl = 8.0 * 0.5 * w * (double)w * q.nrhs * q.batch;
+  KernelTimer kt(q.tag, s, fl, 2.0 * sizeof(cplx<R>) * (0.5 * w * (double)w + 2.0 * w * q.nrhs) * q.batch,
+                 timers_on() ? std::string("lu_group_solve_kernel<") + (sizeof(R) == 8 ? "double" : "float") +
+                                   (q.gauss3m ? ", true>" : ", false>")
+                             : std::string());
+  if (q.gauss3m)
+    hipLaunchKernelGGL((lu_group_solve_kernel<R, true>), grid, dim3(gemm_threads<R>()), 0, s, q);
+  else
+    hipLaunchKernelGGL((lu_group_solve_kernel<R, false>), grid, dim3(gemm_threads<R>()), 0, s, q);
+  RSRR_LAUNCH_CHECK();
+  return ST_OK;
+}
+
+template int lu_group_solve<double>(const LUGroupSolve<double>&, hipStream_t);
+template int lu_group_solve<float>(const LUGroupSolve<float>&, hipStream_t);
+
 __global__ __launch_bounds__(512) void bem_gemm_kernel(GemmBatch<double> g, BemGen bg) {
   gemm_body<double, OP_N, OP_N, false, false, true>(g, bg, blockIdx.x * BM, blockIdx.y * BN, blockIdx.z);
 }

@@ -27,6 +27,21 @@ template <typename R> struct GemmBatch {
   const char* tag = "gemm";   // kernel-timer class
 };
 template <typename R> int gemm_batched(const GemmBatch<R>& g, hipStream_t s);
+// The triangular solves inside one group of panels p0 .. p1-1 of a batched LU
+// (lu_solve): each panel's diagonal block by its inverse from dinv, then the
+// group's rows below it (lower) or above it (upper) updated, panel after panel,
+// for all nrhs right-hand sides of B in one launch.  Every 64x64 product is
+// computed as gemm_batched computes it.
+template <typename R> struct LUGroupSolve {
+  const cplx<R>* A = nullptr; long lda = 0, sA = 0;      // the factors
+  const cplx<R>* dinv = nullptr; long sD = 0;             // per panel: L then U block inverses
+  cplx<R>* B = nullptr; long ldb = 0, sB = 0;
+  int n = 0, nb = 0, nrhs = 0, batch = 0, p0 = 0, p1 = 0;
+  bool lower = true, gauss3m = false;
+  const int* active = nullptr;
+  const char* tag = "solve";
+};
+template <typename R> int lu_group_solve(const LUGroupSolve<R>& q, hipStream_t s);
 // Up to GSEG strided batches of different shapes in one launch (the LU
 // updates of instances of different orders): a persistent grid of workgroups
 // walks the 64x64 tiles of all segments in a fixed order, with no atomics,

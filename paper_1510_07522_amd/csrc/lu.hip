@@ -471,6 +471,35 @@ __global__ __launch_bounds__(256) void lu_permute_seg_kernel(LUSegArgs<R> a) {
                      sg.k, sg.nbe, c0);
 }
 
+// The interchanges of panels p0 .. p1-1 in order, on columns [0, ncols) of
+// every active matrix: one launch for a group of panels of the solves.
+template <typename R>
+__global__ __launch_bounds__(256) void lu_permute_group_kernel(cplx<R>* X, long ldx, long sX, int ncols,
+                                                               const int* ipiv, int n, int nb, int p0, int p1,
+                                                               const int* active) {
+  const int b = blockIdx.y;
+  if (active && !active[b]) return;
+  for (int p = p0; p < p1; ++p) {
+    lu_permute_body<R>(X + (long)b * sX, ldx, ncols, ipiv + (long)b * n, p * nb, min(nb, n - p * nb),
+                       blockIdx.x * SwCols<R>::v);
+    __syncthreads();
+  }
+}
+
+template <typename R>
+static int launch_permute_group(cplx<R>* X, long ldx, long sX, int ncols, const int* ipiv, int n, int nb,
+                                int p0, int p1, int batch, hipStream_t s, const int* active) {
+  if (ncols <= 0 || p1 <= p0) return ST_OK;
+  dim3 grid((unsigned)cdivl(ncols, SwCols<R>::v), (unsigned)batch);
+  KernelTimer kt("lu_permute", s, 0.0, 4.0 * sizeof(cplx<R>) * nb * (double)(p1 - p0) * ncols * batch,
+                 timers_on() ? std::string("lu_permute_group_kernel<") + (sizeof(R) == 8 ? "double" : "float") + ">"
+                             : std::string());
+  hipLaunchKernelGGL((lu_permute_group_kernel<R>), grid, dim3(256), 0, s, X, ldx, sX, ncols, ipiv, n, nb, p0, p1,
+                     active);
+  RSRR_LAUNCH_CHECK();
+  return ST_OK;
+}
+
 template <typename R>
 static int launch_permute(cplx<R>* X, long ldx, long sX, int ncols, const int* ipiv,
                           int ipiv_stride, int k, int nbe, int batch, hipStream_t s,
@@ -811,6 +840,13 @@ int lu_solve(const LUWork<R>& w, cplx<R>* B, long ldb, long sB, int nrhs, hipStr
     g.active = active;
     return gemm_batched<R>(g, s);
   };
+  // the triangular solves and updates inside a group, one launch
+  LUGroupSolve<R> gq;
+  gq.A = w.A; gq.lda = w.lda; gq.sA = w.sA;
+  gq.dinv = w.dinv; gq.sD = sD;
+  gq.B = B; gq.ldb = ldb; gq.sB = sB;
+  gq.n = n; gq.nb = nb; gq.nrhs = nrhs; gq.batch = w.batch;
+  gq.gauss3m = w.gauss3m; gq.active = active; gq.tag = t_solve.c_str();
   // forward, L: per group of lu_group(nb) panels (the row order lu_factor gives its L
   // columns): the group's interchanges on B, the triangular solves with the
   // diagonal-block inverses and updates inside the group, then the rows below
@@ -818,15 +854,9 @@ int lu_solve(const LUWork<R>& w, cplx<R>* B, long ldb, long sB, int nrhs, hipStr
   for (int p0 = 0; p0 < np; p0 += SB) {
     const int p1 = min(np, p0 + SB);
     const int k0 = p0 * nb, k1 = min(n, p1 * nb);
-    for (int p = p0; p < p1; ++p)
-      RSRR_TRY(launch_permute<R>(B, ldb, sB, nrhs, w.ipiv, n, p * nb, min(nb, n - p * nb), w.batch, s, active));
-    for (int p = p0; p < p1; ++p) {
-      const int k = p * nb, nbe = min(nb, n - k);
-      // in place: one workgroup row (M <= 64) reads all of B_k before writing it
-      RSRR_TRY(mm(nbe, nbe, w.dinv + (long)p * 2 * nb * nb, nb, sD, B + k, B + k, false));
-      if (k + nbe < k1)
-        RSRR_TRY(mm(k1 - k - nbe, nbe, w.A + (k + nbe) + (long)k * w.lda, w.lda, w.sA, B + k, B + k + nbe, true));
-    }
+    RSRR_TRY(launch_permute_group<R>(B, ldb, sB, nrhs, w.ipiv, n, nb, p0, p1, w.batch, s, active));
+    gq.p0 = p0; gq.p1 = p1; gq.lower = true;
+    RSRR_TRY(lu_group_solve<R>(gq, s));
     if (k1 < n) RSRR_TRY(mm(n - k1, k1 - k0, w.A + k1 + (long)k0 * w.lda, w.lda, w.sA, B + k0, B + k1, true));
   }
   // backward, U: per group from the last, solves and updates inside the
@@ -834,11 +864,8 @@ int lu_solve(const LUWork<R>& w, cplx<R>* B, long ldb, long sB, int nrhs, hipStr
   for (int p0 = ((np - 1) / SB) * SB; p0 >= 0; p0 -= SB) {
     const int p1 = min(np, p0 + SB);
     const int k0 = p0 * nb, k1 = min(n, p1 * nb);
-    for (int p = p1 - 1; p >= p0; --p) {
-      const int k = p * nb, nbe = min(nb, n - k);
-      RSRR_TRY(mm(nbe, nbe, w.dinv + (long)p * 2 * nb * nb + (long)nb * nb, nb, sD, B + k, B + k, false));
-      if (k > k0) RSRR_TRY(mm(k - k0, nbe, w.A + k0 + (long)k * w.lda, w.lda, w.sA, B + k, B + k0, true));
-    }
+    gq.p0 = p0; gq.p1 = p1; gq.lower = false;
+    RSRR_TRY(lu_group_solve<R>(gq, s));
     if (k0 > 0) RSRR_TRY(mm(k0, k1 - k0, w.A + (long)k0 * w.lda, w.lda, w.sA, B + k0, B, true));
   }
   return ST_OK;
